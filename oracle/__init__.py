@@ -1,0 +1,242 @@
+"""FP64 CPU oracle for the SPH density and force stages (TEST INFRASTRUCTURE).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never calls it and
+shares no code with it.
+
+The arithmetic lives in ``sph_oracle.c`` (plain C, FP64, one-sided gathers
+over a periodic cell list); this module only marshals numpy arrays.  Each
+function names the part of Gonnet (2014) it evaluates:
+
+* :func:`kernel_w`, :func:`kernel_dw` -- cubic spline w(q), w'(q), Sec. 2.1.
+* :func:`solve_h` -- Newton iteration of Eq. (3) for N_i(h_i) = N_ngb.
+* :func:`density` -- Eq. (2), Eq. (3) and dN/dh, drho/dh (for Omega), and the
+  velocity divergence and curl of Sec. 4.1.
+* :func:`ghost` -- Omega, P, sound speed, A = P/(Omega rho^2), Balsara f.
+* :func:`force` -- Eqs. (4)-(5) plus the Monaghan-Balsara viscosity, Sec. 4.1.
+* :func:`full_pass` -- the two stages in the paper's order (Sec. 2.1:
+  density for all particles first, then force).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sph_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+GAMMA = 5.0 / 3.0   # Sec. 4.2 constants
+ALPHA = 0.8
+N_NGB = 48.0
+
+ORA_OK, ORA_E_ARG, ORA_E_H_TOO_LARGE, ORA_E_NOT_CONVERGED, ORA_E_OOM = 0, 1, 2, 3, 4
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def build(force: bool = True) -> str:
+    """Compile sph_oracle.c into liboracle.so (gcc, -O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        d, i64, i32 = ctypes.c_double, ctypes.c_int64, ctypes.c_int
+        P = ctypes.c_void_p
+        lib.ora_w.restype = d
+        lib.ora_w.argtypes = [d]
+        lib.ora_dw.restype = d
+        lib.ora_dw.argtypes = [d]
+        lib.ora_W.restype = d
+        lib.ora_W.argtypes = [d, d]
+        lib.ora_dWdr.restype = d
+        lib.ora_dWdr.argtypes = [d, d]
+        lib.ora_dWdh.restype = d
+        lib.ora_dWdh.argtypes = [d, d]
+        lib.ora_solve_h.restype = i32
+        lib.ora_solve_h.argtypes = [i64, P, P, P, P, d, d, i32, i64, P, P, P]
+        lib.ora_density.restype = i32
+        lib.ora_density.argtypes = [i64, P, P, P, P, P, P, P, P, P, i64, P] + [P] * 8
+        lib.ora_ghost.restype = None
+        lib.ora_ghost.argtypes = [i64, P, P, P, P, P, P, d, P, P, P, P, P]
+        lib.ora_force.restype = i32
+        lib.ora_force.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, P, P, d, i64, P] + [P] * 8
+        lib.ora_brute_count.restype = None
+        lib.ora_brute_count.argtypes = [i64, P, P, P, P, P, P]
+        lib.ora_num_threads.restype = i32
+        lib.ora_num_threads.argtypes = []
+        _lib = lib
+    return _lib
+
+
+def _c(a, dtype=np.float64):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(st, what):
+    if st != ORA_OK:
+        names = {1: "invalid argument", 2: "h too large for the periodic box",
+                 3: "not converged", 4: "out of memory"}
+        raise OracleError(f"{what}: {names.get(st, st)}")
+
+
+def num_threads() -> int:
+    return int(_load().ora_num_threads())
+
+
+def kernel_w(q):
+    lib = _load()
+    return np.array([lib.ora_w(float(v)) for v in np.atleast_1d(q)])
+
+
+def kernel_dw(q):
+    lib = _load()
+    return np.array([lib.ora_dw(float(v)) for v in np.atleast_1d(q)])
+
+
+def kernel_W(r, h):
+    return _load().ora_W(float(r), float(h))
+
+
+def kernel_dWdr(r, h):
+    return _load().ora_dWdr(float(r), float(h))
+
+
+def kernel_dWdh(r, h):
+    return _load().ora_dWdh(float(r), float(h))
+
+
+def _split(pos):
+    pos = np.asarray(pos, dtype=np.float64)
+    return _c(pos[:, 0]), _c(pos[:, 1]), _c(pos[:, 2])
+
+
+def _sel(sel, n):
+    if sel is None:
+        return n, None
+    s = _c(sel, np.int64)
+    return len(s), s
+
+
+def solve_h(pos, h0, box, target=N_NGB, tol=1e-10, maxit=100, sel=None, raise_on_fail=True):
+    """Smoothing lengths with N_i(h_i) = target (Eq. (3)); returns (h, iters)."""
+    lib = _load()
+    x, y, z = _split(pos)
+    n = len(x)
+    h = _c(np.broadcast_to(np.asarray(h0, dtype=np.float64), (n,))).copy()
+    it = np.zeros(n, dtype=np.int32)
+    L = _c(box)
+    ns, s = _sel(sel, n)
+    st = lib.ora_solve_h(n, _p(x), _p(y), _p(z), _p(L), float(target), float(tol), int(maxit),
+                         ns, _p(s), _p(h), _p(it))
+    if raise_on_fail:
+        _check(st, "solve_h")
+    return h, it
+
+
+def density(pos, vel, m, h, box, sel=None):
+    """Density-stage sums at fixed h (Eq. (2), Eq. (3), Sec. 4.1 div/curl)."""
+    lib = _load()
+    x, y, z = _split(pos)
+    n = len(x)
+    vel = np.zeros((n, 3)) if vel is None else np.asarray(vel, dtype=np.float64)
+    vx, vy, vz = _c(vel[:, 0]), _c(vel[:, 1]), _c(vel[:, 2])
+    m = _c(np.broadcast_to(np.asarray(m, dtype=np.float64), (n,)))
+    h = _c(h)
+    L = _c(box)
+    ns, s = _sel(sel, n)
+    out = {k: np.full(n, np.nan) for k in ("rho", "nngb", "dndh", "drhodh", "div")}
+    out["curl"] = np.full((n, 3), np.nan)
+    out["count"] = np.full(n, -1, dtype=np.int32)
+    out["band"] = np.full(n, -1, dtype=np.int32)
+    st = lib.ora_density(n, _p(x), _p(y), _p(z), _p(vx), _p(vy), _p(vz), _p(m), _p(h), _p(L),
+                         ns, _p(s), _p(out["rho"]), _p(out["nngb"]), _p(out["dndh"]),
+                         _p(out["drhodh"]), _p(out["div"]), _p(out["curl"]), _p(out["count"]),
+                         _p(out["band"]))
+    _check(st, "density")
+    return out
+
+
+def ghost(dens, u, h, gamma=GAMMA):
+    """Omega, P, c, A, Balsara f from the density-stage sums (Sec. 2.1, Sec. 4.1)."""
+    lib = _load()
+    rho = _c(dens["rho"])
+    n = len(rho)
+    u = _c(np.broadcast_to(np.asarray(u, dtype=np.float64), (n,)))
+    out = {k: np.empty(n) for k in ("omega", "P", "c", "A", "f")}
+    lib.ora_ghost(n, _p(rho), _p(_c(dens["drhodh"])), _p(_c(h)), _p(u), _p(_c(dens["div"])),
+                  _p(_c(dens["curl"])), float(gamma), _p(out["omega"]), _p(out["P"]),
+                  _p(out["c"]), _p(out["A"]), _p(out["f"]))
+    return out
+
+
+def force(pos, vel, m, h, rho, A, c, f, box, alpha=ALPHA, sel=None):
+    """Eqs. (4)-(5) with Monaghan-Balsara viscosity (Sec. 4.1)."""
+    lib = _load()
+    x, y, z = _split(pos)
+    n = len(x)
+    vel = np.zeros((n, 3)) if vel is None else np.asarray(vel, dtype=np.float64)
+    vx, vy, vz = _c(vel[:, 0]), _c(vel[:, 1]), _c(vel[:, 2])
+    m = _c(np.broadcast_to(np.asarray(m, dtype=np.float64), (n,)))
+    L = _c(box)
+    ns, s = _sel(sel, n)
+    out = {k: np.full(n, np.nan) for k in ("ax", "ay", "az", "dudt", "kappa_a", "kappa_u")}
+    out["count"] = np.full(n, -1, dtype=np.int32)
+    out["band"] = np.full(n, -1, dtype=np.int32)
+    st = lib.ora_force(n, _p(x), _p(y), _p(z), _p(vx), _p(vy), _p(vz), _p(m), _p(_c(h)),
+                       _p(_c(rho)), _p(_c(A)), _p(_c(c)), _p(_c(f)), _p(L), float(alpha), ns, _p(s),
+                       _p(out["ax"]), _p(out["ay"]), _p(out["az"]), _p(out["dudt"]),
+                       _p(out["kappa_a"]), _p(out["kappa_u"]), _p(out["count"]), _p(out["band"]))
+    _check(st, "force")
+    out["a"] = np.stack([out["ax"], out["ay"], out["az"]], axis=1)
+    return out
+
+
+def brute_count(pos, R, box):
+    """O(N^2) count of j != i with minimum-image r_ij < R_i."""
+    lib = _load()
+    x, y, z = _split(pos)
+    n = len(x)
+    R = _c(np.broadcast_to(np.asarray(R, dtype=np.float64), (n,)))
+    cnt = np.empty(n, dtype=np.int32)
+    lib.ora_brute_count(n, _p(x), _p(y), _p(z), _p(_c(box)), _p(R), _p(cnt))
+    return cnt
+
+
+def full_pass(pos, vel, m, u, h0, box, target=N_NGB, tol=1e-10, maxit=100,
+              gamma=GAMMA, alpha=ALPHA, force_sel=None):
+    """Density stage for every particle (h solved), then the force stage.
+
+    The two stages run in the order of Sec. 2.1: all densities (and the
+    per-particle ghost quantities) before any force.  ``force_sel`` restricts
+    the force stage to a subset of particles (their neighbours' ghost
+    quantities are still computed for all particles).
+    """
+    h, iters = solve_h(pos, h0, box, target=target, tol=tol, maxit=maxit)
+    dens = density(pos, vel, m, h, box)
+    gh = ghost(dens, u, h, gamma=gamma)
+    frc = force(pos, vel, m, h, dens["rho"], gh["A"], gh["c"], gh["f"], box, alpha=alpha,
+                sel=force_sel)
+    return {"h": h, "iters": iters, "dens": dens, "ghost": gh, "force": frc}
