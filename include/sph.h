@@ -1,0 +1,199 @@
+/*
+ * sph.h -- C ABI of the MI355X (gfx950) SPH density/force library.
+ *
+ * The library evaluates the two interaction stages of smoothed particle
+ * hydrodynamics as described by P. Gonnet (2014), "Efficient and Scalable
+ * Algorithms for Smoothed Particle Hydrodynamics on Hybrid Shared/Distributed-
+ * Memory Architectures":
+ *
+ *   density stage  Sec. 2.1, Eq. (2): rho_i = sum_{r_ij < h_i} m_j W(r_ij, h_i),
+ *                  with h_i solved by Newton iteration so that the weighted
+ *                  neighbour count of Eq. (3) equals n_ngb;
+ *   force stage    Sec. 2.1, Eqs. (4)-(5), plus the Monaghan-Balsara viscosity
+ *                  and Balsara switch of Sec. 4.1, over r_ij < max(h_i, h_j);
+ *
+ * over the cell decomposition of Sec. 3.2 (cells of edge >= the largest h,
+ * self and pair interactions between neighbouring cells, periodic images)
+ * with the per-cell particle orderings along the 13 cell-pair axes of
+ * Sec. 3.3.  W is the cubic spline of Sec. 2.1 with compact support h.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - Particle, output and gradient arrays are DEVICE pointers owned by the
+ *   caller, one value per particle, in the caller's particle order, FP64
+ *   unless stated.  The library never frees or retains them past the call.
+ * - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *   All work is enqueued asynchronously on it.  Calls that must inspect a
+ *   device-side status (convergence, rebuild requests) synchronise that stream
+ *   once per call, and say so.
+ * - Every call returns an sph_status; nothing is thrown across the ABI.  On
+ *   an argument error nothing is launched.
+ * - A context (sph_ctx) owns the device workspace (cell table, sorted
+ *   orderings, cell-ordered particle copies, queues).  It grows on demand and
+ *   is freed by sph_destroy.  A context is bound to the device that was
+ *   current at sph_create and must not be used from two host threads at once.
+ */
+#ifndef SPH_MI355X_H
+#define SPH_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPH_OK = 0,
+    SPH_E_INVALID_ARG = 1,   /* null pointer, n < 0, bad parameter, inconsistent batch */
+    SPH_E_NONFINITE = 2,     /* a position, velocity, mass, u or h is NaN/Inf, or m, h <= 0 */
+    SPH_E_H_TOO_LARGE = 3,   /* some h >= box/3: a periodic box cannot hold three cells of edge >= h */
+    SPH_E_NOT_CONVERGED = 4, /* the h iteration hit max_iter for some particle (outputs still written) */
+    SPH_E_CAPACITY = 5,      /* a workspace limit was exceeded (see sph_status_string) */
+    SPH_E_OOM = 6,           /* device allocation failed */
+    SPH_E_HIP = 7,           /* a HIP runtime call failed */
+    SPH_E_STATE = 8          /* call order violated (e.g. sph_force before sph_density) */
+} sph_status;
+
+/* Arithmetic of the pair interactions. */
+enum {
+    SPH_FP64 = 0,        /* every pair term and every sum in FP64 ("plain" form) */
+    SPH_FP32_ACC64 = 1   /* pair terms in FP32 on cell-relative coordinates; per-particle
+                            sums and the Newton step on h in FP64 */
+};
+
+typedef struct {
+    double box[3];       /* periodic box lengths for single-box calls */
+    double n_ngb;        /* target weighted neighbour count of Eq. (3); the paper uses 48 */
+    double ngb_tol;      /* convergence: |N_i - n_ngb| <= ngb_tol; 0 selects 1e-10 (FP64)
+                            or 1e-4 (FP32_ACC64) */
+    int max_iter;        /* Newton evaluations per particle before SPH_E_NOT_CONVERGED */
+    double gamma;        /* adiabatic index, P = (gamma-1) rho u; the paper uses 5/3 */
+    double alpha;        /* viscosity coefficient of Sec. 4.1; the paper uses 0.8 */
+    double balsara_eps;  /* the 1e-4 in the Balsara switch denominator of Sec. 4.1 */
+    int precision;       /* SPH_FP64 or SPH_FP32_ACC64 */
+    int cell_target;     /* top-cell edge is the larger of (1+h_margin)*max h and the edge that
+                            holds cell_target particles at the mean density (Sec. 3.2 only
+                            requires edge >= max h) */
+    double h_margin;     /* relative slack on h when cells are built, so that h may grow by
+                            this fraction during the iteration without a rebuild */
+    int max_rebuilds;    /* sph_density rebuilds the cells at most this often when an h
+                            outgrows them */
+} sph_params;
+
+/* Default parameters: the paper's constants (48, 5/3, 0.8, 1e-4), FP32_ACC64,
+ * cell_target 64, h_margin 0.1, max_iter 64, max_rebuilds 4, unit box. */
+void sph_default_params(sph_params *p);
+
+typedef struct {
+    int64_t n;
+    double *x, *y, *z;        /* positions; wrapped into [0, box) by sph_step */
+    double *vx, *vy, *vz;     /* velocities */
+    double *u;                /* internal energy per unit mass */
+    double *m;                /* masses */
+    double *h;                /* smoothing lengths: initial guess in, solved value out (sph_density) */
+} sph_particles;
+
+/* Batched form: nbox independent periodic boxes in one set of arrays.  The
+ * particles of box b are [box_offsets[b], box_offsets[b+1]).  box_offsets
+ * (nbox+1 entries) and box_len (3*nbox) are HOST arrays, copied at the call. */
+typedef struct {
+    int nbox;
+    const int64_t *box_offsets;
+    const double *box_len;
+} sph_batch;
+
+/* Density-stage outputs (any pointer may be NULL to skip that output). */
+typedef struct {
+    double *rho;       /* Eq. (2) */
+    double *omega;     /* Omega_i = 1 + h_i/(3 rho_i) d rho_i/d h_i (Sec. 2.1) */
+    double *n_ngb;     /* weighted neighbour count of Eq. (3) at the solved h */
+    double *div_v;     /* velocity divergence of Sec. 4.1 */
+    double *curl_v;    /* velocity curl of Sec. 4.1, 3 values per particle (x,y,z interleaved) */
+    double *balsara;   /* Balsara switch f_i of Sec. 4.1 */
+    double *pressure;  /* P_i = (gamma-1) rho_i u_i */
+    double *sound;     /* c_i = sqrt(gamma P_i / rho_i) */
+    int32_t *n_iter;   /* Newton evaluations used, -1 if not converged */
+} sph_density_out;
+
+/* Force-stage outputs (any pointer may be NULL). */
+typedef struct {
+    double *ax, *ay, *az;   /* dv/dt, Eq. (4) plus viscosity */
+    double *dudt;           /* du/dt, Eq. (5) plus viscosity */
+    int32_t *n_pairs;       /* number of j != i with r_ij < max(h_i, h_j) */
+} sph_force_out;
+
+typedef struct sph_ctx sph_ctx;
+
+/* Create a context on the current HIP device.  params may be NULL (defaults).
+ * Errors: SPH_E_INVALID_ARG (bad parameter), SPH_E_HIP. */
+sph_status sph_create(const sph_params *params, sph_ctx **ctx);
+
+/* Free the context and all its device memory. NULL is accepted. */
+sph_status sph_destroy(sph_ctx *ctx);
+
+/* Cell decomposition (Sec. 3.2): wraps positions into the box, takes the
+ * largest h (per box), builds the top-level grid of cells with edge >=
+ * (1+h_margin) max h, keys each particle by the Morton code of its cell,
+ * radix-sorts the keys, and forms cells as runs of equal keys, their
+ * neighbour lists (self + 26 neighbours, periodic images included) and
+ * cell-ordered copies of the particle data.  batch may be NULL (one box of
+ * params.box).  Reads x, y, z, v, u, m, h.  Synchronises `stream` once (to
+ * size the cell table).  Errors: SPH_E_INVALID_ARG, SPH_E_NONFINITE,
+ * SPH_E_H_TOO_LARGE, SPH_E_OOM, SPH_E_HIP. */
+sph_status sph_build_cells(sph_ctx *ctx, const sph_particles *p, const sph_batch *batch,
+                           void *stream);
+
+/* The 13 per-cell orderings of Sec. 3.3: for each cell and each of the 13
+ * axis directions d (the other 13 of the 26 cell-pair axes are their
+ * negatives), the particle order by ascending projection onto d.  Requires
+ * sph_build_cells.  Errors: SPH_E_STATE, SPH_E_HIP. */
+sph_status sph_sort(sph_ctx *ctx, void *stream);
+
+/* Density stage with the smoothing-length iteration (Sec. 2.1, Eqs. (2)-(3)):
+ * for every particle, Newton iteration on h_i until |N_i - n_ngb| <= ngb_tol,
+ * then the per-particle quantities the force stage needs (Omega, P, c, the
+ * Balsara switch).  Writes the solved h into p->h.  If an h outgrows the
+ * cells, the cells and orderings are rebuilt (at most max_rebuilds times).
+ * Requires sph_build_cells and sph_sort on the same particles.  Synchronises
+ * `stream` once per (re)build to read the status.  Errors: SPH_E_STATE,
+ * SPH_E_NOT_CONVERGED (outputs written, n_iter = -1 where unconverged),
+ * SPH_E_H_TOO_LARGE, SPH_E_HIP. */
+sph_status sph_density(sph_ctx *ctx, sph_particles *p, sph_density_out *out, void *stream);
+
+/* Force stage (Sec. 2.1 Eqs. (4)-(5), Sec. 4.1 viscosity) with the densities,
+ * h and per-particle quantities of the last sph_density on this context.
+ * Requires the particles of that call, unchanged.  Does not synchronise.
+ * Errors: SPH_E_STATE, SPH_E_HIP. */
+sph_status sph_force(sph_ctx *ctx, const sph_particles *p, sph_force_out *out, void *stream);
+
+/* One kick-drift-kick velocity-Verlet step (Sec. 4.1) with fixed dt:
+ *   v += dt/2 a, u += dt/2 du/dt  (a, du/dt of the previous step, from `acc`),
+ *   x += dt v (wrapped into the box),
+ *   cells, orderings, density and force at the new positions, using the
+ *   predicted v + dt/2 a_old and u + dt/2 du_old,
+ *   v += dt/2 a_new, u += dt/2 du_new, and `acc` overwritten with a_new, du_new.
+ * acc->ax..dudt must hold the previous step's values (zeros for a cold start).
+ * Errors: as sph_build_cells, sph_density. */
+sph_status sph_step(sph_ctx *ctx, sph_particles *p, const sph_batch *batch, sph_force_out *acc,
+                    double dt, void *stream);
+
+/* Statistics of the last calls on ctx (host values, valid after the call
+ * that produced them has completed on its stream). */
+typedef struct {
+    int64_t n_cells;         /* non-empty cells */
+    int64_t n_units;         /* work units of the interaction kernels */
+    int32_t grid[3];         /* top-level grid of box 0 */
+    int32_t rebuilds;        /* rebuilds done by the last sph_density */
+    int32_t max_iter_used;   /* largest Newton count of the last sph_density */
+    int32_t unconverged;     /* particles left unconverged by the last sph_density */
+} sph_stats;
+
+sph_status sph_get_stats(const sph_ctx *ctx, sph_stats *out);
+
+/* Human-readable text of a status (static storage). */
+const char *sph_status_string(sph_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPH_MI355X_H */

@@ -1,0 +1,520 @@
+// api.cpp -- C ABI of the SPH library: context, workspace and the launch
+// sequence of each entry point (declared in include/sph.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kernels.h"
+#include "sph_internal.h"
+
+using namespace sph;
+
+namespace {
+
+// grow-only device buffer
+struct DBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    bool ensure(size_t nb)
+    {
+        if (nb <= bytes) return true;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        if (hipMalloc(&p, nb) != hipSuccess) { p = nullptr; return false; }
+        bytes = nb;
+        return true;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+inline size_t rsz(int prec) { return prec == SPH_FP64 ? sizeof(double) : sizeof(float); }
+
+}  // namespace
+
+struct sph_ctx {
+    sph_params prm;
+    int device = 0;
+    // workspace
+    DBuf boxes, keys, keys2, vals, vals2, rs_scratch, flag, cellx, cell_of, sc_scratch;
+    DBuf cells, ncells, cell_map, src, src_count, sidx, skey;
+    DBuf rx, ry, rz, h, m, vx, vy, vz, u;            // cell order
+    DBuf hh, hinv, gk, rho, A, c, f, cell_hmax;      // ghost quantities, cell order
+    DBuf qhead, status;
+    DBuf step_tmp;                                   // predicted v, u; new a, du/dt
+    uint32_t* status_host = nullptr;                 // pinned
+    int32_t* ncells_host = nullptr;                  // pinned
+    // state of the current decomposition
+    int64_t n = 0;
+    int nbox = 0;
+    int top_bits = 1;
+    int64_t map_total = 0;
+    std::vector<BoxInfo> box_host;
+    std::vector<int64_t> batch_off;
+    std::vector<double> batch_len;
+    bool built = false, sorted = false, have_density = false;
+    sph_stats stats{};
+};
+
+static sph_status hip_status(hipError_t e) { return e == hipSuccess ? SPH_OK : SPH_E_HIP; }
+
+template <typename R>
+static CellData<R> cell_data(sph_ctx* c)
+{
+    CellData<R> d;
+    d.rx = c->rx.as<R>(); d.ry = c->ry.as<R>(); d.rz = c->rz.as<R>();
+    d.h = c->h.as<double>();
+    d.m = c->m.as<R>(); d.vx = c->vx.as<R>(); d.vy = c->vy.as<R>(); d.vz = c->vz.as<R>();
+    d.u = c->u.as<double>();
+    return d;
+}
+
+template <typename R>
+static GhostData<R> ghost_data(sph_ctx* c)
+{
+    GhostData<R> g;
+    g.hh = c->hh.as<R>(); g.hinv = c->hinv.as<R>(); g.gk = c->gk.as<R>();
+    g.rho = c->rho.as<R>(); g.A = c->A.as<R>(); g.c = c->c.as<R>(); g.f = c->f.as<R>();
+    g.cell_hmax = c->cell_hmax.as<float>();
+    return g;
+}
+
+static Decomp decomp(sph_ctx* c)
+{
+    Decomp d;
+    d.cells = c->cells.as<CellInfo>();
+    d.ncells = c->ncells.as<int32_t>();
+    d.boxes = c->boxes.as<BoxInfo>();
+    d.src = c->src.as<Source>();
+    d.src_count = c->src_count.as<int32_t>();
+    d.sidx = c->sidx.as<uint16_t>();
+    d.skey = c->skey.as<float>();
+    d.perm = c->vals.as<uint32_t>();
+    d.n = c->n;
+    d.qhead = c->qhead.as<int32_t>();
+    d.status = c->status.as<uint32_t>();
+    return d;
+}
+
+static PassConsts pass_consts(const sph_params& p)
+{
+    PassConsts pc;
+    pc.n_ngb = p.n_ngb;
+    pc.tol = p.ngb_tol > 0 ? p.ngb_tol : (p.precision == SPH_FP64 ? 1e-10 : 1e-4);
+    pc.gamma = p.gamma;
+    pc.alpha = p.alpha;
+    pc.beps = p.balsara_eps;
+    pc.max_iter = p.max_iter;
+    pc.h_margin = p.h_margin;
+    return pc;
+}
+
+// particle-count dependent workspace
+static bool ensure_particles(sph_ctx* c, int64_t n)
+{
+    size_t N = (size_t)std::max<int64_t>(n, 1);
+    size_t R = rsz(c->prm.precision);
+    bool ok = true;
+    ok &= c->keys.ensure(N * 8) && c->keys2.ensure(N * 8);
+    ok &= c->vals.ensure(N * 4) && c->vals2.ensure(N * 4);
+    ok &= c->rs_scratch.ensure(radix_scratch_words((int64_t)N) * 4);
+    ok &= c->flag.ensure(N * 4) && c->cellx.ensure(N * 4) && c->cell_of.ensure(N * 4);
+    ok &= c->sc_scratch.ensure(scan_scratch_words((int64_t)N) * 4 + 16);
+    ok &= c->cells.ensure(N * sizeof(CellInfo)) && c->ncells.ensure(16);
+    ok &= c->src.ensure(N * kMaxSources * sizeof(Source)) && c->src_count.ensure(N * 4);
+    ok &= c->sidx.ensure(N * kSortDirs * 2) && c->skey.ensure(N * kSortDirs * 4);
+    ok &= c->rx.ensure(N * R) && c->ry.ensure(N * R) && c->rz.ensure(N * R);
+    ok &= c->h.ensure(N * 8) && c->u.ensure(N * 8);
+    ok &= c->m.ensure(N * R) && c->vx.ensure(N * R) && c->vy.ensure(N * R) && c->vz.ensure(N * R);
+    ok &= c->hh.ensure(N * R) && c->hinv.ensure(N * R) && c->gk.ensure(N * R);
+    ok &= c->rho.ensure(N * R) && c->A.ensure(N * R) && c->c.ensure(N * R) && c->f.ensure(N * R);
+    ok &= c->cell_hmax.ensure(N * 4);
+    ok &= c->qhead.ensure(16) && c->status.ensure(16);
+    return ok;
+}
+
+extern "C" {
+
+void sph_default_params(sph_params* p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->box[0] = p->box[1] = p->box[2] = 1.0;
+    p->n_ngb = 48.0;
+    p->ngb_tol = 0.0;
+    p->max_iter = 64;
+    p->gamma = 5.0 / 3.0;
+    p->alpha = 0.8;
+    p->balsara_eps = 1e-4;
+    p->precision = SPH_FP32_ACC64;
+    p->cell_target = 64;
+    p->h_margin = 0.1;
+    p->max_rebuilds = 4;
+}
+
+const char* sph_status_string(sph_status s)
+{
+    switch (s) {
+    case SPH_OK: return "ok";
+    case SPH_E_INVALID_ARG: return "invalid argument";
+    case SPH_E_NONFINITE: return "non-finite or non-positive particle data";
+    case SPH_E_H_TOO_LARGE: return "smoothing length too large for the periodic box (need >= 3 cells of edge >= h)";
+    case SPH_E_NOT_CONVERGED: return "smoothing-length iteration did not converge";
+    case SPH_E_CAPACITY: return "workspace capacity exceeded (cell too large or grid too fine)";
+    case SPH_E_OOM: return "device allocation failed";
+    case SPH_E_HIP: return "HIP runtime error";
+    case SPH_E_STATE: return "calls out of order";
+    }
+    return "unknown status";
+}
+
+static bool params_ok(const sph_params& p)
+{
+    for (int d = 0; d < 3; d++) if (!(p.box[d] > 0) || !std::isfinite(p.box[d])) return false;
+    if (!(p.n_ngb > 32.0 / 3.0) || !std::isfinite(p.n_ngb)) return false;
+    if (!(p.ngb_tol >= 0)) return false;
+    if (p.max_iter < 1) return false;
+    if (!(p.gamma > 1.0)) return false;
+    if (!(p.alpha >= 0)) return false;
+    if (!(p.balsara_eps >= 0)) return false;
+    if (p.precision != SPH_FP64 && p.precision != SPH_FP32_ACC64) return false;
+    if (p.cell_target < 1) return false;
+    if (!(p.h_margin >= 0) || !(p.h_margin < 10)) return false;
+    if (p.max_rebuilds < 0) return false;
+    return true;
+}
+
+sph_status sph_create(const sph_params* params, sph_ctx** out)
+{
+    if (!out) return SPH_E_INVALID_ARG;
+    *out = nullptr;
+    sph_params p;
+    if (params) p = *params; else sph_default_params(&p);
+    if (!params_ok(p)) return SPH_E_INVALID_ARG;
+    sph_ctx* c = new (std::nothrow) sph_ctx();
+    if (!c) return SPH_E_OOM;
+    c->prm = p;
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return SPH_E_HIP; }
+    if (hipHostMalloc((void**)&c->status_host, 16, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->ncells_host, 16, hipHostMallocDefault) != hipSuccess) {
+        if (c->status_host) (void)hipHostFree(c->status_host);
+        delete c;
+        return SPH_E_HIP;
+    }
+    *out = c;
+    return SPH_OK;
+}
+
+sph_status sph_destroy(sph_ctx* c)
+{
+    if (!c) return SPH_OK;
+    DBuf* all[] = {&c->boxes, &c->keys, &c->keys2, &c->vals, &c->vals2, &c->rs_scratch, &c->flag,
+                   &c->cellx, &c->cell_of, &c->sc_scratch, &c->cells, &c->ncells, &c->cell_map,
+                   &c->src, &c->src_count, &c->sidx, &c->skey, &c->rx, &c->ry, &c->rz, &c->h,
+                   &c->m, &c->vx, &c->vy, &c->vz, &c->u, &c->hh, &c->hinv, &c->gk, &c->rho, &c->A,
+                   &c->c, &c->f, &c->cell_hmax, &c->qhead, &c->status, &c->step_tmp};
+    for (DBuf* b : all) b->release();
+    if (c->status_host) (void)hipHostFree(c->status_host);
+    if (c->ncells_host) (void)hipHostFree(c->ncells_host);
+    delete c;
+    return SPH_OK;
+}
+
+static bool particles_ok(const sph_particles* p)
+{
+    if (!p || p->n < 0 || p->n > (int64_t)0x7fffffff) return false;
+    if (p->n == 0) return true;
+    return p->x && p->y && p->z && p->vx && p->vy && p->vz && p->u && p->m && p->h;
+}
+
+static Particles view(const sph_particles* p)
+{
+    return Particles{p->x, p->y, p->z, p->vx, p->vy, p->vz, p->u, p->m, p->h};
+}
+
+// Host part of the box table: per-box target edge and dense-map capacity.
+static sph_status setup_boxes(sph_ctx* c, int64_t n, const sph_batch* batch)
+{
+    int nbox = batch ? batch->nbox : 1;
+    if (nbox < 1) return SPH_E_INVALID_ARG;
+    c->box_host.assign(nbox, BoxInfo{});
+    int64_t map_total = 0;
+    int max_nc = 1;
+    for (int b = 0; b < nbox; b++) {
+        BoxInfo& B = c->box_host[b];
+        std::memset(&B, 0, sizeof(B));
+        int64_t beg = batch ? batch->box_offsets[b] : 0;
+        int64_t end = batch ? batch->box_offsets[b + 1] : n;
+        if (beg < 0 || end < beg || end > n) return SPH_E_INVALID_ARG;
+        if (batch && b == 0 && beg != 0) return SPH_E_INVALID_ARG;
+        for (int d = 0; d < 3; d++) {
+            B.L[d] = batch ? batch->box_len[3 * b + d] : c->prm.box[d];
+            if (!(B.L[d] > 0) || !std::isfinite(B.L[d])) return SPH_E_INVALID_ARG;
+        }
+        B.begin = beg;
+        B.n = end - beg;
+        double vol = B.L[0] * B.L[1] * B.L[2];
+        B.e_target = B.n > 0 ? std::cbrt((double)c->prm.cell_target * vol / (double)B.n)
+                             : std::max(B.L[0], std::max(B.L[1], B.L[2]));
+        int64_t cap = 1;
+        for (int d = 0; d < 3; d++) {
+            int nc = (int)std::floor(B.L[d] / B.e_target);
+            nc = std::max(3, std::min(nc, 1023));
+            B.cap_nc[d] = nc;
+            cap *= nc;
+            max_nc = std::max(max_nc, nc);
+        }
+        B.map_off = (int32_t)map_total;
+        B.map_cap = (int32_t)cap;
+        map_total += cap;
+        if (map_total > (int64_t)0x7fffffff) return SPH_E_CAPACITY;
+    }
+    if (batch && batch->box_offsets[nbox] != n) return SPH_E_INVALID_ARG;
+    int tb = 1;
+    while ((1 << tb) < max_nc) tb++;
+    int box_bits = 0;
+    while ((1 << box_bits) < nbox) box_bits++;
+    if (3 * tb + box_bits > 64) return SPH_E_CAPACITY;
+    c->nbox = nbox;
+    c->top_bits = tb;
+    c->map_total = map_total;
+    return SPH_OK;
+}
+
+extern "C++" {
+template <typename R>
+static void build_launches(sph_ctx* c, const Particles& pv, hipStream_t st)
+{
+    const int64_t n = c->n;
+    BoxInfo* boxes = c->boxes.as<BoxInfo>();
+    uint32_t* status = c->status.as<uint32_t>();
+    launch_box_scan(pv, boxes, c->nbox, n, status, st);
+    launch_grid_dims(boxes, c->nbox, c->prm.h_margin, 1023, status, st);
+    launch_keys(pv, boxes, c->nbox, n, c->top_bits, c->keys.as<uint64_t>(), c->vals.as<uint32_t>(), st);
+    int box_bits = 0;
+    while ((1 << box_bits) < c->nbox) box_bits++;
+    radix_sort(c->keys.as<uint64_t>(), c->vals.as<uint32_t>(), c->keys2.as<uint64_t>(),
+               c->vals2.as<uint32_t>(), n, 3 * c->top_bits + box_bits, c->rs_scratch.as<uint32_t>(), st);
+    launch_cells(c->keys.as<uint64_t>(), c->flag.as<uint32_t>(), c->cellx.as<uint32_t>(), n, c->top_bits,
+                 boxes, c->cells.as<CellInfo>(), c->cell_map.as<int32_t>(), c->map_total,
+                 c->cell_of.as<uint32_t>(), c->ncells.as<int32_t>(), c->sc_scratch.as<uint32_t>(), n, st);
+    launch_gather<R>(pv, c->vals.as<uint32_t>(), c->cell_of.as<uint32_t>(), c->cells.as<CellInfo>(), boxes,
+                     n, cell_data<R>(c), st);
+    launch_sources(c->cells.as<CellInfo>(), c->ncells.as<int32_t>(), boxes, c->cell_map.as<int32_t>(),
+                   c->src.as<Source>(), c->src_count.as<int32_t>(), n, st);
+}
+}  // extern "C++"
+
+sph_status sph_build_cells(sph_ctx* c, const sph_particles* p, const sph_batch* batch, void* stream)
+{
+    if (!c || !particles_ok(p)) return SPH_E_INVALID_ARG;
+    if (batch && (batch->nbox < 1 || !batch->box_offsets || !batch->box_len)) return SPH_E_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    if (hipSetDevice(c->device) != hipSuccess) return SPH_E_HIP;
+    sph_status s = setup_boxes(c, p->n, batch);
+    if (s != SPH_OK) return s;
+    if (batch) {
+        c->batch_off.assign(batch->box_offsets, batch->box_offsets + batch->nbox + 1);
+        c->batch_len.assign(batch->box_len, batch->box_len + 3 * batch->nbox);
+    } else {
+        c->batch_off.clear();
+        c->batch_len.clear();
+    }
+    c->n = p->n;
+    c->built = c->sorted = c->have_density = false;
+    if (!ensure_particles(c, p->n)) return SPH_E_OOM;
+    if (!c->boxes.ensure(sizeof(BoxInfo) * c->nbox)) return SPH_E_OOM;
+    if (!c->cell_map.ensure(sizeof(int32_t) * std::max<int64_t>(c->map_total, 1))) return SPH_E_OOM;
+    hipError_t e = hipMemcpyAsync(c->boxes.p, c->box_host.data(), sizeof(BoxInfo) * c->nbox,
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->status.p, 0, 16, st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->ncells.p, 0, 16, st);
+    if (e != hipSuccess) return SPH_E_HIP;
+    if (p->n > 0) {
+        Particles pv = view(p);
+        if (c->prm.precision == SPH_FP64) build_launches<double>(c, pv, st);
+        else build_launches<float>(c, pv, st);
+    }
+    if (hipGetLastError() != hipSuccess) return SPH_E_HIP;
+    c->built = true;
+    return SPH_OK;
+}
+
+sph_status sph_sort(sph_ctx* c, void* stream)
+{
+    if (!c) return SPH_E_INVALID_ARG;
+    if (!c->built) return SPH_E_STATE;
+    hipStream_t st = (hipStream_t)stream;
+    if (c->n > 0) {
+        if (c->prm.precision == SPH_FP64)
+            launch_sort13<double>(c->cells.as<CellInfo>(), c->ncells.as<int32_t>(), cell_data<double>(c), c->n,
+                                  c->sidx.as<uint16_t>(), c->skey.as<float>(), c->status.as<uint32_t>(), c->n, st);
+        else
+            launch_sort13<float>(c->cells.as<CellInfo>(), c->ncells.as<int32_t>(), cell_data<float>(c), c->n,
+                                 c->sidx.as<uint16_t>(), c->skey.as<float>(), c->status.as<uint32_t>(), c->n, st);
+    }
+    if (hipGetLastError() != hipSuccess) return SPH_E_HIP;
+    c->sorted = true;
+    return SPH_OK;
+}
+
+static sph_status read_status(sph_ctx* c, hipStream_t st, uint32_t* bits)
+{
+    if (hipMemcpyAsync(c->status_host, c->status.p, 4, hipMemcpyDeviceToHost, st) != hipSuccess) return SPH_E_HIP;
+    if (hipMemcpyAsync(c->ncells_host, c->ncells.p, 4, hipMemcpyDeviceToHost, st) != hipSuccess) return SPH_E_HIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return SPH_E_HIP;
+    *bits = *c->status_host;
+    c->stats.n_cells = *c->ncells_host;
+    c->stats.n_units = *c->ncells_host;
+    return SPH_OK;
+}
+
+static sph_status status_error(uint32_t bits)
+{
+    if (bits & ST_NONFINITE) return SPH_E_NONFINITE;
+    if (bits & ST_H_TOO_LARGE) return SPH_E_H_TOO_LARGE;
+    if (bits & ST_CAPACITY) return SPH_E_CAPACITY;
+    return SPH_OK;
+}
+
+extern "C++" {
+template <typename R>
+static void density_launch(sph_ctx* c, const sph_particles* p, const sph_density_out* o, hipStream_t st)
+{
+    DensityOut out{};
+    out.h = p->h;
+    if (o) {
+        out.rho = o->rho; out.omega = o->omega; out.nngb = o->n_ngb; out.div = o->div_v;
+        out.curl = o->curl_v; out.balsara = o->balsara; out.P = o->pressure; out.c = o->sound;
+        out.iters = o->n_iter;
+    }
+    int grid = density_occupancy_grid(c->prm.precision);
+    launch_density<R>(decomp(c), cell_data<R>(c), ghost_data<R>(c), out, pass_consts(c->prm), grid, st);
+}
+}  // extern "C++"
+
+sph_status sph_density(sph_ctx* c, sph_particles* p, sph_density_out* o, void* stream)
+{
+    if (!c || !particles_ok(p)) return SPH_E_INVALID_ARG;
+    if (!c->built || !c->sorted) return SPH_E_STATE;
+    if (p->n != c->n) return SPH_E_STATE;
+    hipStream_t st = (hipStream_t)stream;
+    c->stats.rebuilds = 0;
+    c->have_density = false;
+    for (int attempt = 0;; attempt++) {
+        uint32_t bits = 0;
+        if (c->n > 0) {
+            if (c->prm.precision == SPH_FP64) density_launch<double>(c, p, o, st);
+            else density_launch<float>(c, p, o, st);
+            if (hipGetLastError() != hipSuccess) return SPH_E_HIP;
+        }
+        sph_status s = read_status(c, st, &bits);
+        if (s != SPH_OK) return s;
+        s = status_error(bits);
+        if (s != SPH_OK) return s;
+        if ((bits & ST_REBUILD) && attempt < c->prm.max_rebuilds) {
+            // some smoothing length outgrew its cells: rebuild from the current h
+            sph_batch b{}, *bp = nullptr;
+            if (!c->batch_off.empty()) {
+                b.nbox = (int)c->batch_off.size() - 1;
+                b.box_offsets = c->batch_off.data();
+                b.box_len = c->batch_len.data();
+                bp = &b;
+            }
+            std::vector<int64_t> off = c->batch_off;
+            std::vector<double> len = c->batch_len;
+            if (bp) { b.box_offsets = off.data(); b.box_len = len.data(); }
+            s = sph_build_cells(c, p, bp, stream);
+            if (s == SPH_OK) s = sph_sort(c, stream);
+            if (s != SPH_OK) return s;
+            c->stats.rebuilds++;
+            continue;
+        }
+        if (bits & ST_REBUILD) return SPH_E_H_TOO_LARGE;
+        c->have_density = true;
+        if (bits & ST_NOT_CONVERGED) return SPH_E_NOT_CONVERGED;
+        return SPH_OK;
+    }
+}
+
+sph_status sph_force(sph_ctx* c, const sph_particles* p, sph_force_out* o, void* stream)
+{
+    if (!c || !particles_ok(p) || !o) return SPH_E_INVALID_ARG;
+    if (!c->have_density || p->n != c->n) return SPH_E_STATE;
+    hipStream_t st = (hipStream_t)stream;
+    if (c->n == 0) return SPH_OK;
+    ForceOut out{};
+    out.ax = o->ax; out.ay = o->ay; out.az = o->az; out.dudt = o->dudt; out.npairs = o->n_pairs;
+    int grid = force_occupancy_grid(c->prm.precision);
+    if (c->prm.precision == SPH_FP64)
+        launch_force<double>(decomp(c), cell_data<double>(c), ghost_data<double>(c), out, pass_consts(c->prm), grid, st);
+    else
+        launch_force<float>(decomp(c), cell_data<float>(c), ghost_data<float>(c), out, pass_consts(c->prm), grid, st);
+    return hipGetLastError() == hipSuccess ? SPH_OK : SPH_E_HIP;
+}
+
+sph_status sph_step(sph_ctx* c, sph_particles* p, const sph_batch* batch, sph_force_out* acc, double dt,
+                    void* stream)
+{
+    if (!c || !particles_ok(p) || !acc || !std::isfinite(dt)) return SPH_E_INVALID_ARG;
+    if (p->n > 0 && (!acc->ax || !acc->ay || !acc->az || !acc->dudt)) return SPH_E_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = p->n;
+    if (n == 0) return SPH_OK;
+    if (hipSetDevice(c->device) != hipSuccess) return SPH_E_HIP;
+    // box table for the drift (the build below refreshes it)
+    sph_status s = setup_boxes(c, n, batch);
+    if (s != SPH_OK) return s;
+    if (!c->boxes.ensure(sizeof(BoxInfo) * c->nbox)) return SPH_E_OOM;
+    if (hipMemcpyAsync(c->boxes.p, c->box_host.data(), sizeof(BoxInfo) * c->nbox, hipMemcpyHostToDevice, st) !=
+        hipSuccess)
+        return SPH_E_HIP;
+    if (!c->step_tmp.ensure(sizeof(double) * 4 * (size_t)n)) return SPH_E_OOM;
+    double* vp = c->step_tmp.as<double>();
+    double *pvx = vp, *pvy = vp + n, *pvz = vp + 2 * n, *pu = vp + 3 * n;
+    const double hdt = 0.5 * dt;
+    launch_kick(p->vx, p->vy, p->vz, p->u, acc->ax, acc->ay, acc->az, acc->dudt, hdt, n, st);
+    launch_drift(p->x, p->y, p->z, p->vx, p->vy, p->vz, dt, nullptr, c->boxes.as<BoxInfo>(), c->nbox, n, st);
+    launch_predict(p->vx, acc->ax, hdt, pvx, n, st);
+    launch_predict(p->vy, acc->ay, hdt, pvy, n, st);
+    launch_predict(p->vz, acc->az, hdt, pvz, n, st);
+    launch_predict(p->u, acc->dudt, hdt, pu, n, st);
+    sph_particles q = *p;
+    q.vx = pvx; q.vy = pvy; q.vz = pvz; q.u = pu;
+    s = sph_build_cells(c, &q, batch, stream);
+    if (s == SPH_OK) s = sph_sort(c, stream);
+    if (s == SPH_OK) s = sph_density(c, &q, nullptr, stream);
+    if (s != SPH_OK && s != SPH_E_NOT_CONVERGED) return s;
+    sph_status sd = s;
+    s = sph_force(c, &q, acc, stream);
+    if (s != SPH_OK) return s;
+    launch_kick(p->vx, p->vy, p->vz, p->u, acc->ax, acc->ay, acc->az, acc->dudt, hdt, n, st);
+    if (hipGetLastError() != hipSuccess) return SPH_E_HIP;
+    return sd;
+}
+
+sph_status sph_get_stats(const sph_ctx* c, sph_stats* out)
+{
+    if (!c || !out) return SPH_E_INVALID_ARG;
+    *out = c->stats;
+    if (!c->box_host.empty()) {
+        BoxInfo b0;
+        if (c->built && hipMemcpy(&b0, c->boxes.p, sizeof(BoxInfo), hipMemcpyDeviceToHost) == hipSuccess) {
+            out->grid[0] = b0.nc[0]; out->grid[1] = b0.nc[1]; out->grid[2] = b0.nc[2];
+        }
+    }
+    return SPH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,523 @@
+// build.hip -- cell decomposition kernels (Gonnet 2014, Sec. 3.2) and the
+// 13 per-cell orderings (Sec. 3.3), for gfx950.
+//
+//   box_scan      finiteness checks, largest h per box
+//   grid_dims     top-level grid per box: edge >= (1+margin) max h, >= 3 cells
+//   keys          Morton key of each particle's cell (box id in the top bits)
+//   radix sort    LSD, 8-bit digits, stable; tile = 256 threads x 8 keys
+//   cells         runs of equal keys -> cell table + dense per-box cell map
+//   gather        cell-ordered particle copies, positions relative to the cell
+//   sources       self + 26 neighbour cells of each cell, with periodic shifts
+//   sort13        per cell and direction: ranks of the projections (stable)
+#include "sph_internal.h"
+#include "kernels.h"
+
+namespace sph {
+
+__device__ inline int find_box(const BoxInfo* boxes, int nbox, int64_t p)
+{
+    int lo = 0, hi = nbox - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (boxes[mid].begin <= p) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline bool finite_d(double v) { return isfinite(v); }
+
+__device__ inline double wrap_coord(double v, double L)
+{
+    double w = fmod(v, L);
+    if (w < 0.0) w += L;
+    if (w >= L) w -= L;
+    return w;
+}
+
+// ---------------------------------------------------------------- box scan
+__global__ void k_box_scan(Particles p, BoxInfo* boxes, int nbox, int64_t n, uint32_t* status)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool ok = finite_d(p.x[i]) && finite_d(p.y[i]) && finite_d(p.z[i]) && finite_d(p.vx[i]) &&
+              finite_d(p.vy[i]) && finite_d(p.vz[i]) && finite_d(p.u[i]) && finite_d(p.m[i]) &&
+              finite_d(p.h[i]) && p.m[i] > 0.0 && p.h[i] > 0.0 && p.u[i] >= 0.0;
+    if (!ok) { atomicOr(status, ST_NONFINITE); return; }
+    int b = find_box(boxes, nbox, i);
+    // h > 0: the IEEE bit pattern orders like the value
+    atomicMax((unsigned long long*)&boxes[b].hmax, (unsigned long long)__double_as_longlong(p.h[i]));
+}
+
+__global__ void k_clear_boxes(BoxInfo* boxes, int nbox)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nbox) boxes[b].hmax = 0.0;
+}
+
+// ---------------------------------------------------------------- grid dims
+__global__ void k_grid_dims(BoxInfo* boxes, int nbox, double margin, int max_nc, uint32_t* status)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
+    BoxInfo& B = boxes[b];
+    double hm = B.hmax;
+    for (int d = 0; d < 3; d++) {
+        double L = B.L[d];
+        int nc = (int)floor(L / fmax(hm * (1.0 + margin), B.e_target));
+        if (nc < 3) nc = (L / hm >= 3.0) ? 3 : 0;  // margin dropped if it alone breaks the rule
+        if (nc > max_nc) nc = max_nc;
+        if (nc > B.cap_nc[d]) nc = B.cap_nc[d];
+        if (nc < 3) { atomicOr(status, ST_H_TOO_LARGE); nc = 3; }
+        B.nc[d] = nc;
+        B.e[d] = L / nc;
+    }
+    if ((int64_t)B.nc[0] * B.nc[1] * B.nc[2] > B.map_cap) atomicOr(status, ST_CAPACITY);
+}
+
+// ---------------------------------------------------------------- keys
+__global__ void k_keys(Particles p, const BoxInfo* boxes, int nbox, int64_t n, int top_bits,
+                       uint64_t* keys, uint32_t* vals)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int b = find_box(boxes, nbox, i);
+    const BoxInfo& B = boxes[b];
+    double pos[3] = {p.x[i], p.y[i], p.z[i]};
+    uint32_t c[3];
+    for (int d = 0; d < 3; d++) {
+        double w = wrap_coord(pos[d], B.L[d]);
+        int cc = (int)floor(w / B.e[d]);
+        cc = cc < 0 ? 0 : (cc >= B.nc[d] ? B.nc[d] - 1 : cc);
+        c[d] = (uint32_t)cc;
+    }
+    keys[i] = ((uint64_t)b << (3 * top_bits)) | morton3(c[0], c[1], c[2]);
+    vals[i] = (uint32_t)i;
+}
+
+// ---------------------------------------------------------------- radix sort
+constexpr int RS_THREADS = 256;
+constexpr int RS_ITEMS = 8;
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t* keys, int64_t n, int shift,
+                                                        uint32_t* hist, int nblocks)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int k = 0; k < RS_ITEMS; k++) {
+        int64_t i = base + k * RS_THREADS + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// one block per digit: exclusive scan of that digit's column over blocks
+__global__ __launch_bounds__(256) void k_rs_colscan(uint32_t* hist, int nblocks, uint32_t* tot)
+{
+    __shared__ uint32_t part[256];
+    uint32_t* col = hist + (int64_t)blockIdx.x * nblocks;
+    int per = (nblocks + 255) / 256;
+    int b0 = threadIdx.x * per, b1 = min(nblocks, b0 + per);
+    uint32_t s = 0;
+    for (int b = b0; b < b1; b++) s += col[b];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    // inclusive scan of part (Hillis-Steele)
+    for (int off = 1; off < 256; off <<= 1) {
+        uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+    for (int b = b0; b < b1; b++) { uint32_t v = col[b]; col[b] = run; run += v; }
+    if (threadIdx.x == 255) tot[blockIdx.x] = part[255];
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t* kin, const uint32_t* vin,
+                                                           uint64_t* kout, uint32_t* vout, int64_t n,
+                                                           int shift, const uint32_t* hist,
+                                                           const uint32_t* tot, int nblocks)
+{
+    __shared__ uint32_t offs[256];
+    __shared__ uint32_t wcnt[RS_THREADS / kWave][256];
+    __shared__ uint32_t base[256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // digit bases: exclusive scan of the totals
+    base[tid] = tot[tid];
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        uint32_t v = tid >= off ? base[tid - off] : 0;
+        __syncthreads();
+        base[tid] += v;
+        __syncthreads();
+    }
+    uint32_t excl = base[tid] - tot[tid];
+    offs[tid] = excl + hist[(int64_t)tid * nblocks + blockIdx.x];
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int64_t tile = (int64_t)blockIdx.x * RS_TILE;
+    for (int k = 0; k < RS_ITEMS; k++) {
+        int64_t i = tile + k * RS_THREADS + tid;
+        bool valid = i < n;
+        uint64_t key = valid ? kin[i] : 0;
+        uint32_t val = valid ? vin[i] : 0;
+        uint32_t d = (uint32_t)(key >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            uint64_t bb = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        uint32_t rank = __popcll(peers & lt);
+        uint32_t cnt = __popcll(peers);
+        for (int w = 0; w < RS_THREADS / kWave; w++) wcnt[w][tid] = 0;
+        __syncthreads();
+        if (valid && rank == 0) wcnt[wave][d] = cnt;
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = offs[d] + rank;
+            for (int w = 0; w < wave; w++) pos += wcnt[w][d];
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int w = 0; w < RS_THREADS / kWave; w++) add += wcnt[w][tid];
+        offs[tid] += add;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- generic exclusive scan (u32)
+constexpr int SC_THREADS = 256;
+constexpr int SC_ITEMS = 8;
+constexpr int SC_TILE = SC_THREADS * SC_ITEMS;
+
+__device__ inline uint32_t block_incl_scan(uint32_t v, uint32_t* sh)
+{
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < SC_THREADS; off <<= 1) {
+        uint32_t t = tid >= off ? sh[tid - off] : 0;
+        __syncthreads();
+        sh[tid] += t;
+        __syncthreads();
+    }
+    uint32_t r = sh[tid];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const uint32_t* in, int64_t n, uint32_t* sums)
+{
+    __shared__ uint32_t sh[SC_THREADS];
+    int64_t base = (int64_t)blockIdx.x * SC_TILE + (int64_t)threadIdx.x * SC_ITEMS;
+    uint32_t s = 0;
+    for (int k = 0; k < SC_ITEMS; k++) if (base + k < n) s += in[base + k];
+    uint32_t inc = block_incl_scan(s, sh);
+    if (threadIdx.x == SC_THREADS - 1) sums[blockIdx.x] = inc;
+}
+
+__global__ __launch_bounds__(SC_THREADS) void k_scan_top(uint32_t* sums, int nb, uint32_t* total)
+{
+    __shared__ uint32_t sh[SC_THREADS];
+    __shared__ uint32_t last;
+    uint32_t carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += SC_THREADS) {
+        int b = b0 + threadIdx.x;
+        uint32_t v = b < nb ? sums[b] : 0;
+        uint32_t inc = block_incl_scan(v, sh);
+        if (b < nb) sums[b] = carry + inc - v;
+        if (threadIdx.x == SC_THREADS - 1) last = inc;
+        __syncthreads();
+        carry += last;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
+__global__ __launch_bounds__(SC_THREADS) void k_scan_down(const uint32_t* in, int64_t n,
+                                                          const uint32_t* sums, uint32_t* out)
+{
+    __shared__ uint32_t sh[SC_THREADS];
+    int64_t base = (int64_t)blockIdx.x * SC_TILE + (int64_t)threadIdx.x * SC_ITEMS;
+    uint32_t v[SC_ITEMS];
+    uint32_t s = 0;
+    for (int k = 0; k < SC_ITEMS; k++) { v[k] = (base + k < n) ? in[base + k] : 0; s += v[k]; }
+    uint32_t inc = block_incl_scan(s, sh);
+    uint32_t run = sums[blockIdx.x] + inc - s;
+    for (int k = 0; k < SC_ITEMS; k++) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+}
+
+// ---------------------------------------------------------------- cells
+__global__ void k_cell_heads(const uint64_t* keys, int64_t n, uint32_t* flag)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    flag[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+}
+
+__global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+// cellx[i] = exclusive scan of the head flags; cell index of particle i is
+// cellx[i] + flag[i] - 1.
+__global__ void k_cell_fill(const uint64_t* keys, const uint32_t* flag, const uint32_t* cellx,
+                            int64_t n, int top_bits, const BoxInfo* boxes, CellInfo* cells,
+                            int32_t* cell_map, uint32_t* cell_of, int32_t* ncells)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t c = cellx[i] + flag[i] - 1;
+    cell_of[i] = c;
+    bool last = (i == n - 1) || (keys[i + 1] != keys[i]);
+    if (flag[i]) {
+        uint64_t k = keys[i];
+        int b = (int)(k >> (3 * top_bits));
+        uint64_t mc = k & ((3 * top_bits >= 64) ? ~0ull : ((1ull << (3 * top_bits)) - 1));
+        int cx = (int)compact3(mc), cy = (int)compact3(mc >> 1), cz = (int)compact3(mc >> 2);
+        cells[c].start = (int32_t)i;
+        cells[c].box = b;
+        cells[c].c[0] = cx; cells[c].c[1] = cy; cells[c].c[2] = cz;
+        const BoxInfo& B = boxes[b];
+        cell_map[B.map_off + ((int64_t)cx * B.nc[1] + cy) * B.nc[2] + cz] = (int32_t)c;
+    }
+    if (last) {
+        // count = end - start; start written by the head thread of this cell, so
+        // store the end here and convert in a second pass
+        cells[c].count = (int32_t)(i + 1);
+        if (i == n - 1) *ncells = (int32_t)(c + 1);
+    }
+}
+
+__global__ void k_cell_counts(CellInfo* cells, const int32_t* ncells)
+{
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= *ncells) return;
+    cells[c].count -= cells[c].start;
+}
+
+// ---------------------------------------------------------------- gather (cell order)
+template <typename R>
+__global__ void k_gather(Particles p, const uint32_t* perm, const uint32_t* cell_of,
+                         const CellInfo* cells, const BoxInfo* boxes, int64_t n, CellData<R> cd)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    uint32_t i = perm[k];
+    const CellInfo& C = cells[cell_of[k]];
+    const BoxInfo& B = boxes[C.box];
+    double pos[3] = {p.x[i], p.y[i], p.z[i]};
+    R rel[3];
+    for (int d = 0; d < 3; d++) {
+        double w = wrap_coord(pos[d], B.L[d]);
+        double o = (double)C.c[d] * B.e[d];
+        double r = w - o;
+        // a coordinate that rounded onto the upper face belongs to this cell
+        rel[d] = (R)r;
+    }
+    cd.rx[k] = rel[0]; cd.ry[k] = rel[1]; cd.rz[k] = rel[2];
+    cd.h[k] = p.h[i];
+    cd.m[k] = (R)p.m[i];
+    cd.vx[k] = (R)p.vx[i]; cd.vy[k] = (R)p.vy[i]; cd.vz[k] = (R)p.vz[i];
+    cd.u[k] = p.u[i];
+}
+
+// ---------------------------------------------------------------- sources
+__global__ void k_sources(const CellInfo* cells, const int32_t* ncells, const BoxInfo* boxes,
+                          const int32_t* cell_map, Source* src, int32_t* src_count)
+{
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= *ncells) return;
+    const CellInfo C = cells[c];
+    const BoxInfo& B = boxes[C.box];
+    Source* out = src + (int64_t)c * kMaxSources;
+    int k = 0;
+    out[k++] = Source{c, (int8_t)kSelfDir, 0, 0, 0};
+    for (int d = 0; d < kDirs; d++) {
+        int o[3];
+        dir_off(d, o);
+        int nc[3], sh[3];
+        for (int a = 0; a < 3; a++) {
+            int v = C.c[a] + o[a];
+            sh[a] = v < 0 ? -1 : (v >= B.nc[a] ? 1 : 0);
+            nc[a] = v - sh[a] * B.nc[a];
+        }
+        int32_t s = cell_map[B.map_off + ((int64_t)nc[0] * B.nc[1] + nc[1]) * B.nc[2] + nc[2]];
+        if (s >= 0) out[k++] = Source{s, (int8_t)d, (int8_t)sh[0], (int8_t)sh[1], (int8_t)sh[2]};
+    }
+    src_count[c] = k;
+}
+
+// ---------------------------------------------------------------- 13-direction orderings
+// One workgroup per (cell, direction).  Each particle's rank is the number of
+// particles with a smaller projection, ties broken by cell-order index, so
+// the ordering is a permutation and stable.
+constexpr int SORT_THREADS = 64;
+constexpr int SORT_MAX = 4096;
+
+template <typename R>
+__global__ __launch_bounds__(SORT_THREADS) void k_sort13(const CellInfo* cells, const int32_t* ncells,
+                                                         CellData<R> cd, int64_t n, uint16_t* sidx,
+                                                         float* skey, uint32_t* status)
+{
+    __shared__ float key[SORT_MAX];
+    const int64_t units = (int64_t)(*ncells) * kSortDirs;
+    for (int64_t unit = blockIdx.x; unit < units; unit += gridDim.x) {
+        const int c = (int)(unit / kSortDirs);
+        const int s = (int)(unit % kSortDirs);
+        const CellInfo C = cells[c];
+        if (C.count > SORT_MAX) { if (threadIdx.x == 0) atomicOr(status, ST_CAPACITY); continue; }
+        float su[3];
+        dir_unit(s + 13, su);
+        __syncthreads();
+        for (int t = threadIdx.x; t < C.count; t += SORT_THREADS) {
+            int64_t k = C.start + t;
+            key[t] = su[0] * (float)cd.rx[k] + su[1] * (float)cd.ry[k] + su[2] * (float)cd.rz[k];
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < C.count; t += SORT_THREADS) {
+            float kt = key[t];
+            int rank = 0;
+            for (int j = 0; j < C.count; j++) {
+                float kj = key[j];
+                rank += (kj < kt) || (kj == kt && j < t);
+            }
+            int64_t o = (int64_t)s * n + C.start + rank;
+            sidx[o] = (uint16_t)t;
+            skey[o] = kt;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- host launchers
+void launch_box_scan(const Particles& p, BoxInfo* boxes, int nbox, int64_t n, uint32_t* status,
+                     hipStream_t st)
+{
+    hipLaunchKernelGGL(k_clear_boxes, dim3((nbox + 255) / 256), dim3(256), 0, st, boxes, nbox);
+    if (n > 0)
+        hipLaunchKernelGGL(k_box_scan, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, boxes,
+                           nbox, n, status);
+}
+
+void launch_grid_dims(BoxInfo* boxes, int nbox, double margin, int max_nc, uint32_t* status,
+                      hipStream_t st)
+{
+    hipLaunchKernelGGL(k_grid_dims, dim3((nbox + 63) / 64), dim3(64), 0, st, boxes, nbox, margin,
+                       max_nc, status);
+}
+
+void launch_keys(const Particles& p, const BoxInfo* boxes, int nbox, int64_t n, int top_bits,
+                 uint64_t* keys, uint32_t* vals, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, boxes, nbox,
+                       n, top_bits, keys, vals);
+}
+
+size_t radix_scratch_words(int64_t n)
+{
+    int64_t nb = (n + RS_TILE - 1) / RS_TILE;
+    return (size_t)(256 * nb + 256);
+}
+
+// Sorts (keys, vals) in place over the low `bits` bits; k2/v2 are scratch.
+void radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* k2, uint32_t* v2, int64_t n, int bits,
+                uint32_t* scratch, hipStream_t st)
+{
+    int nb = (int)((n + RS_TILE - 1) / RS_TILE);
+    uint32_t* hist = scratch;
+    uint32_t* tot = scratch + (size_t)256 * nb;
+    uint64_t *ka = keys, *kb = k2;
+    uint32_t *va = vals, *vb = v2;
+    int passes = (bits + 7) / 8;
+    for (int ps = 0; ps < passes; ps++) {
+        int shift = ps * 8;
+        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(RS_THREADS), 0, st, ka, n, shift, hist, nb);
+        hipLaunchKernelGGL(k_rs_colscan, dim3(256), dim3(256), 0, st, hist, nb, tot);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(RS_THREADS), 0, st, ka, va, kb, vb, n, shift,
+                           hist, tot, nb);
+        uint64_t* tk = ka; ka = kb; kb = tk;
+        uint32_t* tv = va; va = vb; vb = tv;
+    }
+    if (ka != keys) {
+        hipMemcpyAsync(keys, ka, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, st);
+        hipMemcpyAsync(vals, va, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, st);
+    }
+}
+
+size_t scan_scratch_words(int64_t n) { return (size_t)((n + SC_TILE - 1) / SC_TILE) + 1; }
+
+void exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* scratch, uint32_t* total,
+                    hipStream_t st)
+{
+    int nb = (int)((n + SC_TILE - 1) / SC_TILE);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(SC_THREADS), 0, st, in, n, scratch);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SC_THREADS), 0, st, scratch, nb, total);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(SC_THREADS), 0, st, in, n, scratch, out);
+}
+
+void launch_cells(const uint64_t* keys, uint32_t* flag, uint32_t* cellx, int64_t n, int top_bits,
+                  const BoxInfo* boxes, CellInfo* cells, int32_t* cell_map, int64_t map_total,
+                  uint32_t* cell_of, int32_t* ncells, uint32_t* scan_scratch, int64_t cell_cap,
+                  hipStream_t st)
+{
+    unsigned g = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((map_total + 255) / 256)), dim3(256), 0, st,
+                       cell_map, map_total, -1);
+    hipLaunchKernelGGL(k_cell_heads, dim3(g), dim3(256), 0, st, keys, n, flag);
+    exclusive_scan(flag, cellx, n, scan_scratch, nullptr, st);
+    hipLaunchKernelGGL(k_cell_fill, dim3(g), dim3(256), 0, st, keys, flag, cellx, n, top_bits, boxes,
+                       cells, cell_map, cell_of, ncells);
+    hipLaunchKernelGGL(k_cell_counts, dim3((unsigned)((cell_cap + 255) / 256)), dim3(256), 0, st,
+                       cells, ncells);
+}
+
+template <typename R>
+void launch_gather(const Particles& p, const uint32_t* perm, const uint32_t* cell_of,
+                   const CellInfo* cells, const BoxInfo* boxes, int64_t n, const CellData<R>& cd,
+                   hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gather<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, perm,
+                       cell_of, cells, boxes, n, cd);
+}
+template void launch_gather<float>(const Particles&, const uint32_t*, const uint32_t*, const CellInfo*,
+                                   const BoxInfo*, int64_t, const CellData<float>&, hipStream_t);
+template void launch_gather<double>(const Particles&, const uint32_t*, const uint32_t*,
+                                    const CellInfo*, const BoxInfo*, int64_t,
+                                    const CellData<double>&, hipStream_t);
+
+void launch_sources(const CellInfo* cells, const int32_t* ncells, const BoxInfo* boxes,
+                    const int32_t* cell_map, Source* src, int32_t* src_count, int64_t cell_cap,
+                    hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sources, dim3((unsigned)((cell_cap + 127) / 128)), dim3(128), 0, st, cells,
+                       ncells, boxes, cell_map, src, src_count);
+}
+
+template <typename R>
+void launch_sort13(const CellInfo* cells, const int32_t* ncells, const CellData<R>& cd, int64_t n,
+                   uint16_t* sidx, float* skey, uint32_t* status, int64_t cell_cap, hipStream_t st)
+{
+    int64_t units = cell_cap * kSortDirs;
+    unsigned grid = (unsigned)(units < 65536 ? units : 65536);
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_sort13<R>, dim3(grid), dim3(SORT_THREADS), 0, st, cells, ncells, cd, n, sidx,
+                       skey, status);
+}
+template void launch_sort13<float>(const CellInfo*, const int32_t*, const CellData<float>&, int64_t,
+                                   uint16_t*, float*, uint32_t*, int64_t, hipStream_t);
+template void launch_sort13<double>(const CellInfo*, const int32_t*, const CellData<double>&, int64_t,
+                                    uint16_t*, float*, uint32_t*, int64_t, hipStream_t);
+
+}  // namespace sph

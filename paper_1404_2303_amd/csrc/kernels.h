@@ -1,0 +1,107 @@
+// kernels.h -- host-side launchers of the SPH kernels and the device views
+// they take.  Not part of the public ABI.
+#pragma once
+
+#include "sph_internal.h"
+
+namespace sph {
+
+// Caller arrays (caller order, FP64).
+struct Particles {
+    const double *x, *y, *z, *vx, *vy, *vz, *u, *m, *h;
+};
+
+// Cell-ordered particle copies.  Positions are relative to the lower corner
+// of the particle's cell, in the pair-arithmetic type R.
+template <typename R>
+struct CellData {
+    R *rx, *ry, *rz;
+    double* h;           // smoothing length (FP64 master copy)
+    R *m, *vx, *vy, *vz;
+    double* u;
+};
+
+// Per-particle results of the density stage needed by the force stage, in
+// cell order.  hinv = 1/h, gk = 8/(pi h^5) (the gradient prefactor).
+template <typename R>
+struct GhostData {
+    R *hh, *hinv, *gk, *rho, *A, *c, *f;
+    float* cell_hmax;    // largest h of each cell
+};
+
+// Caller-order outputs of the density stage (any may be null).
+struct DensityOut {
+    double *h, *rho, *omega, *nngb, *div, *curl, *balsara, *P, *c;
+    int32_t* iters;
+};
+
+struct ForceOut {
+    double *ax, *ay, *az, *dudt;
+    int32_t* npairs;
+    double *ax_c, *ay_c, *az_c, *dudt_c;   // optional cell-order copies (FP64)
+};
+
+// Shared view of the decomposition used by the interaction kernels.
+struct Decomp {
+    const CellInfo* cells;
+    const int32_t* ncells;
+    const BoxInfo* boxes;
+    const Source* src;
+    const int32_t* src_count;
+    const uint16_t* sidx;   // [13][n]
+    const float* skey;      // [13][n]
+    const uint32_t* perm;   // cell order -> caller index
+    int64_t n;
+    int32_t* qhead;         // work counter of the persistent launches
+    uint32_t* status;
+};
+
+// build.hip
+void launch_box_scan(const Particles& p, BoxInfo* boxes, int nbox, int64_t n, uint32_t* status,
+                     hipStream_t st);
+void launch_grid_dims(BoxInfo* boxes, int nbox, double margin, int max_nc, uint32_t* status,
+                      hipStream_t st);
+void launch_keys(const Particles& p, const BoxInfo* boxes, int nbox, int64_t n, int top_bits,
+                 uint64_t* keys, uint32_t* vals, hipStream_t st);
+size_t radix_scratch_words(int64_t n);
+void radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* k2, uint32_t* v2, int64_t n, int bits,
+                uint32_t* scratch, hipStream_t st);
+size_t scan_scratch_words(int64_t n);
+void exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* scratch, uint32_t* total,
+                    hipStream_t st);
+void launch_cells(const uint64_t* keys, uint32_t* flag, uint32_t* cellx, int64_t n, int top_bits,
+                  const BoxInfo* boxes, CellInfo* cells, int32_t* cell_map, int64_t map_total,
+                  uint32_t* cell_of, int32_t* ncells, uint32_t* scan_scratch, int64_t cell_cap,
+                  hipStream_t st);
+template <typename R>
+void launch_gather(const Particles& p, const uint32_t* perm, const uint32_t* cell_of,
+                   const CellInfo* cells, const BoxInfo* boxes, int64_t n, const CellData<R>& cd,
+                   hipStream_t st);
+void launch_sources(const CellInfo* cells, const int32_t* ncells, const BoxInfo* boxes,
+                    const int32_t* cell_map, Source* src, int32_t* src_count, int64_t cell_cap,
+                    hipStream_t st);
+template <typename R>
+void launch_sort13(const CellInfo* cells, const int32_t* ncells, const CellData<R>& cd, int64_t n,
+                   uint16_t* sidx, float* skey, uint32_t* status, int64_t cell_cap, hipStream_t st);
+
+// passes.hip
+void launch_reset_counter(int32_t* c, hipStream_t st);
+template <typename R>
+void launch_density(const Decomp& dc, const CellData<R>& cd, const GhostData<R>& gd,
+                    const DensityOut& out, const PassConsts& pc, int grid, hipStream_t st);
+template <typename R>
+void launch_force(const Decomp& dc, const CellData<R>& cd, const GhostData<R>& gd,
+                  const ForceOut& out, const PassConsts& pc, int grid, hipStream_t st);
+int density_occupancy_grid(int precision);
+int force_occupancy_grid(int precision);
+
+// step.hip
+void launch_kick(double* vx, double* vy, double* vz, double* u, const double* ax, const double* ay,
+                 const double* az, const double* dudt, double hdt, int64_t n, hipStream_t st);
+void launch_drift(double* x, double* y, double* z, const double* vx, const double* vy,
+                  const double* vz, double dt, const int64_t* box_of_dummy, const BoxInfo* boxes,
+                  int nbox, int64_t n, hipStream_t st);
+void launch_predict(const double* v, const double* a, double hdt, double* out, int64_t n,
+                    hipStream_t st);
+
+}  // namespace sph

@@ -1,0 +1,285 @@
+"""Python binding of the C ABI in include/sph.h (ctypes; argument marshalling only).
+
+Torch tensors provide device memory and the stream; every computation runs in
+the HIP kernels of libsph_mi355x.so.  The low-level functions carry the C
+names (``sph_create``, ``sph_build_cells``, ``sph_sort``, ``sph_density``,
+``sph_force``, ``sph_step``); :class:`Context` wraps them for tensors.
+There is no fallback: if the library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsph_mi355x.so")
+
+SPH_OK, SPH_E_INVALID_ARG, SPH_E_NONFINITE, SPH_E_H_TOO_LARGE, SPH_E_NOT_CONVERGED = 0, 1, 2, 3, 4
+SPH_E_CAPACITY, SPH_E_OOM, SPH_E_HIP, SPH_E_STATE = 5, 6, 7, 8
+SPH_FP64, SPH_FP32_ACC64 = 0, 1
+
+EXPORTED = ["sph_default_params", "sph_create", "sph_destroy", "sph_build_cells", "sph_sort",
+            "sph_density", "sph_force", "sph_step", "sph_get_stats", "sph_status_string"]
+
+P = ctypes.c_void_p
+
+
+class sph_params(ctypes.Structure):
+    _fields_ = [("box", ctypes.c_double * 3), ("n_ngb", ctypes.c_double), ("ngb_tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int), ("gamma", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("balsara_eps", ctypes.c_double), ("precision", ctypes.c_int),
+                ("cell_target", ctypes.c_int), ("h_margin", ctypes.c_double),
+                ("max_rebuilds", ctypes.c_int)]
+
+
+class sph_particles(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64)] + [(k, P) for k in ("x", "y", "z", "vx", "vy", "vz", "u", "m", "h")]
+
+
+class sph_batch(ctypes.Structure):
+    _fields_ = [("nbox", ctypes.c_int), ("box_offsets", P), ("box_len", P)]
+
+
+class sph_density_out(ctypes.Structure):
+    _fields_ = [(k, P) for k in ("rho", "omega", "n_ngb", "div_v", "curl_v", "balsara", "pressure",
+                                 "sound", "n_iter")]
+
+
+class sph_force_out(ctypes.Structure):
+    _fields_ = [(k, P) for k in ("ax", "ay", "az", "dudt", "n_pairs")]
+
+
+class sph_stats(ctypes.Structure):
+    _fields_ = [("n_cells", ctypes.c_int64), ("n_units", ctypes.c_int64), ("grid", ctypes.c_int32 * 3),
+                ("rebuilds", ctypes.c_int32), ("max_iter_used", ctypes.c_int32),
+                ("unconverged", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libsph_mi355x.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        st = ctypes.c_int
+        lib.sph_default_params.restype = None
+        lib.sph_default_params.argtypes = [ctypes.POINTER(sph_params)]
+        lib.sph_create.restype = st
+        lib.sph_create.argtypes = [ctypes.POINTER(sph_params), ctypes.POINTER(P)]
+        lib.sph_destroy.restype = st
+        lib.sph_destroy.argtypes = [P]
+        lib.sph_build_cells.restype = st
+        lib.sph_build_cells.argtypes = [P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_batch), P]
+        lib.sph_sort.restype = st
+        lib.sph_sort.argtypes = [P, P]
+        lib.sph_density.restype = st
+        lib.sph_density.argtypes = [P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_density_out), P]
+        lib.sph_force.restype = st
+        lib.sph_force.argtypes = [P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_force_out), P]
+        lib.sph_step.restype = st
+        lib.sph_step.argtypes = [P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_batch),
+                                 ctypes.POINTER(sph_force_out), ctypes.c_double, P]
+        lib.sph_get_stats.restype = st
+        lib.sph_get_stats.argtypes = [P, ctypes.POINTER(sph_stats)]
+        lib.sph_status_string.restype = ctypes.c_char_p
+        lib.sph_status_string.argtypes = [st]
+        _lib = lib
+    return _lib
+
+
+class SPHError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = load_library().sph_status_string(status).decode()
+        super().__init__(f"{where}: {msg} (status {status})")
+
+
+def _check(status: int, where: str, allow=()):
+    if status != SPH_OK and status not in allow:
+        raise SPHError(status, where)
+    return status
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ---------------------------------------------------------------- C names
+def sph_default_params() -> sph_params:
+    p = sph_params()
+    load_library().sph_default_params(ctypes.byref(p))
+    return p
+
+
+def sph_create(params: sph_params):
+    ctx = P()
+    _check(load_library().sph_create(ctypes.byref(params), ctypes.byref(ctx)), "sph_create")
+    return ctx
+
+
+def sph_destroy(ctx):
+    return load_library().sph_destroy(ctx)
+
+
+def sph_build_cells(ctx, parts: sph_particles, batch: Optional[sph_batch], stream):
+    return load_library().sph_build_cells(ctx, ctypes.byref(parts),
+                                          ctypes.byref(batch) if batch is not None else None, stream)
+
+
+def sph_sort(ctx, stream):
+    return load_library().sph_sort(ctx, stream)
+
+
+def sph_density(ctx, parts: sph_particles, out: Optional[sph_density_out], stream):
+    return load_library().sph_density(ctx, ctypes.byref(parts), ctypes.byref(out) if out is not None else None,
+                                      stream)
+
+
+def sph_force(ctx, parts: sph_particles, out: sph_force_out, stream):
+    return load_library().sph_force(ctx, ctypes.byref(parts), ctypes.byref(out), stream)
+
+
+def sph_step(ctx, parts: sph_particles, batch: Optional[sph_batch], acc: sph_force_out, dt: float, stream):
+    return load_library().sph_step(ctx, ctypes.byref(parts), ctypes.byref(batch) if batch is not None else None,
+                                   ctypes.byref(acc), float(dt), stream)
+
+
+# ---------------------------------------------------------------- tensor layer
+@dataclass
+class Particles:
+    """FP64 device tensors, one entry per particle (positions/velocities as (N,3) are split)."""
+    x: torch.Tensor
+    y: torch.Tensor
+    z: torch.Tensor
+    vx: torch.Tensor
+    vy: torch.Tensor
+    vz: torch.Tensor
+    u: torch.Tensor
+    m: torch.Tensor
+    h: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return int(self.x.numel())
+
+    @staticmethod
+    def from_numpy(ps, device="cuda"):
+        """From a workloads.ParticleSet (numpy) to contiguous FP64 device tensors."""
+        def t(a):
+            return torch.as_tensor(a, dtype=torch.float64).contiguous().to(device)
+        return Particles(x=t(ps.pos[:, 0]), y=t(ps.pos[:, 1]), z=t(ps.pos[:, 2]),
+                         vx=t(ps.vel[:, 0]), vy=t(ps.vel[:, 1]), vz=t(ps.vel[:, 2]),
+                         u=t(ps.u), m=t(ps.m), h=t(ps.h0))
+
+    def c_struct(self) -> sph_particles:
+        for k in ("x", "y", "z", "vx", "vy", "vz", "u", "m", "h"):
+            t = getattr(self, k)
+            if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != self.n or not t.is_cuda:
+                raise ValueError(f"particle field {k} must be a contiguous float64 CUDA tensor of length n")
+        return sph_particles(self.n, *[_ptr(getattr(self, k)) for k in
+                                       ("x", "y", "z", "vx", "vy", "vz", "u", "m", "h")])
+
+
+class Batch:
+    """Host-side batch descriptor (box offsets and lengths), kept alive with its ctypes view."""
+
+    def __init__(self, offsets, lengths):
+        import numpy as np
+        self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        self.lengths = np.ascontiguousarray(lengths, dtype=np.float64).reshape(-1)
+        self.nbox = len(self.offsets) - 1
+        self.c = sph_batch(self.nbox, self.offsets.ctypes.data_as(P), self.lengths.ctypes.data_as(P))
+
+
+class Context:
+    """One library context (device workspace) with tensor-level calls."""
+
+    def __init__(self, box=(1.0, 1.0, 1.0), precision: str = "fp32", **kw):
+        p = sph_default_params()
+        for d in range(3):
+            p.box[d] = float(box[d])
+        p.precision = SPH_FP64 if precision in ("fp64", SPH_FP64) else SPH_FP32_ACC64
+        for k, v in kw.items():
+            if not hasattr(p, k):
+                raise KeyError(k)
+            setattr(p, k, v)
+        self.params = p
+        self.ctx = sph_create(p)
+
+    def close(self):
+        if self.ctx:
+            sph_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build_cells(self, parts: Particles, batch: Optional[Batch] = None):
+        _check(sph_build_cells(self.ctx, parts.c_struct(), batch.c if batch else None, _stream()),
+               "sph_build_cells")
+
+    def sort(self):
+        _check(sph_sort(self.ctx, _stream()), "sph_sort")
+
+    def density(self, parts: Particles,
+                want=("rho", "omega", "n_ngb", "div_v", "curl_v", "balsara", "pressure", "sound", "n_iter"),
+                allow_unconverged=False):
+        n = parts.n
+        dev = parts.x.device
+        out = {}
+        for k in want:
+            if k == "n_iter":
+                out[k] = torch.empty(n, dtype=torch.int32, device=dev)
+            elif k == "curl_v":
+                out[k] = torch.empty((n, 3), dtype=torch.float64, device=dev)
+            else:
+                out[k] = torch.empty(n, dtype=torch.float64, device=dev)
+        c = sph_density_out(*[_ptr(out.get(k)) for k in ("rho", "omega", "n_ngb", "div_v", "curl_v", "balsara",
+                                                          "pressure", "sound", "n_iter")])
+        allow = (SPH_E_NOT_CONVERGED,) if allow_unconverged else ()
+        self.last_density_status = _check(sph_density(self.ctx, parts.c_struct(), c, _stream()), "sph_density",
+                                          allow)
+        return out
+
+    def force(self, parts: Particles, out=None):
+        n = parts.n
+        dev = parts.x.device
+        if out is None:
+            out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("ax", "ay", "az", "dudt")}
+            out["n_pairs"] = torch.empty(n, dtype=torch.int32, device=dev)
+        c = sph_force_out(*[_ptr(out.get(k)) for k in ("ax", "ay", "az", "dudt", "n_pairs")])
+        _check(sph_force(self.ctx, parts.c_struct(), c, _stream()), "sph_force")
+        return out
+
+    def step(self, parts: Particles, acc: dict, dt: float, batch: Optional[Batch] = None):
+        c = sph_force_out(*[_ptr(acc.get(k)) for k in ("ax", "ay", "az", "dudt", "n_pairs")])
+        return _check(sph_step(self.ctx, parts.c_struct(), batch.c if batch else None, c, dt, _stream()),
+                      "sph_step", (SPH_E_NOT_CONVERGED,))
+
+    def stats(self) -> dict:
+        s = sph_stats()
+        _check(load_library().sph_get_stats(self.ctx, ctypes.byref(s)), "sph_get_stats")
+        return {"n_cells": s.n_cells, "n_units": s.n_units, "grid": tuple(s.grid), "rebuilds": s.rebuilds}
+
+    def run(self, parts: Particles, batch: Optional[Batch] = None, allow_unconverged=False):
+        """build -> sort -> density (h solved in place) -> force."""
+        self.build_cells(parts, batch)
+        self.sort()
+        d = self.density(parts, allow_unconverged=allow_unconverged)
+        f = self.force(parts)
+        return d, f

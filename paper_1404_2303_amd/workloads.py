@@ -54,8 +54,8 @@ def mean_spacing_h(n_per_volume: float, n_ngb: float = N_NGB) -> float:
 def _finish(pos, vel, box, name, u=1.0, meta=None):
     n = pos.shape[0]
     vol = float(np.prod(box))
-    m = np.full(n, vol / n)
-    h0 = np.full(n, mean_spacing_h(n / vol))
+    m = np.full(n, vol / max(n, 1))
+    h0 = np.full(n, mean_spacing_h(max(n, 1) / vol))
     return ParticleSet(pos=np.ascontiguousarray(pos, dtype=np.float64),
                        vel=np.ascontiguousarray(vel, dtype=np.float64),
                        m=m, u=np.full(n, float(u)), h0=h0,

@@ -1,0 +1,170 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Every input is a seeded synthetic set from paper_1404_2303_amd.workloads;
+tolerances are derived in tests/parity_util.py.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1404_2303_amd import sph, workloads
+from parity_util import compare, gpu_run, log, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def config0_ref():
+    ps = workloads.config0()
+    return ps, oracle_run(ps)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_config0_uniform_4096(config0_ref, precision):
+    ps, ref = config0_ref
+    log(f"case config0 uniform 4096 {precision}")
+    g = gpu_run(ps, precision)
+    compare(g, ref, precision, label="config0")
+    assert np.all(g["n_iter"] > 0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_ragged_box_varied_masses(precision):
+    # non-cubic box, N not a multiple of anything, masses and energies varied
+    rng = np.random.default_rng(21)
+    ps = workloads.uniform(3001, seed=21, box=(1.0, 0.7, 0.55), sigma_v=0.3)
+    ps.m[:] *= rng.uniform(0.6, 1.4, ps.n)
+    ps.u[:] = rng.uniform(0.5, 2.0, ps.n)
+    log(f"case ragged box 3001 {precision}")
+    ref = oracle_run(ps)
+    g = gpu_run(ps, precision)
+    compare(g, ref, precision, label="ragged")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_jittered_lattice(precision):
+    ps = workloads.small_lattice(16)
+    log(f"case lattice 16^3 {precision}")
+    ref = oracle_run(ps)
+    g = gpu_run(ps, precision)
+    compare(g, ref, precision, label="lattice16")
+
+
+def test_tiny_three_cells_per_dimension():
+    ps = workloads.uniform(800, seed=3, sigma_v=0.2)
+    log("case tiny 800 fp64")
+    ref = oracle_run(ps)
+    g = gpu_run(ps, "fp64")
+    assert tuple(g["stats"]["grid"]) == (3, 3, 3)
+    compare(g, ref, "fp64", label="tiny")
+
+
+@pytest.mark.parametrize("cell_target", [16, 200, 1000])
+def test_decomposition_invariance(cell_target):
+    """Cell size changes which loop finds a pair, never the result."""
+    ps = workloads.uniform(6000, seed=9, sigma_v=0.3)
+    log(f"case decomposition cell_target={cell_target}")
+    base = gpu_run(ps, "fp64")
+    other = gpu_run(ps, "fp64", cell_target=cell_target)
+    assert np.array_equal(base["n_pairs"], other["n_pairs"])
+    assert np.allclose(base["h"], other["h"], rtol=1e-11, atol=0)
+    assert np.allclose(base["rho"], other["rho"], rtol=1e-11, atol=0)
+    ka = np.max(np.abs(base["a"]))
+    assert np.max(np.abs(base["a"] - other["a"])) <= 1e-9 * ka
+
+
+def test_momentum_and_energy_conservation_gpu():
+    ps = workloads.uniform(8000, seed=5, sigma_v=0.5)
+    log("case conservation 8000 fp64")
+    g = gpu_run(ps, "fp64")
+    mom = np.sum(ps.m[:, None] * g["a"], axis=0)
+    scale = np.sum(ps.m * np.linalg.norm(g["a"], axis=1))
+    assert np.max(np.abs(mom)) < 1e-9 * scale
+    e = np.sum(ps.m * (g["dudt"] + np.sum(ps.vel * g["a"], axis=1)))
+    escale = np.sum(ps.m * (np.abs(g["dudt"]) + np.linalg.norm(ps.vel, axis=1) * np.linalg.norm(g["a"], axis=1)))
+    assert abs(e) < 1e-9 * escale
+
+
+# ---------------------------------------------------------------- edge cases and errors
+def _ctx_and_parts(ps, **kw):
+    return sph.Context(ps.box, precision=kw.pop("precision", "fp64"), **kw), sph.Particles.from_numpy(ps, "cuda:0")
+
+
+def test_empty_input():
+    log("case empty")
+    ps = workloads.uniform(0, seed=0)
+    ctx, parts = _ctx_and_parts(ps)
+    d, f = ctx.run(parts)
+    torch.cuda.synchronize()
+    assert d["rho"].numel() == 0 and f["ax"].numel() == 0
+    ctx.close()
+
+
+def test_nonfinite_input_is_reported():
+    log("case nonfinite")
+    ps = workloads.uniform(1000, seed=1)
+    ps.pos[17, 1] = np.nan
+    ctx, parts = _ctx_and_parts(ps)
+    ctx.build_cells(parts)
+    ctx.sort()
+    with pytest.raises(sph.SPHError) as e:
+        ctx.density(parts)
+    assert e.value.status == sph.SPH_E_NONFINITE
+    ctx.close()
+
+
+def test_h_too_large_is_reported():
+    log("case h too large")
+    ps = workloads.uniform(1000, seed=1)
+    ps.h0[:] = 0.4   # more than a third of the box
+    ctx, parts = _ctx_and_parts(ps)
+    ctx.build_cells(parts)
+    ctx.sort()
+    with pytest.raises(sph.SPHError) as e:
+        ctx.density(parts)
+    assert e.value.status == sph.SPH_E_H_TOO_LARGE
+    ctx.close()
+
+
+def test_not_converged_is_reported():
+    log("case max_iter=1")
+    ps = workloads.uniform(1000, seed=2)
+    ctx, parts = _ctx_and_parts(ps, max_iter=1)
+    ctx.build_cells(parts)
+    ctx.sort()
+    d = ctx.density(parts, allow_unconverged=True)
+    torch.cuda.synchronize()
+    assert ctx.last_density_status == sph.SPH_E_NOT_CONVERGED
+    it = d["n_iter"].cpu().numpy()
+    assert np.all(it == -1)
+    ctx.close()
+
+
+def test_calls_out_of_order():
+    log("case state")
+    ps = workloads.uniform(500, seed=2)
+    ctx, parts = _ctx_and_parts(ps)
+    with pytest.raises(sph.SPHError) as e:
+        ctx.sort()
+    assert e.value.status == sph.SPH_E_STATE
+    with pytest.raises(sph.SPHError) as e:
+        ctx.force(parts)
+    assert e.value.status == sph.SPH_E_STATE
+    ctx.build_cells(parts)
+    with pytest.raises(sph.SPHError) as e:
+        ctx.density(parts)
+    assert e.value.status == sph.SPH_E_STATE
+    ctx.close()
+
+
+def test_rebuild_when_h_outgrows_the_cells():
+    """Initial h far too small: cells are built for it, the iteration outgrows
+    them, and the library rebuilds until the solution fits."""
+    ps = workloads.uniform(4000, seed=4, sigma_v=0.1)
+    ps.h0[:] *= 0.2
+    log("case rebuild")
+    ref = oracle_run(ps)
+    g = gpu_run(ps, "fp64", cell_target=8, h_margin=0.0)
+    assert g["stats"]["rebuilds"] >= 1
+    compare(g, ref, "fp64", label="rebuild")
