@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Benchmark: SPH pair interactions per second (density + force) on one MI355X.
+
+Workload: 2^20 particles on a 128 x 128 x 64 cubic lattice of spacing 1/128
+(periodic 1 x 1 x 1/2 box), every site jittered by U(-0.1, 0.1) spacings,
+velocities N(0, 0.1), u = 1, equal masses; seeded.
+
+One step = the whole hot path over that input, starting from the initial
+smoothing lengths: cell build (keys, radix sort, cells, neighbour lists,
+cell-ordered copies) -> 13-direction orderings -> density with the Newton
+iteration on h (and the per-particle quantities between the stages) ->
+force with viscosity.  The initial h is restored (one device copy) at the
+start of every step, inside the timed region.
+
+Unit of work: one unordered pair {i, j} with r_ij < max(h_i, h_j) at the solved
+h, counted once per stage, so a step credits P = P_density + P_force =
+sum_i n_pairs_i pair interactions.  Extra Newton rounds are timed but not
+credited.
+
+Roofline: the interaction kernels are bound by plain FP32/FP64 vector ALU
+work.  Algorithmic FLOPs per launch (FMA = 2, add/mul = 1, sqrt/div = 1,
+compare/select = 0, counted from the equations once per unordered pair as a
+symmetric evaluation would do them):
+    density: 12 per pair (separation, distance, velocity difference)
+             + 41 per side with r < h_side (kernel, derivative, four sums,
+               divergence, curl)
+    force:   68 per pair (both kernel gradients, viscosity, both sides'
+               acceleration and du/dt)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOPS_DENSITY_PAIR = 12
+FLOPS_DENSITY_SIDE = 41
+FLOPS_FORCE_PAIR = 68
+PEAK = {"fp32": 157.3, "fp64": 78.6}   # MI355X vector TFLOP/s (published)
+
+METRIC = "pair interactions/sec (density+force) at 1M particles; plain vs batched/FP32 form"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def ensure_built():
+    from paper_1404_2303_amd import sph
+    if not os.path.exists(sph.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+
+
+def run_form(ps, precision, steps, warmup):
+    import torch
+    from paper_1404_2303_amd import sph
+    parts = sph.Particles.from_numpy(ps, "cuda:0")
+    h0 = parts.h.clone()
+    ctx = sph.Context(ps.box, precision=precision)
+    ctx.enable_timing(True)
+    n = parts.n
+    fout = {k: torch.empty(n, dtype=torch.float64, device="cuda:0") for k in ("ax", "ay", "az", "dudt")}
+    fout["n_pairs"] = torch.empty(n, dtype=torch.int32, device="cuda:0")
+
+    def step():
+        parts.h.copy_(h0)
+        ctx.build_cells(parts)
+        ctx.sort()
+        ctx.density(parts, want=("rho", "n_dens", "n_iter"))
+        ctx.force(parts, out=fout)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    kt = {"build_ms": [], "sort_ms": [], "density_ms": [], "force_ms": []}
+    step_ms = []
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        start.record()
+        step()
+        end.record()
+        end.synchronize()
+        step_ms.append(start.elapsed_time(end))
+        for k, v in ctx.kernel_times().items():
+            kt[k].append(v)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # counts from one more pass over the same input
+    parts.h.copy_(h0)
+    ctx.build_cells(parts)
+    ctx.sort()
+    dd = ctx.density(parts, want=("n_dens", "n_iter"))
+    ff = ctx.force(parts, out=fout)
+    torch.cuda.synchronize()
+    P = int(ff["n_pairs"].sum().item())          # ordered -> 2 stages x unordered
+    S = int(dd["n_dens"].sum().item())           # density sides with r < h_side
+    iters = dd["n_iter"].cpu().numpy()
+    stats = ctx.stats()
+    ctx.close()
+    med = lambda v: float(np.median(v))
+    return {
+        "precision": precision,
+        "P": P,
+        "S": S,
+        "ms_per_step": float(np.mean(step_ms)),
+        "ms_median": med(step_ms),
+        "wall_s": wall,
+        "kernel_ms": {k: med(v) for k, v in kt.items()},
+        "newton_mean": float(np.mean(iters)),
+        "newton_max": int(np.max(iters)),
+        "cells": int(stats["n_cells"]),
+        "grid": list(stats["grid"]),
+    }
+
+
+def roofline(res):
+    """Dominant interaction kernel's algorithmic FLOP rate against the vector peak."""
+    P_unordered = res["P"] / 2.0
+    dens_flops = FLOPS_DENSITY_PAIR * P_unordered + FLOPS_DENSITY_SIDE * res["S"]
+    force_flops = FLOPS_FORCE_PAIR * P_unordered
+    km = res["kernel_ms"]
+    cand = [("density", dens_flops, km["density_ms"]), ("force", force_flops, km["force_ms"])]
+    name, flops, ms = max(cand, key=lambda c: c[2])
+    achieved = flops / (ms * 1e-3) / 1e12
+    peak = PEAK["fp64" if res["precision"] == "fp64" else "fp32"]
+    return {"bound": "alu", "kernel": name, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": None,
+            "other": {c[0]: {"TFLOP/s": c[1] / (c[2] * 1e-3) / 1e12, "ms": c[2]} for c in cand}}
+
+
+def cpu_baseline(seed=0):
+    """The FP64 oracle on a bounded sample: the same lattice law on 128 x 64 x 32 sites."""
+    import oracle
+    from paper_1404_2303_amd import workloads
+    ps = workloads.lattice((128, 64, 32), 1.0 / 128, 0.1, 0.1, seed)
+    t0 = time.perf_counter()
+    out = oracle.full_pass(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box, tol=1e-10)
+    dt = time.perf_counter() - t0
+    P = int(np.sum(out["force"]["count"]))
+    return {"value": P / dt, "unit": "pair interactions/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"FP64 oracle, full density(h-iteration)+force pass on a 128x64x32 jittered lattice "
+                      f"({ps.n} particles, same spacing/jitter/velocity law), {dt:.2f} s, P={P}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the FP64 (plain) form")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    ensure_built()
+    from paper_1404_2303_amd import workloads
+    ps = workloads.config1()
+    log(f"workload: {ps.n} particles, box {ps.box.tolist()}")
+    fast = run_form(ps, "fp32", args.steps, args.warmup)
+    log("fp32_acc64:", json.dumps(fast))
+    plain = None
+    if not args.no_plain:
+        plain = run_form(ps, "fp64", args.steps, args.warmup)
+        log("fp64:", json.dumps(plain))
+    rl = roofline(fast)
+    value = fast["P"] / (fast["ms_per_step"] * 1e-3)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pair interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": fast["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "jittered cubic lattice 128x128x64 (2^20 particles), spacing 1/128, "
+                               "periodic 1x1x0.5 box, v~N(0,0.1), u=1; build+sort+density(h-Newton)+force",
+                   "n": ps.n, "form": "fp32 pair arithmetic, fp64 sums and Newton step",
+                   "pairs_per_step": fast["P"], "kernel_ms": fast["kernel_ms"],
+                   "newton_mean": fast["newton_mean"], "newton_max": fast["newton_max"],
+                   "cells": fast["cells"], "grid": fast["grid"],
+                   "pair_kernel_rate": fast["P"] / ((fast["kernel_ms"]["density_ms"] + fast["kernel_ms"]["force_ms"]) * 1e-3)},
+        "roofline": rl,
+    }
+    if plain is not None:
+        line["plain_fp64"] = {"value": plain["P"] / (plain["ms_per_step"] * 1e-3), "ms_per_step": plain["ms_per_step"],
+                              "kernel_ms": plain["kernel_ms"], "roofline": roofline(plain)}
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -113,6 +113,7 @@ typedef struct {
     double *pressure;  /* P_i = (gamma-1) rho_i u_i */
     double *sound;     /* c_i = sqrt(gamma P_i / rho_i) */
     int32_t *n_iter;   /* Newton evaluations used, -1 if not converged */
+    int32_t *n_dens;   /* number of j != i with r_ij < h_i at the solved h */
 } sph_density_out;
 
 /* Force-stage outputs (any pointer may be NULL). */
@@ -137,9 +138,11 @@ sph_status sph_destroy(sph_ctx *ctx);
  * radix-sorts the keys, and forms cells as runs of equal keys, their
  * neighbour lists (self + 26 neighbours, periodic images included) and
  * cell-ordered copies of the particle data.  batch may be NULL (one box of
- * params.box).  Reads x, y, z, v, u, m, h.  Synchronises `stream` once (to
- * size the cell table).  Errors: SPH_E_INVALID_ARG, SPH_E_NONFINITE,
- * SPH_E_H_TOO_LARGE, SPH_E_OOM, SPH_E_HIP. */
+ * params.box).  Reads x, y, z, v, u, m, h.  Does not synchronise: the
+ * checks that run on the device (non-finite data, h too large for the box,
+ * capacity) are reported by the next sph_density.  Errors returned here:
+ * SPH_E_INVALID_ARG, SPH_E_CAPACITY (key or map too large), SPH_E_OOM,
+ * SPH_E_HIP. */
 sph_status sph_build_cells(sph_ctx *ctx, const sph_particles *p, const sph_batch *batch,
                            void *stream);
 
@@ -189,6 +192,19 @@ typedef struct {
 } sph_stats;
 
 sph_status sph_get_stats(const sph_ctx *ctx, sph_stats *out);
+
+/* Kernel timing.  While enabled, the library records HIP events on the
+ * call's stream immediately around its interaction kernels (and around the
+ * build and sort launch sequences); sph_get_kernel_times waits for those
+ * events and returns the elapsed milliseconds of the last sph_build_cells,
+ * sph_sort, density kernel (every Newton evaluation, summed over rebuild
+ * attempts) and force kernel.  Errors: SPH_E_INVALID_ARG, SPH_E_HIP. */
+typedef struct {
+    float build_ms, sort_ms, density_ms, force_ms;
+} sph_kernel_times;
+
+sph_status sph_enable_timing(sph_ctx *ctx, int on);
+sph_status sph_get_kernel_times(sph_ctx *ctx, sph_kernel_times *out);
 
 /* Human-readable text of a status (static storage). */
 const char *sph_status_string(sph_status s);

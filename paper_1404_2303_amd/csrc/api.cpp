@@ -48,9 +48,9 @@ struct sph_ctx {
     int device = 0;
     // workspace
     DBuf boxes, keys, keys2, vals, vals2, rs_scratch, flag, cellx, cell_of, sc_scratch;
-    DBuf cells, ncells, cell_map, src, src_count, sidx, skey;
-    DBuf rx, ry, rz, h, m, vx, vy, vz, u;            // cell order
-    DBuf hh, hinv, gk, rho, A, c, f, cell_hmax;      // ghost quantities, cell order
+    DBuf cells, ncells, cell_map, src, src_count, sidx, srec;
+    DBuf rx, ry, rz, h, vm, u;                       // cell order
+    DBuf g0, g1, cell_hmax;                          // ghost quantities, cell order
     DBuf qhead, status;
     DBuf step_tmp;                                   // predicted v, u; new a, du/dt
     uint32_t* status_host = nullptr;                 // pinned
@@ -65,27 +65,50 @@ struct sph_ctx {
     std::vector<double> batch_len;
     bool built = false, sorted = false, have_density = false;
     sph_stats stats{};
+    // optional kernel timing
+    bool timing = false;
+    hipEvent_t ev[8] = {};
+    float dens_ms_acc = 0.0f;
+    int dens_pending = 0;     // density events recorded since the last read
 };
+
+enum { EV_BUILD0, EV_BUILD1, EV_SORT0, EV_SORT1, EV_DENS0, EV_DENS1, EV_FORCE0, EV_FORCE1 };
+
+static void ev_record(sph_ctx* c, int k, hipStream_t st)
+{
+    if (c->timing) (void)hipEventRecord(c->ev[k], st);
+}
 
 static sph_status hip_status(hipError_t e) { return e == hipSuccess ? SPH_OK : SPH_E_HIP; }
 
 template <typename R>
 static CellData<R> cell_data(sph_ctx* c)
 {
+    using R4 = typename Vec4T<R>::T;
     CellData<R> d;
     d.rx = c->rx.as<R>(); d.ry = c->ry.as<R>(); d.rz = c->rz.as<R>();
     d.h = c->h.as<double>();
-    d.m = c->m.as<R>(); d.vx = c->vx.as<R>(); d.vy = c->vy.as<R>(); d.vz = c->vz.as<R>();
+    d.vm = c->vm.as<R4>();
     d.u = c->u.as<double>();
     return d;
 }
 
 template <typename R>
+static Sorted<R> sorted_data(sph_ctx* c)
+{
+    using R4 = typename Vec4T<R>::T;
+    Sorted<R> so;
+    so.idx = c->sidx.as<uint16_t>();
+    so.rec = c->srec.as<R4>();
+    return so;
+}
+
+template <typename R>
 static GhostData<R> ghost_data(sph_ctx* c)
 {
+    using R4 = typename Vec4T<R>::T;
     GhostData<R> g;
-    g.hh = c->hh.as<R>(); g.hinv = c->hinv.as<R>(); g.gk = c->gk.as<R>();
-    g.rho = c->rho.as<R>(); g.A = c->A.as<R>(); g.c = c->c.as<R>(); g.f = c->f.as<R>();
+    g.g0 = c->g0.as<R4>(); g.g1 = c->g1.as<R4>();
     g.cell_hmax = c->cell_hmax.as<float>();
     return g;
 }
@@ -98,8 +121,6 @@ static Decomp decomp(sph_ctx* c)
     d.boxes = c->boxes.as<BoxInfo>();
     d.src = c->src.as<Source>();
     d.src_count = c->src_count.as<int32_t>();
-    d.sidx = c->sidx.as<uint16_t>();
-    d.skey = c->skey.as<float>();
     d.perm = c->vals.as<uint32_t>();
     d.n = c->n;
     d.qhead = c->qhead.as<int32_t>();
@@ -133,12 +154,11 @@ static bool ensure_particles(sph_ctx* c, int64_t n)
     ok &= c->sc_scratch.ensure(scan_scratch_words((int64_t)N) * 4 + 16);
     ok &= c->cells.ensure(N * sizeof(CellInfo)) && c->ncells.ensure(16);
     ok &= c->src.ensure(N * kMaxSources * sizeof(Source)) && c->src_count.ensure(N * 4);
-    ok &= c->sidx.ensure(N * kSortDirs * 2) && c->skey.ensure(N * kSortDirs * 4);
+    ok &= c->sidx.ensure(N * kSortDirs * 2) && c->srec.ensure(N * kSortDirs * 4 * R);
     ok &= c->rx.ensure(N * R) && c->ry.ensure(N * R) && c->rz.ensure(N * R);
     ok &= c->h.ensure(N * 8) && c->u.ensure(N * 8);
-    ok &= c->m.ensure(N * R) && c->vx.ensure(N * R) && c->vy.ensure(N * R) && c->vz.ensure(N * R);
-    ok &= c->hh.ensure(N * R) && c->hinv.ensure(N * R) && c->gk.ensure(N * R);
-    ok &= c->rho.ensure(N * R) && c->A.ensure(N * R) && c->c.ensure(N * R) && c->f.ensure(N * R);
+    ok &= c->vm.ensure(N * 4 * R);
+    ok &= c->g0.ensure(N * 4 * R) && c->g1.ensure(N * 4 * R);
     ok &= c->cell_hmax.ensure(N * 4);
     ok &= c->qhead.ensure(16) && c->status.ensure(16);
     return ok;
@@ -221,12 +241,12 @@ sph_status sph_destroy(sph_ctx* c)
     if (!c) return SPH_OK;
     DBuf* all[] = {&c->boxes, &c->keys, &c->keys2, &c->vals, &c->vals2, &c->rs_scratch, &c->flag,
                    &c->cellx, &c->cell_of, &c->sc_scratch, &c->cells, &c->ncells, &c->cell_map,
-                   &c->src, &c->src_count, &c->sidx, &c->skey, &c->rx, &c->ry, &c->rz, &c->h,
-                   &c->m, &c->vx, &c->vy, &c->vz, &c->u, &c->hh, &c->hinv, &c->gk, &c->rho, &c->A,
-                   &c->c, &c->f, &c->cell_hmax, &c->qhead, &c->status, &c->step_tmp};
+                   &c->src, &c->src_count, &c->sidx, &c->srec, &c->rx, &c->ry, &c->rz, &c->h,
+                   &c->vm, &c->u, &c->g0, &c->g1, &c->cell_hmax, &c->qhead, &c->status, &c->step_tmp};
     for (DBuf* b : all) b->release();
     if (c->status_host) (void)hipHostFree(c->status_host);
     if (c->ncells_host) (void)hipHostFree(c->ncells_host);
+    for (hipEvent_t& e : c->ev) if (e) (void)hipEventDestroy(e);
     delete c;
     return SPH_OK;
 }
@@ -343,8 +363,10 @@ sph_status sph_build_cells(sph_ctx* c, const sph_particles* p, const sph_batch* 
     if (e != hipSuccess) return SPH_E_HIP;
     if (p->n > 0) {
         Particles pv = view(p);
+        ev_record(c, EV_BUILD0, st);
         if (c->prm.precision == SPH_FP64) build_launches<double>(c, pv, st);
         else build_launches<float>(c, pv, st);
+        ev_record(c, EV_BUILD1, st);
     }
     if (hipGetLastError() != hipSuccess) return SPH_E_HIP;
     c->built = true;
@@ -357,12 +379,14 @@ sph_status sph_sort(sph_ctx* c, void* stream)
     if (!c->built) return SPH_E_STATE;
     hipStream_t st = (hipStream_t)stream;
     if (c->n > 0) {
+        ev_record(c, EV_SORT0, st);
         if (c->prm.precision == SPH_FP64)
             launch_sort13<double>(c->cells.as<CellInfo>(), c->ncells.as<int32_t>(), cell_data<double>(c), c->n,
-                                  c->sidx.as<uint16_t>(), c->skey.as<float>(), c->status.as<uint32_t>(), c->n, st);
+                                  sorted_data<double>(c), c->status.as<uint32_t>(), c->n, st);
         else
             launch_sort13<float>(c->cells.as<CellInfo>(), c->ncells.as<int32_t>(), cell_data<float>(c), c->n,
-                                 c->sidx.as<uint16_t>(), c->skey.as<float>(), c->status.as<uint32_t>(), c->n, st);
+                                 sorted_data<float>(c), c->status.as<uint32_t>(), c->n, st);
+        ev_record(c, EV_SORT1, st);
     }
     if (hipGetLastError() != hipSuccess) return SPH_E_HIP;
     c->sorted = true;
@@ -398,9 +422,11 @@ static void density_launch(sph_ctx* c, const sph_particles* p, const sph_density
         out.rho = o->rho; out.omega = o->omega; out.nngb = o->n_ngb; out.div = o->div_v;
         out.curl = o->curl_v; out.balsara = o->balsara; out.P = o->pressure; out.c = o->sound;
         out.iters = o->n_iter;
+        out.ndens = o->n_dens;
     }
     int grid = density_occupancy_grid(c->prm.precision);
-    launch_density<R>(decomp(c), cell_data<R>(c), ghost_data<R>(c), out, pass_consts(c->prm), grid, st);
+    launch_density<R>(decomp(c), cell_data<R>(c), sorted_data<R>(c), ghost_data<R>(c), out, pass_consts(c->prm),
+                      grid, st);
 }
 }  // extern "C++"
 
@@ -412,14 +438,21 @@ sph_status sph_density(sph_ctx* c, sph_particles* p, sph_density_out* o, void* s
     hipStream_t st = (hipStream_t)stream;
     c->stats.rebuilds = 0;
     c->have_density = false;
+    c->dens_ms_acc = 0.0f;
     for (int attempt = 0;; attempt++) {
         uint32_t bits = 0;
         if (c->n > 0) {
+            ev_record(c, EV_DENS0, st);
             if (c->prm.precision == SPH_FP64) density_launch<double>(c, p, o, st);
             else density_launch<float>(c, p, o, st);
+            ev_record(c, EV_DENS1, st);
             if (hipGetLastError() != hipSuccess) return SPH_E_HIP;
         }
         sph_status s = read_status(c, st, &bits);
+        if (c->timing && c->n > 0) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, c->ev[EV_DENS0], c->ev[EV_DENS1]) == hipSuccess) c->dens_ms_acc += ms;
+        }
         if (s != SPH_OK) return s;
         s = status_error(bits);
         if (s != SPH_OK) return s;
@@ -457,10 +490,14 @@ sph_status sph_force(sph_ctx* c, const sph_particles* p, sph_force_out* o, void*
     ForceOut out{};
     out.ax = o->ax; out.ay = o->ay; out.az = o->az; out.dudt = o->dudt; out.npairs = o->n_pairs;
     int grid = force_occupancy_grid(c->prm.precision);
+    ev_record(c, EV_FORCE0, st);
     if (c->prm.precision == SPH_FP64)
-        launch_force<double>(decomp(c), cell_data<double>(c), ghost_data<double>(c), out, pass_consts(c->prm), grid, st);
+        launch_force<double>(decomp(c), cell_data<double>(c), sorted_data<double>(c), ghost_data<double>(c), out,
+                             pass_consts(c->prm), grid, st);
     else
-        launch_force<float>(decomp(c), cell_data<float>(c), ghost_data<float>(c), out, pass_consts(c->prm), grid, st);
+        launch_force<float>(decomp(c), cell_data<float>(c), sorted_data<float>(c), ghost_data<float>(c), out,
+                            pass_consts(c->prm), grid, st);
+    ev_record(c, EV_FORCE1, st);
     return hipGetLastError() == hipSuccess ? SPH_OK : SPH_E_HIP;
 }
 
@@ -502,6 +539,30 @@ sph_status sph_step(sph_ctx* c, sph_particles* p, const sph_batch* batch, sph_fo
     launch_kick(p->vx, p->vy, p->vz, p->u, acc->ax, acc->ay, acc->az, acc->dudt, hdt, n, st);
     if (hipGetLastError() != hipSuccess) return SPH_E_HIP;
     return sd;
+}
+
+sph_status sph_enable_timing(sph_ctx* c, int on)
+{
+    if (!c) return SPH_E_INVALID_ARG;
+    if (on && !c->ev[0]) {
+        for (hipEvent_t& e : c->ev)
+            if (hipEventCreate(&e) != hipSuccess) return SPH_E_HIP;
+    }
+    c->timing = on != 0;
+    return SPH_OK;
+}
+
+sph_status sph_get_kernel_times(sph_ctx* c, sph_kernel_times* out)
+{
+    if (!c || !out) return SPH_E_INVALID_ARG;
+    std::memset(out, 0, sizeof(*out));
+    if (!c->timing) return SPH_OK;
+    if (hipEventSynchronize(c->ev[EV_FORCE1]) != hipSuccess) return SPH_E_HIP;
+    (void)hipEventElapsedTime(&out->build_ms, c->ev[EV_BUILD0], c->ev[EV_BUILD1]);
+    (void)hipEventElapsedTime(&out->sort_ms, c->ev[EV_SORT0], c->ev[EV_SORT1]);
+    (void)hipEventElapsedTime(&out->force_ms, c->ev[EV_FORCE0], c->ev[EV_FORCE1]);
+    out->density_ms = c->dens_ms_acc;
+    return SPH_OK;
 }
 
 sph_status sph_get_stats(const sph_ctx* c, sph_stats* out)

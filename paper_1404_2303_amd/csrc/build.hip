@@ -35,17 +35,45 @@ __device__ inline double wrap_coord(double v, double L)
 }
 
 // ---------------------------------------------------------------- box scan
-__global__ void k_box_scan(Particles p, BoxInfo* boxes, int nbox, int64_t n, uint32_t* status)
+// Each block takes a contiguous chunk of particles; when the chunk lies in one
+// box (the common case) the largest h is reduced in the block and merged
+// with one atomic, otherwise per particle.
+constexpr int BS_THREADS = 256;
+
+__global__ __launch_bounds__(BS_THREADS) void k_box_scan(Particles p, BoxInfo* boxes, int nbox, int64_t n,
+                                                         int64_t chunk, uint32_t* status)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    bool ok = finite_d(p.x[i]) && finite_d(p.y[i]) && finite_d(p.z[i]) && finite_d(p.vx[i]) &&
-              finite_d(p.vy[i]) && finite_d(p.vz[i]) && finite_d(p.u[i]) && finite_d(p.m[i]) &&
-              finite_d(p.h[i]) && p.m[i] > 0.0 && p.h[i] > 0.0 && p.u[i] >= 0.0;
-    if (!ok) { atomicOr(status, ST_NONFINITE); return; }
-    int b = find_box(boxes, nbox, i);
-    // h > 0: the IEEE bit pattern orders like the value
-    atomicMax((unsigned long long*)&boxes[b].hmax, (unsigned long long)__double_as_longlong(p.h[i]));
+    __shared__ double red[BS_THREADS / kWave];
+    const int64_t beg = (int64_t)blockIdx.x * chunk;
+    const int64_t end = beg + chunk < n ? beg + chunk : n;
+    if (beg >= n) return;
+    const int b0 = find_box(boxes, nbox, beg), b1 = find_box(boxes, nbox, end - 1);
+    const bool one_box = b0 == b1;
+    double hm = 0.0;
+    bool bad = false;
+    for (int64_t i = beg + threadIdx.x; i < end; i += BS_THREADS) {
+        bool ok = finite_d(p.x[i]) && finite_d(p.y[i]) && finite_d(p.z[i]) && finite_d(p.vx[i]) &&
+                  finite_d(p.vy[i]) && finite_d(p.vz[i]) && finite_d(p.u[i]) && finite_d(p.m[i]) &&
+                  finite_d(p.h[i]) && p.m[i] > 0.0 && p.h[i] > 0.0 && p.u[i] >= 0.0;
+        if (!ok) { bad = true; continue; }
+        if (one_box) {
+            hm = fmax(hm, p.h[i]);
+        } else {
+            int b = find_box(boxes, nbox, i);
+            // h > 0: the IEEE bit pattern orders like the value
+            atomicMax((unsigned long long*)&boxes[b].hmax, (unsigned long long)__double_as_longlong(p.h[i]));
+        }
+    }
+    if (bad) atomicOr(status, ST_NONFINITE);
+    if (!one_box) return;
+    for (int o = 32; o > 0; o >>= 1) hm = fmax(hm, __shfl_xor(hm, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = hm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < BS_THREADS / kWave; w++) hm = fmax(hm, red[w]);
+        if (hm > 0.0)
+            atomicMax((unsigned long long*)&boxes[b0].hmax, (unsigned long long)__double_as_longlong(hm));
+    }
 }
 
 __global__ void k_clear_boxes(BoxInfo* boxes, int nbox)
@@ -86,8 +114,8 @@ __global__ void k_keys(Particles p, const BoxInfo* boxes, int nbox, int64_t n, i
     uint32_t c[3];
     for (int d = 0; d < 3; d++) {
         double w = wrap_coord(pos[d], B.L[d]);
-        int cc = (int)floor(w / B.e[d]);
-        cc = cc < 0 ? 0 : (cc >= B.nc[d] ? B.nc[d] - 1 : cc);
+        double fc = floor(w / B.e[d]);
+        int cc = (fc >= 0.0) ? (int)fmin(fc, (double)(B.nc[d] - 1)) : 0;  // NaN -> 0 (flagged by the box scan)
         c[d] = (uint32_t)cc;
     }
     keys[i] = ((uint64_t)b << (3 * top_bits)) | morton3(c[0], c[1], c[2]);
@@ -329,8 +357,9 @@ __global__ void k_gather(Particles p, const uint32_t* perm, const uint32_t* cell
     }
     cd.rx[k] = rel[0]; cd.ry[k] = rel[1]; cd.rz[k] = rel[2];
     cd.h[k] = p.h[i];
-    cd.m[k] = (R)p.m[i];
-    cd.vx[k] = (R)p.vx[i]; cd.vy[k] = (R)p.vy[i]; cd.vz[k] = (R)p.vz[i];
+    typename CellData<R>::R4 vm;
+    vm.x = (R)p.vx[i]; vm.y = (R)p.vy[i]; vm.z = (R)p.vz[i]; vm.w = (R)p.m[i];
+    cd.vm[k] = vm;
     cd.u[k] = p.u[i];
 }
 
@@ -369,10 +398,10 @@ constexpr int SORT_MAX = 4096;
 
 template <typename R>
 __global__ __launch_bounds__(SORT_THREADS) void k_sort13(const CellInfo* cells, const int32_t* ncells,
-                                                         CellData<R> cd, int64_t n, uint16_t* sidx,
-                                                         float* skey, uint32_t* status)
+                                                         CellData<R> cd, int64_t n, Sorted<R> so,
+                                                         uint32_t* status)
 {
-    __shared__ float key[SORT_MAX];
+    __shared__ uint32_t key[SORT_MAX];
     const int64_t units = (int64_t)(*ncells) * kSortDirs;
     for (int64_t unit = blockIdx.x; unit < units; unit += gridDim.x) {
         const int c = (int)(unit / kSortDirs);
@@ -382,21 +411,29 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort13(const CellInfo* cells, 
         float su[3];
         dir_unit(s + 13, su);
         __syncthreads();
+        // ranks are taken on an order-preserving integer image of the projection,
+        // a total order (NaN included), so every cell's ordering is a permutation
         for (int t = threadIdx.x; t < C.count; t += SORT_THREADS) {
             int64_t k = C.start + t;
-            key[t] = su[0] * (float)cd.rx[k] + su[1] * (float)cd.ry[k] + su[2] * (float)cd.rz[k];
+            const float f = su[0] * (float)cd.rx[k] + su[1] * (float)cd.ry[k] + su[2] * (float)cd.rz[k];
+            const uint32_t b = __float_as_uint(f);
+            key[t] = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
         }
         __syncthreads();
         for (int t = threadIdx.x; t < C.count; t += SORT_THREADS) {
-            float kt = key[t];
+            const uint32_t kt = key[t];
             int rank = 0;
             for (int j = 0; j < C.count; j++) {
-                float kj = key[j];
+                const uint32_t kj = key[j];
                 rank += (kj < kt) || (kj == kt && j < t);
             }
             int64_t o = (int64_t)s * n + C.start + rank;
-            sidx[o] = (uint16_t)t;
-            skey[o] = kt;
+            int64_t k = C.start + t;
+            so.idx[o] = (uint16_t)t;
+            const uint32_t b = (kt & 0x80000000u) ? (kt & 0x7fffffffu) : ~kt;
+            typename Sorted<R>::R4 r;
+            r.x = cd.rx[k]; r.y = cd.ry[k]; r.z = cd.rz[k]; r.w = (R)__uint_as_float(b);
+            so.rec[o] = r;
         }
     }
 }
@@ -406,9 +443,14 @@ void launch_box_scan(const Particles& p, BoxInfo* boxes, int nbox, int64_t n, ui
                      hipStream_t st)
 {
     hipLaunchKernelGGL(k_clear_boxes, dim3((nbox + 255) / 256), dim3(256), 0, st, boxes, nbox);
-    if (n > 0)
-        hipLaunchKernelGGL(k_box_scan, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, boxes,
-                           nbox, n, status);
+    if (n > 0) {
+        int64_t nb = (n + BS_THREADS - 1) / BS_THREADS;
+        if (nb > 1024) nb = 1024;
+        int64_t chunk = (n + nb - 1) / nb;
+        nb = (n + chunk - 1) / chunk;
+        hipLaunchKernelGGL(k_box_scan, dim3((unsigned)nb), dim3(BS_THREADS), 0, st, p, boxes, nbox, n, chunk,
+                           status);
+    }
 }
 
 void launch_grid_dims(BoxInfo* boxes, int nbox, double margin, int max_nc, uint32_t* status,
@@ -507,17 +549,16 @@ void launch_sources(const CellInfo* cells, const int32_t* ncells, const BoxInfo*
 
 template <typename R>
 void launch_sort13(const CellInfo* cells, const int32_t* ncells, const CellData<R>& cd, int64_t n,
-                   uint16_t* sidx, float* skey, uint32_t* status, int64_t cell_cap, hipStream_t st)
+                   const Sorted<R>& so, uint32_t* status, int64_t cell_cap, hipStream_t st)
 {
     int64_t units = cell_cap * kSortDirs;
     unsigned grid = (unsigned)(units < 65536 ? units : 65536);
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_sort13<R>, dim3(grid), dim3(SORT_THREADS), 0, st, cells, ncells, cd, n, sidx,
-                       skey, status);
+    hipLaunchKernelGGL(k_sort13<R>, dim3(grid), dim3(SORT_THREADS), 0, st, cells, ncells, cd, n, so, status);
 }
 template void launch_sort13<float>(const CellInfo*, const int32_t*, const CellData<float>&, int64_t,
-                                   uint16_t*, float*, uint32_t*, int64_t, hipStream_t);
+                                   const Sorted<float>&, uint32_t*, int64_t, hipStream_t);
 template void launch_sort13<double>(const CellInfo*, const int32_t*, const CellData<double>&, int64_t,
-                                    uint16_t*, float*, uint32_t*, int64_t, hipStream_t);
+                                    const Sorted<double>&, uint32_t*, int64_t, hipStream_t);
 
 }  // namespace sph

@@ -11,28 +11,45 @@ struct Particles {
     const double *x, *y, *z, *vx, *vy, *vz, *u, *m, *h;
 };
 
+template <typename R> struct Vec4T;
+template <> struct Vec4T<float> { using T = float4; };
+template <> struct Vec4T<double> { using T = double4; };
+
 // Cell-ordered particle copies.  Positions are relative to the lower corner
 // of the particle's cell, in the pair-arithmetic type R.
 template <typename R>
 struct CellData {
+    using R4 = typename Vec4T<R>::T;
     R *rx, *ry, *rz;
     double* h;           // smoothing length (FP64 master copy)
-    R *m, *vx, *vy, *vz;
+    R4* vm;              // (vx, vy, vz, m)
     double* u;
 };
 
+// The 13 orderings of every cell: for stored direction s and rank k within
+// cell C, entry s*n + C.start + k holds the particle's cell-local index and
+// (x, y, z relative to the cell, projection on the direction).
+template <typename R>
+struct Sorted {
+    using R4 = typename Vec4T<R>::T;
+    uint16_t* idx;
+    R4* rec;
+};
+
 // Per-particle results of the density stage needed by the force stage, in
-// cell order.  hinv = 1/h, gk = 8/(pi h^5) (the gradient prefactor).
+// cell order: g0 = (1/h, 8/(pi h^5), A = P/(Omega rho^2), rho),
+// g1 = (c, Balsara f, h, 0).
 template <typename R>
 struct GhostData {
-    R *hh, *hinv, *gk, *rho, *A, *c, *f;
+    using R4 = typename Vec4T<R>::T;
+    R4 *g0, *g1;
     float* cell_hmax;    // largest h of each cell
 };
 
 // Caller-order outputs of the density stage (any may be null).
 struct DensityOut {
     double *h, *rho, *omega, *nngb, *div, *curl, *balsara, *P, *c;
-    int32_t* iters;
+    int32_t *iters, *ndens;
 };
 
 struct ForceOut {
@@ -48,8 +65,6 @@ struct Decomp {
     const BoxInfo* boxes;
     const Source* src;
     const int32_t* src_count;
-    const uint16_t* sidx;   // [13][n]
-    const float* skey;      // [13][n]
     const uint32_t* perm;   // cell order -> caller index
     int64_t n;
     int32_t* qhead;         // work counter of the persistent launches
@@ -82,15 +97,15 @@ void launch_sources(const CellInfo* cells, const int32_t* ncells, const BoxInfo*
                     hipStream_t st);
 template <typename R>
 void launch_sort13(const CellInfo* cells, const int32_t* ncells, const CellData<R>& cd, int64_t n,
-                   uint16_t* sidx, float* skey, uint32_t* status, int64_t cell_cap, hipStream_t st);
+                   const Sorted<R>& so, uint32_t* status, int64_t cell_cap, hipStream_t st);
 
 // passes.hip
 void launch_reset_counter(int32_t* c, hipStream_t st);
 template <typename R>
-void launch_density(const Decomp& dc, const CellData<R>& cd, const GhostData<R>& gd,
+void launch_density(const Decomp& dc, const CellData<R>& cd, const Sorted<R>& so, const GhostData<R>& gd,
                     const DensityOut& out, const PassConsts& pc, int grid, hipStream_t st);
 template <typename R>
-void launch_force(const Decomp& dc, const CellData<R>& cd, const GhostData<R>& gd,
+void launch_force(const Decomp& dc, const CellData<R>& cd, const Sorted<R>& so, const GhostData<R>& gd,
                   const ForceOut& out, const PassConsts& pc, int grid, hipStream_t st);
 int density_occupancy_grid(int precision);
 int force_occupancy_grid(int precision);

@@ -2,32 +2,35 @@
 // the cell decomposition of Sec. 3.2 with the sorted pair sweeps of
 // Sec. 3.3, for gfx950.
 //
-// Work unit: one target cell T, processed by one 64-lane wavefront with one
-// lane per target particle (cells with more than 64 particles are taken in
-// chunks of 64).  The unit gathers from T itself (self interaction) and from
-// its 26 neighbours (pair interactions, periodic images included).
+// Work unit: one target cell T and up to 64 of its particles, processed by a
+// workgroup of four 64-lane wavefronts.  Every wavefront holds the same 64
+// targets (one per lane) and owns a quarter of the interaction sources: a
+// quarter of T itself (self interaction) and a fixed share of the 26
+// neighbour cells (pair interactions, periodic images included).  The
+// partial sums of the four wavefronts are added in LDS.
 //
-// Staging.  For each neighbour S in direction d (unit vector u, from T to S)
-// the particles of S are read in the stored order along d (reversed for the
-// 13 directions that are negatives of stored ones), shifted into T's frame,
-// and copied to LDS while their projection u.x stays within reach of T:
-// u.x_j <= max_{x in T} u.x + H + margin.  Because the projection never
-// exceeds the distance, nothing beyond that prefix can be in range.
+// Staging.  For a neighbour S in direction d (unit vector u, from T to S) a
+// wavefront reads the stored ordering of S along d (reversed for the 13
+// directions that are negatives of stored ones) and copies the particles,
+// shifted into T's frame, to LDS while their projection u.x stays within
+// reach of T: u.x_j <= max_{x in T} u.x + H + margin.  Because a projection
+// never exceeds the distance, nothing beyond that prefix can be in range.
 //
-// Sweep.  Each lane walks the staged segments one after the other; inside a
-// segment it stops at the first particle with u.x_j > u.x_i + H_i + margin
-// (the early exit of the sorted pair interaction), and otherwise tests the
-// true distance.  Particles in range are appended to the lane's neighbour
-// list in LDS (the compaction step); when any list is full, or the walk is
-// over, every lane evaluates the interaction for its own list.  Lanes thus
-// run the expensive arithmetic only on pairs that are in range, each on its
-// own particle (a gather: the target particle is written by this wavefront
-// alone, so no atomics are needed).
+// Sweep.  Each lane walks its wavefront's staged segments one after the
+// other; inside a segment it stops at the first particle with
+// u.x_j > u.x_i + H_i + margin (the early exit of the sorted pair
+// interaction) and otherwise tests the distance.  Particles in range are
+// appended to the lane's neighbour list in LDS (the compaction step); when a
+// list is full, or the walk is over, every lane evaluates the interaction
+// terms for its own list, so the expensive arithmetic only runs on pairs in
+// range.  The target particle is written by this workgroup alone (a gather),
+// so no global atomics are needed.
 //
-// Density (Eqs. (2)-(3)): the Newton iteration on h runs inside the unit,
-// re-sweeping the staged neighbourhood for the lanes that have not yet
-// converged; the per-particle quantities of the force stage (Omega, P, c,
-// A = P/(Omega rho^2), the Balsara switch of Sec. 4.1) are formed at the end.
+// Density (Eqs. (2)-(3)): the Newton iteration on h runs inside the unit.
+// The first sweep lists the neighbours within a slightly larger radius; later
+// Newton evaluations reuse the lists while h stays inside it.  The
+// per-particle quantities of the force stage (Omega, P, c, A = P/(Omega rho^2),
+// the Balsara switch of Sec. 4.1) are formed at the end.
 // Force (Eqs. (4)-(5) + Sec. 4.1 viscosity): one sweep over r < max(h_i, h_j).
 //
 // Arithmetic: pair terms in R (float or double); every per-particle sum and
@@ -37,11 +40,21 @@
 
 namespace sph {
 
-constexpr int WG = 64;
+constexpr int NW = 4;                 // wavefronts per target cell
+constexpr int WGS = NW * kWave;
+constexpr int kMaxSegW = 28;          // staged segments per wavefront and batch
+constexpr int NACC_D = 9;             // density partial sums per target
+constexpr int NACC_F = 5;             // force partial sums per target
+constexpr float kCacheSlack = 0.08f;  // neighbour lists cover h (1 + slack)
 
-template <typename R> struct StageCfg;
-template <> struct StageCfg<float> { static constexpr int CAP = 1024; static constexpr int LIST = 64; };
-template <> struct StageCfg<double> { static constexpr int CAP = 640; static constexpr int LIST = 64; };
+template <typename R> struct PCfg;
+template <> struct PCfg<float> { static constexpr int CAPW = 256, LISTW = 48; };
+template <> struct PCfg<double> { static constexpr int CAPW = 144, LISTW = 48; };
+
+// share of the 26 neighbour directions per wavefront: faces 2/2/1/1,
+// edges 3/3/3/3, corners 1/1/3/3
+__constant__ int8_t kDirWave[kDirs] = {2, 2, 3, 3, 0, 0, 2, 1, 3, 2, 1, 3, 2,
+                                       3, 0, 0, 1, 2, 2, 3, 3, 1, 0, 0, 1, 1};
 
 // ---------------------------------------------------------------- kernel W (Sec. 2.1)
 // w(q) = 1 - 6q^2 + 6q^3 (q <= 1/2), 2(1-q)^3 (1/2 < q <= 1); callers ensure q < 1.
@@ -69,76 +82,79 @@ template <typename R> __device__ __forceinline__ R kern_g(R q, R qinv)
     return q <= (R)0.5 ? a : b;
 }
 
-template <typename R> __device__ __forceinline__ R rsqrt_t(R v);
-template <> __device__ __forceinline__ float rsqrt_t<float>(float v) { return __frsqrt_rn(v); }
-template <> __device__ __forceinline__ double rsqrt_t<double>(double v) { return 1.0 / sqrt(v); }
-
 __device__ __forceinline__ double wave_max(double v)
 {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
     return v;
 }
-__device__ __forceinline__ int wave_max_i(int v)
+
+// LDS writes of one lane become visible to the other lanes of its wavefront
+__device__ __forceinline__ void wave_sync()
 {
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // ---------------------------------------------------------------- LDS layout
-template <typename R, bool FORCE>
+template <typename R, int NACC>
 struct Smem {
-    static constexpr int CAP = StageCfg<R>::CAP;
-    static constexpr int LIST = StageCfg<R>::LIST;
-    R sx[CAP], sy[CAP], sz[CAP];
-    R sh[FORCE ? CAP : 1];
-    float sp[CAP];
-    uint32_t sg[CAP];
-    uint16_t list[LIST][WG];
-    int seg_b[kMaxSources], seg_e[kMaxSources];
-    float seg_u[kMaxSources][3];
-    float seg_bound_extra[kMaxSources];  // force: the source cell's largest h
-    int nseg;
+    using R4 = typename Vec4T<R>::T;
+    static constexpr int CAPW = PCfg<R>::CAPW;
+    static constexpr int LISTW = PCfg<R>::LISTW;
+    R4 st[NW][CAPW];                  // staged (x, y, z in T's frame, h_j for the force stage)
+    uint32_t sg[NW][CAPW];            // cell-order index of each staged particle
+    uint16_t list[NW][LISTW][kWave];  // per-lane neighbour lists (staged indices)
+    double red[NACC][kWave];          // partial sums of the four wavefronts
+    double hsh[kWave];                // current h of each target (density)
+    int seg_b[NW][kMaxSegW], seg_e[NW][kMaxSegW];
+    float seg_u[NW][kMaxSegW][3];
+    float seg_hx[NW][kMaxSegW];       // force: largest h of the source cell
+    int nseg[NW];
+    int conv[kWave];
+    int ctl[4];                       // 0: all converged, 1: restage
+    int unit;
 };
 
-// Stage sources [k0, ...) starting at traversal position p0 of source k0.
-// Returns through (k1, p1) the first source/position not staged.
-template <typename R, bool FORCE>
-__device__ void stage_batch(Smem<R, FORCE>& s, const Decomp& dc, const CellData<R>& cd,
-                            const GhostData<R>& gd, const CellInfo& T, const BoxInfo& B, int tcell,
-                            int nsrc, int k0, int p0, float Hst, float margin, int& k1, int& p1)
+// Stage, for wavefront w, its sources from cursor (k, p) on; advance the
+// cursor past what was staged (k == nsrc when every source is staged).
+template <typename R, bool FORCE, int NACC>
+__device__ void stage_wave(Smem<R, NACC>& s, const int w, const Decomp& dc, const CellData<R>& cd,
+                           const Sorted<R>& so, const GhostData<R>& gd, const BoxInfo& B, const int tcell,
+                           const int nsrc, int& k, int& p, const float Hst, const float margin)
 {
-    const int lane = threadIdx.x;
-    const int CAP = Smem<R, FORCE>::CAP;
+    using R4 = typename Vec4T<R>::T;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int CAPW = Smem<R, NACC>::CAPW;
     int fill = 0, nseg = 0;
-    int k = k0, p = p0;
-    __syncthreads();  // previous readers of the staging buffer are done
+    wave_sync();  // earlier readers of this wavefront's staging area are done
     while (k < nsrc) {
-        Source src = dc.src[(int64_t)tcell * kMaxSources + k];
+        const Source src = dc.src[(int64_t)tcell * kMaxSources + k];
+        const bool self = src.dir == kSelfDir;
+        if (!self && kDirWave[src.dir] != w) { k++; p = 0; continue; }
+        if (nseg == kMaxSegW || fill >= CAPW) break;
         const CellInfo S = dc.cells[src.cell];
-        int segb = fill;
+        const int segb = fill;
         bool complete = true;
-        if (src.dir == kSelfDir) {
-            int n = S.count - p;
-            int take = min(n, CAP - fill);
-            for (int t = lane; t < take; t += WG) {
-                int g = S.start + p + t;
-                s.sx[fill + t] = cd.rx[g];
-                s.sy[fill + t] = cd.ry[g];
-                s.sz[fill + t] = cd.rz[g];
-                if constexpr (FORCE) s.sh[fill + t] = gd.hh[g];
-                s.sp[fill + t] = 0.0f;
-                s.sg[fill + t] = (uint32_t)g;
+        float u[3] = {0.f, 0.f, 0.f};
+        float hx = 0.f;
+        if (self) {
+            const int q0 = (S.count * w) / NW, q1 = (S.count * (w + 1)) / NW;
+            const int n = q1 - q0 - p;
+            const int take = min(n, CAPW - fill);
+            for (int t = lane; t < take; t += kWave) {
+                const int g = S.start + q0 + p + t;
+                R4 e;
+                e.x = cd.rx[g]; e.y = cd.ry[g]; e.z = cd.rz[g];
+                e.w = FORCE ? gd.g1[g].z : (R)0;
+                s.st[w][fill + t] = e;
+                s.sg[w][fill + t] = (uint32_t)g;
             }
             fill += take;
             if (take < n) { complete = false; p += take; }
-            if (lane == 0) {
-                s.seg_u[nseg][0] = 0.0f; s.seg_u[nseg][1] = 0.0f; s.seg_u[nseg][2] = 0.0f;
-                s.seg_bound_extra[nseg] = 0.0f;
-            }
         } else {
             int o[3];
             dir_off(src.dir, o);
-            float u[3];
             dir_unit(src.dir, u);
             const int sd = dir_sort(src.dir);
             const bool flip = dir_flip(src.dir);
@@ -146,218 +162,372 @@ __device__ void stage_batch(Smem<R, FORCE>& s, const Decomp& dc, const CellData<
             const float udo = u[0] * (float)(o[0] * B.e[0]) + u[1] * (float)(o[1] * B.e[1]) +
                               u[2] * (float)(o[2] * B.e[2]);
             float hs = Hst;
-            if constexpr (FORCE) hs = fmaxf(Hst, gd.cell_hmax[src.cell]);
+            if (FORCE) { hx = gd.cell_hmax[src.cell]; hs = fmaxf(Hst, hx); }
             const float reach = fmaxf(u[0], 0.f) * (float)B.e[0] + fmaxf(u[1], 0.f) * (float)B.e[1] +
                                 fmaxf(u[2], 0.f) * (float)B.e[2] + hs + margin;
             const int64_t sbase = (int64_t)sd * dc.n + S.start;
-            // stage the prefix of the ordering with projection <= reach
             while (p < S.count) {
-                int pos = p + lane;
+                const int pos = p + lane;
                 bool ok = false;
+                R4 r = {};
                 int l = 0;
-                float proj = 0.0f;
                 if (pos < S.count) {
-                    int idx = flip ? (S.count - 1 - pos) : pos;
-                    l = dc.sidx[sbase + idx];
-                    float key = dc.skey[sbase + idx];
-                    proj = (flip ? -key : key) + udo;
+                    const int idx = flip ? (S.count - 1 - pos) : pos;
+                    r = so.rec[sbase + idx];
+                    l = so.idx[sbase + idx];
+                    const float proj = (flip ? -(float)r.w : (float)r.w) + udo;
                     ok = proj <= reach;
                 }
-                uint64_t bal = __ballot(ok);
-                int cnt = __popcll(bal);  // valid lanes form a prefix (monotone projections)
-                int room = CAP - fill;
-                int take = min(cnt, room);
+                const int cnt = __popcll(__ballot(ok));  // projections are monotone: a prefix
+                const int take = min(cnt, CAPW - fill);
                 if (lane < take) {
-                    int g = S.start + l;
-                    s.sx[fill + lane] = cd.rx[g] + dox;
-                    s.sy[fill + lane] = cd.ry[g] + doy;
-                    s.sz[fill + lane] = cd.rz[g] + doz;
-                    if constexpr (FORCE) s.sh[fill + lane] = gd.hh[g];
-                    s.sp[fill + lane] = proj;
-                    s.sg[fill + lane] = (uint32_t)g;
+                    const int g = S.start + l;
+                    R4 e;
+                    e.x = r.x + dox; e.y = r.y + doy; e.z = r.z + doz;
+                    e.w = FORCE ? gd.g1[g].z : (R)0;
+                    s.st[w][fill + lane] = e;
+                    s.sg[w][fill + lane] = (uint32_t)g;
                 }
                 fill += take;
                 p += take;
                 if (take < cnt) { complete = false; break; }  // out of room
-                if (cnt < WG) { p = S.count; break; }          // prefix ended
-            }
-            if (lane == 0) {
-                s.seg_u[nseg][0] = u[0]; s.seg_u[nseg][1] = u[1]; s.seg_u[nseg][2] = u[2];
-                s.seg_bound_extra[nseg] = FORCE ? gd.cell_hmax[src.cell] : 0.0f;
+                if (cnt < kWave) { p = S.count; break; }       // the prefix ended
             }
         }
-        if (lane == 0) { s.seg_b[nseg] = segb; s.seg_e[nseg] = fill; }
+        if (lane == 0) {
+            s.seg_b[w][nseg] = segb;
+            s.seg_e[w][nseg] = fill;
+            s.seg_u[w][nseg][0] = u[0]; s.seg_u[w][nseg][1] = u[1]; s.seg_u[w][nseg][2] = u[2];
+            s.seg_hx[w][nseg] = hx;
+        }
         nseg++;
         if (!complete) break;
         k++;
         p = 0;
-        if (fill >= CAP) break;
     }
-    if (lane == 0) s.nseg = nseg;
-    k1 = k;
-    p1 = p;
-    __syncthreads();
+    if (lane == 0) s.nseg[w] = nseg;
+    wave_sync();
 }
 
+// One lane's walk over the staged segments of its wavefront (state in
+// registers); in-range staged indices go to the lane's list.
+template <typename R, bool FORCE, int NACC>
+struct Walker {
+    int seg, jj, je, nseg;
+    float bound, ux, uy, uz, hx;
+    bool active;
+
+    __device__ void load(const Smem<R, NACC>& s, int w, int q, float fxi, float fyi, float fzi, float fh,
+                         float margin)
+    {
+        jj = s.seg_b[w][q];
+        je = s.seg_e[w][q];
+        ux = s.seg_u[w][q][0]; uy = s.seg_u[w][q][1]; uz = s.seg_u[w][q][2];
+        hx = s.seg_hx[w][q];
+        const bool self = (ux == 0.0f && uy == 0.0f && uz == 0.0f);
+        bound = self ? INFINITY : (ux * fxi + uy * fyi + uz * fzi + fmaxf(fh, hx) + margin);
+    }
+
+    __device__ void start(const Smem<R, NACC>& s, int w, bool act, float fxi, float fyi, float fzi, float fh,
+                          float margin)
+    {
+        nseg = s.nseg[w];
+        seg = 0;
+        active = act && nseg > 0;
+        jj = je = 0;
+        if (active) load(s, w, 0, fxi, fyi, fzi, fh, margin);
+    }
+
+    // rad: search radius of this lane (density); for the force stage the
+    // radius of a pair is max(h_i, h_j).  Returns when the walk is over or
+    // some lane's list is full.
+    __device__ int run(Smem<R, NACC>& s, int w, int lane, R xi, R yi, R zi, R rad, uint32_t gi, int cnt,
+                       float fxi, float fyi, float fzi, float fh, float margin)
+    {
+        constexpr int LISTW = Smem<R, NACC>::LISTW;
+        const R rad2 = rad * rad;
+        while (true) {
+            if (active) {
+                bool adv = jj >= je;
+                if (!adv) {
+                    const auto e = s.st[w][jj];
+                    const float proj = ux * (float)e.x + uy * (float)e.y + uz * (float)e.z;
+                    if (proj > bound) {
+                        adv = true;
+                    } else {
+                        const R dx = xi - e.x, dy = yi - e.y, dz = zi - e.z;
+                        const R r2 = dx * dx + dy * dy + dz * dz;
+                        R lim2 = rad2;
+                        if (FORCE) { const R hm = rad > e.w ? rad : e.w; lim2 = hm * hm; }
+                        if (r2 < lim2 && s.sg[w][jj] != gi) { s.list[w][cnt][lane] = (uint16_t)jj; cnt++; }
+                        jj++;
+                    }
+                }
+                if (adv) {
+                    seg++;
+                    if (seg < nseg) load(s, w, seg, fxi, fyi, fzi, fh, margin); else active = false;
+                }
+            }
+            if (__any(cnt == LISTW) || !__any(active)) break;
+        }
+        wave_sync();
+        return cnt;
+    }
+};
+
 // ---------------------------------------------------------------- density
+struct DensAcc {
+    double w, qdw, mw, mqdw, div, cx, cy, cz, n;
+};
+
+// Newton evaluation: the sums of Eq. (3) only (N and dN/dh need w and q w')
 template <typename R>
-__global__ __launch_bounds__(WG) void k_density(Decomp dc, CellData<R> cd, GhostData<R> gd,
-                                                DensityOut out, PassConsts pc)
+__device__ __forceinline__ void count_pair(DensAcc& a, R xi, R yi, R zi, R hinv, R h2, typename Vec4T<R>::T e)
 {
-    __shared__ Smem<R, false> s;
-    const int lane = threadIdx.x;
+    const R dx = xi - e.x, dy = yi - e.y, dz = zi - e.z;
+    const R r2 = dx * dx + dy * dy + dz * dz;
+    if (!(r2 < h2)) return;
+    const R q = sqrt(r2) * hinv;
+    a.w += (double)kern_w(q);
+    a.qdw += (double)(q * kern_dw(q));
+}
+
+// Full density-stage terms of one pair: Eq. (2), Eq. (3), d rho/dh, and the
+// velocity divergence and curl of Sec. 4.1 (gradient prefactor applied later)
+template <typename R>
+__device__ __forceinline__ void density_pair(DensAcc& a, R xi, R yi, R zi, R vxi, R vyi, R vzi, R h, R hinv,
+                                             R h2, typename Vec4T<R>::T e, typename Vec4T<R>::T vm)
+{
+    const R dx = xi - e.x, dy = yi - e.y, dz = zi - e.z;
+    const R r2 = dx * dx + dy * dy + dz * dz;
+    if (!(r2 < h2)) return;
+    const R r = sqrt(r2);
+    const R q = r * hinv;
+    const R qinv = h / r;
+    const R w = kern_w(q), dw = kern_dw(q), gq = kern_g(q, qinv);
+    const R mj = vm.w;
+    const R dvx = vm.x - vxi, dvy = vm.y - vyi, dvz = vm.z - vzi;
+    const R mg = mj * gq;
+    const R qdw = q * dw;
+    a.w += (double)w;
+    a.qdw += (double)qdw;
+    a.mw += (double)(mj * w);
+    a.mqdw += (double)(mj * qdw);
+    a.div += (double)(mg * (dvx * dx + dvy * dy + dvz * dz));
+    a.cx += (double)(mg * (dvy * dz - dvz * dy));
+    a.cy += (double)(mg * (dvz * dx - dvx * dz));
+    a.cz += (double)(mg * (dvx * dy - dvy * dx));
+    a.n += 1.0;
+}
+
+template <typename R>
+__global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sorted<R> so, GhostData<R> gd,
+                                                 DensityOut out, PassConsts pc)
+{
+    using R4 = typename Vec4T<R>::T;
+    using SM = Smem<R, NACC_D>;
+    __shared__ SM s;
+    const int tid = threadIdx.x;
+    const int w = tid >> 6;
+    const int lane = tid & (kWave - 1);
     const int ncells = *dc.ncells;
     const double kNorm = 8.0 / kPi;
+    // a decomposition flagged by the build (non-finite data, capacity, h too
+    // large for the box) is not swept: its orderings need not be complete
+    if (*dc.status & (ST_NONFINITE | ST_H_TOO_LARGE | ST_CAPACITY)) return;
     while (true) {
-        int unit = 0;
-        if (lane == 0) unit = atomicAdd(dc.qhead, 1);
-        unit = __shfl(unit, 0, 64);
+        if (tid == 0) s.unit = atomicAdd(dc.qhead, 1);
+        __syncthreads();
+        const int unit = s.unit;
+        __syncthreads();
         if (unit >= ncells) break;
         const CellInfo T = dc.cells[unit];
         const BoxInfo B = dc.boxes[T.box];
         const int nsrc = dc.src_count[unit];
         const double h_lim = fmin(B.e[0], fmin(B.e[1], B.e[2]));
         const float margin = 1e-5f * (float)fmax(B.e[0], fmax(B.e[1], B.e[2]));
-        // staging reach: the largest h of the cell, with slack for the iteration
         double hc = 0.0;
-        for (int t = lane; t < T.count; t += WG) hc = fmax(hc, cd.h[T.start + t]);
+        for (int t = lane; t < T.count; t += kWave) hc = fmax(hc, cd.h[T.start + t]);
         hc = wave_max(hc);
         float Hst = (float)fmin(hc * (1.0 + pc.h_margin), h_lim);
-        int staged_k1 = -1, staged_p1 = 0;  // single-batch staging cache
-        bool single = false;
         float cell_hmax = 0.0f;
 
-        for (int c0 = 0; c0 < T.count; c0 += WG) {
+        // staging of the first batch, kept while it holds every source of the wavefront
+        int k = 0, p = 0;
+        stage_wave<R, false, NACC_D>(s, w, dc, cd, so, gd, B, unit, nsrc, k, p, Hst, margin);
+        bool single = k >= nsrc;
+
+        for (int c0 = 0; c0 < T.count; c0 += kWave) {
             const int ti = c0 + lane;
             const bool valid = ti < T.count;
-            const int64_t gi = T.start + (valid ? ti : 0);
+            const uint32_t gi = (uint32_t)(T.start + (valid ? ti : 0));
             const R xi = cd.rx[gi], yi = cd.ry[gi], zi = cd.rz[gi];
-            const R mi = cd.m[gi], vxi = cd.vx[gi], vyi = cd.vy[gi], vzi = cd.vz[gi];
+            const R4 vmi = cd.vm[gi];
+            const float fxi = (float)xi, fyi = (float)yi, fzi = (float)zi;
             double h = cd.h[gi];
-            double lo = 0.0, hi = INFINITY;
-            bool conv = !valid;
+            // Newton state (kept by wavefront 0)
+            double lo = 0.0, hi = INFINITY, h_rebuild = 0.0;
             int iters = 0;
             bool failed = false;
-            double h_rebuild = 0.0;
-            double Sw = 0, Sqdw = 0, Smw = 0, Smqdw = 0, Sdiv = 0, Scx = 0, Scy = 0, Scz = 0;
-            while (true) {
-                if (!conv) { Sw = Sqdw = Smw = Smqdw = Sdiv = Scx = Scy = Scz = 0.0; iters++; }
+            bool conv = !valid;
+            // neighbour lists of this wavefront: valid while every lane's h <= hcache
+            bool cached = false;
+            bool cached_all = false;  // the lists were built with every valid lane active
+            float hcache = 0.0f;
+            int cnt = 0;
+            DensAcc acc;
+
+            // Sums over this wavefront's sources at the current h, for the lanes in
+            // `act`: the two of Eq. (3) (full = false) or all of them (full = true).
+            auto evaluate = [&](bool act, bool full) {
+                acc = DensAcc{};
                 const R hr = (R)h, hinv = (R)(1.0 / h), h2 = hr * hr;
-                const float fxi = (float)xi, fyi = (float)yi, fzi = (float)zi;
-                const float fh = (float)h + margin;
-                int k = 0, p = 0;
-                do {
-                    int k1, p1;
-                    if (!(single && staged_k1 >= 0)) {
-                        stage_batch<R, false>(s, dc, cd, gd, T, B, unit, nsrc, k, p, Hst, margin, k1, p1);
-                        if (k == 0 && p == 0) { single = (k1 >= nsrc); staged_k1 = k1; staged_p1 = p1; }
+                auto process = [&](int n) {
+                    if (full) {
+                        int t = 0;
+                        for (; t + 1 < n; t += 2) {
+                            const int j0 = s.list[w][t][lane], j1 = s.list[w][t + 1][lane];
+                            const R4 e0 = s.st[w][j0], e1 = s.st[w][j1];
+                            const R4 v0 = cd.vm[s.sg[w][j0]], v1 = cd.vm[s.sg[w][j1]];
+                            density_pair<R>(acc, xi, yi, zi, vmi.x, vmi.y, vmi.z, hr, hinv, h2, e0, v0);
+                            density_pair<R>(acc, xi, yi, zi, vmi.x, vmi.y, vmi.z, hr, hinv, h2, e1, v1);
+                        }
+                        if (t < n) {
+                            const int j0 = s.list[w][t][lane];
+                            density_pair<R>(acc, xi, yi, zi, vmi.x, vmi.y, vmi.z, hr, hinv, h2, s.st[w][j0],
+                                            cd.vm[s.sg[w][j0]]);
+                        }
                     } else {
-                        k1 = staged_k1; p1 = staged_p1;
+                        for (int t = 0; t < n; t++) count_pair<R>(acc, xi, yi, zi, hinv, h2, s.st[w][s.list[w][t][lane]]);
                     }
-                    // ---- sweep with early exit, compaction into per-lane lists
-                    const int nseg = s.nseg;
-                    bool active = !conv;
-                    int seg = 0, jj = 0, je = 0;
-                    float bound = 0.0f;
-                    bool selfseg = false;
-                    auto load_seg = [&](int q) {
-                        jj = s.seg_b[q]; je = s.seg_e[q];
-                        float ux = s.seg_u[q][0], uy = s.seg_u[q][1], uz = s.seg_u[q][2];
-                        selfseg = (ux == 0.0f && uy == 0.0f && uz == 0.0f);
-                        bound = selfseg ? INFINITY : (ux * fxi + uy * fyi + uz * fzi + fh);
-                    };
-                    if (active) { if (nseg > 0) load_seg(0); else active = false; }
-                    while (__any(active)) {
-                        int cnt = 0;
-                        while (true) {
-                            if (active) {
-                                if (jj < je && s.sp[jj] <= bound) {
-                                    R dx = xi - s.sx[jj], dy = yi - s.sy[jj], dz = zi - s.sz[jj];
-                                    R r2 = dx * dx + dy * dy + dz * dz;
-                                    if (r2 < h2 && s.sg[jj] != (uint32_t)gi) { s.list[cnt][lane] = (uint16_t)jj; cnt++; }
-                                    jj++;
+                };
+                const bool reuse = cached && (!full || cached_all) && __all(!act || (float)h <= hcache);
+                if (reuse) {
+                    if (act) process(cnt);
+                    return;
+                }
+                // sweep(s) with early exit; the lists keep r < h (1 + slack)
+                hcache = fminf((float)h * (1.0f + kCacheSlack), Hst);
+                const R rad = (R)hcache;
+                const float fh = hcache + margin;
+                bool flushed = false;
+                int kk = 0, pp = 0;
+                do {
+                    if (!single) stage_wave<R, false, NACC_D>(s, w, dc, cd, so, gd, B, unit, nsrc, kk, pp, Hst, margin);
+                    else kk = nsrc;
+                    Walker<R, false, NACC_D> wk;
+                    wk.start(s, w, act, fxi, fyi, fzi, fh, margin);
+                    cnt = 0;
+                    while (true) {
+                        cnt = wk.run(s, w, lane, xi, yi, zi, rad, gi, cnt, fxi, fyi, fzi, fh, margin);
+                        if (!__any(wk.active)) break;
+                        process(cnt);  // a list is full: evaluate it and continue the walk
+                        cnt = 0;
+                        flushed = true;
+                    }
+                    if (!single) { process(cnt); cnt = 0; flushed = true; }
+                } while (kk < nsrc);
+                if (single) process(cnt);
+                cached = single && !flushed;
+                cached_all = __all(act || !valid);
+            };
+
+            // ---- Newton iteration on h (Eq. (3)) in FP64, safeguarded by a bracket
+            while (true) {
+                for (int a = w; a < 2; a += NW) s.red[a][lane] = 0.0;
+                __syncthreads();
+                evaluate(!conv, false);
+                if (!conv) {
+                    atomicAdd(&s.red[0][lane], acc.w);
+                    atomicAdd(&s.red[1][lane], acc.qdw);
+                }
+                __syncthreads();
+                if (w == 0) {
+                    bool restage = false;
+                    if (!conv) {
+                        iters++;
+                        const double N = 32.0 / 3.0 * (s.red[0][lane] + 1.0);
+                        const double dN = -32.0 / 3.0 / h * s.red[1][lane];
+                        const double f = N - pc.n_ngb;
+                        if (fabs(f) <= pc.tol) {
+                            conv = true;
+                        } else if (iters >= pc.max_iter) {
+                            conv = true; failed = true;
+                        } else {
+                            if (f < 0.0) lo = h; else hi = h;
+                            double hn = h - f / dN;
+                            const bool ok = (dN > 0.0) && (hn > lo) && (hn < hi) && (hn >= 0.5 * h) && (hn <= 2.0 * h);
+                            if (!ok) hn = isinf(hi) ? 2.0 * h : 0.5 * (lo + hi);
+                            if (hn > h_lim) {
+                                if (h >= h_lim) {  // the root lies beyond what the cells allow
+                                    atomicOr(dc.status, ST_REBUILD);
+                                    conv = true; failed = true;
+                                    h_rebuild = hn;
                                 } else {
-                                    seg++;
-                                    if (seg < nseg) load_seg(seg); else active = false;
+                                    hn = h_lim;
                                 }
                             }
-                            if (__any(cnt == Smem<R, false>::LIST) || !__any(active)) break;
-                        }
-                        // ---- interactions of this lane's list (Eq. (2), Eq. (3), Sec. 4.1)
-                        for (int t = 0; t < cnt; t++) {
-                            const int j = s.list[t][lane];
-                            const uint32_t g = s.sg[j];
-                            R dx = xi - s.sx[j], dy = yi - s.sy[j], dz = zi - s.sz[j];
-                            R r2 = dx * dx + dy * dy + dz * dz;
-                            R r = sqrt(r2);
-                            R q = r * hinv;
-                            R qinv = hr / r;
-                            R w = kern_w(q), dw = kern_dw(q), gq = kern_g(q, qinv);
-                            R mj = cd.m[g];
-                            R dvx = cd.vx[g] - vxi, dvy = cd.vy[g] - vyi, dvz = cd.vz[g] - vzi;
-                            R mg = mj * gq;
-                            R qdw = q * dw;
-                            Sw += (double)w;
-                            Sqdw += (double)qdw;
-                            Smw += (double)(mj * w);
-                            Smqdw += (double)(mj * qdw);
-                            Sdiv += (double)(mg * (dvx * dx + dvy * dy + dvz * dz));
-                            Scx += (double)(mg * (dvy * dz - dvz * dy));
-                            Scy += (double)(mg * (dvz * dx - dvx * dz));
-                            Scz += (double)(mg * (dvx * dy - dvy * dx));
-                        }
-                    }
-                    k = k1; p = p1;
-                } while (k < nsrc);
-                // ---- Newton step on h (Eq. (3)), FP64, safeguarded by a bracket
-                bool need_restage = false;
-                if (!conv) {
-                    const double N = 32.0 / 3.0 * (Sw + 1.0);
-                    const double dN = -32.0 / 3.0 / h * Sqdw;
-                    const double f = N - pc.n_ngb;
-                    if (fabs(f) <= pc.tol) {
-                        conv = true;
-                    } else if (iters >= pc.max_iter) {
-                        conv = true; failed = true;
-                    } else {
-                        if (f < 0.0) lo = h; else hi = h;
-                        double hn = h - f / dN;
-                        bool ok = (dN > 0.0) && (hn > lo) && (hn < hi) && (hn >= 0.5 * h) && (hn <= 2.0 * h);
-                        if (!ok) hn = isinf(hi) ? 2.0 * h : 0.5 * (lo + hi);
-                        if (hn > h_lim) {
-                            if (h >= h_lim) {  // root lies beyond what the cells allow
-                                atomicOr(dc.status, ST_REBUILD);
-                                conv = true; failed = true;
-                                h_rebuild = hn;  // handed back as the next guess
-                            } else {
-                                hn = h_lim;
+                            if (!conv) {
+                                h = hn;
+                                restage = (float)h > Hst;
                             }
                         }
-                        if (!conv) {
-                            h = hn;
-                            if ((float)h > Hst) need_restage = true;
-                        }
                     }
+                    s.hsh[lane] = h;
+                    s.conv[lane] = conv;
+                    const bool all = __all(conv);
+                    const bool any_restage = __any(restage);
+                    if (lane == 0) { s.ctl[0] = all; s.ctl[1] = any_restage; }
                 }
-                if (__all(conv)) break;
-                if (__any(need_restage)) {
-                    double hm = wave_max(conv ? 0.0 : h);
+                __syncthreads();
+                h = s.hsh[lane];
+                conv = s.conv[lane];
+                const bool all = s.ctl[0];
+                const bool rs = s.ctl[1];
+                __syncthreads();
+                if (all) break;
+                if (rs) {
+                    const double hm = wave_max(conv ? 0.0 : h);
                     Hst = (float)fmin(fmax((double)Hst, hm * (1.0 + pc.h_margin)), h_lim);
-                    staged_k1 = -1;  // force a fresh staging with the larger reach
-                    single = false;
+                    k = 0; p = 0;
+                    stage_wave<R, false, NACC_D>(s, w, dc, cd, so, gd, B, unit, nsrc, k, p, Hst, margin);
+                    single = k >= nsrc;
+                    cached = false;
                 }
             }
-            // ---- per-particle quantities between the stages
+
+            // ---- every sum at the solved h
+            for (int a = w; a < NACC_D; a += NW) s.red[a][lane] = 0.0;
+            __syncthreads();
+            evaluate(valid, true);
             if (valid) {
-                const double m = (double)mi;
+                atomicAdd(&s.red[0][lane], acc.w);
+                atomicAdd(&s.red[1][lane], acc.qdw);
+                atomicAdd(&s.red[2][lane], acc.mw);
+                atomicAdd(&s.red[3][lane], acc.mqdw);
+                atomicAdd(&s.red[4][lane], acc.div);
+                atomicAdd(&s.red[5][lane], acc.cx);
+                atomicAdd(&s.red[6][lane], acc.cy);
+                atomicAdd(&s.red[7][lane], acc.cz);
+                atomicAdd(&s.red[8][lane], acc.n);
+            }
+            __syncthreads();
+
+            // ---- per-particle quantities between the stages (wavefront 0)
+            if (w == 0 && valid) {
+                DensAcc tot;
+                tot.w = s.red[0][lane]; tot.qdw = s.red[1][lane]; tot.mw = s.red[2][lane];
+                tot.mqdw = s.red[3][lane]; tot.div = s.red[4][lane]; tot.cx = s.red[5][lane];
+                tot.cy = s.red[6][lane]; tot.cz = s.red[7][lane]; tot.n = s.red[8][lane];
+                const double m = (double)vmi.w;
                 const double k3 = kNorm / (h * h * h);
                 const double k5 = k3 / (h * h);
-                const double rho = k3 * (Smw + m);
-                const double drho = -kNorm / (h * h * h * h) * (3.0 * (Smw + m) + Smqdw);
+                const double rho = k3 * (tot.mw + m);
+                const double drho = -kNorm / (h * h * h * h) * (3.0 * (tot.mw + m) + tot.mqdw);
                 const double omega = 1.0 + h / (3.0 * rho) * drho;
-                const double N = 32.0 / 3.0 * (Sw + 1.0);
-                const double div = k5 * Sdiv / rho;
-                const double cx = -k5 * Scx / rho, cy = -k5 * Scy / rho, cz = -k5 * Scz / rho;
+                const double N = 32.0 / 3.0 * (tot.w + 1.0);
+                const double div = k5 * tot.div / rho;
+                const double cx = -k5 * tot.cx / rho, cy = -k5 * tot.cy / rho, cz = -k5 * tot.cz / rho;
                 const double u = cd.u[gi];
                 const double P = (pc.gamma - 1.0) * rho * u;
                 const double c = sqrt(pc.gamma * P / rho);
@@ -366,142 +536,170 @@ __global__ __launch_bounds__(WG) void k_density(Decomp dc, CellData<R> cd, Ghost
                 const double den = fabs(div) + cm + pc.beps * c / h;
                 const double bal = den > 0.0 ? cm / den : 0.0;
                 cd.h[gi] = h;
-                gd.hh[gi] = (R)h; gd.hinv[gi] = (R)(1.0 / h); gd.gk[gi] = (R)k5;
-                gd.rho[gi] = (R)rho; gd.A[gi] = (R)A; gd.c[gi] = (R)c; gd.f[gi] = (R)bal;
+                R4 g0, g1;
+                g0.x = (R)(1.0 / h); g0.y = (R)k5; g0.z = (R)A; g0.w = (R)rho;
+                g1.x = (R)c; g1.y = (R)bal; g1.z = (R)h; g1.w = (R)0;
+                gd.g0[gi] = g0;
+                gd.g1[gi] = g1;
                 const uint32_t pi = dc.perm[gi];
                 if (out.h) out.h[pi] = h_rebuild > 0.0 ? h_rebuild : h;
                 if (out.rho) out.rho[pi] = rho;
                 if (out.omega) out.omega[pi] = omega;
                 if (out.nngb) out.nngb[pi] = N;
                 if (out.div) out.div[pi] = div;
-                if (out.curl) { out.curl[3 * (int64_t)pi] = cx; out.curl[3 * (int64_t)pi + 1] = cy; out.curl[3 * (int64_t)pi + 2] = cz; }
+                if (out.curl) {
+                    out.curl[3 * (int64_t)pi] = cx; out.curl[3 * (int64_t)pi + 1] = cy; out.curl[3 * (int64_t)pi + 2] = cz;
+                }
                 if (out.balsara) out.balsara[pi] = bal;
                 if (out.P) out.P[pi] = P;
                 if (out.c) out.c[pi] = c;
                 if (out.iters) out.iters[pi] = failed ? -1 : iters;
+                if (out.ndens) out.ndens[pi] = (int32_t)tot.n;
                 if (failed) atomicOr(dc.status, ST_NOT_CONVERGED);
                 cell_hmax = fmaxf(cell_hmax, (float)h * (1.0f + 1e-6f));
             }
+            __syncthreads();
         }
-        cell_hmax = (float)wave_max((double)cell_hmax);
-        if (lane == 0) gd.cell_hmax[unit] = cell_hmax;
+        if (w == 0) {
+            cell_hmax = (float)wave_max((double)cell_hmax);
+            if (lane == 0) gd.cell_hmax[unit] = cell_hmax;
+        }
         __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------- force
+struct ForceAcc {
+    double ax, ay, az, du, n;
+};
+
 template <typename R>
-__global__ __launch_bounds__(WG) void k_force(Decomp dc, CellData<R> cd, GhostData<R> gd,
-                                              ForceOut out, PassConsts pc)
+struct ForceTarget {
+    R x, y, z, vx, vy, vz, h, hinv, gk, A, rho, c, f;
+};
+
+template <typename R>
+__device__ __forceinline__ void force_pair(ForceAcc& a, const ForceTarget<R>& ti, R alpha,
+                                           typename Vec4T<R>::T e, typename Vec4T<R>::T vm,
+                                           typename Vec4T<R>::T g0, typename Vec4T<R>::T g1)
 {
-    __shared__ Smem<R, true> s;
-    const int lane = threadIdx.x;
+    const R dx = ti.x - e.x, dy = ti.y - e.y, dz = ti.z - e.z;
+    const R r2 = dx * dx + dy * dy + dz * dz;
+    const R r = sqrt(r2);
+    const R rinv = r > (R)0 ? (R)1 / r : (R)0;
+    const R qi = r * ti.hinv, qj = r * g0.x;
+    // grad W(r, h) = 8/(pi h^5) g(q) r_vec, zero outside the support and at r = 0
+    R gwi = qi < (R)1 ? ti.gk * kern_g(qi, ti.h * rinv) : (R)0;
+    R gwj = qj < (R)1 ? g0.y * kern_g(qj, g1.z * rinv) : (R)0;
+    if (r == (R)0) { gwi = (R)0; gwj = (R)0; }
+    const R mj = vm.w;
+    const R vxij = ti.vx - vm.x, vyij = ti.vy - vm.y, vzij = ti.vz - vm.z;
+    const R vr = vxij * dx + vyij * dy + vzij * dz;
+    R wij = vr * rinv;
+    wij = wij < (R)0 ? wij : (R)0;
+    const R Pi = -alpha * (ti.c + g1.x - (R)3 * wij) * wij / (ti.rho + g0.w);
+    const R fij = ti.f + g1.y;
+    const R gsum = gwi + gwj;
+    const R sc = -mj * (ti.A * gwi + g0.z * gwj) - (R)0.25 * mj * Pi * gsum * fij;
+    const R pdu = ti.A * mj * vr * gwi + (R)0.125 * mj * Pi * vr * gsum * fij;
+    a.ax += (double)(sc * dx);
+    a.ay += (double)(sc * dy);
+    a.az += (double)(sc * dz);
+    a.du += (double)pdu;
+    a.n += 1.0;
+}
+
+template <typename R>
+__global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted<R> so, GhostData<R> gd,
+                                               ForceOut out, PassConsts pc)
+{
+    using R4 = typename Vec4T<R>::T;
+    using SM = Smem<R, NACC_F>;
+    __shared__ SM s;
+    const int tid = threadIdx.x;
+    const int w = tid >> 6;
+    const int lane = tid & (kWave - 1);
     const int ncells = *dc.ncells;
     const R alpha = (R)pc.alpha;
+    if (*dc.status & (ST_NONFINITE | ST_H_TOO_LARGE | ST_CAPACITY)) return;
     while (true) {
-        int unit = 0;
-        if (lane == 0) unit = atomicAdd(dc.qhead, 1);
-        unit = __shfl(unit, 0, 64);
+        if (tid == 0) s.unit = atomicAdd(dc.qhead, 1);
+        __syncthreads();
+        const int unit = s.unit;
+        __syncthreads();
         if (unit >= ncells) break;
         const CellInfo T = dc.cells[unit];
         const BoxInfo B = dc.boxes[T.box];
         const int nsrc = dc.src_count[unit];
         const float margin = 1e-5f * (float)fmax(B.e[0], fmax(B.e[1], B.e[2]));
         const float Hst = gd.cell_hmax[unit];
-        int staged_k1 = -1, staged_p1 = 0;
-        bool single = false;
-        for (int c0 = 0; c0 < T.count; c0 += WG) {
-            const int ti = c0 + lane;
-            const bool valid = ti < T.count;
-            const int64_t gi = T.start + (valid ? ti : 0);
-            const R xi = cd.rx[gi], yi = cd.ry[gi], zi = cd.rz[gi];
-            const R vxi = cd.vx[gi], vyi = cd.vy[gi], vzi = cd.vz[gi];
-            const R hi = gd.hh[gi], hinvi = gd.hinv[gi], gki = gd.gk[gi];
-            const R rhoi = gd.rho[gi], Ai = gd.A[gi], ci = gd.c[gi], fi = gd.f[gi];
-            const float fxi = (float)xi, fyi = (float)yi, fzi = (float)zi, fhi = (float)hi;
-            double ax = 0, ay = 0, az = 0, du = 0;
-            int npairs = 0;
-            int k = 0, p = 0;
+        int k = 0, p = 0;
+        stage_wave<R, true, NACC_F>(s, w, dc, cd, so, gd, B, unit, nsrc, k, p, Hst, margin);
+        const bool single = k >= nsrc;
+        for (int c0 = 0; c0 < T.count; c0 += kWave) {
+            const int ti_ = c0 + lane;
+            const bool valid = ti_ < T.count;
+            const uint32_t gi = (uint32_t)(T.start + (valid ? ti_ : 0));
+            ForceTarget<R> ti;
+            ti.x = cd.rx[gi]; ti.y = cd.ry[gi]; ti.z = cd.rz[gi];
+            const R4 vmi = cd.vm[gi], g0i = gd.g0[gi], g1i = gd.g1[gi];
+            ti.vx = vmi.x; ti.vy = vmi.y; ti.vz = vmi.z;
+            ti.hinv = g0i.x; ti.gk = g0i.y; ti.A = g0i.z; ti.rho = g0i.w;
+            ti.c = g1i.x; ti.f = g1i.y; ti.h = g1i.z;
+            const float fxi = (float)ti.x, fyi = (float)ti.y, fzi = (float)ti.z, fh = (float)ti.h;
+            for (int a = w; a < NACC_F; a += NW) s.red[a][lane] = 0.0;
+            __syncthreads();
+            ForceAcc acc = {};
+            auto heavy = [&](int n) {
+                int t = 0;
+                for (; t + 1 < n; t += 2) {
+                    const int j0 = s.list[w][t][lane], j1 = s.list[w][t + 1][lane];
+                    const uint32_t q0 = s.sg[w][j0], q1 = s.sg[w][j1];
+                    const R4 e0 = s.st[w][j0], e1 = s.st[w][j1];
+                    const R4 v0 = cd.vm[q0], v1 = cd.vm[q1];
+                    const R4 a0 = gd.g0[q0], a1 = gd.g0[q1];
+                    const R4 b0 = gd.g1[q0], b1 = gd.g1[q1];
+                    force_pair<R>(acc, ti, alpha, e0, v0, a0, b0);
+                    force_pair<R>(acc, ti, alpha, e1, v1, a1, b1);
+                }
+                if (t < n) {
+                    const int j0 = s.list[w][t][lane];
+                    const uint32_t q0 = s.sg[w][j0];
+                    force_pair<R>(acc, ti, alpha, s.st[w][j0], cd.vm[q0], gd.g0[q0], gd.g1[q0]);
+                }
+            };
+            int kk = 0, pp = 0;
             do {
-                int k1, p1;
-                if (!(single && staged_k1 >= 0)) {
-                    stage_batch<R, true>(s, dc, cd, gd, T, B, unit, nsrc, k, p, Hst, margin, k1, p1);
-                    if (k == 0 && p == 0) { single = (k1 >= nsrc); staged_k1 = k1; staged_p1 = p1; }
-                } else {
-                    k1 = staged_k1; p1 = staged_p1;
+                if (!single) stage_wave<R, true, NACC_F>(s, w, dc, cd, so, gd, B, unit, nsrc, kk, pp, Hst, margin);
+                else kk = nsrc;
+                Walker<R, true, NACC_F> wk;
+                wk.start(s, w, valid, fxi, fyi, fzi, fh, margin);
+                int cnt = 0;
+                while (true) {
+                    cnt = wk.run(s, w, lane, ti.x, ti.y, ti.z, ti.h, gi, cnt, fxi, fyi, fzi, fh, margin);
+                    heavy(cnt);
+                    cnt = 0;
+                    if (!__any(wk.active)) break;
                 }
-                const int nseg = s.nseg;
-                bool active = valid;
-                int seg = 0, jj = 0, je = 0;
-                float bound = 0.0f;
-                auto load_seg = [&](int q) {
-                    jj = s.seg_b[q]; je = s.seg_e[q];
-                    float ux = s.seg_u[q][0], uy = s.seg_u[q][1], uz = s.seg_u[q][2];
-                    bool selfseg = (ux == 0.0f && uy == 0.0f && uz == 0.0f);
-                    bound = selfseg ? INFINITY
-                                    : (ux * fxi + uy * fyi + uz * fzi + fmaxf(fhi, s.seg_bound_extra[q]) + margin);
-                };
-                if (active) { if (nseg > 0) load_seg(0); else active = false; }
-                while (__any(active)) {
-                    int cnt = 0;
-                    while (true) {
-                        if (active) {
-                            if (jj < je && s.sp[jj] <= bound) {
-                                R dx = xi - s.sx[jj], dy = yi - s.sy[jj], dz = zi - s.sz[jj];
-                                R r2 = dx * dx + dy * dy + dz * dz;
-                                R hm = hi > s.sh[jj] ? hi : s.sh[jj];
-                                if (r2 < hm * hm && s.sg[jj] != (uint32_t)gi) { s.list[cnt][lane] = (uint16_t)jj; cnt++; }
-                                jj++;
-                            } else {
-                                seg++;
-                                if (seg < nseg) load_seg(seg); else active = false;
-                            }
-                        }
-                        if (__any(cnt == Smem<R, true>::LIST) || !__any(active)) break;
-                    }
-                    npairs += cnt;
-                    // ---- Eqs. (4)-(5) and the viscosity of Sec. 4.1 for this lane's list
-                    for (int t = 0; t < cnt; t++) {
-                        const int j = s.list[t][lane];
-                        const uint32_t g = s.sg[j];
-                        R dx = xi - s.sx[j], dy = yi - s.sy[j], dz = zi - s.sz[j];
-                        R r2 = dx * dx + dy * dy + dz * dz;
-                        R r = sqrt(r2);
-                        R rinv = r > (R)0 ? (R)1 / r : (R)0;
-                        R qi = r * hinvi, qj = r * gd.hinv[g];
-                        // grad W(r, h) = 8/(pi h^5) g(q) r_vec, zero outside the support
-                        R gwi = qi < (R)1 ? gki * kern_g(qi, hi * rinv) : (R)0;
-                        R hj = gd.hh[g];
-                        R gwj = qj < (R)1 ? gd.gk[g] * kern_g(qj, hj * rinv) : (R)0;
-                        if (r == (R)0) { gwi = (R)0; gwj = (R)0; }
-                        R mj = cd.m[g];
-                        R vxij = vxi - cd.vx[g], vyij = vyi - cd.vy[g], vzij = vzi - cd.vz[g];
-                        R vr = vxij * dx + vyij * dy + vzij * dz;
-                        R wij = vr * rinv;
-                        wij = wij < (R)0 ? wij : (R)0;
-                        R Pi = -alpha * (ci + gd.c[g] - (R)3 * wij) * wij / (rhoi + gd.rho[g]);
-                        R fij = fi + gd.f[g];
-                        R gsum = gwi + gwj;
-                        R sc = -mj * (Ai * gwi + gd.A[g] * gwj) - (R)0.25 * mj * Pi * gsum * fij;
-                        R pdu = Ai * mj * vr * gwi + (R)0.125 * mj * Pi * vr * gsum * fij;
-                        ax += (double)(sc * dx);
-                        ay += (double)(sc * dy);
-                        az += (double)(sc * dz);
-                        du += (double)pdu;
-                    }
-                }
-                k = k1; p = p1;
-            } while (k < nsrc);
+            } while (kk < nsrc);
             if (valid) {
-                const uint32_t pi = dc.perm[gi];
-                if (out.ax) out.ax[pi] = ax;
-                if (out.ay) out.ay[pi] = ay;
-                if (out.az) out.az[pi] = az;
-                if (out.dudt) out.dudt[pi] = du;
-                if (out.npairs) out.npairs[pi] = npairs;
+                atomicAdd(&s.red[0][lane], acc.ax);
+                atomicAdd(&s.red[1][lane], acc.ay);
+                atomicAdd(&s.red[2][lane], acc.az);
+                atomicAdd(&s.red[3][lane], acc.du);
+                atomicAdd(&s.red[4][lane], acc.n);
             }
+            __syncthreads();
+            if (w == 0 && valid) {
+                const uint32_t pi = dc.perm[gi];
+                if (out.ax) out.ax[pi] = s.red[0][lane];
+                if (out.ay) out.ay[pi] = s.red[1][lane];
+                if (out.az) out.az[pi] = s.red[2][lane];
+                if (out.dudt) out.dudt[pi] = s.red[3][lane];
+                if (out.npairs) out.npairs[pi] = (int32_t)s.red[4][lane];
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -514,36 +712,36 @@ void launch_reset_counter(int32_t* c, hipStream_t st)
 }
 
 template <typename R>
-void launch_density(const Decomp& dc, const CellData<R>& cd, const GhostData<R>& gd,
+void launch_density(const Decomp& dc, const CellData<R>& cd, const Sorted<R>& so, const GhostData<R>& gd,
                     const DensityOut& out, const PassConsts& pc, int grid, hipStream_t st)
 {
     launch_reset_counter(dc.qhead, st);
-    hipLaunchKernelGGL(k_density<R>, dim3(grid), dim3(WG), 0, st, dc, cd, gd, out, pc);
+    hipLaunchKernelGGL(k_density<R>, dim3(grid), dim3(WGS), 0, st, dc, cd, so, gd, out, pc);
 }
 
 template <typename R>
-void launch_force(const Decomp& dc, const CellData<R>& cd, const GhostData<R>& gd,
+void launch_force(const Decomp& dc, const CellData<R>& cd, const Sorted<R>& so, const GhostData<R>& gd,
                   const ForceOut& out, const PassConsts& pc, int grid, hipStream_t st)
 {
     launch_reset_counter(dc.qhead, st);
-    hipLaunchKernelGGL(k_force<R>, dim3(grid), dim3(WG), 0, st, dc, cd, gd, out, pc);
+    hipLaunchKernelGGL(k_force<R>, dim3(grid), dim3(WGS), 0, st, dc, cd, so, gd, out, pc);
 }
 
-template void launch_density<float>(const Decomp&, const CellData<float>&, const GhostData<float>&,
-                                    const DensityOut&, const PassConsts&, int, hipStream_t);
-template void launch_density<double>(const Decomp&, const CellData<double>&, const GhostData<double>&,
-                                     const DensityOut&, const PassConsts&, int, hipStream_t);
-template void launch_force<float>(const Decomp&, const CellData<float>&, const GhostData<float>&,
-                                  const ForceOut&, const PassConsts&, int, hipStream_t);
-template void launch_force<double>(const Decomp&, const CellData<double>&, const GhostData<double>&,
-                                   const ForceOut&, const PassConsts&, int, hipStream_t);
+template void launch_density<float>(const Decomp&, const CellData<float>&, const Sorted<float>&,
+                                    const GhostData<float>&, const DensityOut&, const PassConsts&, int, hipStream_t);
+template void launch_density<double>(const Decomp&, const CellData<double>&, const Sorted<double>&,
+                                     const GhostData<double>&, const DensityOut&, const PassConsts&, int, hipStream_t);
+template void launch_force<float>(const Decomp&, const CellData<float>&, const Sorted<float>&,
+                                  const GhostData<float>&, const ForceOut&, const PassConsts&, int, hipStream_t);
+template void launch_force<double>(const Decomp&, const CellData<double>&, const Sorted<double>&,
+                                   const GhostData<double>&, const ForceOut&, const PassConsts&, int, hipStream_t);
 
 static int occupancy_grid(const void* fn)
 {
     int dev = 0, ncu = 0, per = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, WG, 0) != hipSuccess || per < 1) per = 1;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, WGS, 0) != hipSuccess || per < 1) per = 1;
     if (ncu < 1) ncu = 1;
     return ncu * per;
 }

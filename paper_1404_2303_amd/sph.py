@@ -23,7 +23,8 @@ SPH_E_CAPACITY, SPH_E_OOM, SPH_E_HIP, SPH_E_STATE = 5, 6, 7, 8
 SPH_FP64, SPH_FP32_ACC64 = 0, 1
 
 EXPORTED = ["sph_default_params", "sph_create", "sph_destroy", "sph_build_cells", "sph_sort",
-            "sph_density", "sph_force", "sph_step", "sph_get_stats", "sph_status_string"]
+            "sph_density", "sph_force", "sph_step", "sph_get_stats", "sph_status_string",
+            "sph_enable_timing", "sph_get_kernel_times"]
 
 P = ctypes.c_void_p
 
@@ -44,9 +45,17 @@ class sph_batch(ctypes.Structure):
     _fields_ = [("nbox", ctypes.c_int), ("box_offsets", P), ("box_len", P)]
 
 
+DENSITY_FIELDS = ("rho", "omega", "n_ngb", "div_v", "curl_v", "balsara", "pressure", "sound", "n_iter",
+                  "n_dens")
+
+
 class sph_density_out(ctypes.Structure):
-    _fields_ = [(k, P) for k in ("rho", "omega", "n_ngb", "div_v", "curl_v", "balsara", "pressure",
-                                 "sound", "n_iter")]
+    _fields_ = [(k, P) for k in DENSITY_FIELDS]
+
+
+class sph_kernel_times(ctypes.Structure):
+    _fields_ = [("build_ms", ctypes.c_float), ("sort_ms", ctypes.c_float), ("density_ms", ctypes.c_float),
+                ("force_ms", ctypes.c_float)]
 
 
 class sph_force_out(ctypes.Structure):
@@ -89,6 +98,10 @@ def load_library():
                                  ctypes.POINTER(sph_force_out), ctypes.c_double, P]
         lib.sph_get_stats.restype = st
         lib.sph_get_stats.argtypes = [P, ctypes.POINTER(sph_stats)]
+        lib.sph_enable_timing.restype = st
+        lib.sph_enable_timing.argtypes = [P, ctypes.c_int]
+        lib.sph_get_kernel_times.restype = st
+        lib.sph_get_kernel_times.argtypes = [P, ctypes.POINTER(sph_kernel_times)]
         lib.sph_status_string.restype = ctypes.c_char_p
         lib.sph_status_string.argtypes = [st]
         _lib = lib
@@ -236,21 +249,18 @@ class Context:
     def sort(self):
         _check(sph_sort(self.ctx, _stream()), "sph_sort")
 
-    def density(self, parts: Particles,
-                want=("rho", "omega", "n_ngb", "div_v", "curl_v", "balsara", "pressure", "sound", "n_iter"),
-                allow_unconverged=False):
+    def density(self, parts: Particles, want=DENSITY_FIELDS, allow_unconverged=False):
         n = parts.n
         dev = parts.x.device
         out = {}
         for k in want:
-            if k == "n_iter":
+            if k in ("n_iter", "n_dens"):
                 out[k] = torch.empty(n, dtype=torch.int32, device=dev)
             elif k == "curl_v":
                 out[k] = torch.empty((n, 3), dtype=torch.float64, device=dev)
             else:
                 out[k] = torch.empty(n, dtype=torch.float64, device=dev)
-        c = sph_density_out(*[_ptr(out.get(k)) for k in ("rho", "omega", "n_ngb", "div_v", "curl_v", "balsara",
-                                                          "pressure", "sound", "n_iter")])
+        c = sph_density_out(*[_ptr(out.get(k)) for k in DENSITY_FIELDS])
         allow = (SPH_E_NOT_CONVERGED,) if allow_unconverged else ()
         self.last_density_status = _check(sph_density(self.ctx, parts.c_struct(), c, _stream()), "sph_density",
                                           allow)
@@ -270,6 +280,14 @@ class Context:
         c = sph_force_out(*[_ptr(acc.get(k)) for k in ("ax", "ay", "az", "dudt", "n_pairs")])
         return _check(sph_step(self.ctx, parts.c_struct(), batch.c if batch else None, c, dt, _stream()),
                       "sph_step", (SPH_E_NOT_CONVERGED,))
+
+    def enable_timing(self, on=True):
+        _check(load_library().sph_enable_timing(self.ctx, int(on)), "sph_enable_timing")
+
+    def kernel_times(self) -> dict:
+        t = sph_kernel_times()
+        _check(load_library().sph_get_kernel_times(self.ctx, ctypes.byref(t)), "sph_get_kernel_times")
+        return {"build_ms": t.build_ms, "sort_ms": t.sort_ms, "density_ms": t.density_ms, "force_ms": t.force_ms}
 
     def stats(self) -> dict:
         s = sph_stats()
