@@ -45,16 +45,30 @@ constexpr int WGS = NW * kWave;
 constexpr int kMaxSegW = 28;          // staged segments per wavefront and batch
 constexpr int NACC_D = 9;             // density partial sums per target
 constexpr int NACC_F = 5;             // force partial sums per target
+constexpr int NACC_F_DEF = NACC_F;
 constexpr float kCacheSlack = 0.08f;  // neighbour lists cover h (1 + slack)
 
-template <typename R> struct PCfg;
-template <> struct PCfg<float> { static constexpr int CAPW = 256, LISTW = 48; };
-template <> struct PCfg<double> { static constexpr int CAPW = 144, LISTW = 48; };
+// staged particles per wavefront and list slots per lane (density lists also
+// serve the Newton iteration, so they are longer)
+template <typename R, bool FORCE> struct PCfg;
+template <> struct PCfg<float, false> { static constexpr int CAPW = 256, LISTW = 48; };
+template <> struct PCfg<float, true> { static constexpr int CAPW = 256, LISTW = 32; };
+template <> struct PCfg<double, false> { static constexpr int CAPW = 256, LISTW = 48; };
+template <> struct PCfg<double, true> { static constexpr int CAPW = 256, LISTW = 32; };
 
-// share of the 26 neighbour directions per wavefront: faces 2/2/1/1,
-// edges 3/3/3/3, corners 1/1/3/3
-__constant__ int8_t kDirWave[kDirs] = {2, 2, 3, 3, 0, 0, 2, 1, 3, 2, 1, 3, 2,
-                                       3, 0, 0, 1, 2, 2, 3, 3, 1, 0, 0, 1, 1};
+// share of the 26 neighbour directions per wavefront (2 bits per direction):
+// faces 2/2/1/1, edges 3/3/3/3, corners 1/1/3/3
+constexpr uint64_t kDirWavePacked = 0x507e90edb60faull;
+__device__ __forceinline__ int dir_wave(int d) { return (int)((kDirWavePacked >> (2 * d)) & 3u); }
+
+// square root and reciprocal of the pair arithmetic: the hardware
+// instructions in FP32 (about 1 ulp), correctly rounded in FP64
+template <typename R> __device__ __forceinline__ R fast_sqrt(R x);
+template <> __device__ __forceinline__ float fast_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <> __device__ __forceinline__ double fast_sqrt<double>(double x) { return sqrt(x); }
+template <typename R> __device__ __forceinline__ R fast_rcp(R x);
+template <> __device__ __forceinline__ float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double fast_rcp<double>(double x) { return 1.0 / x; }
 
 // ---------------------------------------------------------------- kernel W (Sec. 2.1)
 // w(q) = 1 - 6q^2 + 6q^3 (q <= 1/2), 2(1-q)^3 (1/2 < q <= 1); callers ensure q < 1.
@@ -100,9 +114,10 @@ __device__ __forceinline__ void wave_sync()
 template <typename R, int NACC>
 struct Smem {
     using R4 = typename Vec4T<R>::T;
-    static constexpr int CAPW = PCfg<R>::CAPW;
-    static constexpr int LISTW = PCfg<R>::LISTW;
-    R4 st[NW][CAPW];                  // staged (x, y, z in T's frame, h_j for the force stage)
+    static constexpr int CAPW = PCfg<R, NACC == NACC_F_DEF>::CAPW;
+    static constexpr int LISTW = PCfg<R, NACC == NACC_F_DEF>::LISTW;
+    R4 st[NW][CAPW];                  // staged (x, y, z in T's frame, projection on the segment axis)
+    R sh[NW][NACC == NACC_F_DEF ? CAPW : 1];  // force stage: h of each staged particle
     uint32_t sg[NW][CAPW];            // cell-order index of each staged particle
     uint16_t list[NW][LISTW][kWave];  // per-lane neighbour lists (staged indices)
     double red[NACC][kWave];          // partial sums of the four wavefronts
@@ -111,6 +126,7 @@ struct Smem {
     float seg_u[NW][kMaxSegW][3];
     float seg_hx[NW][kMaxSegW];       // force: largest h of the source cell
     int nseg[NW];
+    int self_b[NW], self_t0[NW], self_n[NW];  // self segment: staged start, first cell index, count
     int conv[kWave];
     int ctl[4];                       // 0: all converged, 1: restage
     int unit;
@@ -128,12 +144,21 @@ __device__ void stage_wave(Smem<R, NACC>& s, const int w, const Decomp& dc, cons
     const int CAPW = Smem<R, NACC>::CAPW;
     int fill = 0, nseg = 0;
     wave_sync();  // earlier readers of this wavefront's staging area are done
-    while (k < nsrc) {
-        const Source src = dc.src[(int64_t)tcell * kMaxSources + k];
-        const bool self = src.dir == kSelfDir;
-        if (!self && kDirWave[src.dir] != w) { k++; p = 0; continue; }
+    // lane-parallel view of the source list (at most 27 entries)
+    Source my = {};
+    if (lane < nsrc) my = dc.src[(int64_t)tcell * kMaxSources + lane];
+    const bool mine = lane < nsrc && (my.dir == kSelfDir || dir_wave(my.dir) == w);
+    const uint64_t mask = __ballot(mine);
+    if (lane == 0) s.self_n[w] = 0;
+    while (true) {
+        const uint64_t m = k >= 64 ? 0ull : (mask & (~0ull << k));
+        if (m == 0) { k = nsrc; p = 0; break; }
+        k = __builtin_ctzll(m);
         if (nseg == kMaxSegW || fill >= CAPW) break;
-        const CellInfo S = dc.cells[src.cell];
+        const int scell = __shfl(my.cell, k, 64);
+        const int sdir = __shfl((int)my.dir, k, 64);
+        const bool self = sdir == kSelfDir;
+        const CellInfo S = dc.cells[scell];
         const int segb = fill;
         bool complete = true;
         float u[3] = {0.f, 0.f, 0.f};
@@ -146,23 +171,25 @@ __device__ void stage_wave(Smem<R, NACC>& s, const int w, const Decomp& dc, cons
                 const int g = S.start + q0 + p + t;
                 R4 e;
                 e.x = cd.rx[g]; e.y = cd.ry[g]; e.z = cd.rz[g];
-                e.w = FORCE ? gd.g1[g].z : (R)0;
+                e.w = (R)0;
                 s.st[w][fill + t] = e;
+                if constexpr (FORCE) s.sh[w][fill + t] = gd.g1[g].z;
                 s.sg[w][fill + t] = (uint32_t)g;
             }
+            if (lane == 0) { s.self_b[w] = fill; s.self_t0[w] = q0 + p; s.self_n[w] = take; }
             fill += take;
             if (take < n) { complete = false; p += take; }
         } else {
             int o[3];
-            dir_off(src.dir, o);
-            dir_unit(src.dir, u);
-            const int sd = dir_sort(src.dir);
-            const bool flip = dir_flip(src.dir);
+            dir_off(sdir, o);
+            dir_unit(sdir, u);
+            const int sd = dir_sort(sdir);
+            const bool flip = dir_flip(sdir);
             const R dox = (R)(o[0] * B.e[0]), doy = (R)(o[1] * B.e[1]), doz = (R)(o[2] * B.e[2]);
             const float udo = u[0] * (float)(o[0] * B.e[0]) + u[1] * (float)(o[1] * B.e[1]) +
                               u[2] * (float)(o[2] * B.e[2]);
             float hs = Hst;
-            if (FORCE) { hx = gd.cell_hmax[src.cell]; hs = fmaxf(Hst, hx); }
+            if (FORCE) { hx = gd.cell_hmax[scell]; hs = fmaxf(Hst, hx); }
             const float reach = fmaxf(u[0], 0.f) * (float)B.e[0] + fmaxf(u[1], 0.f) * (float)B.e[1] +
                                 fmaxf(u[2], 0.f) * (float)B.e[2] + hs + margin;
             const int64_t sbase = (int64_t)sd * dc.n + S.start;
@@ -184,8 +211,10 @@ __device__ void stage_wave(Smem<R, NACC>& s, const int w, const Decomp& dc, cons
                     const int g = S.start + l;
                     R4 e;
                     e.x = r.x + dox; e.y = r.y + doy; e.z = r.z + doz;
-                    e.w = FORCE ? gd.g1[g].z : (R)0;
+                    // projection on the segment axis, recomputed from the shifted position
+                    e.w = (R)(u[0] * (float)e.x + u[1] * (float)e.y + u[2] * (float)e.z);
                     s.st[w][fill + lane] = e;
+                    if constexpr (FORCE) s.sh[w][fill + lane] = gd.g1[g].z;
                     s.sg[w][fill + lane] = (uint32_t)g;
                 }
                 fill += take;
@@ -209,115 +238,123 @@ __device__ void stage_wave(Smem<R, NACC>& s, const int w, const Decomp& dc, cons
     wave_sync();
 }
 
-// One lane's walk over the staged segments of its wavefront (state in
-// registers); in-range staged indices go to the lane's list.
+// Staged index of the lane's own particle in wavefront w's self segment, or -1.
+template <typename R, int NACC>
+__device__ __forceinline__ int self_index(const Smem<R, NACC>& s, int w, int ti)
+{
+    const int d = ti - s.self_t0[w];
+    return (d >= 0 && d < s.self_n[w]) ? s.self_b[w] + d : -1;
+}
+
+// Walk of wavefront w over its staged segments, one segment at a time for
+// all lanes together: every lane reads the same staged particle (an LDS
+// broadcast), tests it against its own bound and radius, and appends it to
+// its list when in range.  The segment is left as soon as no lane is still
+// within its projected bound (the early exit of the sorted sweep).  The
+// walk state (seg, jj) is uniform; the call returns early when some lane's
+// list might overflow in the next step, and resumes from (seg, jj).
 template <typename R, bool FORCE, int NACC>
-struct Walker {
-    int seg, jj, je, nseg;
-    float bound, ux, uy, uz, hx;
-    bool active;
-
-    __device__ void load(const Smem<R, NACC>& s, int w, int q, float fxi, float fyi, float fzi, float fh,
-                         float margin)
-    {
-        jj = s.seg_b[w][q];
-        je = s.seg_e[w][q];
-        ux = s.seg_u[w][q][0]; uy = s.seg_u[w][q][1]; uz = s.seg_u[w][q][2];
-        hx = s.seg_hx[w][q];
-        const bool self = (ux == 0.0f && uy == 0.0f && uz == 0.0f);
-        bound = self ? INFINITY : (ux * fxi + uy * fyi + uz * fzi + fmaxf(fh, hx) + margin);
-    }
-
-    __device__ void start(const Smem<R, NACC>& s, int w, bool act, float fxi, float fyi, float fzi, float fh,
-                          float margin)
-    {
-        nseg = s.nseg[w];
-        seg = 0;
-        active = act && nseg > 0;
-        jj = je = 0;
-        if (active) load(s, w, 0, fxi, fyi, fzi, fh, margin);
-    }
-
-    // rad: search radius of this lane (density); for the force stage the
-    // radius of a pair is max(h_i, h_j).  Returns when the walk is over or
-    // some lane's list is full.
-    __device__ int run(Smem<R, NACC>& s, int w, int lane, R xi, R yi, R zi, R rad, uint32_t gi, int cnt,
-                       float fxi, float fyi, float fzi, float fh, float margin)
-    {
-        constexpr int LISTW = Smem<R, NACC>::LISTW;
-        const R rad2 = rad * rad;
-        while (true) {
-            if (active) {
-                bool adv = jj >= je;
-                if (!adv) {
-                    const auto e = s.st[w][jj];
-                    const float proj = ux * (float)e.x + uy * (float)e.y + uz * (float)e.z;
-                    if (proj > bound) {
-                        adv = true;
-                    } else {
-                        const R dx = xi - e.x, dy = yi - e.y, dz = zi - e.z;
-                        const R r2 = dx * dx + dy * dy + dz * dz;
-                        R lim2 = rad2;
-                        if (FORCE) { const R hm = rad > e.w ? rad : e.w; lim2 = hm * hm; }
-                        if (r2 < lim2 && s.sg[w][jj] != gi) { s.list[w][cnt][lane] = (uint16_t)jj; cnt++; }
-                        jj++;
-                    }
-                }
-                if (adv) {
-                    seg++;
-                    if (seg < nseg) load(s, w, seg, fxi, fyi, fzi, fh, margin); else active = false;
-                }
+__device__ __forceinline__ int walk(Smem<R, NACC>& s, int w, int lane, bool act, R xi, R yi, R zi, float fxi,
+                                    float fyi, float fzi, R rad, float fh, float margin, int selfj, int& seg_io,
+                                    int& jj_io, int cnt)
+{
+    constexpr int LISTW = Smem<R, NACC>::LISTW;
+    const int nseg = s.nseg[w];
+    const R rad2 = rad * rad;
+    int seg = __builtin_amdgcn_readfirstlane(seg_io);
+    int jj = __builtin_amdgcn_readfirstlane(jj_io);
+    uint16_t* lst = &s.list[w][0][lane];
+    while (seg < nseg) {
+        const int je = s.seg_e[w][seg];
+        const float ux = s.seg_u[w][seg][0], uy = s.seg_u[w][seg][1], uz = s.seg_u[w][seg][2];
+        const float hx = s.seg_hx[w][seg];
+        const bool self = (ux == 0.0f) & (uy == 0.0f) & (uz == 0.0f);
+        const float bound = !act ? -INFINITY : (self ? INFINITY : ux * fxi + uy * fyi + uz * fzi + fmaxf(fh, hx) + margin);
+        bool more = true;
+        for (; jj < je; jj += 2) {
+            // two staged particles per step (the second may lie past the segment end)
+            const bool two = jj + 1 < je;
+            const auto e0 = s.st[w][jj];
+            const auto e1 = s.st[w][two ? jj + 1 : jj];
+            const float p0 = (float)e0.w, p1 = (float)e1.w;
+            const bool in0 = p0 <= bound;
+            const bool in1 = (p1 <= bound) & two;
+            if (!__any(in0)) { more = false; break; }
+            const R dx0 = xi - e0.x, dy0 = yi - e0.y, dz0 = zi - e0.z;
+            const R dx1 = xi - e1.x, dy1 = yi - e1.y, dz1 = zi - e1.z;
+            const R r20 = dx0 * dx0 + dy0 * dy0 + dz0 * dz0;
+            const R r21 = dx1 * dx1 + dy1 * dy1 + dz1 * dz1;
+            R l0 = rad2, l1 = rad2;
+            if constexpr (FORCE) {
+                const R hm0 = rad > s.sh[w][jj] ? rad : s.sh[w][jj];
+                const R hm1 = rad > s.sh[w][jj + (two ? 1 : 0)] ? rad : s.sh[w][jj + (two ? 1 : 0)];
+                l0 = hm0 * hm0; l1 = hm1 * hm1;
             }
-            if (__any(cnt == LISTW) || !__any(active)) break;
+            const bool hit0 = in0 & (r20 < l0) & (jj != selfj);
+            const bool hit1 = in1 & (r21 < l1) & (jj + 1 != selfj);
+            lst[cnt * kWave] = (uint16_t)jj;        // slot cnt is free; kept only on a hit
+            cnt += hit0 ? 1 : 0;
+            lst[cnt * kWave] = (uint16_t)(jj + 1);
+            cnt += hit1 ? 1 : 0;
+            if (!__any(in1)) { more = false; jj += 2; break; }
+            if (__any(cnt > LISTW - 2)) { jj += 2; seg_io = seg; jj_io = jj; return cnt; }
         }
-        wave_sync();
-        return cnt;
+        (void)more;
+        seg++;
+        jj = seg < nseg ? s.seg_b[w][seg] : 0;
     }
-};
+    seg_io = seg;
+    jj_io = jj;
+    return cnt;
+}
 
 // ---------------------------------------------------------------- density
 struct DensAcc {
     double w, qdw, mw, mqdw, div, cx, cy, cz, n;
 };
 
-// Newton evaluation: the sums of Eq. (3) only (N and dN/dh need w and q w')
+// Newton evaluation: the two sums of Eq. (3) (N and dN/dh need w and q w')
 template <typename R>
-__device__ __forceinline__ void count_pair(DensAcc& a, R xi, R yi, R zi, R hinv, R h2, typename Vec4T<R>::T e)
+__device__ __forceinline__ void count_pair(DensAcc& a, bool ok, R xi, R yi, R zi, R hinv, R h2,
+                                           typename Vec4T<R>::T e)
 {
     const R dx = xi - e.x, dy = yi - e.y, dz = zi - e.z;
     const R r2 = dx * dx + dy * dy + dz * dz;
-    if (!(r2 < h2)) return;
-    const R q = sqrt(r2) * hinv;
-    a.w += (double)kern_w(q);
-    a.qdw += (double)(q * kern_dw(q));
+    ok = ok && r2 < h2;
+    const R q = fast_sqrt(r2) * hinv;
+    const R w = kern_w(q), qdw = q * kern_dw(q);
+    a.w += ok ? (double)w : 0.0;
+    a.qdw += ok ? (double)qdw : 0.0;
 }
 
-// Full density-stage terms of one pair: Eq. (2), Eq. (3), d rho/dh, and the
+// All density-stage terms of one pair: Eq. (2), Eq. (3), d rho/dh and the
 // velocity divergence and curl of Sec. 4.1 (gradient prefactor applied later)
 template <typename R>
-__device__ __forceinline__ void density_pair(DensAcc& a, R xi, R yi, R zi, R vxi, R vyi, R vzi, R h, R hinv,
-                                             R h2, typename Vec4T<R>::T e, typename Vec4T<R>::T vm)
+__device__ __forceinline__ void density_pair(DensAcc& a, bool ok, R xi, R yi, R zi, R vxi, R vyi, R vzi, R h,
+                                             R hinv, R h2, typename Vec4T<R>::T e, typename Vec4T<R>::T vm)
 {
     const R dx = xi - e.x, dy = yi - e.y, dz = zi - e.z;
     const R r2 = dx * dx + dy * dy + dz * dz;
-    if (!(r2 < h2)) return;
-    const R r = sqrt(r2);
+    ok = ok && r2 < h2;
+    const R r = fast_sqrt(r2);
     const R q = r * hinv;
-    const R qinv = h / r;
+    const R qinv = h * fast_rcp(r);
     const R w = kern_w(q), dw = kern_dw(q), gq = kern_g(q, qinv);
     const R mj = vm.w;
     const R dvx = vm.x - vxi, dvy = vm.y - vyi, dvz = vm.z - vzi;
     const R mg = mj * gq;
     const R qdw = q * dw;
-    a.w += (double)w;
-    a.qdw += (double)qdw;
-    a.mw += (double)(mj * w);
-    a.mqdw += (double)(mj * qdw);
-    a.div += (double)(mg * (dvx * dx + dvy * dy + dvz * dz));
-    a.cx += (double)(mg * (dvy * dz - dvz * dy));
-    a.cy += (double)(mg * (dvz * dx - dvx * dz));
-    a.cz += (double)(mg * (dvx * dy - dvy * dx));
-    a.n += 1.0;
+    if (ok) {
+        a.w += (double)w;
+        a.qdw += (double)qdw;
+        a.mw += (double)(mj * w);
+        a.mqdw += (double)(mj * qdw);
+        a.div += (double)(mg * (dvx * dx + dvy * dy + dvz * dz));
+        a.cx += (double)(mg * (dvy * dz - dvz * dy));
+        a.cy += (double)(mg * (dvz * dx - dvx * dz));
+        a.cz += (double)(mg * (dvx * dy - dvy * dx));
+        a.n += 1.0;
+    }
 }
 
 template <typename R>
@@ -326,6 +363,7 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
 {
     using R4 = typename Vec4T<R>::T;
     using SM = Smem<R, NACC_D>;
+    constexpr int LISTW = SM::LISTW;
     __shared__ SM s;
     const int tid = threadIdx.x;
     const int w = tid >> 6;
@@ -384,26 +422,32 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
                 const R hr = (R)h, hinv = (R)(1.0 / h), h2 = hr * hr;
                 auto process = [&](int n) {
                     if (full) {
-                        int t = 0;
-                        for (; t + 1 < n; t += 2) {
-                            const int j0 = s.list[w][t][lane], j1 = s.list[w][t + 1][lane];
+                        for (int t = 0;; t += 2) {
+                            const bool v0 = act && t < n, v1 = act && t + 1 < n;
+                            if (!__any(v0)) break;
+                            const int j0 = v0 ? (int)s.list[w][t][lane] : 0;
+                            const int j1 = v1 ? (int)s.list[w][t + 1][lane] : 0;
                             const R4 e0 = s.st[w][j0], e1 = s.st[w][j1];
-                            const R4 v0 = cd.vm[s.sg[w][j0]], v1 = cd.vm[s.sg[w][j1]];
-                            density_pair<R>(acc, xi, yi, zi, vmi.x, vmi.y, vmi.z, hr, hinv, h2, e0, v0);
-                            density_pair<R>(acc, xi, yi, zi, vmi.x, vmi.y, vmi.z, hr, hinv, h2, e1, v1);
-                        }
-                        if (t < n) {
-                            const int j0 = s.list[w][t][lane];
-                            density_pair<R>(acc, xi, yi, zi, vmi.x, vmi.y, vmi.z, hr, hinv, h2, s.st[w][j0],
-                                            cd.vm[s.sg[w][j0]]);
+                            const uint32_t g0 = s.sg[w][j0], g1 = s.sg[w][j1];
+                            const R4 q0 = cd.vm[g0], q1 = cd.vm[g1];
+                            density_pair<R>(acc, v0, xi, yi, zi, vmi.x, vmi.y, vmi.z, hr, hinv, h2, e0, q0);
+                            density_pair<R>(acc, v1, xi, yi, zi, vmi.x, vmi.y, vmi.z, hr, hinv, h2, e1, q1);
                         }
                     } else {
-                        for (int t = 0; t < n; t++) count_pair<R>(acc, xi, yi, zi, hinv, h2, s.st[w][s.list[w][t][lane]]);
+                        for (int t = 0;; t += 2) {
+                            const bool v0 = act && t < n, v1 = act && t + 1 < n;
+                            if (!__any(v0)) break;
+                            const int j0 = v0 ? (int)s.list[w][t][lane] : 0;
+                            const int j1 = v1 ? (int)s.list[w][t + 1][lane] : 0;
+                            const R4 e0 = s.st[w][j0], e1 = s.st[w][j1];
+                            count_pair<R>(acc, v0, xi, yi, zi, hinv, h2, e0);
+                            count_pair<R>(acc, v1, xi, yi, zi, hinv, h2, e1);
+                        }
                     }
                 };
                 const bool reuse = cached && (!full || cached_all) && __all(!act || (float)h <= hcache);
                 if (reuse) {
-                    if (act) process(cnt);
+                    process(cnt);
                     return;
                 }
                 // sweep(s) with early exit; the lists keep r < h (1 + slack)
@@ -415,12 +459,13 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
                 do {
                     if (!single) stage_wave<R, false, NACC_D>(s, w, dc, cd, so, gd, B, unit, nsrc, kk, pp, Hst, margin);
                     else kk = nsrc;
-                    Walker<R, false, NACC_D> wk;
-                    wk.start(s, w, act, fxi, fyi, fzi, fh, margin);
+                    const int selfj = self_index(s, w, ti);
+                    int seg = 0, jj = s.nseg[w] > 0 ? s.seg_b[w][0] : 0;
                     cnt = 0;
                     while (true) {
-                        cnt = wk.run(s, w, lane, xi, yi, zi, rad, gi, cnt, fxi, fyi, fzi, fh, margin);
-                        if (!__any(wk.active)) break;
+                        cnt = walk<R, false, NACC_D>(s, w, lane, act, xi, yi, zi, fxi, fyi, fzi, rad, fh, margin,
+                                                     selfj, seg, jj, cnt);
+                        if (seg >= s.nseg[w]) break;
                         process(cnt);  // a list is full: evaluate it and continue the walk
                         cnt = 0;
                         flushed = true;
@@ -578,35 +623,38 @@ struct ForceTarget {
     R x, y, z, vx, vy, vz, h, hinv, gk, A, rho, c, f;
 };
 
+// Eqs. (4)-(5) and the Monaghan-Balsara viscosity of Sec. 4.1 for one pair
+// (one-sided: the contribution of j to particle i)
 template <typename R>
-__device__ __forceinline__ void force_pair(ForceAcc& a, const ForceTarget<R>& ti, R alpha,
+__device__ __forceinline__ void force_pair(ForceAcc& a, bool ok, const ForceTarget<R>& ti, R alpha,
                                            typename Vec4T<R>::T e, typename Vec4T<R>::T vm,
                                            typename Vec4T<R>::T g0, typename Vec4T<R>::T g1)
 {
     const R dx = ti.x - e.x, dy = ti.y - e.y, dz = ti.z - e.z;
     const R r2 = dx * dx + dy * dy + dz * dz;
-    const R r = sqrt(r2);
-    const R rinv = r > (R)0 ? (R)1 / r : (R)0;
+    const R r = fast_sqrt(r2);
+    const R rinv = r > (R)0 ? fast_rcp(r) : (R)0;
     const R qi = r * ti.hinv, qj = r * g0.x;
     // grad W(r, h) = 8/(pi h^5) g(q) r_vec, zero outside the support and at r = 0
-    R gwi = qi < (R)1 ? ti.gk * kern_g(qi, ti.h * rinv) : (R)0;
-    R gwj = qj < (R)1 ? g0.y * kern_g(qj, g1.z * rinv) : (R)0;
-    if (r == (R)0) { gwi = (R)0; gwj = (R)0; }
+    const R gwi = (qi < (R)1 && r > (R)0) ? ti.gk * kern_g(qi, ti.h * rinv) : (R)0;
+    const R gwj = (qj < (R)1 && r > (R)0) ? g0.y * kern_g(qj, g1.z * rinv) : (R)0;
     const R mj = vm.w;
     const R vxij = ti.vx - vm.x, vyij = ti.vy - vm.y, vzij = ti.vz - vm.z;
     const R vr = vxij * dx + vyij * dy + vzij * dz;
     R wij = vr * rinv;
     wij = wij < (R)0 ? wij : (R)0;
-    const R Pi = -alpha * (ti.c + g1.x - (R)3 * wij) * wij / (ti.rho + g0.w);
+    const R Pi = -alpha * (ti.c + g1.x - (R)3 * wij) * wij * fast_rcp(ti.rho + g0.w);
     const R fij = ti.f + g1.y;
     const R gsum = gwi + gwj;
     const R sc = -mj * (ti.A * gwi + g0.z * gwj) - (R)0.25 * mj * Pi * gsum * fij;
     const R pdu = ti.A * mj * vr * gwi + (R)0.125 * mj * Pi * vr * gsum * fij;
-    a.ax += (double)(sc * dx);
-    a.ay += (double)(sc * dy);
-    a.az += (double)(sc * dz);
-    a.du += (double)pdu;
-    a.n += 1.0;
+    if (ok) {
+        a.ax += (double)(sc * dx);
+        a.ay += (double)(sc * dy);
+        a.az += (double)(sc * dz);
+        a.du += (double)pdu;
+        a.n += 1.0;
+    }
 }
 
 template <typename R>
@@ -650,36 +698,34 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
             for (int a = w; a < NACC_F; a += NW) s.red[a][lane] = 0.0;
             __syncthreads();
             ForceAcc acc = {};
-            auto heavy = [&](int n) {
-                int t = 0;
-                for (; t + 1 < n; t += 2) {
-                    const int j0 = s.list[w][t][lane], j1 = s.list[w][t + 1][lane];
+            auto process = [&](int n) {
+                for (int t = 0;; t += 2) {
+                    const bool v0 = t < n, v1 = t + 1 < n;
+                    if (!__any(v0)) break;
+                    const int j0 = v0 ? (int)s.list[w][t][lane] : 0;
+                    const int j1 = v1 ? (int)s.list[w][t + 1][lane] : 0;
                     const uint32_t q0 = s.sg[w][j0], q1 = s.sg[w][j1];
                     const R4 e0 = s.st[w][j0], e1 = s.st[w][j1];
-                    const R4 v0 = cd.vm[q0], v1 = cd.vm[q1];
+                    const R4 v0m = cd.vm[q0], v1m = cd.vm[q1];
                     const R4 a0 = gd.g0[q0], a1 = gd.g0[q1];
                     const R4 b0 = gd.g1[q0], b1 = gd.g1[q1];
-                    force_pair<R>(acc, ti, alpha, e0, v0, a0, b0);
-                    force_pair<R>(acc, ti, alpha, e1, v1, a1, b1);
-                }
-                if (t < n) {
-                    const int j0 = s.list[w][t][lane];
-                    const uint32_t q0 = s.sg[w][j0];
-                    force_pair<R>(acc, ti, alpha, s.st[w][j0], cd.vm[q0], gd.g0[q0], gd.g1[q0]);
+                    force_pair<R>(acc, v0, ti, alpha, e0, v0m, a0, b0);
+                    force_pair<R>(acc, v1, ti, alpha, e1, v1m, a1, b1);
                 }
             };
             int kk = 0, pp = 0;
             do {
                 if (!single) stage_wave<R, true, NACC_F>(s, w, dc, cd, so, gd, B, unit, nsrc, kk, pp, Hst, margin);
                 else kk = nsrc;
-                Walker<R, true, NACC_F> wk;
-                wk.start(s, w, valid, fxi, fyi, fzi, fh, margin);
+                const int selfj = self_index(s, w, ti_);
+                int seg = 0, jj = s.nseg[w] > 0 ? s.seg_b[w][0] : 0;
                 int cnt = 0;
                 while (true) {
-                    cnt = wk.run(s, w, lane, ti.x, ti.y, ti.z, ti.h, gi, cnt, fxi, fyi, fzi, fh, margin);
-                    heavy(cnt);
+                    cnt = walk<R, true, NACC_F>(s, w, lane, valid, ti.x, ti.y, ti.z, fxi, fyi, fzi, ti.h, fh, margin,
+                                                selfj, seg, jj, cnt);
+                    process(cnt);
                     cnt = 0;
-                    if (!__any(wk.active)) break;
+                    if (seg >= s.nseg[w]) break;
                 }
             } while (kk < nsrc);
             if (valid) {
