@@ -124,6 +124,101 @@ def run_form(ps, precision, steps, warmup):
     }
 
 
+def run_graph(ps, precision, steps, warmup, batch=None, params=None):
+    """The pass captured once as a HIP graph (h restored from the initial guess
+    inside the graph) and replayed; no host synchronisation inside a step."""
+    import torch
+    from paper_1404_2303_amd import sph
+    parts = sph.Particles.from_numpy(ps, "cuda:0")
+    h0 = parts.h.clone()
+    ctx = sph.Context(ps.box, precision=precision, **(params or {}))
+    b = sph.Batch(*batch) if batch is not None else None
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        _, fout = ctx.graph_capture(parts, b, h_init=h0)
+        ctx.check()
+        for _ in range(warmup):
+            ctx.graph_launch()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        for a, e in ev:
+            a.record()
+            ctx.graph_launch()
+            e.record()
+        torch.cuda.synchronize()
+        ms = [a.elapsed_time(e) for a, e in ev]
+        ctx.check()
+        P = int(fout["n_pairs"].sum().item())
+    ctx.close()
+    return {"P": P, "ms_per_step": float(np.mean(ms)), "ms_median": float(np.median(ms))}
+
+
+def run_per_box_loop(ps, precision, offsets, lens, params=None):
+    """Baseline for the batched form: every box through its own plain calls."""
+    import torch
+    from paper_1404_2303_amd import sph, workloads
+    ctxs, parts = [], []
+    for b in range(len(offsets) - 1):
+        sl = slice(offsets[b], offsets[b + 1])
+        sub = workloads.ParticleSet(pos=ps.pos[sl], vel=ps.vel[sl], m=ps.m[sl], u=ps.u[sl], h0=ps.h0[sl],
+                                    box=lens[b])
+        parts.append((sph.Particles.from_numpy(sub, "cuda:0"), None))
+        ctxs.append(sph.Context(lens[b], precision=precision, **(params or {})))
+    h0s = [p.h.clone() for p, _ in parts]
+
+    def one_step():
+        P = 0
+        outs = []
+        for ctx, (p, _), h0 in zip(ctxs, parts, h0s):
+            p.h.copy_(h0)
+            d, f = ctx.run(p)
+            outs.append(f["n_pairs"])
+        return outs
+
+    one_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = one_step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    P = int(sum(int(o.sum().item()) for o in outs))
+    for c in ctxs:
+        c.close()
+    return {"P": P, "ms_per_step": dt * 1e3}
+
+
+def batched_section(steps, warmup, tune=True):
+    """256 independent boxes, log-uniform counts in [2048, 65536]: one captured
+    pass over all boxes vs a loop of per-box plain calls."""
+    import torch
+    from paper_1404_2303_amd import autotune, workloads
+    ps, offsets, lens = workloads.batch()
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    params, tuned = {}, None
+    if tune:
+        key = autotune.workload_class(ps.n, len(offsets) - 1, "fp32")
+        tuned = autotune.tune(autotune.gpu_timer(ps, "fp32", batch=_BatchArgs(offsets, lens)), key, arch)
+        params = {k: v for k, v in tuned.items() if k != "cached"}
+    g = run_graph(ps, "fp32", steps, warmup, batch=(offsets, lens), params=params)
+    loop = run_per_box_loop(ps, "fp32", offsets, lens, params=params)
+    return {"workload": f"{len(offsets) - 1} periodic unit boxes, log-uniform counts in [2048, 65536], "
+                        f"{ps.n} particles, uniform-random positions seeded per box, v=0, u=1",
+            "n": ps.n, "pairs_per_step": g["P"], "value": g["P"] / (g["ms_per_step"] * 1e-3),
+            "ms_per_step": g["ms_per_step"], "per_box_loop_value": loop["P"] / (loop["ms_per_step"] * 1e-3),
+            "per_box_loop_ms": loop["ms_per_step"], "speedup_vs_loop": loop["ms_per_step"] / g["ms_per_step"],
+            "tuned": tuned}
+
+
+class _BatchArgs:
+    """Adapter: a Batch built lazily inside the timer (keeps host arrays alive)."""
+
+    def __init__(self, offsets, lens):
+        from paper_1404_2303_amd import sph
+        self.b = sph.Batch(offsets, lens)
+        self.c = self.b.c
+
+
 def roofline(res):
     """Dominant interaction kernel's algorithmic FLOP rate against the vector peak."""
     P_unordered = res["P"] / 2.0
@@ -160,6 +255,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 (plain) form")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 256-box batched workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -179,8 +275,13 @@ def main():
     if not args.no_plain:
         plain = run_form(ps, "fp64", args.steps, args.warmup)
         log("fp64:", json.dumps(plain))
+    graph = run_graph(ps, "fp32", args.steps, args.warmup)
+    log("fp32 graph:", json.dumps(graph))
     rl = roofline(fast)
-    value = fast["P"] / (fast["ms_per_step"] * 1e-3)
+    # the chosen form: the captured FP32 pass when it is the faster one
+    use_graph = graph["ms_per_step"] < fast["ms_per_step"] and graph["P"] == fast["P"]
+    step_ms = graph["ms_per_step"] if use_graph else fast["ms_per_step"]
+    value = fast["P"] / (step_ms * 1e-3)
     line = {
         "metric": METRIC,
         "value": value,
@@ -188,7 +289,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": fast["ms_per_step"],
+        "ms_per_step": step_ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -196,7 +297,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "jittered cubic lattice 128x128x64 (2^20 particles), spacing 1/128, "
                                "periodic 1x1x0.5 box, v~N(0,0.1), u=1; build+sort+density(h-Newton)+force",
-                   "n": ps.n, "form": "fp32 pair arithmetic, fp64 sums and Newton step",
+                   "n": ps.n, "form": ("graph-captured pass, " if use_graph else "eager calls, ") +
+                                       "fp32 pair arithmetic, fp64 sums and Newton step",
+                   "eager_ms_per_step": fast["ms_per_step"], "graph_ms_per_step": graph["ms_per_step"],
                    "pairs_per_step": fast["P"], "kernel_ms": fast["kernel_ms"],
                    "newton_mean": fast["newton_mean"], "newton_max": fast["newton_max"],
                    "cells": fast["cells"], "grid": fast["grid"],
@@ -206,6 +309,9 @@ def main():
     if plain is not None:
         line["plain_fp64"] = {"value": plain["P"] / (plain["ms_per_step"] * 1e-3), "ms_per_step": plain["ms_per_step"],
                               "kernel_ms": plain["kernel_ms"], "roofline": roofline(plain)}
+    if not args.no_batched:
+        line["batched"] = batched_section(max(3, args.steps // 4), 2)
+        log("batched:", json.dumps(line["batched"]))
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

@@ -163,6 +163,19 @@ sph_status sph_sort(sph_ctx *ctx, void *stream);
  * SPH_E_H_TOO_LARGE, SPH_E_HIP. */
 sph_status sph_density(sph_ctx *ctx, sph_particles *p, sph_density_out *out, void *stream);
 
+/* Density stage without synchronisation: as sph_density, but the device
+ * status is not read back and cells are never rebuilt, so the call can be
+ * captured in a graph.  Problems found on the device (non-finite data, an h
+ * that outgrows its cells, no convergence) are returned by the next
+ * sph_check.  Errors returned here: SPH_E_INVALID_ARG, SPH_E_STATE, SPH_E_HIP. */
+sph_status sph_density_async(sph_ctx *ctx, sph_particles *p, sph_density_out *out, void *stream);
+
+/* Waits for `stream` and returns the device-side status accumulated since the
+ * last sph_build_cells: SPH_OK, SPH_E_NONFINITE, SPH_E_H_TOO_LARGE (also when
+ * an h outgrew its cells during sph_density_async), SPH_E_CAPACITY,
+ * SPH_E_NOT_CONVERGED, or SPH_E_HIP. */
+sph_status sph_check(sph_ctx *ctx, void *stream);
+
 /* Force stage (Sec. 2.1 Eqs. (4)-(5), Sec. 4.1 viscosity) with the densities,
  * h and per-particle quantities of the last sph_density on this context.
  * Requires the particles of that call, unchanged.  Does not synchronise.
@@ -179,6 +192,22 @@ sph_status sph_force(sph_ctx *ctx, const sph_particles *p, sph_force_out *out, v
  * Errors: as sph_build_cells, sph_density. */
 sph_status sph_step(sph_ctx *ctx, sph_particles *p, const sph_batch *batch, sph_force_out *acc,
                     double dt, void *stream);
+
+/* Graph of one whole pass (the batched persistent form): optional copy of
+ * h_init (device, n values; may be NULL) into p->h, then sph_build_cells,
+ * sph_sort, sph_density_async and sph_force, captured once into a HIP graph
+ * on a stream owned by the context.  The call first runs the pass once
+ * without capture (to size the workspace; its results are written) and
+ * synchronises `stream`.  The graph keeps every pointer and size given here:
+ * replay it with sph_graph_launch only while those buffers stay alive and
+ * unchanged in size; a later sph_graph_capture replaces it.  Errors: as the
+ * calls it contains, and SPH_E_HIP if capture fails. */
+sph_status sph_graph_capture(sph_ctx *ctx, sph_particles *p, const sph_batch *batch, const double *h_init,
+                             sph_density_out *dout, sph_force_out *fout, void *stream);
+
+/* Replays the captured pass on `stream` (asynchronous).  Check the outcome
+ * with sph_check.  Errors: SPH_E_STATE (nothing captured), SPH_E_HIP. */
+sph_status sph_graph_launch(sph_ctx *ctx, void *stream);
 
 /* Statistics of the last calls on ctx (host values, valid after the call
  * that produced them has completed on its stream). */

@@ -1,0 +1,117 @@
+"""Autotuner for the decomposition parameters of the interaction kernels.
+
+The kernels' LDS tiles are fixed at compile time; what changes the work per
+unit at run time is the size of the cells (``cell_target``: particles per
+top cell at the mean density, subject to edge >= max h) and the slack on h
+when cells are built (``h_margin``).  For a given workload the tuner times a
+captured pass (build, sort, density, force) for each candidate and keeps the
+fastest.  Results are cached per (GPU architecture, precision, workload
+class) in a JSON file, so a workload of the same class is not re-tuned.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+from typing import Callable, Optional
+
+CANDIDATES = [
+    {"cell_target": 24, "h_margin": 0.1},
+    {"cell_target": 32, "h_margin": 0.1},
+    {"cell_target": 48, "h_margin": 0.1},
+    {"cell_target": 64, "h_margin": 0.1},
+    {"cell_target": 96, "h_margin": 0.1},
+    {"cell_target": 128, "h_margin": 0.1},
+    {"cell_target": 64, "h_margin": 0.05},
+]
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_tune", "autotune.json")
+
+
+def workload_class(n_total: int, n_boxes: int, precision: str) -> str:
+    """Workloads of the same class share a tuning: log2 buckets of the
+    particles per box and of the box count."""
+    ppb = max(1, n_total // max(1, n_boxes))
+    return f"{precision}|ppb2^{int(math.log2(ppb))}|boxes2^{int(math.log2(max(1, n_boxes)))}"
+
+
+def load_cache(path: str = CACHE) -> dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(cache: dict, path: str = CACHE) -> None:
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def choose(timings: dict) -> dict:
+    """Fastest candidate (ties: the earlier one)."""
+    best_key = min(timings, key=lambda k: (timings[k], list(timings).index(k)))
+    return json.loads(best_key)
+
+
+def tune(time_candidate: Callable[[dict], float], key: str, arch: str, candidates=None,
+         cache_path: str = CACHE, force: bool = False) -> dict:
+    """Return the best parameters for (arch, key), timing candidates if needed.
+
+    time_candidate(params) -> seconds per pass (lower is better); it may raise
+    for candidates the workload cannot use, which are then skipped.
+    """
+    candidates = CANDIDATES if candidates is None else candidates
+    cache = load_cache(cache_path)
+    full = f"{arch}|{key}"
+    if not force and full in cache:
+        return dict(cache[full]["best"], cached=True)
+    timings = {}
+    for c in candidates:
+        try:
+            timings[json.dumps(c, sort_keys=True)] = float(time_candidate(c))
+        except Exception:
+            continue
+    if not timings:
+        raise RuntimeError("no autotune candidate ran")
+    best = choose(timings)
+    cache[full] = {"best": best, "timings": timings, "when": time.time()}
+    save_cache(cache, cache_path)
+    return dict(best, cached=False)
+
+
+def gpu_timer(ps, precision: str, batch=None, reps: int = 3, arch: Optional[str] = None):
+    """A time_candidate function for tune(): median of `reps` graph replays of
+    the whole pass (build, sort, density from the initial h, force)."""
+    import torch
+    from . import sph
+
+    def run(params: dict) -> float:
+        parts = sph.Particles.from_numpy(ps, "cuda:0")
+        h0 = parts.h.clone()
+        ctx = sph.Context(ps.box, precision=precision, **params)
+        stream = torch.cuda.Stream()
+        try:
+            with torch.cuda.stream(stream):
+                ctx.graph_capture(parts, batch, h_init=h0)
+                ctx.check(allow_unconverged=False)
+                times = []
+                for _ in range(reps):
+                    a = torch.cuda.Event(enable_timing=True)
+                    b = torch.cuda.Event(enable_timing=True)
+                    a.record()
+                    ctx.graph_launch()
+                    b.record()
+                    b.synchronize()
+                    times.append(a.elapsed_time(b) * 1e-3)
+                ctx.check()
+        finally:
+            ctx.close()
+        times.sort()
+        return times[len(times) // 2]
+
+    return run

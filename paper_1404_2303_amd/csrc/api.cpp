@@ -61,6 +61,11 @@ struct sph_ctx {
     int top_bits = 1;
     int64_t map_total = 0;
     std::vector<BoxInfo> box_host;
+    BoxInfo* box_pinned = nullptr;                   // pinned copy uploaded to the device
+    int box_pinned_cap = 0;
+    hipStream_t cap_stream = nullptr;                // stream used for graph capture
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
     std::vector<int64_t> batch_off;
     std::vector<double> batch_len;
     bool built = false, sorted = false, have_density = false;
@@ -69,7 +74,7 @@ struct sph_ctx {
     bool timing = false;
     hipEvent_t ev[8] = {};
     float dens_ms_acc = 0.0f;
-    int dens_pending = 0;     // density events recorded since the last read
+    bool dens_async_timed = false;  // the last density call was sph_density_async (events not yet read)
 };
 
 enum { EV_BUILD0, EV_BUILD1, EV_SORT0, EV_SORT1, EV_DENS0, EV_DENS1, EV_FORCE0, EV_FORCE1 };
@@ -247,6 +252,10 @@ sph_status sph_destroy(sph_ctx* c)
     if (c->status_host) (void)hipHostFree(c->status_host);
     if (c->ncells_host) (void)hipHostFree(c->ncells_host);
     for (hipEvent_t& e : c->ev) if (e) (void)hipEventDestroy(e);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->box_pinned) (void)hipHostFree(c->box_pinned);
     delete c;
     return SPH_OK;
 }
@@ -312,6 +321,23 @@ static sph_status setup_boxes(sph_ctx* c, int64_t n, const sph_batch* batch)
     return SPH_OK;
 }
 
+// Copies the host box table to the device through a pinned buffer (so the
+// copy can be part of a captured graph).
+static bool upload_boxes(sph_ctx* c, hipStream_t st)
+{
+    if (c->box_pinned_cap < c->nbox) {
+        if (c->box_pinned) (void)hipHostFree(c->box_pinned);
+        c->box_pinned = nullptr;
+        c->box_pinned_cap = 0;
+        if (hipHostMalloc((void**)&c->box_pinned, sizeof(BoxInfo) * c->nbox, hipHostMallocDefault) != hipSuccess)
+            return false;
+        c->box_pinned_cap = c->nbox;
+    }
+    std::memcpy(c->box_pinned, c->box_host.data(), sizeof(BoxInfo) * c->nbox);
+    return hipMemcpyAsync(c->boxes.p, c->box_pinned, sizeof(BoxInfo) * c->nbox, hipMemcpyHostToDevice, st) ==
+           hipSuccess;
+}
+
 extern "C++" {
 template <typename R>
 static void build_launches(sph_ctx* c, const Particles& pv, hipStream_t st)
@@ -356,11 +382,9 @@ sph_status sph_build_cells(sph_ctx* c, const sph_particles* p, const sph_batch* 
     if (!ensure_particles(c, p->n)) return SPH_E_OOM;
     if (!c->boxes.ensure(sizeof(BoxInfo) * c->nbox)) return SPH_E_OOM;
     if (!c->cell_map.ensure(sizeof(int32_t) * std::max<int64_t>(c->map_total, 1))) return SPH_E_OOM;
-    hipError_t e = hipMemcpyAsync(c->boxes.p, c->box_host.data(), sizeof(BoxInfo) * c->nbox,
-                                  hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemsetAsync(c->status.p, 0, 16, st);
-    if (e == hipSuccess) e = hipMemsetAsync(c->ncells.p, 0, 16, st);
-    if (e != hipSuccess) return SPH_E_HIP;
+    if (!upload_boxes(c, st)) return SPH_E_HIP;
+    launch_fill_i32(c->status.as<int32_t>(), 4, 0, st);
+    launch_fill_i32(c->ncells.as<int32_t>(), 4, 0, st);
     if (p->n > 0) {
         Particles pv = view(p);
         ev_record(c, EV_BUILD0, st);
@@ -439,6 +463,7 @@ sph_status sph_density(sph_ctx* c, sph_particles* p, sph_density_out* o, void* s
     c->stats.rebuilds = 0;
     c->have_density = false;
     c->dens_ms_acc = 0.0f;
+    c->dens_async_timed = false;
     for (int attempt = 0;; attempt++) {
         uint32_t bits = 0;
         if (c->n > 0) {
@@ -481,6 +506,39 @@ sph_status sph_density(sph_ctx* c, sph_particles* p, sph_density_out* o, void* s
     }
 }
 
+sph_status sph_density_async(sph_ctx* c, sph_particles* p, sph_density_out* o, void* stream)
+{
+    if (!c || !particles_ok(p)) return SPH_E_INVALID_ARG;
+    if (!c->built || !c->sorted) return SPH_E_STATE;
+    if (p->n != c->n) return SPH_E_STATE;
+    hipStream_t st = (hipStream_t)stream;
+    c->stats.rebuilds = 0;
+    c->dens_ms_acc = 0.0f;
+    if (c->n > 0) {
+        ev_record(c, EV_DENS0, st);
+        if (c->prm.precision == SPH_FP64) density_launch<double>(c, p, o, st);
+        else density_launch<float>(c, p, o, st);
+        ev_record(c, EV_DENS1, st);
+        if (hipGetLastError() != hipSuccess) return SPH_E_HIP;
+    }
+    c->have_density = true;
+    c->dens_async_timed = c->timing && c->n > 0;
+    return SPH_OK;
+}
+
+sph_status sph_check(sph_ctx* c, void* stream)
+{
+    if (!c) return SPH_E_INVALID_ARG;
+    uint32_t bits = 0;
+    sph_status s = read_status(c, (hipStream_t)stream, &bits);
+    if (s != SPH_OK) return s;
+    s = status_error(bits);
+    if (s != SPH_OK) return s;
+    if (bits & ST_REBUILD) return SPH_E_H_TOO_LARGE;
+    if (bits & ST_NOT_CONVERGED) return SPH_E_NOT_CONVERGED;
+    return SPH_OK;
+}
+
 sph_status sph_force(sph_ctx* c, const sph_particles* p, sph_force_out* o, void* stream)
 {
     if (!c || !particles_ok(p) || !o) return SPH_E_INVALID_ARG;
@@ -514,9 +572,7 @@ sph_status sph_step(sph_ctx* c, sph_particles* p, const sph_batch* batch, sph_fo
     sph_status s = setup_boxes(c, n, batch);
     if (s != SPH_OK) return s;
     if (!c->boxes.ensure(sizeof(BoxInfo) * c->nbox)) return SPH_E_OOM;
-    if (hipMemcpyAsync(c->boxes.p, c->box_host.data(), sizeof(BoxInfo) * c->nbox, hipMemcpyHostToDevice, st) !=
-        hipSuccess)
-        return SPH_E_HIP;
+    if (!upload_boxes(c, st)) return SPH_E_HIP;
     if (!c->step_tmp.ensure(sizeof(double) * 4 * (size_t)n)) return SPH_E_OOM;
     double* vp = c->step_tmp.as<double>();
     double *pvx = vp, *pvy = vp + n, *pvz = vp + 2 * n, *pu = vp + 3 * n;
@@ -541,6 +597,62 @@ sph_status sph_step(sph_ctx* c, sph_particles* p, const sph_batch* batch, sph_fo
     return sd;
 }
 
+__global__ void k_copy_f64(double* dst, const double* src, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// One whole pass on a stream: optional reset of h, cells, orderings, density
+// (no synchronisation) and force.
+static sph_status pass_sequence(sph_ctx* c, sph_particles* p, const sph_batch* b, const double* h_init,
+                                sph_density_out* d, sph_force_out* f, hipStream_t st)
+{
+    if (h_init && p->n > 0)
+        hipLaunchKernelGGL(k_copy_f64, dim3((unsigned)((p->n + 255) / 256)), dim3(256), 0, st, p->h, h_init, p->n);
+    sph_status s = sph_build_cells(c, p, b, st);
+    if (s == SPH_OK) s = sph_sort(c, st);
+    if (s == SPH_OK) s = sph_density_async(c, p, d, st);
+    if (s == SPH_OK) s = sph_force(c, p, f, st);
+    return s;
+}
+
+sph_status sph_graph_capture(sph_ctx* c, sph_particles* p, const sph_batch* b, const double* h_init,
+                             sph_density_out* d, sph_force_out* f, void* stream)
+{
+    if (!c || !particles_ok(p) || !f) return SPH_E_INVALID_ARG;
+    if (hipSetDevice(c->device) != hipSuccess) return SPH_E_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return SPH_E_HIP;
+    // a plain run first: it sizes the workspace (no allocation may happen while capturing)
+    const bool timing = c->timing;
+    c->timing = false;
+    sph_status s = pass_sequence(c, p, b, h_init, d, f, st);
+    if (s == SPH_OK) s = sph_check(c, stream);
+    if (s != SPH_OK && s != SPH_E_NOT_CONVERGED) { c->timing = timing; return s; }
+    if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
+    if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+    if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        c->timing = timing;
+        return SPH_E_HIP;
+    }
+    s = pass_sequence(c, p, b, h_init, d, f, c->cap_stream);
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &c->graph);
+    c->timing = timing;
+    if (s != SPH_OK) return s;
+    if (e != hipSuccess) return SPH_E_HIP;
+    if (hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0) != hipSuccess) return SPH_E_HIP;
+    return SPH_OK;
+}
+
+sph_status sph_graph_launch(sph_ctx* c, void* stream)
+{
+    if (!c) return SPH_E_INVALID_ARG;
+    if (!c->graph_exec) return SPH_E_STATE;
+    return hipGraphLaunch(c->graph_exec, (hipStream_t)stream) == hipSuccess ? SPH_OK : SPH_E_HIP;
+}
+
 sph_status sph_enable_timing(sph_ctx* c, int on)
 {
     if (!c) return SPH_E_INVALID_ARG;
@@ -561,6 +673,10 @@ sph_status sph_get_kernel_times(sph_ctx* c, sph_kernel_times* out)
     (void)hipEventElapsedTime(&out->build_ms, c->ev[EV_BUILD0], c->ev[EV_BUILD1]);
     (void)hipEventElapsedTime(&out->sort_ms, c->ev[EV_SORT0], c->ev[EV_SORT1]);
     (void)hipEventElapsedTime(&out->force_ms, c->ev[EV_FORCE0], c->ev[EV_FORCE1]);
+    if (c->dens_async_timed) {
+        (void)hipEventElapsedTime(&c->dens_ms_acc, c->ev[EV_DENS0], c->ev[EV_DENS1]);
+        c->dens_async_timed = false;
+    }
     out->density_ms = c->dens_ms_acc;
     return SPH_OK;
 }

@@ -299,6 +299,13 @@ __global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v)
     if (i < n) a[i] = v;
 }
 
+// clearing by a kernel rather than hipMemsetAsync keeps the sequence capturable in a graph
+void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, n, v);
+}
+
 // cellx[i] = exclusive scan of the head flags; cell index of particle i is
 // cellx[i] + flag[i] - 1.
 __global__ void k_cell_fill(const uint64_t* keys, const uint32_t* flag, const uint32_t* cellx,

@@ -72,6 +72,7 @@ struct Decomp {
 };
 
 // build.hip
+void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t st);
 void launch_box_scan(const Particles& p, BoxInfo* boxes, int nbox, int64_t n, uint32_t* status,
                      hipStream_t st);
 void launch_grid_dims(BoxInfo* boxes, int nbox, double margin, int max_nc, uint32_t* status,

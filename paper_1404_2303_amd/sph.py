@@ -24,7 +24,8 @@ SPH_FP64, SPH_FP32_ACC64 = 0, 1
 
 EXPORTED = ["sph_default_params", "sph_create", "sph_destroy", "sph_build_cells", "sph_sort",
             "sph_density", "sph_force", "sph_step", "sph_get_stats", "sph_status_string",
-            "sph_enable_timing", "sph_get_kernel_times"]
+            "sph_enable_timing", "sph_get_kernel_times", "sph_density_async", "sph_check",
+            "sph_graph_capture", "sph_graph_launch"]
 
 P = ctypes.c_void_p
 
@@ -102,6 +103,15 @@ def load_library():
         lib.sph_enable_timing.argtypes = [P, ctypes.c_int]
         lib.sph_get_kernel_times.restype = st
         lib.sph_get_kernel_times.argtypes = [P, ctypes.POINTER(sph_kernel_times)]
+        lib.sph_density_async.restype = st
+        lib.sph_density_async.argtypes = [P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_density_out), P]
+        lib.sph_check.restype = st
+        lib.sph_check.argtypes = [P, P]
+        lib.sph_graph_capture.restype = st
+        lib.sph_graph_capture.argtypes = [P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_batch), P,
+                                          ctypes.POINTER(sph_density_out), ctypes.POINTER(sph_force_out), P]
+        lib.sph_graph_launch.restype = st
+        lib.sph_graph_launch.argtypes = [P, P]
         lib.sph_status_string.restype = ctypes.c_char_p
         lib.sph_status_string.argtypes = [st]
         _lib = lib
@@ -167,6 +177,26 @@ def sph_force(ctx, parts: sph_particles, out: sph_force_out, stream):
 def sph_step(ctx, parts: sph_particles, batch: Optional[sph_batch], acc: sph_force_out, dt: float, stream):
     return load_library().sph_step(ctx, ctypes.byref(parts), ctypes.byref(batch) if batch is not None else None,
                                    ctypes.byref(acc), float(dt), stream)
+
+
+def sph_density_async(ctx, parts: sph_particles, out: Optional[sph_density_out], stream):
+    return load_library().sph_density_async(ctx, ctypes.byref(parts),
+                                            ctypes.byref(out) if out is not None else None, stream)
+
+
+def sph_check(ctx, stream):
+    return load_library().sph_check(ctx, stream)
+
+
+def sph_graph_capture(ctx, parts: sph_particles, batch: Optional[sph_batch], h_init, dout, fout, stream):
+    return load_library().sph_graph_capture(ctx, ctypes.byref(parts),
+                                            ctypes.byref(batch) if batch is not None else None, h_init,
+                                            ctypes.byref(dout) if dout is not None else None,
+                                            ctypes.byref(fout), stream)
+
+
+def sph_graph_launch(ctx, stream):
+    return load_library().sph_graph_launch(ctx, stream)
 
 
 # ---------------------------------------------------------------- tensor layer
@@ -288,6 +318,35 @@ class Context:
         t = sph_kernel_times()
         _check(load_library().sph_get_kernel_times(self.ctx, ctypes.byref(t)), "sph_get_kernel_times")
         return {"build_ms": t.build_ms, "sort_ms": t.sort_ms, "density_ms": t.density_ms, "force_ms": t.force_ms}
+
+    def check(self, allow_unconverged=False):
+        allow = (SPH_E_NOT_CONVERGED,) if allow_unconverged else ()
+        return _check(sph_check(self.ctx, _stream()), "sph_check", allow)
+
+    def graph_capture(self, parts: Particles, batch: Optional[Batch] = None, h_init: Optional[torch.Tensor] = None,
+                      dout: Optional[dict] = None, fout: Optional[dict] = None):
+        """Capture build -> sort -> density -> force (optionally preceded by h <- h_init) as one graph.
+
+        The tensors passed here (particles, h_init, outputs) are kept by the graph: keep them alive.
+        """
+        n = parts.n
+        dev = parts.x.device
+        if fout is None:
+            fout = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("ax", "ay", "az", "dudt")}
+            fout["n_pairs"] = torch.empty(n, dtype=torch.int32, device=dev)
+        dc = None
+        if dout is not None:
+            dc = sph_density_out(*[_ptr(dout.get(k)) for k in DENSITY_FIELDS])
+        fc = sph_force_out(*[_ptr(fout.get(k)) for k in ("ax", "ay", "az", "dudt", "n_pairs")])
+        self._graph_keep = (parts, batch, h_init, dout, fout, dc, fc)
+        pc = parts.c_struct()
+        self._graph_pc = pc
+        _check(sph_graph_capture(self.ctx, pc, batch.c if batch else None, _ptr(h_init), dc, fc, _stream()),
+               "sph_graph_capture", (SPH_E_NOT_CONVERGED,))
+        return dout, fout
+
+    def graph_launch(self):
+        _check(sph_graph_launch(self.ctx, _stream()), "sph_graph_launch")
 
     def stats(self) -> dict:
         s = sph_stats()
