@@ -1,0 +1,79 @@
+"""Pins of the gradient oracle (dense FP64 autograd model, oracle/grad.py).
+
+The dense model is an independent implementation of the equations of Sec. 2.1
+and Sec. 4.1; it is checked against the C oracle's forward values, against
+central finite differences of the loss through the C oracle (h re-solved at
+every evaluation), and against the translation invariance of the loss."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import grad as og
+from paper_1404_2303_amd import workloads
+
+
+def _state(n=300, seed=3):
+    rng = np.random.default_rng(seed)
+    ps = workloads.uniform(n, seed=seed, sigma_v=0.4)
+    ps.u[:] = rng.uniform(0.5, 1.5, n)
+    rt = workloads.density_target(ps.pos, ps.m[0] * n)
+    return ps, rt
+
+
+def test_dense_model_matches_the_c_oracle():
+    ps, rt = _state(400, 1)
+    ref = oracle.full_pass(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box)
+    t = lambda a: torch.tensor(np.asarray(a, dtype=np.float64))
+    out = og.model(t(ps.pos), t(ps.vel), t(ps.m), t(ps.u), t(ref["h"]), ps.box)
+    assert np.allclose(out["rho"].numpy(), ref["dens"]["rho"], rtol=1e-12)
+    assert np.allclose(out["N"].numpy(), 48.0, atol=1e-10)
+    assert np.allclose(out["omega"].numpy(), ref["ghost"]["omega"], rtol=1e-12)
+    assert np.allclose(out["f"].numpy(), ref["ghost"]["f"], rtol=1e-10, atol=1e-13)
+    ka = ref["force"]["kappa_a"][:, None]
+    assert np.all(np.abs(out["a"].numpy() - ref["force"]["a"]) <= 1e-12 * ka)
+    assert np.all(np.abs(out["dudt"].numpy() - ref["force"]["dudt"]) <= 1e-12 * ref["force"]["kappa_u"])
+
+
+@pytest.mark.parametrize("solve", [False, True])
+def test_gradient_matches_central_differences(solve):
+    ps, rt = _state(300, 5)
+    h = ps.h0 if solve else oracle.solve_h(ps.pos, ps.h0, ps.box)[0] * 1.01
+    gx, gh, L, hs = og.gradients(ps.pos, ps.vel, ps.m, ps.u, h, ps.box, rt, solve=solve)
+    rng = np.random.default_rng(0)
+    eps = 1e-6
+    for k in rng.choice(ps.n, 6, replace=False):
+        for ax in range(3):
+            fd = og.loss_fd(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box, rt, k, ax, eps, solve=solve,
+                            h_fixed=None if solve else h)
+            assert abs(fd - gx[k, ax]) <= 1e-5 * (abs(gx[k, ax]) + 1e-3 * np.max(np.abs(gx))), (k, ax, fd, gx[k, ax])
+    if not solve:
+        # h gradient: perturb h_k with positions fixed
+        for k in rng.choice(ps.n, 4, replace=False):
+            vals = []
+            for sgn in (+1, -1):
+                hh = h.copy()
+                hh[k] += sgn * 1e-7
+                d = oracle.density(ps.pos, ps.vel, ps.m, hh, ps.box)
+                gh_ = oracle.ghost(d, ps.u, hh)
+                fr = oracle.force(ps.pos, ps.vel, ps.m, hh, d["rho"], gh_["A"], gh_["c"], gh_["f"], ps.box)
+                vals.append(np.sum((d["rho"] - rt) ** 2) + np.sum(fr["a"] ** 2))
+            fd = (vals[0] - vals[1]) / 2e-7
+            assert abs(fd - gh[k]) <= 1e-5 * (abs(gh[k]) + 1e-3 * np.max(np.abs(gh))), (k, fd, gh[k])
+
+
+def test_local_differences_equal_global_ones():
+    ps, rt = _state(600, 9)
+    hs, _ = oracle.solve_h(ps.pos, ps.h0, ps.box, tol=1e-13)
+    R = 2.2 * hs.max()
+    for k, ax in ((3, 0), (77, 2)):
+        g = og.loss_fd(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box, rt, k, ax, 1e-6)
+        l = og.loss_fd(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box, rt, k, ax, 1e-6, local=R)
+        assert abs(g - l) <= 1e-6 * max(1.0, abs(g))
+
+
+def test_loss_is_translation_invariant():
+    # rho_target is frozen per particle, so shifting every particle leaves L unchanged
+    ps, rt = _state(300, 7)
+    gx, _, _, _ = og.gradients(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box, rt, solve=True)
+    assert np.max(np.abs(gx.sum(0))) <= 1e-9 * np.sum(np.abs(gx))
