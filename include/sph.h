@@ -182,6 +182,35 @@ sph_status sph_check(sph_ctx *ctx, void *stream);
  * Errors: SPH_E_STATE, SPH_E_HIP. */
 sph_status sph_force(sph_ctx *ctx, const sph_particles *p, sph_force_out *out, void *stream);
 
+/* Upstream gradients of a scalar loss L (caller order; any may be NULL = 0). */
+typedef struct {
+    const double *rho;          /* dL/d rho_i */
+    const double *ax, *ay, *az; /* dL/d a_i */
+    const double *dudt;         /* dL/d (du/dt)_i */
+} sph_grad_in;
+
+/* Gradients of L (caller order; any may be NULL to skip it). */
+typedef struct {
+    double *x, *y, *z;   /* dL/dx_i (total: through rho, Omega, div, curl, f, A and every pair term) */
+    double *h;           /* dL/dh_i with h held fixed; zeros when implicit_h != 0 */
+} sph_grad_out;
+
+/* Reverse mode of the density and force stages (Sec. 2.1 Eqs. (2)-(5) with
+ * the Sec. 4.1 viscosity and Balsara switch) at the state of the last
+ * sph_density on this context: positions, velocities, masses and u as
+ * gathered by the last sph_build_cells, and the solved h.  Given dL/d rho,
+ * dL/da and dL/d(du/dt), writes dL/dx and (fixed h) dL/dh.  Velocities,
+ * masses and u are constants.
+ *   implicit_h = 0: h is an independent input (the fixed-h derivative);
+ *   implicit_h = 1: h_i is the solved root of N_i(h_i) = n_ngb (Eq. (3)), so
+ *     dh_i/dx = -(dN_i/dx)/(dN_i/dh_i) is included in dL/dx (implicit
+ *     function theorem; exact at the root, up to the ngb_tol of the solve).
+ * Pair arithmetic in the context's precision, sums in FP64.  Does not
+ * synchronise.  Errors: SPH_E_INVALID_ARG, SPH_E_STATE (no sph_density yet,
+ * or a different particle count), SPH_E_OOM, SPH_E_HIP. */
+sph_status sph_backward(sph_ctx *ctx, const sph_particles *p, const sph_grad_in *grad_in,
+                        sph_grad_out *grad_out, int implicit_h, void *stream);
+
 /* One kick-drift-kick velocity-Verlet step (Sec. 4.1) with fixed dt:
  *   v += dt/2 a, u += dt/2 du/dt  (a, du/dt of the previous step, from `acc`),
  *   x += dt v (wrapped into the box),
@@ -230,6 +259,7 @@ sph_status sph_get_stats(const sph_ctx *ctx, sph_stats *out);
  * attempts) and force kernel.  Errors: SPH_E_INVALID_ARG, SPH_E_HIP. */
 typedef struct {
     float build_ms, sort_ms, density_ms, force_ms;
+    float backward_ms;       /* the last sph_backward (0 if none since timing was enabled) */
 } sph_kernel_times;
 
 sph_status sph_enable_timing(sph_ctx *ctx, int on);

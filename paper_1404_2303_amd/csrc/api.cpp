@@ -51,6 +51,8 @@ struct sph_ctx {
     DBuf cells, ncells, cell_map, src, src_count, sidx, srec;
     DBuf rx, ry, rz, h, vm, u;                       // cell order
     DBuf g0, g1, cell_hmax;                          // ghost quantities, cell order
+    DBuf sd0, sd1;                                   // density sums kept for the adjoint
+    DBuf adj_ab, adj_sb0, adj_sb1, adj_x, adj_h, adj_fg;  // adjoint workspace
     DBuf qhead, status;
     DBuf step_tmp;                                   // predicted v, u; new a, du/dt
     uint32_t* status_host = nullptr;                 // pinned
@@ -72,12 +74,13 @@ struct sph_ctx {
     sph_stats stats{};
     // optional kernel timing
     bool timing = false;
-    hipEvent_t ev[8] = {};
+    hipEvent_t ev[10] = {};
     float dens_ms_acc = 0.0f;
+    bool adj_timed = false;
     bool dens_async_timed = false;  // the last density call was sph_density_async (events not yet read)
 };
 
-enum { EV_BUILD0, EV_BUILD1, EV_SORT0, EV_SORT1, EV_DENS0, EV_DENS1, EV_FORCE0, EV_FORCE1 };
+enum { EV_BUILD0, EV_BUILD1, EV_SORT0, EV_SORT1, EV_DENS0, EV_DENS1, EV_FORCE0, EV_FORCE1, EV_ADJ0, EV_ADJ1 };
 
 static void ev_record(sph_ctx* c, int k, hipStream_t st)
 {
@@ -115,6 +118,7 @@ static GhostData<R> ghost_data(sph_ctx* c)
     GhostData<R> g;
     g.g0 = c->g0.as<R4>(); g.g1 = c->g1.as<R4>();
     g.cell_hmax = c->cell_hmax.as<float>();
+    g.sd0 = c->sd0.as<double4>(); g.sd1 = c->sd1.as<double4>();
     return g;
 }
 
@@ -165,6 +169,7 @@ static bool ensure_particles(sph_ctx* c, int64_t n)
     ok &= c->vm.ensure(N * 4 * R);
     ok &= c->g0.ensure(N * 4 * R) && c->g1.ensure(N * 4 * R);
     ok &= c->cell_hmax.ensure(N * 4);
+    ok &= c->sd0.ensure(N * sizeof(double4)) && c->sd1.ensure(N * sizeof(double4));
     ok &= c->qhead.ensure(16) && c->status.ensure(16);
     return ok;
 }
@@ -247,7 +252,8 @@ sph_status sph_destroy(sph_ctx* c)
     DBuf* all[] = {&c->boxes, &c->keys, &c->keys2, &c->vals, &c->vals2, &c->rs_scratch, &c->flag,
                    &c->cellx, &c->cell_of, &c->sc_scratch, &c->cells, &c->ncells, &c->cell_map,
                    &c->src, &c->src_count, &c->sidx, &c->srec, &c->rx, &c->ry, &c->rz, &c->h,
-                   &c->vm, &c->u, &c->g0, &c->g1, &c->cell_hmax, &c->qhead, &c->status, &c->step_tmp};
+                   &c->vm, &c->u, &c->g0, &c->g1, &c->cell_hmax, &c->qhead, &c->status, &c->step_tmp,
+                   &c->sd0, &c->sd1, &c->adj_ab, &c->adj_sb0, &c->adj_sb1, &c->adj_x, &c->adj_h, &c->adj_fg};
     for (DBuf* b : all) b->release();
     if (c->status_host) (void)hipHostFree(c->status_host);
     if (c->ncells_host) (void)hipHostFree(c->ncells_host);
@@ -559,6 +565,46 @@ sph_status sph_force(sph_ctx* c, const sph_particles* p, sph_force_out* o, void*
     return hipGetLastError() == hipSuccess ? SPH_OK : SPH_E_HIP;
 }
 
+extern "C++" {
+template <typename R>
+static sph_status backward_launch(sph_ctx* c, const sph_grad_in* gi, sph_grad_out* go, bool implicit_h,
+                                  hipStream_t st)
+{
+    using R4 = typename Vec4T<R>::T;
+    const size_t N = (size_t)c->n;
+    bool ok = c->adj_ab.ensure(N * sizeof(R4)) && c->adj_sb0.ensure(N * sizeof(R4)) &&
+              c->adj_sb1.ensure(N * sizeof(R4)) && c->adj_x.ensure(N * 3 * sizeof(double)) &&
+              c->adj_h.ensure(N * sizeof(double)) && c->adj_fg.ensure(N * sizeof(double4));
+    if (!ok) return SPH_E_OOM;
+    AdjData<R> ad;
+    ad.ab = c->adj_ab.as<R4>(); ad.sb0 = c->adj_sb0.as<R4>(); ad.sb1 = c->adj_sb1.as<R4>();
+    ad.xbar = c->adj_x.as<double>(); ad.hbar = c->adj_h.as<double>(); ad.fg = c->adj_fg.as<double4>();
+    AdjIO io;
+    io.g_rho = gi->rho; io.g_ax = gi->ax; io.g_ay = gi->ay; io.g_az = gi->az; io.g_dudt = gi->dudt;
+    io.gx = go->x; io.gy = go->y; io.gz = go->z; io.gh = go->h;
+    launch_adjoint<R>(decomp(c), cell_data<R>(c), sorted_data<R>(c), ghost_data<R>(c), ad, io, pass_consts(c->prm),
+                      implicit_h, c->n, st);
+    return SPH_OK;
+}
+}  // extern "C++"
+
+sph_status sph_backward(sph_ctx* c, const sph_particles* p, const sph_grad_in* gi, sph_grad_out* go,
+                        int implicit_h, void* stream)
+{
+    if (!c || !particles_ok(p) || !gi || !go) return SPH_E_INVALID_ARG;
+    if (!c->have_density || p->n != c->n) return SPH_E_STATE;
+    hipStream_t st = (hipStream_t)stream;
+    c->adj_timed = false;
+    if (c->n == 0) return SPH_OK;
+    ev_record(c, EV_ADJ0, st);
+    sph_status s = c->prm.precision == SPH_FP64 ? backward_launch<double>(c, gi, go, implicit_h != 0, st)
+                                                : backward_launch<float>(c, gi, go, implicit_h != 0, st);
+    if (s != SPH_OK) return s;
+    ev_record(c, EV_ADJ1, st);
+    c->adj_timed = c->timing;
+    return hipGetLastError() == hipSuccess ? SPH_OK : SPH_E_HIP;
+}
+
 sph_status sph_step(sph_ctx* c, sph_particles* p, const sph_batch* batch, sph_force_out* acc, double dt,
                     void* stream)
 {
@@ -678,6 +724,10 @@ sph_status sph_get_kernel_times(sph_ctx* c, sph_kernel_times* out)
         c->dens_async_timed = false;
     }
     out->density_ms = c->dens_ms_acc;
+    if (c->adj_timed) {
+        if (hipEventSynchronize(c->ev[EV_ADJ1]) != hipSuccess) return SPH_E_HIP;
+        (void)hipEventElapsedTime(&out->backward_ms, c->ev[EV_ADJ0], c->ev[EV_ADJ1]);
+    }
     return SPH_OK;
 }
 

@@ -44,6 +44,27 @@ struct GhostData {
     using R4 = typename Vec4T<R>::T;
     R4 *g0, *g1;
     float* cell_hmax;    // largest h of each cell
+    // sums kept for the adjoint (FP64, cell order; may be null):
+    // sd0 = (sum m w incl. self, sum m q w', dN/dh, sum m g dv.r), sd1 = (sum m g dv x r, 0)
+    double4 *sd0, *sd1;
+};
+
+// Per-particle adjoint data (cell order).
+template <typename R>
+struct AdjData {
+    using R4 = typename Vec4T<R>::T;
+    R4* ab;              // (dL/da_x, dL/da_y, dL/da_z, dL/d(du/dt))
+    R4* sb0;             // (dL/dS_mw, dL/dS_mqw', dL/dD, lambda)
+    R4* sb1;             // (dL/dC_x, dL/dC_y, dL/dC_z, 0)
+    double* xbar;        // dL/dx, 3 per particle
+    double* hbar;        // dL/dh (explicit)
+    double4* fg;         // (dL/dA, dL/drho from the force stage, dL/df, dL/drho from the caller)
+};
+
+// Caller-order upstream gradients and outputs of the adjoint.
+struct AdjIO {
+    const double *g_rho, *g_ax, *g_ay, *g_az, *g_dudt;
+    double *gx, *gy, *gz, *gh;
 };
 
 // Caller-order outputs of the density stage (any may be null).
@@ -110,6 +131,12 @@ void launch_force(const Decomp& dc, const CellData<R>& cd, const Sorted<R>& so, 
                   const ForceOut& out, const PassConsts& pc, int grid, hipStream_t st);
 int density_occupancy_grid(int precision);
 int force_occupancy_grid(int precision);
+
+// adjoint.hip
+template <typename R>
+void launch_adjoint(const Decomp& dc, const CellData<R>& cd, const Sorted<R>& so, const GhostData<R>& gd,
+                    const AdjData<R>& ad, const AdjIO& io, const PassConsts& pc, bool implicit_h, int64_t n,
+                    hipStream_t st);
 
 // step.hip
 void launch_kick(double* vx, double* vy, double* vz, double* u, const double* ax, const double* ay,

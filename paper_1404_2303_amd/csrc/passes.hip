@@ -35,279 +35,9 @@
 //
 // Arithmetic: pair terms in R (float or double); every per-particle sum and
 // the Newton step in double.
-#include "sph_internal.h"
-#include "kernels.h"
+#include "sweep.h"
 
 namespace sph {
-
-constexpr int NW = 4;                 // wavefronts per target cell
-constexpr int WGS = NW * kWave;
-constexpr int kMaxSegW = 28;          // staged segments per wavefront and batch
-constexpr int NACC_D = 9;             // density partial sums per target
-constexpr int NACC_F = 5;             // force partial sums per target
-constexpr int NACC_F_DEF = NACC_F;
-constexpr float kCacheSlack = 0.08f;  // neighbour lists cover h (1 + slack)
-
-// staged particles per wavefront and list slots per lane (density lists also
-// serve the Newton iteration, so they are longer)
-template <typename R, bool FORCE> struct PCfg;
-template <> struct PCfg<float, false> { static constexpr int CAPW = 256, LISTW = 48; };
-template <> struct PCfg<float, true> { static constexpr int CAPW = 256, LISTW = 32; };
-template <> struct PCfg<double, false> { static constexpr int CAPW = 256, LISTW = 48; };
-template <> struct PCfg<double, true> { static constexpr int CAPW = 256, LISTW = 32; };
-
-// share of the 26 neighbour directions per wavefront (2 bits per direction):
-// faces 2/2/1/1, edges 3/3/3/3, corners 1/1/3/3
-constexpr uint64_t kDirWavePacked = 0x507e90edb60faull;
-__device__ __forceinline__ int dir_wave(int d) { return (int)((kDirWavePacked >> (2 * d)) & 3u); }
-
-// square root and reciprocal of the pair arithmetic: the hardware
-// instructions in FP32 (about 1 ulp), correctly rounded in FP64
-template <typename R> __device__ __forceinline__ R fast_sqrt(R x);
-template <> __device__ __forceinline__ float fast_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
-template <> __device__ __forceinline__ double fast_sqrt<double>(double x) { return sqrt(x); }
-template <typename R> __device__ __forceinline__ R fast_rcp(R x);
-template <> __device__ __forceinline__ float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <> __device__ __forceinline__ double fast_rcp<double>(double x) { return 1.0 / x; }
-
-// ---------------------------------------------------------------- kernel W (Sec. 2.1)
-// w(q) = 1 - 6q^2 + 6q^3 (q <= 1/2), 2(1-q)^3 (1/2 < q <= 1); callers ensure q < 1.
-template <typename R> __device__ __forceinline__ R kern_w(R q)
-{
-    R a = (R)1 + q * q * ((R)6 * q - (R)6);
-    R t = (R)1 - q;
-    R b = (R)2 * t * t * t;
-    return q <= (R)0.5 ? a : b;
-}
-// w'(q)
-template <typename R> __device__ __forceinline__ R kern_dw(R q)
-{
-    R a = q * ((R)18 * q - (R)12);
-    R t = (R)1 - q;
-    R b = (R)-6 * t * t;
-    return q <= (R)0.5 ? a : b;
-}
-// g(q) = w'(q)/q, given qinv = 1/q (only read on the outer branch, q > 1/2)
-template <typename R> __device__ __forceinline__ R kern_g(R q, R qinv)
-{
-    R a = (R)18 * q - (R)12;
-    R t = (R)1 - q;
-    R b = (R)-6 * t * t * qinv;
-    return q <= (R)0.5 ? a : b;
-}
-
-__device__ __forceinline__ double wave_max(double v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-// LDS writes of one lane become visible to the other lanes of its wavefront
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// ---------------------------------------------------------------- LDS layout
-template <typename R, int NACC>
-struct Smem {
-    using R4 = typename Vec4T<R>::T;
-    static constexpr int CAPW = PCfg<R, NACC == NACC_F_DEF>::CAPW;
-    static constexpr int LISTW = PCfg<R, NACC == NACC_F_DEF>::LISTW;
-    R4 st[NW][CAPW];                  // staged (x, y, z in T's frame, projection on the segment axis)
-    R sh[NW][NACC == NACC_F_DEF ? CAPW : 1];  // force stage: h of each staged particle
-    uint32_t sg[NW][CAPW];            // cell-order index of each staged particle
-    uint16_t list[NW][LISTW][kWave];  // per-lane neighbour lists (staged indices)
-    double red[NACC][kWave];          // partial sums of the four wavefronts
-    double hsh[kWave];                // current h of each target (density)
-    int seg_b[NW][kMaxSegW], seg_e[NW][kMaxSegW];
-    float seg_u[NW][kMaxSegW][3];
-    float seg_hx[NW][kMaxSegW];       // force: largest h of the source cell
-    int nseg[NW];
-    int self_b[NW], self_t0[NW], self_n[NW];  // self segment: staged start, first cell index, count
-    int conv[kWave];
-    int ctl[4];                       // 0: all converged, 1: restage
-    int unit;
-};
-
-// Stage, for wavefront w, its sources from cursor (k, p) on; advance the
-// cursor past what was staged (k == nsrc when every source is staged).
-template <typename R, bool FORCE, int NACC>
-__device__ void stage_wave(Smem<R, NACC>& s, const int w, const Decomp& dc, const CellData<R>& cd,
-                           const Sorted<R>& so, const GhostData<R>& gd, const BoxInfo& B, const int tcell,
-                           const int nsrc, int& k, int& p, const float Hst, const float margin)
-{
-    using R4 = typename Vec4T<R>::T;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int CAPW = Smem<R, NACC>::CAPW;
-    int fill = 0, nseg = 0;
-    wave_sync();  // earlier readers of this wavefront's staging area are done
-    // lane-parallel view of the source list (at most 27 entries)
-    Source my = {};
-    if (lane < nsrc) my = dc.src[(int64_t)tcell * kMaxSources + lane];
-    const bool mine = lane < nsrc && (my.dir == kSelfDir || dir_wave(my.dir) == w);
-    const uint64_t mask = __ballot(mine);
-    if (lane == 0) s.self_n[w] = 0;
-    while (true) {
-        const uint64_t m = k >= 64 ? 0ull : (mask & (~0ull << k));
-        if (m == 0) { k = nsrc; p = 0; break; }
-        k = __builtin_ctzll(m);
-        if (nseg == kMaxSegW || fill >= CAPW) break;
-        const int scell = __shfl(my.cell, k, 64);
-        const int sdir = __shfl((int)my.dir, k, 64);
-        const bool self = sdir == kSelfDir;
-        const CellInfo S = dc.cells[scell];
-        const int segb = fill;
-        bool complete = true;
-        float u[3] = {0.f, 0.f, 0.f};
-        float hx = 0.f;
-        if (self) {
-            const int q0 = (S.count * w) / NW, q1 = (S.count * (w + 1)) / NW;
-            const int n = q1 - q0 - p;
-            const int take = min(n, CAPW - fill);
-            for (int t = lane; t < take; t += kWave) {
-                const int g = S.start + q0 + p + t;
-                R4 e;
-                e.x = cd.rx[g]; e.y = cd.ry[g]; e.z = cd.rz[g];
-                e.w = (R)0;
-                s.st[w][fill + t] = e;
-                if constexpr (FORCE) s.sh[w][fill + t] = gd.g1[g].z;
-                s.sg[w][fill + t] = (uint32_t)g;
-            }
-            if (lane == 0) { s.self_b[w] = fill; s.self_t0[w] = q0 + p; s.self_n[w] = take; }
-            fill += take;
-            if (take < n) { complete = false; p += take; }
-        } else {
-            int o[3];
-            dir_off(sdir, o);
-            dir_unit(sdir, u);
-            const int sd = dir_sort(sdir);
-            const bool flip = dir_flip(sdir);
-            const R dox = (R)(o[0] * B.e[0]), doy = (R)(o[1] * B.e[1]), doz = (R)(o[2] * B.e[2]);
-            const float udo = u[0] * (float)(o[0] * B.e[0]) + u[1] * (float)(o[1] * B.e[1]) +
-                              u[2] * (float)(o[2] * B.e[2]);
-            float hs = Hst;
-            if (FORCE) { hx = gd.cell_hmax[scell]; hs = fmaxf(Hst, hx); }
-            const float reach = fmaxf(u[0], 0.f) * (float)B.e[0] + fmaxf(u[1], 0.f) * (float)B.e[1] +
-                                fmaxf(u[2], 0.f) * (float)B.e[2] + hs + margin;
-            const int64_t sbase = (int64_t)sd * dc.n + S.start;
-            while (p < S.count) {
-                const int pos = p + lane;
-                bool ok = false;
-                R4 r = {};
-                int l = 0;
-                if (pos < S.count) {
-                    const int idx = flip ? (S.count - 1 - pos) : pos;
-                    r = so.rec[sbase + idx];
-                    l = so.idx[sbase + idx];
-                    const float proj = (flip ? -(float)r.w : (float)r.w) + udo;
-                    ok = proj <= reach;
-                }
-                const int cnt = __popcll(__ballot(ok));  // projections are monotone: a prefix
-                const int take = min(cnt, CAPW - fill);
-                if (lane < take) {
-                    const int g = S.start + l;
-                    R4 e;
-                    e.x = r.x + dox; e.y = r.y + doy; e.z = r.z + doz;
-                    // projection on the segment axis, recomputed from the shifted position
-                    e.w = (R)(u[0] * (float)e.x + u[1] * (float)e.y + u[2] * (float)e.z);
-                    s.st[w][fill + lane] = e;
-                    if constexpr (FORCE) s.sh[w][fill + lane] = gd.g1[g].z;
-                    s.sg[w][fill + lane] = (uint32_t)g;
-                }
-                fill += take;
-                p += take;
-                if (take < cnt) { complete = false; break; }  // out of room
-                if (cnt < kWave) { p = S.count; break; }       // the prefix ended
-            }
-        }
-        if (lane == 0) {
-            s.seg_b[w][nseg] = segb;
-            s.seg_e[w][nseg] = fill;
-            s.seg_u[w][nseg][0] = u[0]; s.seg_u[w][nseg][1] = u[1]; s.seg_u[w][nseg][2] = u[2];
-            s.seg_hx[w][nseg] = hx;
-        }
-        nseg++;
-        if (!complete) break;
-        k++;
-        p = 0;
-    }
-    if (lane == 0) s.nseg[w] = nseg;
-    wave_sync();
-}
-
-// Staged index of the lane's own particle in wavefront w's self segment, or -1.
-template <typename R, int NACC>
-__device__ __forceinline__ int self_index(const Smem<R, NACC>& s, int w, int ti)
-{
-    const int d = ti - s.self_t0[w];
-    return (d >= 0 && d < s.self_n[w]) ? s.self_b[w] + d : -1;
-}
-
-// Walk of wavefront w over its staged segments, one segment at a time for
-// all lanes together: every lane reads the same staged particle (an LDS
-// broadcast), tests it against its own bound and radius, and appends it to
-// its list when in range.  The segment is left as soon as no lane is still
-// within its projected bound (the early exit of the sorted sweep).  The
-// walk state (seg, jj) is uniform; the call returns early when some lane's
-// list might overflow in the next step, and resumes from (seg, jj).
-template <typename R, bool FORCE, int NACC>
-__device__ __forceinline__ int walk(Smem<R, NACC>& s, int w, int lane, bool act, R xi, R yi, R zi, float fxi,
-                                    float fyi, float fzi, R rad, float fh, float margin, int selfj, int& seg_io,
-                                    int& jj_io, int cnt)
-{
-    constexpr int LISTW = Smem<R, NACC>::LISTW;
-    const int nseg = s.nseg[w];
-    const R rad2 = rad * rad;
-    int seg = __builtin_amdgcn_readfirstlane(seg_io);
-    int jj = __builtin_amdgcn_readfirstlane(jj_io);
-    uint16_t* lst = &s.list[w][0][lane];
-    while (seg < nseg) {
-        const int je = s.seg_e[w][seg];
-        const float ux = s.seg_u[w][seg][0], uy = s.seg_u[w][seg][1], uz = s.seg_u[w][seg][2];
-        const float hx = s.seg_hx[w][seg];
-        const bool self = (ux == 0.0f) & (uy == 0.0f) & (uz == 0.0f);
-        const float bound = !act ? -INFINITY : (self ? INFINITY : ux * fxi + uy * fyi + uz * fzi + fmaxf(fh, hx) + margin);
-        bool more = true;
-        for (; jj < je; jj += 2) {
-            // two staged particles per step (the second may lie past the segment end)
-            const bool two = jj + 1 < je;
-            const auto e0 = s.st[w][jj];
-            const auto e1 = s.st[w][two ? jj + 1 : jj];
-            const float p0 = (float)e0.w, p1 = (float)e1.w;
-            const bool in0 = p0 <= bound;
-            const bool in1 = (p1 <= bound) & two;
-            if (!__any(in0)) { more = false; break; }
-            const R dx0 = xi - e0.x, dy0 = yi - e0.y, dz0 = zi - e0.z;
-            const R dx1 = xi - e1.x, dy1 = yi - e1.y, dz1 = zi - e1.z;
-            const R r20 = dx0 * dx0 + dy0 * dy0 + dz0 * dz0;
-            const R r21 = dx1 * dx1 + dy1 * dy1 + dz1 * dz1;
-            R l0 = rad2, l1 = rad2;
-            if constexpr (FORCE) {
-                const R hm0 = rad > s.sh[w][jj] ? rad : s.sh[w][jj];
-                const R hm1 = rad > s.sh[w][jj + (two ? 1 : 0)] ? rad : s.sh[w][jj + (two ? 1 : 0)];
-                l0 = hm0 * hm0; l1 = hm1 * hm1;
-            }
-            const bool hit0 = in0 & (r20 < l0) & (jj != selfj);
-            const bool hit1 = in1 & (r21 < l1) & (jj + 1 != selfj);
-            lst[cnt * kWave] = (uint16_t)jj;        // slot cnt is free; kept only on a hit
-            cnt += hit0 ? 1 : 0;
-            lst[cnt * kWave] = (uint16_t)(jj + 1);
-            cnt += hit1 ? 1 : 0;
-            if (!__any(in1)) { more = false; jj += 2; break; }
-            if (__any(cnt > LISTW - 2)) { jj += 2; seg_io = seg; jj_io = jj; return cnt; }
-        }
-        (void)more;
-        seg++;
-        jj = seg < nseg ? s.seg_b[w][seg] : 0;
-    }
-    seg_io = seg;
-    jj_io = jj;
-    return cnt;
-}
-
 // ---------------------------------------------------------------- density
 struct DensAcc {
     double w, qdw, mw, mqdw, div, cx, cy, cz, n;
@@ -362,7 +92,7 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
                                                  DensityOut out, PassConsts pc)
 {
     using R4 = typename Vec4T<R>::T;
-    using SM = Smem<R, NACC_D>;
+    using SM = Smem<R, NACC_D, false>;
     constexpr int LISTW = SM::LISTW;
     __shared__ SM s;
     const int tid = threadIdx.x;
@@ -586,6 +316,10 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
                 g1.x = (R)c; g1.y = (R)bal; g1.z = (R)h; g1.w = (R)0;
                 gd.g0[gi] = g0;
                 gd.g1[gi] = g1;
+                if (gd.sd0) {
+                    gd.sd0[gi] = make_double4(tot.mw + m, tot.mqdw, -32.0 / 3.0 / h * tot.qdw, tot.div);
+                    gd.sd1[gi] = make_double4(tot.cx, tot.cy, tot.cz, 0.0);
+                }
                 const uint32_t pi = dc.perm[gi];
                 if (out.h) out.h[pi] = h_rebuild > 0.0 ? h_rebuild : h;
                 if (out.rho) out.rho[pi] = rho;
@@ -662,7 +396,7 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
                                                ForceOut out, PassConsts pc)
 {
     using R4 = typename Vec4T<R>::T;
-    using SM = Smem<R, NACC_F>;
+    using SM = Smem<R, NACC_F, true>;
     __shared__ SM s;
     const int tid = threadIdx.x;
     const int w = tid >> 6;

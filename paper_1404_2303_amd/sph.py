@@ -3,7 +3,8 @@
 Torch tensors provide device memory and the stream; every computation runs in
 the HIP kernels of libsph_mi355x.so.  The low-level functions carry the C
 names (``sph_create``, ``sph_build_cells``, ``sph_sort``, ``sph_density``,
-``sph_force``, ``sph_step``); :class:`Context` wraps them for tensors.
+``sph_force``, ``sph_step``, ``sph_backward``); :class:`Context` wraps them
+for tensors and :class:`SPHPass` exposes the pass to torch.autograd.
 There is no fallback: if the library is missing, loading raises.
 """
 from __future__ import annotations
@@ -25,7 +26,7 @@ SPH_FP64, SPH_FP32_ACC64 = 0, 1
 EXPORTED = ["sph_default_params", "sph_create", "sph_destroy", "sph_build_cells", "sph_sort",
             "sph_density", "sph_force", "sph_step", "sph_get_stats", "sph_status_string",
             "sph_enable_timing", "sph_get_kernel_times", "sph_density_async", "sph_check",
-            "sph_graph_capture", "sph_graph_launch"]
+            "sph_graph_capture", "sph_graph_launch", "sph_backward"]
 
 P = ctypes.c_void_p
 
@@ -56,11 +57,19 @@ class sph_density_out(ctypes.Structure):
 
 class sph_kernel_times(ctypes.Structure):
     _fields_ = [("build_ms", ctypes.c_float), ("sort_ms", ctypes.c_float), ("density_ms", ctypes.c_float),
-                ("force_ms", ctypes.c_float)]
+                ("force_ms", ctypes.c_float), ("backward_ms", ctypes.c_float)]
 
 
 class sph_force_out(ctypes.Structure):
     _fields_ = [(k, P) for k in ("ax", "ay", "az", "dudt", "n_pairs")]
+
+
+class sph_grad_in(ctypes.Structure):
+    _fields_ = [(k, P) for k in ("rho", "ax", "ay", "az", "dudt")]
+
+
+class sph_grad_out(ctypes.Structure):
+    _fields_ = [(k, P) for k in ("x", "y", "z", "h")]
 
 
 class sph_stats(ctypes.Structure):
@@ -112,6 +121,9 @@ def load_library():
                                           ctypes.POINTER(sph_density_out), ctypes.POINTER(sph_force_out), P]
         lib.sph_graph_launch.restype = st
         lib.sph_graph_launch.argtypes = [P, P]
+        lib.sph_backward.restype = st
+        lib.sph_backward.argtypes = [P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_grad_in),
+                                     ctypes.POINTER(sph_grad_out), ctypes.c_int, P]
         lib.sph_status_string.restype = ctypes.c_char_p
         lib.sph_status_string.argtypes = [st]
         _lib = lib
@@ -199,6 +211,11 @@ def sph_graph_launch(ctx, stream):
     return load_library().sph_graph_launch(ctx, stream)
 
 
+def sph_backward(ctx, parts: sph_particles, gin: sph_grad_in, gout: sph_grad_out, implicit_h: int, stream):
+    return load_library().sph_backward(ctx, ctypes.byref(parts), ctypes.byref(gin), ctypes.byref(gout),
+                                       int(implicit_h), stream)
+
+
 # ---------------------------------------------------------------- tensor layer
 @dataclass
 class Particles:
@@ -233,6 +250,10 @@ class Particles:
                 raise ValueError(f"particle field {k} must be a contiguous float64 CUDA tensor of length n")
         return sph_particles(self.n, *[_ptr(getattr(self, k)) for k in
                                        ("x", "y", "z", "vx", "vy", "vz", "u", "m", "h")])
+
+
+def _as_f64(t):
+    return None if t is None else t.to(torch.float64).contiguous()
 
 
 class Batch:
@@ -311,13 +332,32 @@ class Context:
         return _check(sph_step(self.ctx, parts.c_struct(), batch.c if batch else None, c, dt, _stream()),
                       "sph_step", (SPH_E_NOT_CONVERGED,))
 
+    def backward(self, parts: Particles, g_rho=None, g_a=None, g_dudt=None, implicit_h=True, want_h=False):
+        """Gradients of L at the state of the last density(): dL/dx as (N,3) and, if want_h
+        (fixed h only), dL/dh.  g_a is (N,3) or None; missing upstream gradients count as 0."""
+        n = parts.n
+        dev = parts.x.device
+
+        def col(t, k):
+            return None if t is None else t[:, k].contiguous()
+
+        keep = [_as_f64(g_rho), col(g_a, 0), col(g_a, 1), col(g_a, 2), _as_f64(g_dudt)]
+        gin = sph_grad_in(*[_ptr(t) for t in keep])
+        gx, gy, gz = (torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3))
+        gh = torch.empty(n, dtype=torch.float64, device=dev) if want_h else None
+        gout = sph_grad_out(_ptr(gx), _ptr(gy), _ptr(gz), _ptr(gh))
+        _check(sph_backward(self.ctx, parts.c_struct(), gin, gout, int(bool(implicit_h)), _stream()), "sph_backward")
+        gpos = torch.stack([gx, gy, gz], dim=1)
+        return (gpos, gh) if want_h else gpos
+
     def enable_timing(self, on=True):
         _check(load_library().sph_enable_timing(self.ctx, int(on)), "sph_enable_timing")
 
     def kernel_times(self) -> dict:
         t = sph_kernel_times()
         _check(load_library().sph_get_kernel_times(self.ctx, ctypes.byref(t)), "sph_get_kernel_times")
-        return {"build_ms": t.build_ms, "sort_ms": t.sort_ms, "density_ms": t.density_ms, "force_ms": t.force_ms}
+        return {"build_ms": t.build_ms, "sort_ms": t.sort_ms, "density_ms": t.density_ms, "force_ms": t.force_ms,
+                "backward_ms": t.backward_ms}
 
     def check(self, allow_unconverged=False):
         allow = (SPH_E_NOT_CONVERGED,) if allow_unconverged else ()
@@ -360,3 +400,34 @@ class Context:
         d = self.density(parts, allow_unconverged=allow_unconverged)
         f = self.force(parts)
         return d, f
+
+
+class SPHPass(torch.autograd.Function):
+    """rho, a (N,3) and du/dt of one pass as a differentiable function of the
+    positions pos (N,3), with h the solved root of Eq. (3) (its dependence on
+    the positions enters through the implicit derivative).
+
+    SPHPass.apply(pos, vel, m, u, h0, context) runs build, sort, density (h
+    solved from the guess h0) and force through ``context``; backward calls
+    sph_backward.  The solved h is left in context.last_h.  Velocities,
+    masses and u are treated as constants.
+    """
+
+    @staticmethod
+    def forward(fctx, pos, vel, m, u, h0, context: "Context"):
+        pos = pos.detach().to(torch.float64)
+        vel = vel.detach().to(torch.float64)
+        parts = Particles(x=pos[:, 0].contiguous(), y=pos[:, 1].contiguous(), z=pos[:, 2].contiguous(),
+                          vx=vel[:, 0].contiguous(), vy=vel[:, 1].contiguous(), vz=vel[:, 2].contiguous(),
+                          u=_as_f64(u.detach()), m=_as_f64(m.detach()), h=h0.detach().to(torch.float64).clone())
+        d, f = context.run(parts)
+        context.last_h = parts.h
+        fctx.context = context
+        fctx.parts = parts
+        a = torch.stack([f["ax"], f["ay"], f["az"]], dim=1)
+        return d["rho"], a, f["dudt"]
+
+    @staticmethod
+    def backward(fctx, g_rho, g_a, g_dudt):
+        gpos = fctx.context.backward(fctx.parts, g_rho, g_a, g_dudt, implicit_h=True)
+        return gpos, None, None, None, None, None

@@ -51,6 +51,36 @@ def test_jittered_lattice(precision):
     compare(g, ref, precision, label="lattice16")
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_particle_in_a_void(precision):
+    # one particle at the centre of an empty sphere: its h is the largest and its
+    # ~100 pairs overflow the per-lane neighbour lists several times, across
+    # segment boundaries
+    ps = workloads.uniform(3000, seed=31, sigma_v=0.3)
+    c = np.array([0.5, 0.5, 0.5])
+    keep = np.linalg.norm(ps.pos - c, axis=1) > 0.12
+    n = int(keep.sum()) + 1
+    ps = workloads.ParticleSet(pos=np.concatenate([ps.pos[keep], c[None]]),
+                               vel=np.concatenate([ps.vel[keep], np.zeros((1, 3))]),
+                               m=np.full(n, 1.0 / n), u=np.ones(n), h0=np.full(n, ps.h0[0]), box=ps.box,
+                               name="void")
+    log(f"case void {n} {precision}")
+    ref = oracle_run(ps)
+    assert ref["force"]["count"][-1] > 100
+    g = gpu_run(ps, precision)
+    compare(g, ref, precision, label="void")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_isolated_particle_many_pairs(precision):
+    # uniform set whose sparsest particle has h = 2x the smallest and 74 pairs
+    ps = workloads.uniform(1200, seed=17, sigma_v=0.4)
+    log(f"case uniform 1200 seed 17 {precision}")
+    ref = oracle_run(ps)
+    g = gpu_run(ps, precision)
+    compare(g, ref, precision, label="u1200")
+
+
 def test_tiny_three_cells_per_dimension():
     ps = workloads.uniform(800, seed=3, sigma_v=0.2)
     log("case tiny 800 fp64")

@@ -77,3 +77,38 @@ def test_loss_is_translation_invariant():
     ps, rt = _state(300, 7)
     gx, _, _, _ = og.gradients(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box, rt, solve=True)
     assert np.max(np.abs(gx.sum(0))) <= 1e-9 * np.sum(np.abs(gx))
+
+
+def _weights(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.normal(size=n), rng.normal(size=(n, 3)), rng.normal(size=n)
+
+
+@pytest.mark.parametrize("solve", [False, True])
+def test_vjp_matches_central_differences(solve):
+    # L = sum g_rho rho + g_a . a + g_u du/dt: the vector-Jacobian product the adjoint computes
+    ps, _ = _state(300, 11)
+    w = _weights(ps.n, 4)
+    h = ps.h0 if solve else oracle.solve_h(ps.pos, ps.h0, ps.box)[0] * 0.99
+    gx, gh, _, _ = og.vjp(ps.pos, ps.vel, ps.m, ps.u, h, ps.box, *w, solve=solve)
+    rng = np.random.default_rng(1)
+    scale = np.max(np.abs(gx))
+    for k in rng.choice(ps.n, 5, replace=False):
+        for ax in range(3):
+            fd = og.loss_fd(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box, None, k, ax, 1e-6, solve=solve,
+                            h_fixed=None if solve else h, weights=w)
+            assert abs(fd - gx[k, ax]) <= 1e-5 * (abs(gx[k, ax]) + 1e-3 * scale), (k, ax, fd, gx[k, ax])
+    if not solve:
+        for k in rng.choice(ps.n, 4, replace=False):
+            fd = og.loss_fd_h(ps.pos, ps.vel, ps.m, ps.u, h, ps.box, None, k, 1e-7, weights=w)
+            assert abs(fd - gh[k]) <= 1e-5 * (abs(gh[k]) + 1e-3 * np.max(np.abs(gh))), (k, fd, gh[k])
+
+
+def test_local_h_differences_equal_global_ones():
+    ps, rt = _state(600, 19)
+    hs, _ = oracle.solve_h(ps.pos, ps.h0, ps.box, tol=1e-13)
+    R = 2.2 * hs.max()
+    for k in (5, 301):
+        g = og.loss_fd_h(ps.pos, ps.vel, ps.m, ps.u, hs, ps.box, rt, k, 1e-7)
+        l = og.loss_fd_h(ps.pos, ps.vel, ps.m, ps.u, hs, ps.box, rt, k, 1e-7, local=R)
+        assert abs(g - l) <= 1e-6 * max(1.0, abs(g))
