@@ -16,6 +16,8 @@ function names the part of Gonnet (2014) it evaluates:
 * :func:`force` -- Eqs. (4)-(5) plus the Monaghan-Balsara viscosity, Sec. 4.1.
 * :func:`full_pass` -- the two stages in the paper's order (Sec. 2.1:
   density for all particles first, then force).
+* :func:`kdk_step` -- one kick-drift-kick velocity-Verlet step with a fixed
+  time step (the integrator of Sec. 4.1).
 """
 from __future__ import annotations
 
@@ -240,3 +242,27 @@ def full_pass(pos, vel, m, u, h0, box, target=N_NGB, tol=1e-10, maxit=100,
     frc = force(pos, vel, m, h, dens["rho"], gh["A"], gh["c"], gh["f"], box, alpha=alpha,
                 sel=force_sel)
     return {"h": h, "iters": iters, "dens": dens, "ghost": gh, "force": frc}
+
+
+def kdk_step(pos, vel, m, u, h, box, a_old, dudt_old, dt, target=N_NGB, tol=1e-10, gamma=GAMMA, alpha=ALPHA):
+    """One kick-drift-kick step (Sec. 4.1 names velocity Verlet with a fixed
+    step).  The forces at the new positions need velocities and energies at
+    the new time, which the kick has not produced yet; they are predicted
+    with the old accelerations (v_half + dt/2 a_old, u_half + dt/2 dudt_old).
+
+    Returns a dict with the new pos (wrapped into the box), vel, u, the solved
+    h (h is the initial guess), and the new a and du/dt.
+    """
+    box = np.asarray(box, dtype=np.float64)
+    hdt = 0.5 * dt
+    v_half = np.asarray(vel, dtype=np.float64) + hdt * np.asarray(a_old, dtype=np.float64)
+    u_half = np.asarray(u, dtype=np.float64) + hdt * np.asarray(dudt_old, dtype=np.float64)
+    x_new = np.mod(np.asarray(pos, dtype=np.float64) + dt * v_half, box)
+    x_new = np.where(x_new >= box, x_new - box, x_new)
+    v_pred = v_half + hdt * np.asarray(a_old, dtype=np.float64)
+    u_pred = u_half + hdt * np.asarray(dudt_old, dtype=np.float64)
+    out = full_pass(x_new, v_pred, m, u_pred, h, box, target=target, tol=tol, gamma=gamma, alpha=alpha)
+    a_new = out["force"]["a"]
+    du_new = out["force"]["dudt"]
+    return {"pos": x_new, "vel": v_half + hdt * a_new, "u": u_half + hdt * du_new, "h": out["h"],
+            "a": a_new, "dudt": du_new}
