@@ -92,8 +92,9 @@ def run_form(ps, precision, steps, warmup):
         end.record()
         end.synchronize()
         step_ms.append(start.elapsed_time(end))
-        for k, v in ctx.kernel_times().items():
-            kt[k].append(v)
+        times = ctx.kernel_times()
+        for k in kt:
+            kt[k].append(times[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     # counts from one more pass over the same input
@@ -210,6 +211,55 @@ def batched_section(steps, warmup, tune=True):
             "tuned": tuned}
 
 
+def adjoint_section(steps, warmup):
+    """Reverse mode on the 64^3 jittered lattice (262,144 particles, FP32 pair
+    arithmetic): loss sum (rho - rho_t)^2 + sum |a|^2; the forward pass once,
+    then sph_backward with the implicit h derivative timed alone and a full
+    forward + backward step timed together."""
+    import torch
+    from paper_1404_2303_amd import sph, workloads
+    ps = workloads.config4()
+    rt = torch.as_tensor(workloads.density_target(ps.pos, float(np.sum(ps.m))), device="cuda:0")
+    parts = sph.Particles.from_numpy(ps, "cuda:0")
+    h0 = parts.h.clone()
+    ctx = sph.Context(ps.box, precision="fp32")
+    ctx.enable_timing(True)
+
+    def forward():
+        parts.h.copy_(h0)
+        d, f = ctx.run(parts)
+        return d, f
+
+    def backward(d, f):
+        a = torch.stack([f["ax"], f["ay"], f["az"]], 1)
+        return ctx.backward(parts, 2 * (d["rho"] - rt), 2 * a, None, implicit_h=True)
+
+    d, f = forward()
+    for _ in range(warmup):
+        backward(d, f)
+    torch.cuda.synchronize()
+    bw = []
+    for _ in range(steps):
+        backward(d, f)
+        bw.append(ctx.kernel_times()["backward_ms"])
+    P = int(f["n_pairs"].sum().item())
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fb = []
+    for _ in range(max(3, steps // 2)):
+        start.record()
+        d, f = forward()
+        backward(d, f)
+        end.record()
+        end.synchronize()
+        fb.append(start.elapsed_time(end))
+    ctx.close()
+    bms = float(np.median(bw))
+    return {"workload": "jittered cubic lattice 64^3 (262,144 particles), spacing 1/64, unit box, v~N(0,0.1); "
+                        "loss sum (rho-rho_t)^2 + sum |a|^2, gradient in x through the solved h",
+            "n": ps.n, "pairs": P, "backward_ms": bms, "backward_pairs_per_s": P / (bms * 1e-3),
+            "forward_backward_ms": float(np.median(fb))}
+
+
 class _BatchArgs:
     """Adapter: a Batch built lazily inside the timer (keeps host arrays alive)."""
 
@@ -256,6 +306,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 (plain) form")
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-box batched workload")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -312,6 +363,9 @@ def main():
     if not args.no_batched:
         line["batched"] = batched_section(max(3, args.steps // 4), 2)
         log("batched:", json.dumps(line["batched"]))
+    if not args.no_adjoint:
+        line["adjoint"] = adjoint_section(args.steps, args.warmup)
+        log("adjoint:", json.dumps(line["adjoint"]))
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
