@@ -78,10 +78,16 @@ typedef struct {
                             this fraction during the iteration without a rebuild */
     int max_rebuilds;    /* sph_density rebuilds the cells at most this often when an h
                             outgrows them */
+    int max_depth;       /* hierarchical decomposition (Sec. 3.2): levels of bisection allowed
+                            below the top grid; 0 keeps the single-level grid.  Capped at 12
+                            and by the 64-bit keys. */
+    int split_count;     /* a cell is split when it holds more than this many particles ... */
+    double split_frac;   /* ... and at least this fraction of them has h below half its edge */
 } sph_params;
 
 /* Default parameters: the paper's constants (48, 5/3, 0.8, 1e-4), FP32_ACC64,
- * cell_target 64, h_margin 0.1, max_iter 64, max_rebuilds 4, unit box. */
+ * cell_target 64, h_margin 0.1, max_iter 64, max_rebuilds 4, unit box,
+ * max_depth 0 (single-level grid), split_count 64, split_frac 0.875. */
 void sph_default_params(sph_params *p);
 
 typedef struct {
@@ -137,14 +143,30 @@ sph_status sph_destroy(sph_ctx *ctx);
  * (1+h_margin) max h, keys each particle by the Morton code of its cell,
  * radix-sorts the keys, and forms cells as runs of equal keys, their
  * neighbour lists (self + 26 neighbours, periodic images included) and
- * cell-ordered copies of the particle data.  batch may be NULL (one box of
- * params.box).  Reads x, y, z, v, u, m, h.  Does not synchronise: the
+ * cell-ordered copies of the particle data.  With max_depth > 0 the keys
+ * encode cells down to max_depth bisections of the top cells, a cell is split
+ * while it holds more than split_count particles of which at least split_frac
+ * have h below half its edge, and the cells are the leaves of that
+ * hierarchy; each leaf's list then holds every leaf whose box lies within
+ * the largest h either cell covers (so every pair in range is listed).
+ * batch may be NULL (one box of params.box).  Reads x, y, z, v, u, m, h.  Does not synchronise: the
  * checks that run on the device (non-finite data, h too large for the box,
  * capacity) are reported by the next sph_density.  Errors returned here:
  * SPH_E_INVALID_ARG, SPH_E_CAPACITY (key or map too large), SPH_E_OOM,
  * SPH_E_HIP. */
 sph_status sph_build_cells(sph_ctx *ctx, const sph_particles *p, const sph_batch *batch,
                            void *stream);
+
+/* Initial smoothing lengths for particles without a usable guess: builds the
+ * hierarchy of cells down to max_depth levels (params.max_depth >= 1) with
+ * the current h only for the top grid, and sets every h from the local
+ * number density n_loc: h = (3 n_ngb / (4 pi n_loc))^(1/3), n_loc being the
+ * count over the volume of the smallest cell around the particle that holds
+ * at least 2 n_ngb particles.  Writes p->h; the decomposition it builds is
+ * not kept (call sph_build_cells afterwards).  Does not synchronise.
+ * Errors: SPH_E_INVALID_ARG (also max_depth == 0), SPH_E_CAPACITY, SPH_E_OOM,
+ * SPH_E_HIP. */
+sph_status sph_estimate_h(sph_ctx *ctx, sph_particles *p, const sph_batch *batch, void *stream);
 
 /* The 13 per-cell orderings of Sec. 3.3: for each cell and each of the 13
  * axis directions d (the other 13 of the 26 cell-pair axes are their
@@ -247,6 +269,7 @@ typedef struct {
     int32_t rebuilds;        /* rebuilds done by the last sph_density */
     int32_t max_iter_used;   /* largest Newton count of the last sph_density */
     int32_t unconverged;     /* particles left unconverged by the last sph_density */
+    int32_t depth;           /* levels below the top grid in the keys of the last build */
 } sph_stats;
 
 sph_status sph_get_stats(const sph_ctx *ctx, sph_stats *out);

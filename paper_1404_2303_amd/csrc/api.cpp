@@ -52,6 +52,12 @@ struct sph_ctx {
     DBuf rx, ry, rz, h, vm, u;                       // cell order
     DBuf g0, g1, cell_hmax;                          // ghost quantities, cell order
     DBuf sd0, sd1;                                   // density sums kept for the adjoint
+    DBuf src_off;                                    // first source of each cell
+    // hierarchy (max_depth > 0)
+    DBuf t_chg, t_node_of, t_node_start, t_node_flag, t_node_hmax, t_node_H, t_node_leaf, t_nnodes;
+    DBuf t_flag, t_scan, t_small, t_psmall, t_lev;
+    int depth = 0;                                   // levels below the top grid of the current build
+    int64_t src_cap = 0;
     DBuf adj_ab, adj_sb0, adj_sb1, adj_x, adj_h, adj_fg;  // adjoint workspace
     DBuf qhead, status;
     DBuf step_tmp;                                   // predicted v, u; new a, du/dt
@@ -129,6 +135,7 @@ static Decomp decomp(sph_ctx* c)
     d.ncells = c->ncells.as<int32_t>();
     d.boxes = c->boxes.as<BoxInfo>();
     d.src = c->src.as<Source>();
+    d.src_off = c->src_off.as<int32_t>();
     d.src_count = c->src_count.as<int32_t>();
     d.perm = c->vals.as<uint32_t>();
     d.n = c->n;
@@ -162,7 +169,20 @@ static bool ensure_particles(sph_ctx* c, int64_t n)
     ok &= c->flag.ensure(N * 4) && c->cellx.ensure(N * 4) && c->cell_of.ensure(N * 4);
     ok &= c->sc_scratch.ensure(scan_scratch_words((int64_t)N) * 4 + 16);
     ok &= c->cells.ensure(N * sizeof(CellInfo)) && c->ncells.ensure(16);
-    ok &= c->src.ensure(N * kMaxSources * sizeof(Source)) && c->src_count.ensure(N * 4);
+    // interaction lists: 27 per cell on the single-level grid; on the hierarchy
+    // a bound per particle (exceeding it sets SPH_E_CAPACITY)
+    c->src_cap = (int64_t)N * (c->depth > 0 ? kTreeSourcesPerParticle : kMaxSources);
+    ok &= c->src.ensure((size_t)c->src_cap * sizeof(Source)) && c->src_count.ensure(N * 4);
+    ok &= c->src_off.ensure(N * 4);
+    if (c->depth > 0) {
+        const size_t L = (size_t)c->depth + 1, S = N + 1;
+        ok &= c->t_chg.ensure(N) && c->t_lev.ensure(N);
+        ok &= c->t_node_of.ensure(L * N * 4) && c->t_node_start.ensure(L * S * 4);
+        ok &= c->t_node_flag.ensure(L * S) && c->t_node_hmax.ensure(L * S * 4) && c->t_node_H.ensure(L * S * 4);
+        ok &= c->t_node_leaf.ensure(L * S * 4) && c->t_nnodes.ensure(L * 4 + 16);
+        ok &= c->t_flag.ensure(N * 4) && c->t_scan.ensure(S * 4);
+        ok &= c->t_small.ensure(N * 4) && c->t_psmall.ensure(S * 4);
+    }
     ok &= c->sidx.ensure(N * kSortDirs * 2) && c->srec.ensure(N * kSortDirs * 4 * R);
     ok &= c->rx.ensure(N * R) && c->ry.ensure(N * R) && c->rz.ensure(N * R);
     ok &= c->h.ensure(N * 8) && c->u.ensure(N * 8);
@@ -191,6 +211,9 @@ void sph_default_params(sph_params* p)
     p->cell_target = 64;
     p->h_margin = 0.1;
     p->max_rebuilds = 4;
+    p->max_depth = 0;
+    p->split_count = 64;
+    p->split_frac = 0.875;
 }
 
 const char* sph_status_string(sph_status s)
@@ -222,6 +245,7 @@ static bool params_ok(const sph_params& p)
     if (p.cell_target < 1) return false;
     if (!(p.h_margin >= 0) || !(p.h_margin < 10)) return false;
     if (p.max_rebuilds < 0) return false;
+    if (p.max_depth < 0 || p.split_count < 1 || !(p.split_frac >= 0.0) || !(p.split_frac <= 1.0)) return false;
     return true;
 }
 
@@ -253,7 +277,10 @@ sph_status sph_destroy(sph_ctx* c)
                    &c->cellx, &c->cell_of, &c->sc_scratch, &c->cells, &c->ncells, &c->cell_map,
                    &c->src, &c->src_count, &c->sidx, &c->srec, &c->rx, &c->ry, &c->rz, &c->h,
                    &c->vm, &c->u, &c->g0, &c->g1, &c->cell_hmax, &c->qhead, &c->status, &c->step_tmp,
-                   &c->sd0, &c->sd1, &c->adj_ab, &c->adj_sb0, &c->adj_sb1, &c->adj_x, &c->adj_h, &c->adj_fg};
+                   &c->sd0, &c->sd1, &c->adj_ab, &c->adj_sb0, &c->adj_sb1, &c->adj_x, &c->adj_h, &c->adj_fg,
+                   &c->src_off, &c->t_chg, &c->t_node_of, &c->t_node_start, &c->t_node_flag, &c->t_node_hmax,
+                   &c->t_node_H, &c->t_node_leaf, &c->t_nnodes, &c->t_flag, &c->t_scan, &c->t_small,
+                   &c->t_psmall, &c->t_lev};
     for (DBuf* b : all) b->release();
     if (c->status_host) (void)hipHostFree(c->status_host);
     if (c->ncells_host) (void)hipHostFree(c->ncells_host);
@@ -321,6 +348,15 @@ static sph_status setup_boxes(sph_ctx* c, int64_t n, const sph_batch* batch)
     int box_bits = 0;
     while ((1 << box_bits) < nbox) box_bits++;
     if (3 * tb + box_bits > 64) return SPH_E_CAPACITY;
+    // levels of the hierarchy: bounded by the key width and the 21 bits per
+    // dimension of the Morton code
+    int depth = std::min(c->prm.max_depth, kMaxDepth);
+    depth = std::min(depth, (64 - box_bits) / 3 - tb);
+    depth = std::min(depth, 21 - tb);
+    if (depth < 0) depth = 0;
+    if (depth > 0 && n >= ((int64_t)1 << 27)) return SPH_E_CAPACITY;
+    for (int b = 0; b < nbox; b++) c->box_host[b].depth = depth;
+    c->depth = depth;
     c->nbox = nbox;
     c->top_bits = tb;
     c->map_total = map_total;
@@ -344,27 +380,77 @@ static bool upload_boxes(sph_ctx* c, hipStream_t st)
            hipSuccess;
 }
 
-extern "C++" {
-template <typename R>
-static void build_launches(sph_ctx* c, const Particles& pv, hipStream_t st)
+static TreeView tree_view(sph_ctx* c)
+{
+    TreeView tv;
+    tv.depth = c->depth;
+    tv.top_bits = c->top_bits;
+    tv.n = c->n;
+    tv.stride = c->n + 1;
+    tv.keys = c->keys.as<uint64_t>();
+    tv.perm = c->vals.as<uint32_t>();
+    tv.chg = c->t_chg.as<uint8_t>();
+    tv.node_of = c->t_node_of.as<uint32_t>();
+    tv.node_start = c->t_node_start.as<uint32_t>();
+    tv.node_flag = c->t_node_flag.as<uint8_t>();
+    tv.node_hmax = c->t_node_hmax.as<float>();
+    tv.node_H = c->t_node_H.as<float>();
+    tv.node_leaf = c->t_node_leaf.as<int32_t>();
+    tv.nnodes = c->t_nnodes.as<int32_t>();
+    tv.flag = c->t_flag.as<uint32_t>();
+    tv.scan = c->t_scan.as<uint32_t>();
+    tv.small = c->t_small.as<uint32_t>();
+    tv.psmall = c->t_psmall.as<uint32_t>();
+    tv.lev = c->t_lev.as<uint8_t>();
+    return tv;
+}
+
+// box scan, top grid, keys (down to the current depth) and their sort
+static void key_launches(sph_ctx* c, const Particles& pv, hipStream_t st)
 {
     const int64_t n = c->n;
     BoxInfo* boxes = c->boxes.as<BoxInfo>();
     uint32_t* status = c->status.as<uint32_t>();
     launch_box_scan(pv, boxes, c->nbox, n, status, st);
     launch_grid_dims(boxes, c->nbox, c->prm.h_margin, 1023, status, st);
-    launch_keys(pv, boxes, c->nbox, n, c->top_bits, c->keys.as<uint64_t>(), c->vals.as<uint32_t>(), st);
+    launch_keys_depth(pv, boxes, c->nbox, n, c->top_bits, c->depth, c->keys.as<uint64_t>(), c->vals.as<uint32_t>(),
+                      st);
     int box_bits = 0;
     while ((1 << box_bits) < c->nbox) box_bits++;
     radix_sort(c->keys.as<uint64_t>(), c->vals.as<uint32_t>(), c->keys2.as<uint64_t>(),
-               c->vals2.as<uint32_t>(), n, 3 * c->top_bits + box_bits, c->rs_scratch.as<uint32_t>(), st);
-    launch_cells(c->keys.as<uint64_t>(), c->flag.as<uint32_t>(), c->cellx.as<uint32_t>(), n, c->top_bits,
-                 boxes, c->cells.as<CellInfo>(), c->cell_map.as<int32_t>(), c->map_total,
-                 c->cell_of.as<uint32_t>(), c->ncells.as<int32_t>(), c->sc_scratch.as<uint32_t>(), n, st);
+               c->vals2.as<uint32_t>(), n, 3 * (c->top_bits + c->depth) + box_bits, c->rs_scratch.as<uint32_t>(),
+               st);
+}
+
+extern "C++" {
+template <typename R>
+static void build_launches(sph_ctx* c, const Particles& pv, hipStream_t st)
+{
+    const int64_t n = c->n;
+    BoxInfo* boxes = c->boxes.as<BoxInfo>();
+    key_launches(c, pv, st);
+    if (c->depth == 0) {
+        launch_cells(c->keys.as<uint64_t>(), c->flag.as<uint32_t>(), c->cellx.as<uint32_t>(), n, c->top_bits,
+                     boxes, c->cells.as<CellInfo>(), c->cell_map.as<int32_t>(), c->map_total,
+                     c->cell_of.as<uint32_t>(), c->ncells.as<int32_t>(), c->sc_scratch.as<uint32_t>(), n, st);
+    } else {
+        const TreeView tv = tree_view(c);
+        launch_tree(pv, tv, boxes, c->prm.split_count, c->prm.split_frac, c->prm.h_margin,
+                    c->sc_scratch.as<uint32_t>(), st);
+        launch_tree_cells(tv, boxes, c->cells.as<CellInfo>(), c->cell_map.as<int32_t>(), c->map_total,
+                          c->cell_of.as<uint32_t>(), c->ncells.as<int32_t>(), c->prm.h_margin,
+                          c->sc_scratch.as<uint32_t>(), st);
+    }
     launch_gather<R>(pv, c->vals.as<uint32_t>(), c->cell_of.as<uint32_t>(), c->cells.as<CellInfo>(), boxes,
                      n, cell_data<R>(c), st);
-    launch_sources(c->cells.as<CellInfo>(), c->ncells.as<int32_t>(), boxes, c->cell_map.as<int32_t>(),
-                   c->src.as<Source>(), c->src_count.as<int32_t>(), n, st);
+    if (c->depth == 0)
+        launch_sources(c->cells.as<CellInfo>(), c->ncells.as<int32_t>(), boxes, c->cell_map.as<int32_t>(),
+                       c->src.as<Source>(), c->src_off.as<int32_t>(), c->src_count.as<int32_t>(), n, st);
+    else
+        launch_tree_sources(tree_view(c), c->cells.as<CellInfo>(), c->ncells.as<int32_t>(), boxes,
+                            c->cell_map.as<int32_t>(), c->src.as<Source>(), c->src_cap, c->src_off.as<int32_t>(),
+                            c->src_count.as<int32_t>(), c->status.as<uint32_t>(), c->sc_scratch.as<uint32_t>(), n,
+                            st);
 }
 }  // extern "C++"
 
@@ -401,6 +487,32 @@ sph_status sph_build_cells(sph_ctx* c, const sph_particles* p, const sph_batch* 
     if (hipGetLastError() != hipSuccess) return SPH_E_HIP;
     c->built = true;
     return SPH_OK;
+}
+
+sph_status sph_estimate_h(sph_ctx* c, sph_particles* p, const sph_batch* batch, void* stream)
+{
+    if (!c || !particles_ok(p) || c->prm.max_depth < 1) return SPH_E_INVALID_ARG;
+    if (batch && (batch->nbox < 1 || !batch->box_offsets || !batch->box_len)) return SPH_E_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    if (hipSetDevice(c->device) != hipSuccess) return SPH_E_HIP;
+    sph_status s = setup_boxes(c, p->n, batch);
+    if (s != SPH_OK) return s;
+    if (c->depth < 1) return SPH_E_CAPACITY;
+    c->n = p->n;
+    c->built = c->sorted = c->have_density = false;
+    if (!ensure_particles(c, p->n)) return SPH_E_OOM;
+    if (!c->boxes.ensure(sizeof(BoxInfo) * c->nbox)) return SPH_E_OOM;
+    if (!upload_boxes(c, st)) return SPH_E_HIP;
+    launch_fill_i32(c->status.as<int32_t>(), 4, 0, st);
+    if (p->n > 0) {
+        Particles pv = view(p);
+        key_launches(c, pv, st);
+        const TreeView tv = tree_view(c);
+        launch_tree(pv, tv, c->boxes.as<BoxInfo>(), c->prm.split_count, c->prm.split_frac, c->prm.h_margin,
+                    c->sc_scratch.as<uint32_t>(), st);
+        launch_estimate_h(tv, c->boxes.as<BoxInfo>(), c->prm.n_ngb, p->h, p->n, st);
+    }
+    return hipGetLastError() == hipSuccess ? SPH_OK : SPH_E_HIP;
 }
 
 sph_status sph_sort(sph_ctx* c, void* stream)
@@ -735,6 +847,7 @@ sph_status sph_get_stats(const sph_ctx* c, sph_stats* out)
 {
     if (!c || !out) return SPH_E_INVALID_ARG;
     *out = c->stats;
+    out->depth = c->depth;
     if (!c->box_host.empty()) {
         BoxInfo b0;
         if (c->built && hipMemcpy(&b0, c->boxes.p, sizeof(BoxInfo), hipMemcpyDeviceToHost) == hipSuccess) {

@@ -7,7 +7,7 @@
 //   radix sort    LSD, 8-bit digits, stable; tile = 256 threads x 8 keys
 //   cells         runs of equal keys -> cell table + dense per-box cell map
 //   gather        cell-ordered particle copies, positions relative to the cell
-//   sources       self + 26 neighbour cells of each cell, with periodic shifts
+//   sources       self + 26 neighbour cells of each cell (single-level grid)
 //   sort13        per cell and direction: ranks of the projections (stable)
 #include "sph_internal.h"
 #include "kernels.h"
@@ -103,7 +103,10 @@ __global__ void k_grid_dims(BoxInfo* boxes, int nbox, double margin, int max_nc,
 }
 
 // ---------------------------------------------------------------- keys
-__global__ void k_keys(Particles p, const BoxInfo* boxes, int nbox, int64_t n, int top_bits,
+// Key = box id above the Morton code of the particle's cell at the finest
+// level (top grid refined `depth` times by bisection), so that the cells of
+// every level are runs of equal key prefixes.
+__global__ void k_keys(Particles p, const BoxInfo* boxes, int nbox, int64_t n, int top_bits, int depth,
                        uint64_t* keys, uint32_t* vals)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -113,12 +116,14 @@ __global__ void k_keys(Particles p, const BoxInfo* boxes, int nbox, int64_t n, i
     double pos[3] = {p.x[i], p.y[i], p.z[i]};
     uint32_t c[3];
     for (int d = 0; d < 3; d++) {
-        double w = wrap_coord(pos[d], B.L[d]);
-        double fc = floor(w / B.e[d]);
-        int cc = (fc >= 0.0) ? (int)fmin(fc, (double)(B.nc[d] - 1)) : 0;  // NaN -> 0 (flagged by the box scan)
+        const double w = wrap_coord(pos[d], B.L[d]);
+        const double ef = ldexp(B.e[d], -depth);
+        const double fc = floor(w / ef);
+        const double top = ldexp((double)B.nc[d], depth) - 1.0;
+        int cc = (fc >= 0.0) ? (int)fmin(fc, top) : 0;  // NaN -> 0 (flagged by the box scan)
         c[d] = (uint32_t)cc;
     }
-    keys[i] = ((uint64_t)b << (3 * top_bits)) | morton3(c[0], c[1], c[2]);
+    keys[i] = ((uint64_t)b << (3 * (top_bits + depth))) | morton3(c[0], c[1], c[2]);
     vals[i] = (uint32_t)i;
 }
 
@@ -336,11 +341,14 @@ __global__ void k_cell_fill(const uint64_t* keys, const uint32_t* flag, const ui
     }
 }
 
-__global__ void k_cell_counts(CellInfo* cells, const int32_t* ncells)
+__global__ void k_cell_counts(CellInfo* cells, const int32_t* ncells, const BoxInfo* boxes)
 {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= *ncells) return;
     cells[c].count -= cells[c].start;
+    cells[c].level = 0;
+    const BoxInfo& B = boxes[cells[c].box];
+    cells[c].hlim = (float)fmin(B.e[0], fmin(B.e[1], B.e[2]));
 }
 
 // ---------------------------------------------------------------- gather (cell order)
@@ -357,7 +365,7 @@ __global__ void k_gather(Particles p, const uint32_t* perm, const uint32_t* cell
     R rel[3];
     for (int d = 0; d < 3; d++) {
         double w = wrap_coord(pos[d], B.L[d]);
-        double o = (double)C.c[d] * B.e[d];
+        double o = (double)C.c[d] * ldexp(B.e[d], -B.depth);
         double r = w - o;
         // a coordinate that rounded onto the upper face belongs to this cell
         rel[d] = (R)r;
@@ -371,8 +379,12 @@ __global__ void k_gather(Particles p, const uint32_t* perm, const uint32_t* cell
 }
 
 // ---------------------------------------------------------------- sources
+// share of the 26 neighbour directions per wavefront on the single-level
+// grid (2 bits per direction): faces 2/2/1/1, edges 3/3/3/3, corners 1/1/3/3
+constexpr uint64_t kDirWavePacked = 0x507e90edb60faull;
+
 __global__ void k_sources(const CellInfo* cells, const int32_t* ncells, const BoxInfo* boxes,
-                          const int32_t* cell_map, Source* src, int32_t* src_count)
+                          const int32_t* cell_map, Source* src, int32_t* src_off, int32_t* src_count)
 {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= *ncells) return;
@@ -380,19 +392,21 @@ __global__ void k_sources(const CellInfo* cells, const int32_t* ncells, const Bo
     const BoxInfo& B = boxes[C.box];
     Source* out = src + (int64_t)c * kMaxSources;
     int k = 0;
-    out[k++] = Source{c, (int8_t)kSelfDir, 0, 0, 0};
+    out[k++] = Source{c, (int8_t)kSelfDir, (int8_t)kAllWaves, 0, 0, 0};
     for (int d = 0; d < kDirs; d++) {
         int o[3];
         dir_off(d, o);
-        int nc[3], sh[3];
+        int nc[3];
         for (int a = 0; a < 3; a++) {
             int v = C.c[a] + o[a];
-            sh[a] = v < 0 ? -1 : (v >= B.nc[a] ? 1 : 0);
-            nc[a] = v - sh[a] * B.nc[a];
+            nc[a] = v < 0 ? v + B.nc[a] : (v >= B.nc[a] ? v - B.nc[a] : v);
         }
         int32_t s = cell_map[B.map_off + ((int64_t)nc[0] * B.nc[1] + nc[1]) * B.nc[2] + nc[2]];
-        if (s >= 0) out[k++] = Source{s, (int8_t)d, (int8_t)sh[0], (int8_t)sh[1], (int8_t)sh[2]};
+        if (s >= 0)
+            out[k++] = Source{s, (int8_t)d, (int8_t)((kDirWavePacked >> (2 * d)) & 3u), (int16_t)o[0],
+                              (int16_t)o[1], (int16_t)o[2]};
     }
+    src_off[c] = c * kMaxSources;
     src_count[c] = k;
 }
 
@@ -470,8 +484,14 @@ void launch_grid_dims(BoxInfo* boxes, int nbox, double margin, int max_nc, uint3
 void launch_keys(const Particles& p, const BoxInfo* boxes, int nbox, int64_t n, int top_bits,
                  uint64_t* keys, uint32_t* vals, hipStream_t st)
 {
+    launch_keys_depth(p, boxes, nbox, n, top_bits, 0, keys, vals, st);
+}
+
+void launch_keys_depth(const Particles& p, const BoxInfo* boxes, int nbox, int64_t n, int top_bits, int depth,
+                       uint64_t* keys, uint32_t* vals, hipStream_t st)
+{
     hipLaunchKernelGGL(k_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, boxes, nbox,
-                       n, top_bits, keys, vals);
+                       n, top_bits, depth, keys, vals);
 }
 
 size_t radix_scratch_words(int64_t n)
@@ -500,8 +520,8 @@ void radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* k2, uint32_t* v2, int6
         uint32_t* tv = va; va = vb; vb = tv;
     }
     if (ka != keys) {
-        hipMemcpyAsync(keys, ka, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, st);
-        hipMemcpyAsync(vals, va, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, st);
+        (void)hipMemcpyAsync(keys, ka, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, st);
+        (void)hipMemcpyAsync(vals, va, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, st);
     }
 }
 
@@ -529,7 +549,7 @@ void launch_cells(const uint64_t* keys, uint32_t* flag, uint32_t* cellx, int64_t
     hipLaunchKernelGGL(k_cell_fill, dim3(g), dim3(256), 0, st, keys, flag, cellx, n, top_bits, boxes,
                        cells, cell_map, cell_of, ncells);
     hipLaunchKernelGGL(k_cell_counts, dim3((unsigned)((cell_cap + 255) / 256)), dim3(256), 0, st,
-                       cells, ncells);
+                       cells, ncells, boxes);
 }
 
 template <typename R>
@@ -547,11 +567,11 @@ template void launch_gather<double>(const Particles&, const uint32_t*, const uin
                                     const CellData<double>&, hipStream_t);
 
 void launch_sources(const CellInfo* cells, const int32_t* ncells, const BoxInfo* boxes,
-                    const int32_t* cell_map, Source* src, int32_t* src_count, int64_t cell_cap,
-                    hipStream_t st)
+                    const int32_t* cell_map, Source* src, int32_t* src_off, int32_t* src_count,
+                    int64_t cell_cap, hipStream_t st)
 {
     hipLaunchKernelGGL(k_sources, dim3((unsigned)((cell_cap + 127) / 128)), dim3(128), 0, st, cells,
-                       ncells, boxes, cell_map, src, src_count);
+                       ncells, boxes, cell_map, src, src_off, src_count);
 }
 
 template <typename R>

@@ -85,6 +85,7 @@ struct Decomp {
     const int32_t* ncells;
     const BoxInfo* boxes;
     const Source* src;
+    const int32_t* src_off;     // first source of each cell
     const int32_t* src_count;
     const uint32_t* perm;   // cell order -> caller index
     int64_t n;
@@ -115,11 +116,49 @@ void launch_gather(const Particles& p, const uint32_t* perm, const uint32_t* cel
                    const CellInfo* cells, const BoxInfo* boxes, int64_t n, const CellData<R>& cd,
                    hipStream_t st);
 void launch_sources(const CellInfo* cells, const int32_t* ncells, const BoxInfo* boxes,
-                    const int32_t* cell_map, Source* src, int32_t* src_count, int64_t cell_cap,
-                    hipStream_t st);
+                    const int32_t* cell_map, Source* src, int32_t* src_off, int32_t* src_count,
+                    int64_t cell_cap, hipStream_t st);
 template <typename R>
 void launch_sort13(const CellInfo* cells, const int32_t* ncells, const CellData<R>& cd, int64_t n,
                    const Sorted<R>& so, uint32_t* status, int64_t cell_cap, hipStream_t st);
+
+// tree.hip -- hierarchical decomposition below the top grid
+struct TreeView {
+    int depth;                  // levels below the top grid (>= 1)
+    int top_bits;
+    int64_t n;
+    int64_t stride;             // per-level stride of the node arrays (n + 1)
+    const uint64_t* keys;       // sorted keys
+    const uint32_t* perm;       // cell order -> caller index
+    uint8_t* chg;               // first level whose prefix differs from the previous particle
+    uint32_t* node_of;          // [level * n + i]: node of particle i at that level
+    uint32_t* node_start;       // [level * stride + m]: first particle of node m (sentinel n)
+    uint8_t* node_flag;         // bit 0: live (parent split), bit 1: split
+    float* node_hmax;           // largest h of the node's particles at build time
+    float* node_H;              // largest interaction bound (cell hlim) of the node's leaves
+    int32_t* node_leaf;         // cell index of a leaf node, else -1
+    int32_t* nnodes;            // nodes per level
+    uint32_t* flag;             // scratch (n)
+    uint32_t* scan;             // scratch (n + 1)
+    uint32_t* small;            // scratch (n)
+    uint32_t* psmall;           // scratch (n + 1)
+    uint8_t* lev;               // leaf level of each particle
+};
+enum : uint8_t { NODE_LIVE = 1, NODE_SPLIT = 2 };
+
+void launch_keys_depth(const Particles& p, const BoxInfo* boxes, int nbox, int64_t n, int top_bits, int depth,
+                       uint64_t* keys, uint32_t* vals, hipStream_t st);
+void launch_tree(const Particles& p, const TreeView& tv, const BoxInfo* boxes, int split_count, double split_frac,
+                 double h_margin, uint32_t* scan_scratch, hipStream_t st);
+void launch_tree_cells(const TreeView& tv, const BoxInfo* boxes, CellInfo* cells, int32_t* cell_map,
+                       int64_t map_total, uint32_t* cell_of, int32_t* ncells, double h_margin,
+                       uint32_t* scan_scratch, hipStream_t st);
+void launch_tree_sources(const TreeView& tv, const CellInfo* cells, const int32_t* ncells, const BoxInfo* boxes,
+                         const int32_t* cell_map, Source* src, int64_t src_cap, int32_t* src_off,
+                         int32_t* src_count, uint32_t* status, uint32_t* scan_scratch, int64_t cell_cap,
+                         hipStream_t st);
+void launch_estimate_h(const TreeView& tv, const BoxInfo* boxes, double n_ngb, double* h, int64_t n,
+                       hipStream_t st);
 
 // passes.hip
 void launch_reset_counter(int32_t* c, hipStream_t st);

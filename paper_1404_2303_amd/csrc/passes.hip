@@ -93,7 +93,6 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
 {
     using R4 = typename Vec4T<R>::T;
     using SM = Smem<R, NACC_D, false>;
-    constexpr int LISTW = SM::LISTW;
     __shared__ SM s;
     const int tid = threadIdx.x;
     const int w = tid >> 6;
@@ -112,7 +111,8 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
         const CellInfo T = dc.cells[unit];
         const BoxInfo B = dc.boxes[T.box];
         const int nsrc = dc.src_count[unit];
-        const double h_lim = fmin(B.e[0], fmin(B.e[1], B.e[2]));
+        const double h_lim = (double)T.hlim;  // the interaction lists cover h up to this
+        const double h_box = fmin(B.L[0], fmin(B.L[1], B.L[2])) / 3.0;
         const float margin = 1e-5f * (float)fmax(B.e[0], fmax(B.e[1], B.e[2]));
         double hc = 0.0;
         for (int t = lane; t < T.count; t += kWave) hc = fmax(hc, cd.h[T.start + t]);
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
 
         // staging of the first batch, kept while it holds every source of the wavefront
         int k = 0, p = 0;
-        stage_wave<R, false, NACC_D>(s, w, dc, cd, so, gd, B, unit, nsrc, k, p, Hst, margin);
+        stage_wave<R, false, NACC_D>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, margin);
         bool single = k >= nsrc;
 
         for (int c0 = 0; c0 < T.count; c0 += kWave) {
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
                 bool flushed = false;
                 int kk = 0, pp = 0;
                 do {
-                    if (!single) stage_wave<R, false, NACC_D>(s, w, dc, cd, so, gd, B, unit, nsrc, kk, pp, Hst, margin);
+                    if (!single) stage_wave<R, false, NACC_D>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, kk, pp, Hst, margin);
                     else kk = nsrc;
                     const int selfj = self_index(s, w, ti);
                     int seg = 0, jj = s.nseg[w] > 0 ? s.seg_b[w][0] : 0;
@@ -237,7 +237,9 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
                                 if (h >= h_lim) {  // the root lies beyond what the cells allow
                                     atomicOr(dc.status, ST_REBUILD);
                                     conv = true; failed = true;
-                                    h_rebuild = hn;
+                                    // the next build takes it from here, within what a
+                                    // periodic box allows (three cells of edge >= h)
+                                    h_rebuild = fmin(hn, h_box);
                                 } else {
                                     hn = h_lim;
                                 }
@@ -265,7 +267,7 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
                     const double hm = wave_max(conv ? 0.0 : h);
                     Hst = (float)fmin(fmax((double)Hst, hm * (1.0 + pc.h_margin)), h_lim);
                     k = 0; p = 0;
-                    stage_wave<R, false, NACC_D>(s, w, dc, cd, so, gd, B, unit, nsrc, k, p, Hst, margin);
+                    stage_wave<R, false, NACC_D>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, margin);
                     single = k >= nsrc;
                     cached = false;
                 }
@@ -416,7 +418,7 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
         const float margin = 1e-5f * (float)fmax(B.e[0], fmax(B.e[1], B.e[2]));
         const float Hst = gd.cell_hmax[unit];
         int k = 0, p = 0;
-        stage_wave<R, true, NACC_F>(s, w, dc, cd, so, gd, B, unit, nsrc, k, p, Hst, margin);
+        stage_wave<R, true, NACC_F>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, margin);
         const bool single = k >= nsrc;
         for (int c0 = 0; c0 < T.count; c0 += kWave) {
             const int ti_ = c0 + lane;
@@ -449,7 +451,7 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
             };
             int kk = 0, pp = 0;
             do {
-                if (!single) stage_wave<R, true, NACC_F>(s, w, dc, cd, so, gd, B, unit, nsrc, kk, pp, Hst, margin);
+                if (!single) stage_wave<R, true, NACC_F>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, kk, pp, Hst, margin);
                 else kk = nsrc;
                 const int selfj = self_index(s, w, ti_);
                 int seg = 0, jj = s.nseg[w] > 0 ? s.seg_b[w][0] : 0;

@@ -15,6 +15,10 @@ constexpr int kDirs = 26;        // neighbour directions {-1,0,1}^3 \ 0
 constexpr int kSortDirs = 13;    // stored orderings (Sec. 3.3): half of the 26
 constexpr int kSelfDir = 26;     // direction code of a self interaction
 constexpr int kMaxSources = 27;  // self + 26 neighbours (single-level grid)
+constexpr int kSweepWaves = 4;   // wavefronts per target cell in the interaction kernels
+constexpr int kAllWaves = 4;     // wave code of a source shared by every wavefront (self)
+constexpr int kMaxDepth = 12;    // levels below the top grid in the hierarchical decomposition
+constexpr int kTreeSourcesPerParticle = 32;  // bound on list entries per particle (hierarchy)
 constexpr double kPi = 3.14159265358979323846;
 
 // device status bits (accumulated with atomicOr, read back by the host)
@@ -37,26 +41,34 @@ struct BoxInfo {
     int32_t map_off;      // offset of this box's dense cell map
     int32_t map_cap;      // capacity of the dense cell map (host upper bound)
     int32_t cap_nc[3];    // per-dimension bound on nc (host)
-    int32_t pad;
+    int32_t depth;        // levels below the top grid encoded in the keys (0: single level)
     double e[3];          // cell edges (device-written)
     double hmax;          // largest h in the box (device-written)
 };
 
 // ---------------------------------------------------------------- cells
+// A cell of the decomposition: a top-grid cell, or a leaf of the hierarchy
+// below it (a cube of edge e / 2^level).  Corners are integer coordinates in
+// units of the finest edge e / 2^depth of the box.
 struct CellInfo {
     int32_t start;        // first particle (cell order)
     int32_t count;
     int32_t box;
-    int32_t c[3];         // integer cell coordinates in the box grid
+    int32_t c[3];         // lower corner in finest-level units
+    int32_t level;        // 0: top grid
+    float hlim;           // largest h the cell's interaction lists cover
 };
 
 // An interaction source of a target cell: the source cell, the direction
-// from target to source (0..25, or kSelfDir) and the periodic image shift
-// of the source in box lengths.
+// along which its ordering is swept (0..25, or kSelfDir), the wavefront that
+// sweeps it (kAllWaves: shared, the self source), and the position of the
+// source's corner relative to the target's corner in finest-level units
+// (periodic images included).
 struct Source {
     int32_t cell;
     int8_t dir;
-    int8_t sx, sy, sz;
+    int8_t wave;
+    int16_t ox, oy, oz;
 };
 
 // Directions.  Index d in 0..25 enumerates (dx,dy,dz) in {-1,0,1}^3 \ 0 in

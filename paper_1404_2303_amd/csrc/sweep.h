@@ -9,7 +9,7 @@
 namespace sph {
 
 
-constexpr int NW = 4;                 // wavefronts per target cell
+constexpr int NW = kSweepWaves;       // wavefronts per target cell
 constexpr int WGS = NW * kWave;
 constexpr int kMaxSegW = 28;          // staged segments per wavefront and batch
 constexpr int NACC_D = 9;             // density partial sums per target
@@ -23,11 +23,6 @@ template <> struct PCfg<float, false> { static constexpr int CAPW = 256, LISTW =
 template <> struct PCfg<float, true> { static constexpr int CAPW = 256, LISTW = 32; };
 template <> struct PCfg<double, false> { static constexpr int CAPW = 256, LISTW = 48; };
 template <> struct PCfg<double, true> { static constexpr int CAPW = 256, LISTW = 32; };
-
-// share of the 26 neighbour directions per wavefront (2 bits per direction):
-// faces 2/2/1/1, edges 3/3/3/3, corners 1/1/3/3
-constexpr uint64_t kDirWavePacked = 0x507e90edb60faull;
-__device__ __forceinline__ int dir_wave(int d) { return (int)((kDirWavePacked >> (2 * d)) & 3u); }
 
 // square root and reciprocal of the pair arithmetic: the hardware
 // instructions in FP32 (about 1 ulp), correctly rounded in FP64
@@ -101,30 +96,44 @@ struct Smem {
 };
 
 // Stage, for wavefront w, its sources from cursor (k, p) on; advance the
-// cursor past what was staged (k == nsrc when every source is staged).
+// cursor past what was staged (k == nsrc when every source is staged).  The
+// sources of the target cell are read 64 at a time, one per lane.
 template <typename R, bool FORCE, int NACC>
 __device__ void stage_wave(Smem<R, NACC, FORCE>& s, const int w, const Decomp& dc, const CellData<R>& cd,
                            const Sorted<R>& so, const GhostData<R>& gd, const BoxInfo& B, const int tcell,
-                           const int nsrc, int& k, int& p, const float Hst, const float margin)
+                           const int tlevel, const int nsrc, int& k, int& p, const float Hst, const float margin)
 {
     using R4 = typename Vec4T<R>::T;
     const int lane = threadIdx.x & (kWave - 1);
     const int CAPW = Smem<R, NACC, FORCE>::CAPW;
+    // edges of the target cell and the finest-level unit of the source offsets
+    const float et[3] = {(float)ldexp(B.e[0], -tlevel), (float)ldexp(B.e[1], -tlevel),
+                         (float)ldexp(B.e[2], -tlevel)};
+    const double ef[3] = {ldexp(B.e[0], -B.depth), ldexp(B.e[1], -B.depth), ldexp(B.e[2], -B.depth)};
+    const int64_t soff = dc.src_off[tcell];
     int fill = 0, nseg = 0;
     wave_sync();  // earlier readers of this wavefront's staging area are done
-    // lane-parallel view of the source list (at most 27 entries)
+    int chunk = -1;
     Source my = {};
-    if (lane < nsrc) my = dc.src[(int64_t)tcell * kMaxSources + lane];
-    const bool mine = lane < nsrc && (my.dir == kSelfDir || dir_wave(my.dir) == w);
-    const uint64_t mask = __ballot(mine);
+    uint64_t mask = 0;
     if (lane == 0) s.self_n[w] = 0;
     while (true) {
-        const uint64_t m = k >= 64 ? 0ull : (mask & (~0ull << k));
-        if (m == 0) { k = nsrc; p = 0; break; }
-        k = __builtin_ctzll(m);
+        if (k >= nsrc) { k = nsrc; p = 0; break; }
+        if ((k & ~(kWave - 1)) != chunk) {  // lane-parallel view of the next 64 sources
+            chunk = k & ~(kWave - 1);
+            const bool in = chunk + lane < nsrc;
+            my = in ? dc.src[soff + chunk + lane] : Source{};
+            mask = __ballot(in && (my.wave == w || my.wave == kAllWaves));
+        }
+        const uint64_t m = mask & (~0ull << (k - chunk));
+        if (m == 0) { k = chunk + kWave; p = 0; continue; }
+        k = chunk + __builtin_ctzll(m);
         if (nseg == kMaxSegW || fill >= CAPW) break;
-        const int scell = __shfl(my.cell, k, 64);
-        const int sdir = __shfl((int)my.dir, k, 64);
+        const int sl = k - chunk;
+        const int scell = __shfl(my.cell, sl, 64);
+        const int sdir = __shfl((int)my.dir, sl, 64);
+        const int sox = __shfl((int)my.ox, sl, 64), soy = __shfl((int)my.oy, sl, 64),
+                  soz = __shfl((int)my.oz, sl, 64);
         const bool self = sdir == kSelfDir;
         const CellInfo S = dc.cells[scell];
         const int segb = fill;
@@ -148,18 +157,17 @@ __device__ void stage_wave(Smem<R, NACC, FORCE>& s, const int w, const Decomp& d
             fill += take;
             if (take < n) { complete = false; p += take; }
         } else {
-            int o[3];
-            dir_off(sdir, o);
             dir_unit(sdir, u);
             const int sd = dir_sort(sdir);
             const bool flip = dir_flip(sdir);
-            const R dox = (R)(o[0] * B.e[0]), doy = (R)(o[1] * B.e[1]), doz = (R)(o[2] * B.e[2]);
-            const float udo = u[0] * (float)(o[0] * B.e[0]) + u[1] * (float)(o[1] * B.e[1]) +
-                              u[2] * (float)(o[2] * B.e[2]);
+            // source corner in the target's frame
+            const double dxo = sox * ef[0], dyo = soy * ef[1], dzo = soz * ef[2];
+            const R dox = (R)dxo, doy = (R)dyo, doz = (R)dzo;
+            const float udo = u[0] * (float)dxo + u[1] * (float)dyo + u[2] * (float)dzo;
             float hs = Hst;
             if (FORCE) { hx = gd.cell_hmax[scell]; hs = fmaxf(Hst, hx); }
-            const float reach = fmaxf(u[0], 0.f) * (float)B.e[0] + fmaxf(u[1], 0.f) * (float)B.e[1] +
-                                fmaxf(u[2], 0.f) * (float)B.e[2] + hs + margin;
+            const float reach = fmaxf(u[0], 0.f) * et[0] + fmaxf(u[1], 0.f) * et[1] + fmaxf(u[2], 0.f) * et[2] +
+                                hs + margin;
             const int64_t sbase = (int64_t)sd * dc.n + S.start;
             while (p < S.count) {
                 const int pos = p + lane;

@@ -1,0 +1,386 @@
+// tree.hip -- hierarchical cell decomposition below the top grid (Gonnet
+// 2014, Sec. 3.2) and the interaction lists of its leaves, for gfx950.
+//
+// The keys encode the particle's cell at the finest level (the top grid
+// bisected `depth` times), so the cells of every level are runs of equal key
+// prefixes in the sorted order.  Per level, the runs become a node table
+// (first particle, split flag, largest h).  A node is split, as Sec. 3.2
+// states, when it holds more than split_count particles and at least the
+// fraction split_frac of them has h below half its edge; the leaves are the
+// unsplit nodes whose parent is split.  The leaves are the cells of the
+// interaction kernels.
+//
+// Interaction lists: for each leaf T, every leaf Q whose box lies within
+// max(H_T, H_Q) of T's box, where H is the largest h a cell's lists cover
+// (cells' hlim).  A pair of particles in range, r < max(h_i, h_j), is
+// therefore always a pair of listed cells.  The lists are found by walking
+// the tree from the 27 top cells around T and opening nodes whose box is
+// within reach; each source is swept along the one of the 26 cell-pair axes
+// closest to the direction from T to Q.
+#include "sph_internal.h"
+#include "kernels.h"
+
+namespace sph {
+
+__device__ inline void key_coords(uint64_t key, int tb, int depth, uint32_t c[3], int* box)
+{
+    const int bits = 3 * (tb + depth);
+    const uint64_t mc = bits >= 64 ? key : (key & ((1ull << bits) - 1));
+    c[0] = compact3(mc); c[1] = compact3(mc >> 1); c[2] = compact3(mc >> 2);
+    *box = bits >= 64 ? 0 : (int)(key >> bits);
+}
+
+// first level at which the key prefix differs from the previous particle's
+// (0: another top cell or box; depth + 1: the same finest cell)
+__global__ void k_tree_chg(const uint64_t* keys, int64_t n, int depth, uint8_t* chg)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (i == 0) { chg[0] = 0; return; }
+    const uint64_t x = keys[i] ^ keys[i - 1];
+    if (x == 0) { chg[i] = (uint8_t)(depth + 1); return; }
+    const int hb = 63 - __builtin_clzll(x);
+    chg[i] = (uint8_t)(hb >= 3 * depth ? 0 : depth - hb / 3);
+}
+
+// run heads at level l, and whether h is below half the level's edge
+__global__ void k_lvl_prep(TreeView tv, const BoxInfo* boxes, const double* h, int l)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= tv.n) return;
+    tv.flag[i] = tv.chg[i] <= l ? 1u : 0u;
+    uint32_t c[3];
+    int b;
+    key_coords(tv.keys[i], tv.top_bits, tv.depth, c, &b);
+    const BoxInfo& B = boxes[b];
+    const double emin = ldexp(fmin(B.e[0], fmin(B.e[1], B.e[2])), -l);
+    tv.small[i] = h[tv.perm[i]] < 0.5 * emin ? 1u : 0u;
+}
+
+__global__ void k_lvl_nodes(TreeView tv, int l)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= tv.n) return;
+    const uint32_t f = tv.flag[i];
+    const uint32_t m = tv.scan[i] + f - 1;
+    tv.node_of[(int64_t)l * tv.n + i] = m;
+    if (f) tv.node_start[(int64_t)l * tv.stride + m] = (uint32_t)i;
+    if (i == tv.n - 1) tv.node_start[(int64_t)l * tv.stride + m + 1] = (uint32_t)tv.n;
+}
+
+__global__ void k_lvl_split(TreeView tv, int l, int split_count, double split_frac)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= tv.nnodes[l]) return;
+    const uint32_t* ns = tv.node_start + (int64_t)l * tv.stride;
+    const uint32_t start = ns[m], end = ns[m + 1];
+    const uint32_t cnt = end - start;
+    const uint32_t nsmall = tv.psmall[end] - tv.psmall[start];
+    bool live = true;
+    if (l > 0) {
+        const uint32_t parent = tv.node_of[(int64_t)(l - 1) * tv.n + start];
+        live = (tv.node_flag[(int64_t)(l - 1) * tv.stride + parent] & NODE_SPLIT) != 0;
+    }
+    const bool split = live && l < tv.depth && (int64_t)cnt > split_count &&
+                       (double)nsmall >= split_frac * (double)cnt;
+    tv.node_flag[(int64_t)l * tv.stride + m] = (uint8_t)((live ? NODE_LIVE : 0) | (split ? NODE_SPLIT : 0));
+    tv.node_leaf[(int64_t)l * tv.stride + m] = -1;
+}
+
+// largest h per node, from the particles (finest level) or the children
+__global__ void k_lvl_hmax(TreeView tv, const double* h, int l)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= tv.nnodes[l]) return;
+    const uint32_t* ns = tv.node_start + (int64_t)l * tv.stride;
+    const uint32_t start = ns[m], end = ns[m + 1];
+    float hm = 0.0f;
+    if (l == tv.depth) {
+        for (uint32_t i = start; i < end; i++) hm = fmaxf(hm, (float)h[tv.perm[i]]);
+    } else {
+        const uint32_t* no = tv.node_of + (int64_t)(l + 1) * tv.n;
+        const float* ch = tv.node_hmax + (int64_t)(l + 1) * tv.stride;
+        for (uint32_t c = no[start]; c <= no[end - 1]; c++) hm = fmaxf(hm, ch[c]);
+    }
+    tv.node_hmax[(int64_t)l * tv.stride + m] = hm;
+}
+
+// leaf level of each particle: the first level at which its node is live and unsplit
+__global__ void k_leaf_flags(TreeView tv)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= tv.n) return;
+    int lev = tv.depth;
+    for (int l = 0; l <= tv.depth; l++) {
+        const uint32_t m = tv.node_of[(int64_t)l * tv.n + i];
+        if (tv.node_flag[(int64_t)l * tv.stride + m] == NODE_LIVE) { lev = l; break; }
+    }
+    tv.lev[i] = (uint8_t)lev;
+    tv.flag[i] = tv.chg[i] <= lev ? 1u : 0u;
+}
+
+__global__ void k_leaf_cells(TreeView tv, const BoxInfo* boxes, CellInfo* cells, uint32_t* cell_of, double h_margin)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= tv.n) return;
+    const int l = tv.lev[i];
+    const uint32_t f = tv.flag[i];
+    const uint32_t c = tv.scan[i] + f - 1;
+    cell_of[i] = c;
+    if (!f) return;
+    uint32_t cf[3];
+    int b;
+    key_coords(tv.keys[i], tv.top_bits, tv.depth, cf, &b);
+    const BoxInfo& B = boxes[b];
+    const int sh = tv.depth - l;
+    const uint32_t m = tv.node_of[(int64_t)l * tv.n + i];
+    const uint32_t end = tv.node_start[(int64_t)l * tv.stride + m + 1];
+    CellInfo C;
+    C.start = (int32_t)i;
+    C.count = (int32_t)(end - i);
+    C.box = b;
+    for (int d = 0; d < 3; d++) C.c[d] = (int32_t)((cf[d] >> sh) << sh);
+    C.level = l;
+    // the lists cover h up to the cell's edge, or its largest h with the
+    // margin if that is more, and never beyond the top-cell edge
+    const double e0 = fmin(B.e[0], fmin(B.e[1], B.e[2]));
+    const double hm = (double)tv.node_hmax[(int64_t)l * tv.stride + m];
+    C.hlim = (float)fmin(e0, fmax(hm * (1.0 + h_margin), ldexp(e0, -l)));
+    cells[c] = C;
+    tv.node_leaf[(int64_t)l * tv.stride + m] = (int32_t)c;
+}
+
+// per node: the largest list bound of its leaves (0 below a leaf)
+__global__ void k_lvl_H(TreeView tv, const CellInfo* cells, int l)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= tv.nnodes[l]) return;
+    const int64_t o = (int64_t)l * tv.stride + m;
+    const uint8_t fl = tv.node_flag[o];
+    float H = 0.0f;
+    if (fl & NODE_SPLIT) {
+        const uint32_t* ns = tv.node_start + (int64_t)l * tv.stride;
+        const uint32_t start = ns[m], end = ns[m + 1];
+        const uint32_t* no = tv.node_of + (int64_t)(l + 1) * tv.n;
+        const float* ch = tv.node_H + (int64_t)(l + 1) * tv.stride;
+        for (uint32_t c = no[start]; c <= no[end - 1]; c++) H = fmaxf(H, ch[c]);
+    } else if (fl & NODE_LIVE) {
+        H = cells[tv.node_leaf[o]].hlim;
+    }
+    tv.node_H[o] = H;
+}
+
+// dense top-grid map of each box: top cell -> level-0 node
+__global__ void k_top_map(TreeView tv, const BoxInfo* boxes, int32_t* cell_map)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= tv.nnodes[0]) return;
+    uint32_t cf[3];
+    int b;
+    key_coords(tv.keys[tv.node_start[m]], tv.top_bits, tv.depth, cf, &b);
+    const BoxInfo& B = boxes[b];
+    const int64_t x = cf[0] >> tv.depth, y = cf[1] >> tv.depth, z = cf[2] >> tv.depth;
+    cell_map[B.map_off + (x * B.nc[1] + y) * B.nc[2] + z] = (int32_t)m;
+}
+
+// ---------------------------------------------------------------- interaction lists
+constexpr int kTreeStack = 112;
+
+__device__ inline int nearest_dir(double vx, double vy, double vz)
+{
+    int best = 0;
+    double bv = -INFINITY;
+    for (int d = 0; d < kDirs; d++) {
+        float u[3];
+        dir_unit(d, u);
+        const double v = u[0] * vx + u[1] * vy + u[2] * vz;
+        if (v > bv) { bv = v; best = d; }
+    }
+    return best;
+}
+
+// relative sweep cost of a source by direction type (face, edge, corner)
+__device__ inline float dir_weight(int d)
+{
+    int o[3];
+    dir_off(d, o);
+    const int nz = (o[0] != 0) + (o[1] != 0) + (o[2] != 0);
+    return nz == 1 ? 1.0f : (nz == 2 ? 0.7f : 0.5f);
+}
+
+template <bool FILL>
+__global__ void k_tree_sources(TreeView tv, const CellInfo* cells, const int32_t* ncells, const BoxInfo* boxes,
+                               const int32_t* cell_map, Source* src, int64_t src_cap, const int32_t* src_off,
+                               int32_t* src_count, uint32_t* status)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= *ncells) return;
+    const CellInfo T = cells[t];
+    const BoxInfo& B = boxes[T.box];
+    const int D = tv.depth;
+    const int64_t sT = 1ll << (D - T.level);
+    const double ef[3] = {ldexp(B.e[0], -D), ldexp(B.e[1], -D), ldexp(B.e[2], -D)};
+    const double HT = T.hlim;
+    const int64_t base = FILL ? src_off[t] : 0;
+    int cnt = 0;
+    float cost[kSweepWaves] = {0.f, 0.f, 0.f, 0.f};
+    int stack[kTreeStack];
+    for (int oi = 0; oi < 27; oi++) {
+        const int o[3] = {oi / 9 - 1, (oi / 3) % 3 - 1, oi % 3 - 1};
+        int tc[3];
+        int64_t shift[3];
+        for (int d = 0; d < 3; d++) {
+            int v = (T.c[d] >> D) + o[d];
+            shift[d] = 0;
+            if (v < 0) { v += B.nc[d]; shift[d] = -((int64_t)B.nc[d] << D); }
+            else if (v >= B.nc[d]) { v -= B.nc[d]; shift[d] = (int64_t)B.nc[d] << D; }
+            tc[d] = v;
+        }
+        const int32_t m0 = cell_map[B.map_off + ((int64_t)tc[0] * B.nc[1] + tc[1]) * B.nc[2] + tc[2]];
+        if (m0 < 0) continue;
+        int sp = 0;
+        stack[sp++] = m0;  // node index in the low 27 bits, level in the high bits
+        while (sp > 0) {
+            const int e = stack[--sp];
+            const int l = e >> 27, m = e & ((1 << 27) - 1);
+            const int64_t lo = (int64_t)l * tv.stride + m;
+            const uint32_t start = tv.node_start[lo], end = tv.node_start[lo + 1];
+            uint32_t cf[3];
+            int b;
+            key_coords(tv.keys[start], tv.top_bits, D, cf, &b);
+            const int64_t sN = 1ll << (D - l);
+            double dist2 = 0.0;
+            int64_t cn[3];
+            for (int d = 0; d < 3; d++) {
+                cn[d] = (int64_t)((cf[d] >> (D - l)) << (D - l)) + shift[d];
+                const int64_t a0 = T.c[d], a1 = T.c[d] + sT, b0 = cn[d], b1 = cn[d] + sN;
+                const int64_t gap = b0 > a1 ? b0 - a1 : (a0 > b1 ? a0 - b1 : 0);
+                const double g = (double)gap * ef[d];
+                dist2 += g * g;
+            }
+            const double R = fmax(HT, (double)tv.node_H[lo]);
+            if (dist2 >= R * R) continue;
+            const uint8_t fl = tv.node_flag[lo];
+            if (fl & NODE_SPLIT) {
+                const uint32_t* no = tv.node_of + (int64_t)(l + 1) * tv.n;
+                const uint32_t c0 = no[start], c1 = no[end - 1];
+                if (sp + (int)(c1 - c0 + 1) > kTreeStack) { atomicOr(status, ST_CAPACITY); continue; }
+                for (uint32_t c = c0; c <= c1; c++) stack[sp++] = ((l + 1) << 27) | (int)c;
+                continue;
+            }
+            const int32_t q = tv.node_leaf[lo];
+            if (q < 0) continue;  // not reachable for a live tree
+            const bool self = q == (int32_t)t && shift[0] == 0 && shift[1] == 0 && shift[2] == 0;
+            if (FILL) {
+                Source s;
+                s.cell = q;
+                s.ox = (int16_t)(cn[0] - T.c[0]);
+                s.oy = (int16_t)(cn[1] - T.c[1]);
+                s.oz = (int16_t)(cn[2] - T.c[2]);
+                if (self) {
+                    s.dir = (int8_t)kSelfDir;
+                    s.wave = (int8_t)kAllWaves;
+                } else {
+                    // direction between the centres, in length units
+                    const double vx = (double)(2 * cn[0] + sN - 2 * T.c[0] - sT) * ef[0];
+                    const double vy = (double)(2 * cn[1] + sN - 2 * T.c[1] - sT) * ef[1];
+                    const double vz = (double)(2 * cn[2] + sN - 2 * T.c[2] - sT) * ef[2];
+                    const int d = nearest_dir(vx, vy, vz);
+                    int wv = 0;
+                    for (int k = 1; k < kSweepWaves; k++) if (cost[k] < cost[wv]) wv = k;
+                    cost[wv] += (float)(end - start) * dir_weight(d);
+                    s.dir = (int8_t)d;
+                    s.wave = (int8_t)wv;
+                }
+                if (base + cnt < src_cap) src[base + cnt] = s;
+                else atomicOr(status, ST_CAPACITY);
+            }
+            cnt++;
+        }
+    }
+    if (!FILL) src_count[t] = cnt;
+}
+
+// h from the local number density: the particle count of the deepest node
+// around the particle holding at least 2 n_ngb particles, over its volume;
+// the box's mean density where even its top cell holds fewer
+__global__ void k_estimate_h(TreeView tv, const BoxInfo* boxes, double n_ngb, double* h)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= tv.n) return;
+    uint32_t cf[3];
+    int b;
+    key_coords(tv.keys[i], tv.top_bits, tv.depth, cf, &b);
+    const BoxInfo& B = boxes[b];
+    double density = (double)B.n / (B.L[0] * B.L[1] * B.L[2]);
+    for (int l = tv.depth; l >= 0; l--) {
+        const uint32_t m = tv.node_of[(int64_t)l * tv.n + i];
+        const uint32_t* ns = tv.node_start + (int64_t)l * tv.stride;
+        const double cnt = (double)(ns[m + 1] - ns[m]);
+        if (cnt >= 2.0 * n_ngb) {
+            density = cnt / (ldexp(B.e[0], -l) * ldexp(B.e[1], -l) * ldexp(B.e[2], -l));
+            break;
+        }
+    }
+    // a periodic box holds three cells of edge >= h at most
+    const double cap = 0.99 * fmin(B.L[0], fmin(B.L[1], B.L[2])) / 3.0;
+    h[tv.perm[i]] = fmin(cbrt(3.0 * n_ngb / (4.0 * kPi * density)), cap);
+}
+
+// ---------------------------------------------------------------- host launchers
+static inline dim3 grid_for(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
+
+void launch_tree(const Particles& p, const TreeView& tv, const BoxInfo* boxes, int split_count, double split_frac,
+                 double h_margin, uint32_t* scan_scratch, hipStream_t st)
+{
+    (void)h_margin;
+    const int64_t n = tv.n;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_tree_chg, grid_for(n), dim3(256), 0, st, tv.keys, n, tv.depth, tv.chg);
+    for (int l = 0; l <= tv.depth; l++) {
+        hipLaunchKernelGGL(k_lvl_prep, grid_for(n), dim3(256), 0, st, tv, boxes, p.h, l);
+        exclusive_scan(tv.flag, tv.scan, n, scan_scratch, (uint32_t*)(tv.nnodes + l), st);
+        exclusive_scan(tv.small, tv.psmall, n, scan_scratch, tv.psmall + n, st);
+        hipLaunchKernelGGL(k_lvl_nodes, grid_for(n), dim3(256), 0, st, tv, l);
+        hipLaunchKernelGGL(k_lvl_split, grid_for(n), dim3(256), 0, st, tv, l, split_count, split_frac);
+    }
+    for (int l = tv.depth; l >= 0; l--)
+        hipLaunchKernelGGL(k_lvl_hmax, grid_for(n), dim3(256), 0, st, tv, p.h, l);
+}
+
+void launch_tree_cells(const TreeView& tv, const BoxInfo* boxes, CellInfo* cells, int32_t* cell_map,
+                       int64_t map_total, uint32_t* cell_of, int32_t* ncells, double h_margin,
+                       uint32_t* scan_scratch, hipStream_t st)
+{
+    const int64_t n = tv.n;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_leaf_flags, grid_for(n), dim3(256), 0, st, tv);
+    exclusive_scan(tv.flag, tv.scan, n, scan_scratch, (uint32_t*)ncells, st);
+    hipLaunchKernelGGL(k_leaf_cells, grid_for(n), dim3(256), 0, st, tv, boxes, cells, cell_of, h_margin);
+    for (int l = tv.depth; l >= 0; l--)
+        hipLaunchKernelGGL(k_lvl_H, grid_for(n), dim3(256), 0, st, tv, cells, l);
+    launch_fill_i32(cell_map, map_total, -1, st);
+    hipLaunchKernelGGL(k_top_map, grid_for(n), dim3(256), 0, st, tv, boxes, cell_map);
+}
+
+void launch_tree_sources(const TreeView& tv, const CellInfo* cells, const int32_t* ncells, const BoxInfo* boxes,
+                         const int32_t* cell_map, Source* src, int64_t src_cap, int32_t* src_off,
+                         int32_t* src_count, uint32_t* status, uint32_t* scan_scratch, int64_t cell_cap,
+                         hipStream_t st)
+{
+    if (cell_cap <= 0) return;
+    hipLaunchKernelGGL(k_tree_sources<false>, grid_for(cell_cap), dim3(256), 0, st, tv, cells, ncells, boxes,
+                       cell_map, src, src_cap, src_off, src_count, status);
+    exclusive_scan((const uint32_t*)src_count, (uint32_t*)src_off, cell_cap, scan_scratch, nullptr, st);
+    hipLaunchKernelGGL(k_tree_sources<true>, grid_for(cell_cap), dim3(256), 0, st, tv, cells, ncells, boxes,
+                       cell_map, src, src_cap, src_off, src_count, status);
+}
+
+void launch_estimate_h(const TreeView& tv, const BoxInfo* boxes, double n_ngb, double* h, int64_t n,
+                       hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_estimate_h, grid_for(n), dim3(256), 0, st, tv, boxes, n_ngb, h);
+}
+
+}  // namespace sph

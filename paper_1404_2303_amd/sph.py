@@ -26,7 +26,7 @@ SPH_FP64, SPH_FP32_ACC64 = 0, 1
 EXPORTED = ["sph_default_params", "sph_create", "sph_destroy", "sph_build_cells", "sph_sort",
             "sph_density", "sph_force", "sph_step", "sph_get_stats", "sph_status_string",
             "sph_enable_timing", "sph_get_kernel_times", "sph_density_async", "sph_check",
-            "sph_graph_capture", "sph_graph_launch", "sph_backward"]
+            "sph_graph_capture", "sph_graph_launch", "sph_backward", "sph_estimate_h"]
 
 P = ctypes.c_void_p
 
@@ -36,7 +36,8 @@ class sph_params(ctypes.Structure):
                 ("max_iter", ctypes.c_int), ("gamma", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("balsara_eps", ctypes.c_double), ("precision", ctypes.c_int),
                 ("cell_target", ctypes.c_int), ("h_margin", ctypes.c_double),
-                ("max_rebuilds", ctypes.c_int)]
+                ("max_rebuilds", ctypes.c_int), ("max_depth", ctypes.c_int), ("split_count", ctypes.c_int),
+                ("split_frac", ctypes.c_double)]
 
 
 class sph_particles(ctypes.Structure):
@@ -75,7 +76,7 @@ class sph_grad_out(ctypes.Structure):
 class sph_stats(ctypes.Structure):
     _fields_ = [("n_cells", ctypes.c_int64), ("n_units", ctypes.c_int64), ("grid", ctypes.c_int32 * 3),
                 ("rebuilds", ctypes.c_int32), ("max_iter_used", ctypes.c_int32),
-                ("unconverged", ctypes.c_int32)]
+                ("unconverged", ctypes.c_int32), ("depth", ctypes.c_int32)]
 
 
 _lib = None
@@ -124,6 +125,8 @@ def load_library():
         lib.sph_backward.restype = st
         lib.sph_backward.argtypes = [P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_grad_in),
                                      ctypes.POINTER(sph_grad_out), ctypes.c_int, P]
+        lib.sph_estimate_h.restype = st
+        lib.sph_estimate_h.argtypes = [P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_batch), P]
         lib.sph_status_string.restype = ctypes.c_char_p
         lib.sph_status_string.argtypes = [st]
         _lib = lib
@@ -171,6 +174,11 @@ def sph_destroy(ctx):
 def sph_build_cells(ctx, parts: sph_particles, batch: Optional[sph_batch], stream):
     return load_library().sph_build_cells(ctx, ctypes.byref(parts),
                                           ctypes.byref(batch) if batch is not None else None, stream)
+
+
+def sph_estimate_h(ctx, parts: sph_particles, batch: Optional[sph_batch], stream):
+    return load_library().sph_estimate_h(ctx, ctypes.byref(parts), ctypes.byref(batch) if batch is not None else None,
+                                         stream)
 
 
 def sph_sort(ctx, stream):
@@ -300,6 +308,10 @@ class Context:
     def sort(self):
         _check(sph_sort(self.ctx, _stream()), "sph_sort")
 
+    def estimate_h(self, parts: Particles, batch: Optional[Batch] = None):
+        """Overwrite parts.h with the local-density estimate (needs max_depth >= 1)."""
+        _check(sph_estimate_h(self.ctx, parts.c_struct(), batch.c if batch else None, _stream()), "sph_estimate_h")
+
     def density(self, parts: Particles, want=DENSITY_FIELDS, allow_unconverged=False):
         n = parts.n
         dev = parts.x.device
@@ -391,7 +403,8 @@ class Context:
     def stats(self) -> dict:
         s = sph_stats()
         _check(load_library().sph_get_stats(self.ctx, ctypes.byref(s)), "sph_get_stats")
-        return {"n_cells": s.n_cells, "n_units": s.n_units, "grid": tuple(s.grid), "rebuilds": s.rebuilds}
+        return {"n_cells": s.n_cells, "n_units": s.n_units, "grid": tuple(s.grid), "rebuilds": s.rebuilds,
+                "depth": s.depth}
 
     def run(self, parts: Particles, batch: Optional[Batch] = None, allow_unconverged=False):
         """build -> sort -> density (h solved in place) -> force."""
