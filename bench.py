@@ -260,6 +260,69 @@ def adjoint_section(steps, warmup):
             "forward_backward_ms": float(np.median(fb))}
 
 
+def multires_section(steps, warmup, split_count=64):
+    """The 2,097,152-particle Plummer mixture (32 spheres, scale radii log-uniform
+    in [0.005, 0.05], 20% uniform background; h spans ~100x) on the hierarchical
+    decomposition, FP32 pair arithmetic.  First h from sph_estimate_h, solved
+    once outside the timed region; a timed step restores h to that solution
+    (the state a simulation step starts from) and runs build, sort, density
+    and force.  A cold pass from the estimate is timed once as well."""
+    import torch
+    from paper_1404_2303_amd import sph, workloads
+    ps = workloads.config2()
+    parts = sph.Particles.from_numpy(ps, "cuda:0")
+    ctx = sph.Context(ps.box, precision="fp32", max_depth=10, split_count=split_count)
+    ctx.enable_timing(True)
+    n = parts.n
+    fout = {k: torch.empty(n, dtype=torch.float64, device="cuda:0") for k in ("ax", "ay", "az", "dudt")}
+    fout["n_pairs"] = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    ctx.estimate_h(parts)
+    h_est = parts.h.clone()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    ctx.build_cells(parts)
+    ctx.sort()
+    ctx.density(parts, want=("n_dens",))
+    ctx.force(parts, out=fout)
+    end.record()
+    end.synchronize()
+    cold_ms = start.elapsed_time(end)
+    cold_rebuilds = ctx.stats()["rebuilds"]
+    h_sol = parts.h.clone()
+    del h_est
+
+    def step():
+        parts.h.copy_(h_sol)
+        ctx.build_cells(parts)
+        ctx.sort()
+        ctx.density(parts, want=("n_dens",))
+        ctx.force(parts, out=fout)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ms, kt = [], {"build_ms": [], "sort_ms": [], "density_ms": [], "force_ms": []}
+    for _ in range(steps):
+        start.record()
+        step()
+        end.record()
+        end.synchronize()
+        ms.append(start.elapsed_time(end))
+        t = ctx.kernel_times()
+        for k in kt:
+            kt[k].append(t[k])
+    P = int(fout["n_pairs"].sum().item())
+    st = ctx.stats()
+    ctx.close()
+    step_ms = float(np.median(ms))
+    return {"workload": "Plummer mixture: 32 spheres x 52,428 + 419,456 uniform background (2,097,152 particles), "
+                        "scale radii log-uniform [0.005, 0.05], periodic unit cube, v~N(0,0.1), u=1",
+            "n": n, "pairs_per_step": P, "value": P / (step_ms * 1e-3), "ms_per_step": step_ms,
+            "kernel_ms": {k: float(np.median(v)) for k, v in kt.items()},
+            "leaves": int(st["n_cells"]), "depth": int(st["depth"]), "top_grid": list(st["grid"]),
+            "split_count": split_count, "cold_pass_ms": cold_ms, "cold_rebuilds": int(cold_rebuilds)}
+
+
 class _BatchArgs:
     """Adapter: a Batch built lazily inside the timer (keeps host arrays alive)."""
 
@@ -307,6 +370,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 (plain) form")
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-box batched workload")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode timing")
+    ap.add_argument("--no-multires", action="store_true", help="skip the 2M-particle Plummer mixture")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -363,6 +427,9 @@ def main():
     if not args.no_batched:
         line["batched"] = batched_section(max(3, args.steps // 4), 2)
         log("batched:", json.dumps(line["batched"]))
+    if not args.no_multires:
+        line["multires"] = multires_section(max(3, args.steps // 2), 1)
+        log("multires:", json.dumps(line["multires"]))
     if not args.no_adjoint:
         line["adjoint"] = adjoint_section(args.steps, args.warmup)
         log("adjoint:", json.dumps(line["adjoint"]))
