@@ -55,7 +55,7 @@ struct sph_ctx {
     DBuf src_off;                                    // first source of each cell
     // hierarchy (max_depth > 0)
     DBuf t_chg, t_node_of, t_node_start, t_node_flag, t_node_hmax, t_node_H, t_node_leaf, t_nnodes;
-    DBuf t_flag, t_scan, t_small, t_psmall, t_lev;
+    DBuf t_flag, t_scan, t_small, t_psmall, t_lev, t_group;
     int depth = 0;                                   // levels below the top grid of the current build
     int64_t src_cap = 0;
     DBuf adj_ab, adj_sb0, adj_sb1, adj_x, adj_h, adj_fg;  // adjoint workspace
@@ -182,6 +182,7 @@ static bool ensure_particles(sph_ctx* c, int64_t n)
         ok &= c->t_node_leaf.ensure(L * S * 4) && c->t_nnodes.ensure(L * 4 + 16);
         ok &= c->t_flag.ensure(N * 4) && c->t_scan.ensure(S * 4);
         ok &= c->t_small.ensure(N * 4) && c->t_psmall.ensure(S * 4);
+        ok &= c->t_group.ensure((27 * N + 1) * 4) && c->sc_scratch.ensure(scan_scratch_words((int64_t)(27 * N)) * 4 + 16);
     }
     ok &= c->sidx.ensure(N * kSortDirs * 2) && c->srec.ensure(N * kSortDirs * 4 * R);
     ok &= c->rx.ensure(N * R) && c->ry.ensure(N * R) && c->rz.ensure(N * R);
@@ -280,7 +281,7 @@ sph_status sph_destroy(sph_ctx* c)
                    &c->sd0, &c->sd1, &c->adj_ab, &c->adj_sb0, &c->adj_sb1, &c->adj_x, &c->adj_h, &c->adj_fg,
                    &c->src_off, &c->t_chg, &c->t_node_of, &c->t_node_start, &c->t_node_flag, &c->t_node_hmax,
                    &c->t_node_H, &c->t_node_leaf, &c->t_nnodes, &c->t_flag, &c->t_scan, &c->t_small,
-                   &c->t_psmall, &c->t_lev};
+                   &c->t_psmall, &c->t_lev, &c->t_group};
     for (DBuf* b : all) b->release();
     if (c->status_host) (void)hipHostFree(c->status_host);
     if (c->ncells_host) (void)hipHostFree(c->ncells_host);
@@ -449,8 +450,8 @@ static void build_launches(sph_ctx* c, const Particles& pv, hipStream_t st)
     else
         launch_tree_sources(tree_view(c), c->cells.as<CellInfo>(), c->ncells.as<int32_t>(), boxes,
                             c->cell_map.as<int32_t>(), c->src.as<Source>(), c->src_cap, c->src_off.as<int32_t>(),
-                            c->src_count.as<int32_t>(), c->status.as<uint32_t>(), c->sc_scratch.as<uint32_t>(), n,
-                            st);
+                            c->src_count.as<int32_t>(), c->t_group.as<uint32_t>(), c->status.as<uint32_t>(),
+                            c->sc_scratch.as<uint32_t>(), n, st);
 }
 }  // extern "C++"
 

@@ -155,8 +155,8 @@ void launch_tree_cells(const TreeView& tv, const BoxInfo* boxes, CellInfo* cells
                        uint32_t* scan_scratch, hipStream_t st);
 void launch_tree_sources(const TreeView& tv, const CellInfo* cells, const int32_t* ncells, const BoxInfo* boxes,
                          const int32_t* cell_map, Source* src, int64_t src_cap, int32_t* src_off,
-                         int32_t* src_count, uint32_t* status, uint32_t* scan_scratch, int64_t cell_cap,
-                         hipStream_t st);
+                         int32_t* src_count, uint32_t* group, uint32_t* status, uint32_t* scan_scratch,
+                         int64_t cell_cap, hipStream_t st);
 void launch_estimate_h(const TreeView& tv, const BoxInfo* boxes, double n_ngb, double* h, int64_t n,
                        hipStream_t st);
 

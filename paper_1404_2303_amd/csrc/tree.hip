@@ -186,17 +186,31 @@ __global__ void k_top_map(TreeView tv, const BoxInfo* boxes, int32_t* cell_map)
 // ---------------------------------------------------------------- interaction lists
 constexpr int kTreeStack = 112;
 
+// The one of the 26 cell-pair axes closest to v: the unit vectors along one,
+// two or three of v's largest components (with v's signs) are the only
+// candidates; take the one with the largest projection of v.
 __device__ inline int nearest_dir(double vx, double vy, double vz)
 {
-    int best = 0;
-    double bv = -INFINITY;
-    for (int d = 0; d < kDirs; d++) {
-        float u[3];
-        dir_unit(d, u);
-        const double v = u[0] * vx + u[1] * vy + u[2] * vz;
-        if (v > bv) { bv = v; best = d; }
+    const double v[3] = {vx, vy, vz};
+    const double a[3] = {fabs(vx), fabs(vy), fabs(vz)};
+    int i0 = 0, i1 = 1, i2 = 2;
+    if (a[i1] > a[i0]) { const int t = i0; i0 = i1; i1 = t; }
+    if (a[i2] > a[i0]) { const int t = i0; i0 = i2; i2 = t; }
+    if (a[i2] > a[i1]) { const int t = i1; i1 = i2; i2 = t; }
+    const double s1 = a[i0];
+    const double s2 = (a[i0] + a[i1]) * 0.70710678118654752;
+    const double s3 = (a[i0] + a[i1] + a[i2]) * 0.57735026918962576;
+    int o[3] = {0, 0, 0};
+    if (s3 >= s2 && s3 >= s1) {
+        for (int k = 0; k < 3; k++) o[k] = v[k] >= 0.0 ? 1 : -1;
+    } else if (s2 >= s1) {
+        o[i0] = v[i0] >= 0.0 ? 1 : -1;
+        o[i1] = v[i1] >= 0.0 ? 1 : -1;
+    } else {
+        o[i0] = v[i0] >= 0.0 ? 1 : -1;
     }
-    return best;
+    const int idx = (o[0] + 1) * 9 + (o[1] + 1) * 3 + (o[2] + 1);  // 13 is the centre
+    return idx < 13 ? idx : idx - 1;
 }
 
 // relative sweep cost of a source by direction type (face, edge, corner)
@@ -208,12 +222,18 @@ __device__ inline float dir_weight(int d)
     return nz == 1 ? 1.0f : (nz == 2 ? 0.7f : 0.5f);
 }
 
+// One thread per (leaf T, top cell around T's): walk that top cell's subtree,
+// opening nodes within reach, and count (FILL = false) or write the leaves
+// found, in a group of 27 per leaf whose offsets come from a scan of the
+// counts.  The wavefront of each source is assigned afterwards.
 template <bool FILL>
 __global__ void k_tree_sources(TreeView tv, const CellInfo* cells, const int32_t* ncells, const BoxInfo* boxes,
-                               const int32_t* cell_map, Source* src, int64_t src_cap, const int32_t* src_off,
-                               int32_t* src_count, uint32_t* status)
+                               const int32_t* cell_map, Source* src, int64_t src_cap, uint32_t* group,
+                               uint32_t* status)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = g / 27;
+    const int oi = (int)(g - t * 27);
     if (t >= *ncells) return;
     const CellInfo T = cells[t];
     const BoxInfo& B = boxes[T.box];
@@ -221,25 +241,23 @@ __global__ void k_tree_sources(TreeView tv, const CellInfo* cells, const int32_t
     const int64_t sT = 1ll << (D - T.level);
     const double ef[3] = {ldexp(B.e[0], -D), ldexp(B.e[1], -D), ldexp(B.e[2], -D)};
     const double HT = T.hlim;
-    const int64_t base = FILL ? src_off[t] : 0;
+    const int64_t base = FILL ? (int64_t)group[g] : 0;
     int cnt = 0;
-    float cost[kSweepWaves] = {0.f, 0.f, 0.f, 0.f};
-    int stack[kTreeStack];
-    for (int oi = 0; oi < 27; oi++) {
-        const int o[3] = {oi / 9 - 1, (oi / 3) % 3 - 1, oi % 3 - 1};
-        int tc[3];
-        int64_t shift[3];
-        for (int d = 0; d < 3; d++) {
-            int v = (T.c[d] >> D) + o[d];
-            shift[d] = 0;
-            if (v < 0) { v += B.nc[d]; shift[d] = -((int64_t)B.nc[d] << D); }
-            else if (v >= B.nc[d]) { v -= B.nc[d]; shift[d] = (int64_t)B.nc[d] << D; }
-            tc[d] = v;
-        }
-        const int32_t m0 = cell_map[B.map_off + ((int64_t)tc[0] * B.nc[1] + tc[1]) * B.nc[2] + tc[2]];
-        if (m0 < 0) continue;
+    const int o[3] = {oi / 9 - 1, (oi / 3) % 3 - 1, oi % 3 - 1};
+    int tc[3];
+    int64_t shift[3];
+    for (int d = 0; d < 3; d++) {
+        int v = (T.c[d] >> D) + o[d];
+        shift[d] = 0;
+        if (v < 0) { v += B.nc[d]; shift[d] = -((int64_t)B.nc[d] << D); }
+        else if (v >= B.nc[d]) { v -= B.nc[d]; shift[d] = (int64_t)B.nc[d] << D; }
+        tc[d] = v;
+    }
+    const int32_t m0 = cell_map[B.map_off + ((int64_t)tc[0] * B.nc[1] + tc[1]) * B.nc[2] + tc[2]];
+    if (m0 >= 0) {
+        int stack[kTreeStack];
         int sp = 0;
-        stack[sp++] = m0;  // node index in the low 27 bits, level in the high bits
+        stack[sp++] = m0;  // node index in the low 27 bits, level above
         while (sp > 0) {
             const int e = stack[--sp];
             const int l = e >> 27, m = e & ((1 << 27) - 1);
@@ -255,8 +273,8 @@ __global__ void k_tree_sources(TreeView tv, const CellInfo* cells, const int32_t
                 cn[d] = (int64_t)((cf[d] >> (D - l)) << (D - l)) + shift[d];
                 const int64_t a0 = T.c[d], a1 = T.c[d] + sT, b0 = cn[d], b1 = cn[d] + sN;
                 const int64_t gap = b0 > a1 ? b0 - a1 : (a0 > b1 ? a0 - b1 : 0);
-                const double g = (double)gap * ef[d];
-                dist2 += g * g;
+                const double gd = (double)gap * ef[d];
+                dist2 += gd * gd;
             }
             const double R = fmax(HT, (double)tv.node_H[lo]);
             if (dist2 >= R * R) continue;
@@ -270,27 +288,21 @@ __global__ void k_tree_sources(TreeView tv, const CellInfo* cells, const int32_t
             }
             const int32_t q = tv.node_leaf[lo];
             if (q < 0) continue;  // not reachable for a live tree
-            const bool self = q == (int32_t)t && shift[0] == 0 && shift[1] == 0 && shift[2] == 0;
             if (FILL) {
                 Source s;
                 s.cell = q;
+                s.wave = 0;
                 s.ox = (int16_t)(cn[0] - T.c[0]);
                 s.oy = (int16_t)(cn[1] - T.c[1]);
                 s.oz = (int16_t)(cn[2] - T.c[2]);
-                if (self) {
+                if (q == (int32_t)t && oi == 13) {
                     s.dir = (int8_t)kSelfDir;
                     s.wave = (int8_t)kAllWaves;
                 } else {
                     // direction between the centres, in length units
-                    const double vx = (double)(2 * cn[0] + sN - 2 * T.c[0] - sT) * ef[0];
-                    const double vy = (double)(2 * cn[1] + sN - 2 * T.c[1] - sT) * ef[1];
-                    const double vz = (double)(2 * cn[2] + sN - 2 * T.c[2] - sT) * ef[2];
-                    const int d = nearest_dir(vx, vy, vz);
-                    int wv = 0;
-                    for (int k = 1; k < kSweepWaves; k++) if (cost[k] < cost[wv]) wv = k;
-                    cost[wv] += (float)(end - start) * dir_weight(d);
-                    s.dir = (int8_t)d;
-                    s.wave = (int8_t)wv;
+                    s.dir = (int8_t)nearest_dir((double)(2 * cn[0] + sN - 2 * T.c[0] - sT) * ef[0],
+                                                (double)(2 * cn[1] + sN - 2 * T.c[1] - sT) * ef[1],
+                                                (double)(2 * cn[2] + sN - 2 * T.c[2] - sT) * ef[2]);
                 }
                 if (base + cnt < src_cap) src[base + cnt] = s;
                 else atomicOr(status, ST_CAPACITY);
@@ -298,7 +310,29 @@ __global__ void k_tree_sources(TreeView tv, const CellInfo* cells, const int32_t
             cnt++;
         }
     }
-    if (!FILL) src_count[t] = cnt;
+    if (!FILL) group[g] = (uint32_t)cnt;
+}
+
+// Per leaf: its list's offset and length, and the wavefront of each source,
+// greedily to the least loaded (cost: source count by direction type).
+__global__ void k_src_finish(const CellInfo* cells, const int32_t* ncells, const uint32_t* group, Source* src,
+                             int64_t src_cap, int32_t* src_off, int32_t* src_count)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= *ncells) return;
+    const int64_t b = group[27 * t], e = group[27 * t + 27];
+    src_off[t] = (int32_t)b;
+    src_count[t] = (int32_t)(e - b);
+    float cost[kSweepWaves] = {0.f, 0.f, 0.f, 0.f};
+    const int64_t end = e < src_cap ? e : src_cap;
+    for (int64_t k = b; k < end; k++) {
+        Source s = src[k];
+        if (s.dir == kSelfDir) continue;
+        int wv = 0;
+        for (int w = 1; w < kSweepWaves; w++) if (cost[w] < cost[wv]) wv = w;
+        cost[wv] += (float)cells[s.cell].count * dir_weight(s.dir);
+        src[k].wave = (int8_t)wv;
+    }
 }
 
 // h from the local number density: the particle count of the deepest node
@@ -365,15 +399,18 @@ void launch_tree_cells(const TreeView& tv, const BoxInfo* boxes, CellInfo* cells
 
 void launch_tree_sources(const TreeView& tv, const CellInfo* cells, const int32_t* ncells, const BoxInfo* boxes,
                          const int32_t* cell_map, Source* src, int64_t src_cap, int32_t* src_off,
-                         int32_t* src_count, uint32_t* status, uint32_t* scan_scratch, int64_t cell_cap,
-                         hipStream_t st)
+                         int32_t* src_count, uint32_t* group, uint32_t* status, uint32_t* scan_scratch,
+                         int64_t cell_cap, hipStream_t st)
 {
     if (cell_cap <= 0) return;
-    hipLaunchKernelGGL(k_tree_sources<false>, grid_for(cell_cap), dim3(256), 0, st, tv, cells, ncells, boxes,
-                       cell_map, src, src_cap, src_off, src_count, status);
-    exclusive_scan((const uint32_t*)src_count, (uint32_t*)src_off, cell_cap, scan_scratch, nullptr, st);
-    hipLaunchKernelGGL(k_tree_sources<true>, grid_for(cell_cap), dim3(256), 0, st, tv, cells, ncells, boxes,
-                       cell_map, src, src_cap, src_off, src_count, status);
+    const int64_t ng = 27 * cell_cap;
+    hipLaunchKernelGGL(k_tree_sources<false>, grid_for(ng), dim3(256), 0, st, tv, cells, ncells, boxes, cell_map,
+                       src, src_cap, group, status);
+    exclusive_scan(group, group, ng, scan_scratch, group + ng, st);
+    hipLaunchKernelGGL(k_tree_sources<true>, grid_for(ng), dim3(256), 0, st, tv, cells, ncells, boxes, cell_map,
+                       src, src_cap, group, status);
+    hipLaunchKernelGGL(k_src_finish, grid_for(cell_cap), dim3(256), 0, st, cells, ncells, group, src, src_cap,
+                       src_off, src_count);
 }
 
 void launch_estimate_h(const TreeView& tv, const BoxInfo* boxes, double n_ngb, double* h, int64_t n,
