@@ -137,7 +137,7 @@ __global__ __launch_bounds__(WGS) void k_adj_sweep(Decomp dc, CellData<R> cd, So
     using SM = Smem<R, NACC_ADJ, true>;
     __shared__ SM s;
     const int tid = threadIdx.x;
-    const int w = tid >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: the wavefront index
     const int lane = tid & (kWave - 1);
     const int ncells = *dc.ncells;
     const R alpha = (R)pc.alpha;

@@ -417,6 +417,60 @@ __global__ void k_sources(const CellInfo* cells, const int32_t* ncells, const Bo
 constexpr int SORT_THREADS = 64;
 constexpr int SORT_MAX = 4096;
 
+// order-preserving integer image of a float (a total order, NaN included)
+__device__ inline uint32_t float_key(float f)
+{
+    const uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ inline float key_float(uint32_t k) { return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k); }
+
+// Cells of at most one wavefront of particles: one wavefront per cell, the
+// particle of lane t loaded once, and for each of the 13 directions a bitonic
+// sort across the lanes of (key, t), so ties keep the cell order.
+template <typename R>
+__global__ __launch_bounds__(kWave) void k_sort13_wave(const CellInfo* cells, const int32_t* ncells, CellData<R> cd,
+                                                       int64_t n, Sorted<R> so)
+{
+    const int lane = threadIdx.x;
+    const int nc = *ncells;
+    for (int c = blockIdx.x; c < nc; c += gridDim.x) {
+        const CellInfo C = cells[c];
+        if (C.count > kWave) continue;
+        const bool in = lane < C.count;
+        const int64_t k = C.start + (in ? lane : 0);
+        const R x = cd.rx[k], y = cd.ry[k], z = cd.rz[k];
+        for (int s = 0; s < kSortDirs; s++) {
+            float su[3];
+            dir_unit(s + 13, su);
+            const float f = su[0] * (float)x + su[1] * (float)y + su[2] * (float)z;
+            uint64_t v = in ? (((uint64_t)float_key(f) << 32) | (uint32_t)lane) : ~0ull;
+#pragma unroll
+            for (int kk = 2; kk <= kWave; kk <<= 1) {
+#pragma unroll
+                for (int j = kk >> 1; j > 0; j >>= 1) {
+                    const uint64_t o = __shfl_xor(v, j, kWave);
+                    const bool keep_min = ((lane & j) == 0) == ((lane & kk) == 0);
+                    v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
+                }
+            }
+            // lane r now holds the element of rank r
+            const int t = (int)(v & 0xffffffffu);
+            const R xt = __shfl(x, in ? t : 0, kWave), yt = __shfl(y, in ? t : 0, kWave),
+                    zt = __shfl(z, in ? t : 0, kWave);
+            if (in) {
+                const int64_t o = (int64_t)s * n + C.start + lane;
+                so.idx[o] = (uint16_t)t;
+                typename Sorted<R>::R4 r;
+                r.x = xt; r.y = yt; r.z = zt; r.w = (R)key_float((uint32_t)(v >> 32));
+                so.rec[o] = r;
+            }
+        }
+    }
+}
+
+// Larger cells: one workgroup per (cell, direction); each particle's rank is
+// the number of particles with a smaller key, ties broken by cell order.
 template <typename R>
 __global__ __launch_bounds__(SORT_THREADS) void k_sort13(const CellInfo* cells, const int32_t* ncells,
                                                          CellData<R> cd, int64_t n, Sorted<R> so,
@@ -428,6 +482,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort13(const CellInfo* cells, 
         const int c = (int)(unit / kSortDirs);
         const int s = (int)(unit % kSortDirs);
         const CellInfo C = cells[c];
+        if (C.count <= kWave) continue;  // sorted by k_sort13_wave
         if (C.count > SORT_MAX) { if (threadIdx.x == 0) atomicOr(status, ST_CAPACITY); continue; }
         float su[3];
         dir_unit(s + 13, su);
@@ -578,6 +633,9 @@ template <typename R>
 void launch_sort13(const CellInfo* cells, const int32_t* ncells, const CellData<R>& cd, int64_t n,
                    const Sorted<R>& so, uint32_t* status, int64_t cell_cap, hipStream_t st)
 {
+    unsigned gw = (unsigned)(cell_cap < 65536 ? cell_cap : 65536);
+    if (gw < 1) gw = 1;
+    hipLaunchKernelGGL(k_sort13_wave<R>, dim3(gw), dim3(kWave), 0, st, cells, ncells, cd, n, so);
     int64_t units = cell_cap * kSortDirs;
     unsigned grid = (unsigned)(units < 65536 ? units : 65536);
     if (grid < 1) grid = 1;

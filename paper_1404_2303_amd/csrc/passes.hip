@@ -95,7 +95,7 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
     using SM = Smem<R, NACC_D, false>;
     __shared__ SM s;
     const int tid = threadIdx.x;
-    const int w = tid >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: the wavefront index
     const int lane = tid & (kWave - 1);
     const int ncells = *dc.ncells;
     const double kNorm = 8.0 / kPi;
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
     using SM = Smem<R, NACC_F, true>;
     __shared__ SM s;
     const int tid = threadIdx.x;
-    const int w = tid >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: the wavefront index
     const int lane = tid & (kWave - 1);
     const int ncells = *dc.ncells;
     const R alpha = (R)pc.alpha;

@@ -15,6 +15,8 @@ constexpr int kMaxSegW = 28;          // staged segments per wavefront and batch
 constexpr int NACC_D = 9;             // density partial sums per target
 constexpr int NACC_F = 5;             // force partial sums per target
 constexpr float kCacheSlack = 0.08f;  // neighbour lists cover h (1 + slack)
+constexpr int WALK_STEP = 4;          // staged particles tested per walk step
+constexpr int WALK_PAD = WALK_STEP - 1;
 
 // staged particles per wavefront and list slots per lane (density lists also
 // serve the Newton iteration, so they are longer)
@@ -79,8 +81,10 @@ struct Smem {
     using R4 = typename Vec4T<R>::T;
     static constexpr int CAPW = PCfg<R, STAGE_H>::CAPW;
     static constexpr int LISTW = PCfg<R, STAGE_H>::LISTW;
-    R4 st[NW][CAPW];                  // staged (x, y, z in T's frame, projection on the segment axis)
-    R sh[NW][STAGE_H ? CAPW : 1];     // pair range max(h_i, h_j): h of each staged particle
+    // staged (x, y, z in T's frame, projection on the segment axis); the walk
+    // reads up to WALK_PAD entries past a segment's end (masked off)
+    R4 st[NW][CAPW + WALK_PAD];
+    R sh[NW][STAGE_H ? CAPW + WALK_PAD : 1];  // pair range max(h_i, h_j): h^2 of each staged particle
     uint32_t sg[NW][CAPW];            // cell-order index of each staged particle
     uint16_t list[NW][LISTW][kWave];  // per-lane neighbour lists (staged indices)
     double red[NACC][kWave];          // partial sums of the four wavefronts
@@ -150,7 +154,7 @@ __device__ void stage_wave(Smem<R, NACC, FORCE>& s, const int w, const Decomp& d
                 e.x = cd.rx[g]; e.y = cd.ry[g]; e.z = cd.rz[g];
                 e.w = (R)0;
                 s.st[w][fill + t] = e;
-                if constexpr (FORCE) s.sh[w][fill + t] = gd.g1[g].z;
+                if constexpr (FORCE) { const R hj = gd.g1[g].z; s.sh[w][fill + t] = hj * hj; }
                 s.sg[w][fill + t] = (uint32_t)g;
             }
             if (lane == 0) { s.self_b[w] = fill; s.self_t0[w] = q0 + p; s.self_n[w] = take; }
@@ -190,7 +194,7 @@ __device__ void stage_wave(Smem<R, NACC, FORCE>& s, const int w, const Decomp& d
                     // projection on the segment axis, recomputed from the shifted position
                     e.w = (R)(u[0] * (float)e.x + u[1] * (float)e.y + u[2] * (float)e.z);
                     s.st[w][fill + lane] = e;
-                    if constexpr (FORCE) s.sh[w][fill + lane] = gd.g1[g].z;
+                    if constexpr (FORCE) { const R hj = gd.g1[g].z; s.sh[w][fill + lane] = hj * hj; }
                     s.sg[w][fill + lane] = (uint32_t)g;
                 }
                 fill += take;
@@ -222,12 +226,16 @@ __device__ __forceinline__ int self_index(const Smem<R, NACC, F>& s, int w, int 
     return (d >= 0 && d < s.self_n[w]) ? s.self_b[w] + d : -1;
 }
 
+__device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // Walk of wavefront w over its staged segments, one segment at a time for
 // all lanes together: every lane reads the same staged particle (an LDS
 // broadcast), tests it against its own bound and radius, and appends it to
 // its list when in range.  The segment is left as soon as no lane is still
 // within its projected bound (the early exit of the sorted sweep).  The
-// walk state (seg, jj) is uniform; the call returns early when some lane's
+// walk state (seg, jj) is uniform and kept in scalar registers; four staged
+// particles are tested per step.  The call returns early when some lane's
 // list might overflow in the next step (lists hold at most LISTW entries),
 // and resumes from (seg, jj).
 template <typename R, bool FORCE, int NACC>
@@ -236,51 +244,67 @@ __device__ __forceinline__ int walk(Smem<R, NACC, FORCE>& s, int w, int lane, bo
                                     int& jj_io, int cnt)
 {
     constexpr int LISTW = Smem<R, NACC, FORCE>::LISTW;
-    const int nseg = s.nseg[w];
+    constexpr int STEP = WALK_STEP;
+    const int nseg = uniform(s.nseg[w]);
     const R rad2 = rad * rad;
-    int seg = __builtin_amdgcn_readfirstlane(seg_io);
-    int jj = __builtin_amdgcn_readfirstlane(jj_io);
+    int seg = uniform(seg_io);
+    int jj = uniform(jj_io);
     uint16_t* lst = &s.list[w][0][lane];
+    bool full = false;
     while (seg < nseg) {
-        const int je = s.seg_e[w][seg];
+        const int je = uniform(s.seg_e[w][seg]);
         const float ux = s.seg_u[w][seg][0], uy = s.seg_u[w][seg][1], uz = s.seg_u[w][seg][2];
         const float hx = s.seg_hx[w][seg];
-        const bool self = (ux == 0.0f) & (uy == 0.0f) & (uz == 0.0f);
-        const float bound = !act ? -INFINITY : (self ? INFINITY : ux * fxi + uy * fyi + uz * fzi + fmaxf(fh, hx) + margin);
-        bool more = true;
-        for (; jj < je; jj += 2) {
-            // a step appends at most two entries: leave while every list still has room for
-            // them (checked at every step, also the first of a segment)
-            if (__any(cnt > LISTW - 2)) { seg_io = seg; jj_io = jj; return cnt; }
-            // two staged particles per step (the second may lie past the segment end)
-            const bool two = jj + 1 < je;
-            const auto e0 = s.st[w][jj];
-            const auto e1 = s.st[w][two ? jj + 1 : jj];
-            const float p0 = (float)e0.w, p1 = (float)e1.w;
-            const bool in0 = p0 <= bound;
-            const bool in1 = (p1 <= bound) & two;
-            if (!__any(in0)) { more = false; break; }
-            const R dx0 = xi - e0.x, dy0 = yi - e0.y, dz0 = zi - e0.z;
-            const R dx1 = xi - e1.x, dy1 = yi - e1.y, dz1 = zi - e1.z;
-            const R r20 = dx0 * dx0 + dy0 * dy0 + dz0 * dz0;
-            const R r21 = dx1 * dx1 + dy1 * dy1 + dz1 * dz1;
-            R l0 = rad2, l1 = rad2;
-            if constexpr (FORCE) {
-                const R hm0 = rad > s.sh[w][jj] ? rad : s.sh[w][jj];
-                const R hm1 = rad > s.sh[w][jj + (two ? 1 : 0)] ? rad : s.sh[w][jj + (two ? 1 : 0)];
-                l0 = hm0 * hm0; l1 = hm1 * hm1;
+        // the self segment has u = 0; a uniform flag
+        const bool self = uniform((ux == 0.0f) & (uy == 0.0f) & (uz == 0.0f)) != 0;
+        auto test = [&](int j, R& r2, R& lim) {
+            const auto e = s.st[w][j];  // past the segment end: any value, masked by the caller
+            const R dx = xi - e.x, dy = yi - e.y, dz = zi - e.z;
+            r2 = dx * dx + dy * dy + dz * dz;
+            lim = rad2;
+            if constexpr (FORCE) lim = fmax(rad2, s.sh[w][j]);
+            return (float)e.w;
+        };
+        if (self) {
+            // the whole self segment is within every bound; skip the target itself
+            while (jj < je) {
+                if (wave_any(cnt > LISTW - STEP)) { full = true; break; }
+#pragma unroll
+                for (int k = 0; k < STEP; k++) {
+                    const int j = jj + k;
+                    R r2, lim;
+                    (void)test(j, r2, lim);
+                    const bool hit = (j < je) & act & (r2 < lim) & (j != selfj);
+                    lst[cnt * kWave] = (uint16_t)j;  // slot cnt is free; kept only on a hit
+                    cnt += hit ? 1 : 0;
+                }
+                jj += STEP;
             }
-            const bool hit0 = in0 & (r20 < l0) & (jj != selfj);
-            const bool hit1 = in1 & (r21 < l1) & (jj + 1 != selfj);
-            lst[cnt * kWave] = (uint16_t)jj;        // slot cnt is free; kept only on a hit
-            cnt += hit0 ? 1 : 0;
-            lst[cnt * kWave] = (uint16_t)(jj + 1);
-            cnt += hit1 ? 1 : 0;
-            if (!__any(in1)) { more = false; jj += 2; break; }
+        } else {
+            const float bound = !act ? -INFINITY : ux * fxi + uy * fyi + uz * fzi + fmaxf(fh, hx) + margin;
+            while (jj < je) {
+                if (wave_any(cnt > LISTW - STEP)) { full = true; break; }
+                bool in_last = false;
+#pragma unroll
+                for (int k = 0; k < STEP; k++) {
+                    const int j = jj + k;
+                    R r2, lim;
+                    const float p = test(j, r2, lim);
+                    const bool inb = (j < je) & (p <= bound);
+                    const bool hit = inb & (r2 < lim);
+                    lst[cnt * kWave] = (uint16_t)j;
+                    cnt += hit ? 1 : 0;
+                    if (k == STEP - 1) in_last = inb;
+                }
+                jj += STEP;
+                // projections grow along the segment: once the last entry of a step
+                // is beyond every lane's bound, so is the rest of the segment
+                if (!wave_any(in_last)) break;
+            }
         }
-        (void)more;
+        if (full) break;
         seg++;
-        jj = seg < nseg ? s.seg_b[w][seg] : 0;
+        jj = seg < nseg ? uniform(s.seg_b[w][seg]) : 0;
     }
     seg_io = seg;
     jj_io = jj;
