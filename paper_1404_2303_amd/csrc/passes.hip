@@ -133,7 +133,7 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
             const R4 vmi = cd.vm[gi];
             const float fxi = (float)xi, fyi = (float)yi, fzi = (float)zi;
             double h = cd.h[gi];
-            // Newton state (kept by wavefront 0)
+            // Newton state (identical in every wavefront)
             double lo = 0.0, hi = INFINITY, h_rebuild = 0.0;
             int iters = 0;
             bool failed = false;
@@ -207,63 +207,102 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
                 cached_all = __all(act || !valid);
             };
 
-            // ---- Newton iteration on h (Eq. (3)) in FP64, safeguarded by a bracket
+            // ---- Newton iteration on h (Eq. (3)) in FP64, safeguarded by a bracket.
+            // The iteration runs on g(h) = N(h)^(1/3) - n_ngb^(1/3), which is close
+            // to linear in h (N grows like h^3), so it needs fewer steps than
+            // Newton on N itself; the root is the same.  The two sums of each
+            // evaluation are added across the wavefronts into one of three LDS
+            // buffers, so one barrier per step suffices: every wavefront then
+            // takes the same step for its 64 targets.
+            const double cbrt_ngb = cbrt(pc.n_ngb);
+            // A step so small that the next residual is predicted far below the
+            // tolerance: the next evaluation takes every sum, and the iteration
+            // ends there if it confirms convergence.  Once every lane has
+            // converged, one evaluation with every sum ends it too.
+            const double step_final = sqrt(pc.tol / (10.0 * pc.n_ngb));
+            bool full = false;
+            int cit = 0;  // count steps since the buffers were last cleared
+            for (int a = w; a < 2; a += NW) s.red[a][lane] = 0.0;
+            __syncthreads();
             while (true) {
-                for (int a = w; a < 2; a += NW) s.red[a][lane] = 0.0;
-                __syncthreads();
-                evaluate(!conv, false);
-                if (!conv) {
-                    atomicAdd(&s.red[0][lane], acc.w);
-                    atomicAdd(&s.red[1][lane], acc.qdw);
-                }
-                __syncthreads();
-                if (w == 0) {
-                    bool restage = false;
+                if (full) {
+                    // ---- every sum at the current h, into s.red[0..8]
+                    __syncthreads();  // every wavefront has read the last step's sums
+                    for (int a = w; a < NACC_D; a += NW) s.red[a][lane] = 0.0;
+                    __syncthreads();
+                    evaluate(valid, true);
+                    if (valid) {
+                        atomicAdd(&s.red[0][lane], acc.w);
+                        atomicAdd(&s.red[1][lane], acc.qdw);
+                        atomicAdd(&s.red[2][lane], acc.mw);
+                        atomicAdd(&s.red[3][lane], acc.mqdw);
+                        atomicAdd(&s.red[4][lane], acc.div);
+                        atomicAdd(&s.red[5][lane], acc.cx);
+                        atomicAdd(&s.red[6][lane], acc.cy);
+                        atomicAdd(&s.red[7][lane], acc.cz);
+                        atomicAdd(&s.red[8][lane], acc.n);
+                    }
+                    __syncthreads();
                     if (!conv) {
                         iters++;
                         const double N = 32.0 / 3.0 * (s.red[0][lane] + 1.0);
-                        const double dN = -32.0 / 3.0 / h * s.red[1][lane];
-                        const double f = N - pc.n_ngb;
-                        if (fabs(f) <= pc.tol) {
-                            conv = true;
-                        } else if (iters >= pc.max_iter) {
-                            conv = true; failed = true;
-                        } else {
-                            if (f < 0.0) lo = h; else hi = h;
-                            double hn = h - f / dN;
-                            const bool ok = (dN > 0.0) && (hn > lo) && (hn < hi) && (hn >= 0.5 * h) && (hn <= 2.0 * h);
-                            if (!ok) hn = isinf(hi) ? 2.0 * h : 0.5 * (lo + hi);
-                            if (hn > h_lim) {
-                                if (h >= h_lim) {  // the root lies beyond what the cells allow
-                                    atomicOr(dc.status, ST_REBUILD);
-                                    conv = true; failed = true;
-                                    // the next build takes it from here, within what a
-                                    // periodic box allows (three cells of edge >= h)
-                                    h_rebuild = fmin(hn, h_box);
-                                } else {
-                                    hn = h_lim;
-                                }
-                            }
-                            if (!conv) {
-                                h = hn;
-                                restage = (float)h > Hst;
-                            }
-                        }
+                        if (fabs(N - pc.n_ngb) <= pc.tol) conv = true;
                     }
-                    s.hsh[lane] = h;
-                    s.conv[lane] = conv;
-                    const bool all = __all(conv);
-                    const bool any_restage = __any(restage);
-                    if (lane == 0) { s.ctl[0] = all; s.ctl[1] = any_restage; }
+                    if (__all(conv)) break;
+                    // not yet: back to the steps, with cleared buffers
+                    full = false;
+                    cit = 0;
+                    __syncthreads();
+                    for (int a = w; a < 2; a += NW) s.red[a][lane] = 0.0;
+                    __syncthreads();
+                }
+                const int rb = 2 * (cit % 3);        // this step's buffer
+                const int zb = 2 * ((cit + 1) % 3);  // the next step's buffer: last read two steps ago
+                cit++;
+                if (w < 2) s.red[zb + w][lane] = 0.0;
+                evaluate(!conv, false);
+                if (!conv) {
+                    atomicAdd(&s.red[rb][lane], acc.w);
+                    atomicAdd(&s.red[rb + 1][lane], acc.qdw);
                 }
                 __syncthreads();
-                h = s.hsh[lane];
-                conv = s.conv[lane];
-                const bool all = s.ctl[0];
-                const bool rs = s.ctl[1];
-                __syncthreads();
-                if (all) break;
-                if (rs) {
+                bool restage = false;
+                bool close = true;
+                if (!conv) {
+                    iters++;
+                    const double N = 32.0 / 3.0 * (s.red[rb][lane] + 1.0);
+                    const double dN = -32.0 / 3.0 / h * s.red[rb + 1][lane];
+                    const double f = N - pc.n_ngb;
+                    if (fabs(f) <= pc.tol) {
+                        conv = true;
+                    } else if (iters >= pc.max_iter) {
+                        conv = true; failed = true;
+                    } else {
+                        if (f < 0.0) lo = h; else hi = h;
+                        // Newton on g: h - g / g', g' = N' / (3 N^(2/3))
+                        const double c = cbrt(N);
+                        double hn = h - 3.0 * c * c * (c - cbrt_ngb) / dN;
+                        const bool ok = (dN > 0.0) && (hn > lo) && (hn < hi) && (hn >= 0.5 * h) && (hn <= 2.0 * h);
+                        if (!ok) hn = isinf(hi) ? 2.0 * h : 0.5 * (lo + hi);
+                        if (hn > h_lim) {
+                            if (h >= h_lim) {  // the root lies beyond what the cells allow
+                                if (w == 0) atomicOr(dc.status, ST_REBUILD);
+                                conv = true; failed = true;
+                                // the next build takes it from here, within what a
+                                // periodic box allows (three cells of edge >= h)
+                                h_rebuild = fmin(hn, h_box);
+                            } else {
+                                hn = h_lim;
+                            }
+                        }
+                        if (!conv) {
+                            close = fabs(hn - h) <= step_final * h;
+                            h = hn;
+                            restage = (float)h > Hst;
+                        }
+                    }
+                }
+                if (__any(restage)) {
                     const double hm = wave_max(conv ? 0.0 : h);
                     Hst = (float)fmin(fmax((double)Hst, hm * (1.0 + pc.h_margin)), h_lim);
                     k = 0; p = 0;
@@ -271,24 +310,8 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
                     single = k >= nsrc;
                     cached = false;
                 }
+                full = __all(close);  // every lane converged, or its next residual is negligible
             }
-
-            // ---- every sum at the solved h
-            for (int a = w; a < NACC_D; a += NW) s.red[a][lane] = 0.0;
-            __syncthreads();
-            evaluate(valid, true);
-            if (valid) {
-                atomicAdd(&s.red[0][lane], acc.w);
-                atomicAdd(&s.red[1][lane], acc.qdw);
-                atomicAdd(&s.red[2][lane], acc.mw);
-                atomicAdd(&s.red[3][lane], acc.mqdw);
-                atomicAdd(&s.red[4][lane], acc.div);
-                atomicAdd(&s.red[5][lane], acc.cx);
-                atomicAdd(&s.red[6][lane], acc.cy);
-                atomicAdd(&s.red[7][lane], acc.cz);
-                atomicAdd(&s.red[8][lane], acc.n);
-            }
-            __syncthreads();
 
             // ---- per-particle quantities between the stages (wavefront 0)
             if (w == 0 && valid) {

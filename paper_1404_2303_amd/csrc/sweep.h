@@ -88,14 +88,11 @@ struct Smem {
     uint32_t sg[NW][CAPW];            // cell-order index of each staged particle
     uint16_t list[NW][LISTW][kWave];  // per-lane neighbour lists (staged indices)
     double red[NACC][kWave];          // partial sums of the four wavefronts
-    double hsh[kWave];                // current h of each target (density)
     int seg_b[NW][kMaxSegW], seg_e[NW][kMaxSegW];
     float seg_u[NW][kMaxSegW][3];
     float seg_hx[NW][kMaxSegW];       // force: largest h of the source cell
     int nseg[NW];
     int self_b[NW], self_t0[NW], self_n[NW];  // self segment: staged start, first cell index, count
-    int conv[kWave];
-    int ctl[4];                       // 0: all converged, 1: restage
     int unit;
 };
 
