@@ -40,7 +40,8 @@
 namespace sph {
 // ---------------------------------------------------------------- density
 struct DensAcc {
-    double w, qdw, mw, mqdw, div, cx, cy, cz, n;
+    double w, qdw, mw, mqdw, div, cx, cy, cz;
+    int n;
 };
 
 // Newton evaluation: the two sums of Eq. (3) (N and dN/dh need w and q w')
@@ -52,9 +53,9 @@ __device__ __forceinline__ void count_pair(DensAcc& a, bool ok, R xi, R yi, R zi
     const R r2 = dx * dx + dy * dy + dz * dz;
     ok = ok && r2 < h2;
     const R q = fast_sqrt(r2) * hinv;
-    const R w = kern_w(q), qdw = q * kern_dw(q);
-    a.w += ok ? (double)w : 0.0;
-    a.qdw += ok ? (double)qdw : 0.0;
+    const R w = ok ? kern_w(q) : (R)0, qdw = ok ? q * kern_dw(q) : (R)0;
+    a.w += (double)w;
+    a.qdw += (double)qdw;
 }
 
 // All density-stage terms of one pair: Eq. (2), Eq. (3), d rho/dh and the
@@ -66,25 +67,22 @@ __device__ __forceinline__ void density_pair(DensAcc& a, bool ok, R xi, R yi, R 
     const R dx = xi - e.x, dy = yi - e.y, dz = zi - e.z;
     const R r2 = dx * dx + dy * dy + dz * dz;
     ok = ok && r2 < h2;
-    const R r = fast_sqrt(r2);
-    const R q = r * hinv;
-    const R qinv = h * fast_rcp(r);
-    const R w = kern_w(q), dw = kern_dw(q), gq = kern_g(q, qinv);
-    const R mj = vm.w;
+    const R rinv = r2 > (R)0 ? fast_rsqrt(r2) : (R)0;
+    const R q = r2 * rinv * hinv;
+    const R w = kern_w(q), dw = kern_dw(q), gq = kern_g(q, h * rinv);
+    const R mj = ok ? vm.w : (R)0;  // masked pairs contribute nothing
     const R dvx = vm.x - vxi, dvy = vm.y - vyi, dvz = vm.z - vzi;
     const R mg = mj * gq;
     const R qdw = q * dw;
-    if (ok) {
-        a.w += (double)w;
-        a.qdw += (double)qdw;
-        a.mw += (double)(mj * w);
-        a.mqdw += (double)(mj * qdw);
-        a.div += (double)(mg * (dvx * dx + dvy * dy + dvz * dz));
-        a.cx += (double)(mg * (dvy * dz - dvz * dy));
-        a.cy += (double)(mg * (dvz * dx - dvx * dz));
-        a.cz += (double)(mg * (dvx * dy - dvy * dx));
-        a.n += 1.0;
-    }
+    a.w += (double)(ok ? w : (R)0);
+    a.qdw += (double)(ok ? qdw : (R)0);
+    a.mw += (double)(mj * w);
+    a.mqdw += (double)(mj * qdw);
+    a.div += (double)(mg * (dvx * dx + dvy * dy + dvz * dz));
+    a.cx += (double)(mg * (dvy * dz - dvz * dy));
+    a.cy += (double)(mg * (dvz * dx - dvx * dz));
+    a.cz += (double)(mg * (dvx * dy - dvy * dx));
+    a.n += ok ? 1 : 0;
 }
 
 template <typename R>
@@ -240,7 +238,7 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
                         atomicAdd(&s.red[5][lane], acc.cx);
                         atomicAdd(&s.red[6][lane], acc.cy);
                         atomicAdd(&s.red[7][lane], acc.cz);
-                        atomicAdd(&s.red[8][lane], acc.n);
+                        atomicAdd(&s.red[8][lane], (double)acc.n);
                     }
                     __syncthreads();
                     if (!conv) {
@@ -374,7 +372,8 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
 
 // ---------------------------------------------------------------- force
 struct ForceAcc {
-    double ax, ay, az, du, n;
+    double ax, ay, az, du;
+    int n;
 };
 
 template <typename R>
@@ -383,7 +382,8 @@ struct ForceTarget {
 };
 
 // Eqs. (4)-(5) and the Monaghan-Balsara viscosity of Sec. 4.1 for one pair
-// (one-sided: the contribution of j to particle i)
+// (one-sided: the contribution of j to particle i).  Pairs outside both
+// supports contribute exactly zero (both kernel gradients vanish there).
 template <typename R>
 __device__ __forceinline__ void force_pair(ForceAcc& a, bool ok, const ForceTarget<R>& ti, R alpha,
                                            typename Vec4T<R>::T e, typename Vec4T<R>::T vm,
@@ -391,29 +391,25 @@ __device__ __forceinline__ void force_pair(ForceAcc& a, bool ok, const ForceTarg
 {
     const R dx = ti.x - e.x, dy = ti.y - e.y, dz = ti.z - e.z;
     const R r2 = dx * dx + dy * dy + dz * dz;
-    const R r = fast_sqrt(r2);
-    const R rinv = r > (R)0 ? fast_rcp(r) : (R)0;
+    const R rinv = r2 > (R)0 ? fast_rsqrt(r2) : (R)0;
+    const R r = r2 * rinv;
     const R qi = r * ti.hinv, qj = r * g0.x;
     // grad W(r, h) = 8/(pi h^5) g(q) r_vec, zero outside the support and at r = 0
     const R gwi = (qi < (R)1 && r > (R)0) ? ti.gk * kern_g(qi, ti.h * rinv) : (R)0;
     const R gwj = (qj < (R)1 && r > (R)0) ? g0.y * kern_g(qj, g1.z * rinv) : (R)0;
-    const R mj = vm.w;
-    const R vxij = ti.vx - vm.x, vyij = ti.vy - vm.y, vzij = ti.vz - vm.z;
-    const R vr = vxij * dx + vyij * dy + vzij * dz;
-    R wij = vr * rinv;
-    wij = wij < (R)0 ? wij : (R)0;
+    const R mj = ok ? vm.w : (R)0;  // masked pairs contribute nothing
+    const R vr = (ti.vx - vm.x) * dx + (ti.vy - vm.y) * dy + (ti.vz - vm.z) * dz;
+    const R wij = fmin(vr * rinv, (R)0);
     const R Pi = -alpha * (ti.c + g1.x - (R)3 * wij) * wij * fast_rcp(ti.rho + g0.w);
-    const R fij = ti.f + g1.y;
-    const R gsum = gwi + gwj;
-    const R sc = -mj * (ti.A * gwi + g0.z * gwj) - (R)0.25 * mj * Pi * gsum * fij;
-    const R pdu = ti.A * mj * vr * gwi + (R)0.125 * mj * Pi * vr * gsum * fij;
-    if (ok) {
-        a.ax += (double)(sc * dx);
-        a.ay += (double)(sc * dy);
-        a.az += (double)(sc * dz);
-        a.du += (double)pdu;
-        a.n += 1.0;
-    }
+    const R T = Pi * (gwi + gwj) * (ti.f + g1.y);
+    const R agi = ti.A * gwi;
+    const R sc = -mj * (agi + g0.z * gwj + (R)0.25 * T);
+    const R pdu = mj * vr * (agi + (R)0.125 * T);
+    a.ax += (double)(sc * dx);
+    a.ay += (double)(sc * dy);
+    a.az += (double)(sc * dz);
+    a.du += (double)pdu;
+    a.n += ok ? 1 : 0;
 }
 
 template <typename R>
@@ -492,7 +488,7 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
                 atomicAdd(&s.red[1][lane], acc.ay);
                 atomicAdd(&s.red[2][lane], acc.az);
                 atomicAdd(&s.red[3][lane], acc.du);
-                atomicAdd(&s.red[4][lane], acc.n);
+                atomicAdd(&s.red[4][lane], (double)acc.n);
             }
             __syncthreads();
             if (w == 0 && valid) {

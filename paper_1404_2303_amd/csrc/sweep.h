@@ -26,11 +26,14 @@ template <> struct PCfg<float, true> { static constexpr int CAPW = 256, LISTW = 
 template <> struct PCfg<double, false> { static constexpr int CAPW = 256, LISTW = 48; };
 template <> struct PCfg<double, true> { static constexpr int CAPW = 256, LISTW = 32; };
 
-// square root and reciprocal of the pair arithmetic: the hardware
-// instructions in FP32 (about 1 ulp), correctly rounded in FP64
+// square root, reciprocal square root and reciprocal of the pair arithmetic:
+// the hardware instructions in FP32 (about 1 ulp), correctly rounded in FP64
 template <typename R> __device__ __forceinline__ R fast_sqrt(R x);
 template <> __device__ __forceinline__ float fast_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 template <> __device__ __forceinline__ double fast_sqrt<double>(double x) { return sqrt(x); }
+template <typename R> __device__ __forceinline__ R fast_rsqrt(R x);
+template <> __device__ __forceinline__ float fast_rsqrt<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <> __device__ __forceinline__ double fast_rsqrt<double>(double x) { return 1.0 / sqrt(x); }
 template <typename R> __device__ __forceinline__ R fast_rcp(R x);
 template <> __device__ __forceinline__ float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 template <> __device__ __forceinline__ double fast_rcp<double>(double x) { return 1.0 / x; }
