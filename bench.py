@@ -260,17 +260,32 @@ def adjoint_section(steps, warmup):
             "forward_backward_ms": float(np.median(fb))}
 
 
-def multires_section(steps, warmup, split_count=64):
+def multires_section(steps, warmup, tune=True):
     """The 2,097,152-particle Plummer mixture (32 spheres, scale radii log-uniform
     in [0.005, 0.05], 20% uniform background; h spans ~100x) on the hierarchical
-    decomposition, FP32 pair arithmetic.  First h from sph_estimate_h, solved
-    once outside the timed region; a timed step restores h to that solution
-    (the state a simulation step starts from) and runs build, sort, density
-    and force.  A cold pass from the estimate is timed once as well."""
+    decomposition, FP32 pair arithmetic, leaf size autotuned.  First h from
+    sph_estimate_h, solved once outside the timed region; a timed step restores
+    h to that solution (the state a simulation step starts from) and runs build,
+    sort, density and force.  A cold pass from the estimate is timed once as
+    well."""
     import torch
-    from paper_1404_2303_amd import sph, workloads
+    from paper_1404_2303_amd import autotune, sph, workloads
     ps = workloads.config2()
     parts = sph.Particles.from_numpy(ps, "cuda:0")
+    # the leaf size is tuned on the graph-captured pass from the solved h
+    probe = sph.Context(ps.box, precision="fp32", max_depth=10, split_count=256)
+    probe.estimate_h(parts)
+    probe.run(parts)
+    h_solved = parts.h.clone()
+    probe.close()
+    split_count, tuned = 256, None
+    if tune:
+        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+        key = "tree|" + autotune.workload_class(ps.n, 1, "fp32")
+        tuned = autotune.tune(autotune.gpu_timer(ps, "fp32", h_init=h_solved, fixed={"max_depth": 10}), key, arch,
+                              candidates=autotune.TREE_CANDIDATES)
+        split_count = int(tuned["split_count"])
+    parts.h.copy_(torch.as_tensor(ps.h0, device="cuda:0"))
     ctx = sph.Context(ps.box, precision="fp32", max_depth=10, split_count=split_count)
     ctx.enable_timing(True)
     n = parts.n
@@ -320,7 +335,8 @@ def multires_section(steps, warmup, split_count=64):
             "n": n, "pairs_per_step": P, "value": P / (step_ms * 1e-3), "ms_per_step": step_ms,
             "kernel_ms": {k: float(np.median(v)) for k, v in kt.items()},
             "leaves": int(st["n_cells"]), "depth": int(st["depth"]), "top_grid": list(st["grid"]),
-            "split_count": split_count, "cold_pass_ms": cold_ms, "cold_rebuilds": int(cold_rebuilds)}
+            "split_count": split_count, "tuned": tuned, "cold_pass_ms": cold_ms,
+            "cold_rebuilds": int(cold_rebuilds)}
 
 
 class _BatchArgs:

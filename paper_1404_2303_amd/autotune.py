@@ -2,8 +2,9 @@
 
 The kernels' LDS tiles are fixed at compile time; what changes the work per
 unit at run time is the size of the cells (``cell_target``: particles per
-top cell at the mean density, subject to edge >= max h) and the slack on h
-when cells are built (``h_margin``).  For a given workload the tuner times a
+top cell at the mean density, subject to edge >= max h; on the hierarchy,
+``split_count``: the particle count above which a cell is split) and the
+slack on h when cells are built (``h_margin``).  For a given workload the tuner times a
 captured pass (build, sort, density, force) for each candidate and keeps the
 fastest.  Results are cached per (GPU architecture, precision, workload
 class) in a JSON file, so a workload of the same class is not re-tuned.
@@ -24,6 +25,15 @@ CANDIDATES = [
     {"cell_target": 96, "h_margin": 0.1},
     {"cell_target": 128, "h_margin": 0.1},
     {"cell_target": 64, "h_margin": 0.05},
+]
+
+# hierarchical decomposition: leaf size (the split rule's count) for multi-resolution sets
+TREE_CANDIDATES = [
+    {"split_count": 64},
+    {"split_count": 128},
+    {"split_count": 256},
+    {"split_count": 384},
+    {"split_count": 512},
 ]
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_tune", "autotune.json")
@@ -84,16 +94,19 @@ def tune(time_candidate: Callable[[dict], float], key: str, arch: str, candidate
     return dict(best, cached=False)
 
 
-def gpu_timer(ps, precision: str, batch=None, reps: int = 3, arch: Optional[str] = None):
+def gpu_timer(ps, precision: str, batch=None, reps: int = 3, arch: Optional[str] = None, h_init=None,
+              fixed: Optional[dict] = None):
     """A time_candidate function for tune(): median of `reps` graph replays of
-    the whole pass (build, sort, density from the initial h, force)."""
+    the whole pass (build, sort, density from the initial h, force).  h_init
+    (a device tensor) replaces the set's initial h; `fixed` holds parameters
+    common to every candidate (for instance max_depth)."""
     import torch
     from . import sph
 
     def run(params: dict) -> float:
         parts = sph.Particles.from_numpy(ps, "cuda:0")
-        h0 = parts.h.clone()
-        ctx = sph.Context(ps.box, precision=precision, **params)
+        h0 = parts.h.clone() if h_init is None else h_init.clone()
+        ctx = sph.Context(ps.box, precision=precision, **dict(fixed or {}, **params))
         stream = torch.cuda.Stream()
         try:
             with torch.cuda.stream(stream):

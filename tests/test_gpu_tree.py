@@ -153,3 +153,34 @@ def test_config2_sampled_fp32():
     log("  " + " ".join(f"{k}={v:.2e}" if isinstance(v, float) else f"{k}={v}" for k, v in e.items()))
     assert e["h"] <= t["h"] and e["rho"] <= t["rho"] and e["omega"] <= t["omega"] and e["f"] <= t["f"]
     assert e["div"] <= t["vec"] and e["a"] <= t["a"] and e["dudt"] <= t["a"] and e["count"] <= 0
+
+
+def test_graph_replay_on_the_hierarchy(mixture):
+    # the whole tree build and pass captured once and replayed from the solved h:
+    # equal to the eager pass from the same h (up to the order of the cross-wave sums)
+    ps, ref = mixture
+    log("case tree graph replay 30000 fp32")
+    parts = sph.Particles.from_numpy(ps, "cuda:0")
+    ctx = sph.Context(ps.box, precision="fp32", **TREE)
+    ctx.estimate_h(parts)
+    ctx.run(parts)
+    h_sol = parts.h.clone()
+    parts.h.copy_(h_sol)
+    d, f = ctx.run(parts)
+    eager = {k: v.clone() for k, v in f.items()}
+    eager_h = parts.h.clone()
+    scale = float(torch.max(torch.abs(eager["ax"])))
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        _, fout = ctx.graph_capture(parts, None, h_init=h_sol)
+        for rep in range(3):
+            for v in fout.values():
+                v.zero_()
+            ctx.graph_launch()
+            ctx.check()
+            stream.synchronize()
+            assert torch.equal(fout["n_pairs"], eager["n_pairs"]), rep
+            assert torch.allclose(parts.h, eager_h, rtol=1e-12, atol=0), rep
+            for k in ("ax", "ay", "az"):
+                assert float(torch.max(torch.abs(fout[k] - eager[k]))) <= 1e-12 * scale, (rep, k)
+    ctx.close()
