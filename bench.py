@@ -348,6 +348,33 @@ class _BatchArgs:
         self.c = self.b.c
 
 
+KERNEL_SOURCES = ["paper_1404_2303_amd/csrc/passes.hip", "paper_1404_2303_amd/csrc/sweep.h",
+                  "paper_1404_2303_amd/csrc/kernels.h", "paper_1404_2303_amd/csrc/sph_internal.h"]
+TRAFFIC_PROFILE = "profiles/traffic_lattice2p20_fp32.md"
+
+
+def measured_traffic():
+    """HBM bytes per launch of the density kernel from the committed rocprofv3
+    counter summary, or None when the kernel sources changed since it was taken."""
+    import hashlib
+    try:
+        h = hashlib.sha256()
+        for f in KERNEL_SOURCES:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        fields = {}
+        with open(os.path.join(ROOT, TRAFFIC_PROFILE)) as fh:
+            for line in fh:
+                if ":" in line and line.split(":")[0] in ("density_traffic_bytes", "source_sha256"):
+                    k, v = line.split(":", 1)
+                    fields[k.strip()] = v.strip()
+        if fields.get("source_sha256") != h.hexdigest():
+            return None
+        return int(fields["density_traffic_bytes"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def roofline(res):
     """Dominant interaction kernel's algorithmic FLOP rate against the vector peak."""
     P_unordered = res["P"] / 2.0
@@ -358,8 +385,9 @@ def roofline(res):
     name, flops, ms = max(cand, key=lambda c: c[2])
     achieved = flops / (ms * 1e-3) / 1e12
     peak = PEAK["fp64" if res["precision"] == "fp64" else "fp32"]
+    traffic = measured_traffic() if (name == "density" and res["precision"] == "fp32") else None
     return {"bound": "alu", "kernel": name, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": None,
+            "frac": achieved / peak, "traffic": traffic,
             "other": {c[0]: {"TFLOP/s": c[1] / (c[2] * 1e-3) / 1e12, "ms": c[2]} for c in cand}}
 
 
