@@ -83,11 +83,22 @@ typedef struct {
                             and by the 64-bit keys. */
     int split_count;     /* a cell is split when it holds more than this many particles ... */
     double split_frac;   /* ... and at least this fraction of them has h below half its edge */
+    double cfl;          /* C_CFL of the time-step criterion, Eq. (6); the paper uses 1/4 */
+    int balsara_form;    /* numerator of the Balsara switch f_i of Sec. 4.1:
+                            SPH_BALSARA_CURL as printed there, or SPH_BALSARA_DIV */
 } sph_params;
 
-/* Default parameters: the paper's constants (48, 5/3, 0.8, 1e-4), FP32_ACC64,
- * cell_target 64, h_margin 0.1, max_iter 64, max_rebuilds 4, unit box,
- * max_depth 0 (single-level grid), split_count 64, split_frac 0.875. */
+/* Numerator of the Balsara switch f = X / (|div v| + |curl v| + eps c/h). */
+enum {
+    SPH_BALSARA_CURL = 0,  /* X = |curl v|, the formula as printed in Sec. 4.1 */
+    SPH_BALSARA_DIV = 1    /* X = |div v|, the switch of Balsara (1995) that Sec. 4.1 cites:
+                              full viscosity in compressions, none in pure shear */
+};
+
+/* Default parameters: the paper's constants (48, 5/3, 0.8, 1e-4, C_CFL 1/4),
+ * FP32_ACC64, cell_target 64, h_margin 0.1, max_iter 64, max_rebuilds 4, unit
+ * box, max_depth 0 (single-level grid), split_count 64, split_frac 0.875,
+ * balsara_form SPH_BALSARA_CURL. */
 void sph_default_params(sph_params *p);
 
 typedef struct {
@@ -127,6 +138,10 @@ typedef struct {
     double *ax, *ay, *az;   /* dv/dt, Eq. (4) plus viscosity */
     double *dudt;           /* du/dt, Eq. (5) plus viscosity */
     int32_t *n_pairs;       /* number of j != i with r_ij < max(h_i, h_j) */
+    double *dt;             /* time step of Eq. (6): C_CFL 2 h_i / vsig_i with
+                               vsig_i = max_j (c_i + c_j + max(0, -3 v_ij.r_ij / r_ij)) over
+                               the j with r_ij < max(h_i, h_j) and over j = i (term 2 c_i);
+                               +inf where vsig_i = 0 */
 } sph_force_out;
 
 typedef struct sph_ctx sph_ctx;
@@ -243,6 +258,31 @@ sph_status sph_backward(sph_ctx *ctx, const sph_particles *p, const sph_grad_in 
  * Errors: as sph_build_cells, sph_density. */
 sph_status sph_step(sph_ctx *ctx, sph_particles *p, const sph_batch *batch, sph_force_out *acc,
                     double dt, void *stream);
+
+/* Kick-drift-kick step whose length comes from the time-step criterion,
+ * Eq. (6): per box b,
+ *   dt_b = min(min_{i in b} acc->dt[i], dt_max, t_end - t_box[b])   (>= 0),
+ * the smallest particle time step of the previous force evaluation, as the
+ * blast-wave test of Sec. 4.2 steps.  Then the step of sph_step with dt_b for
+ * the particles of box b, after which acc (a, du/dt and dt) holds the new
+ * force evaluation.  t_box (device, nbox values) is advanced by dt_b, and set
+ * to t_end exactly when the step was clipped to it; dt_box (device, nbox
+ * values, may be NULL) receives dt_b.  A box with t_box >= t_end takes a step
+ * of length 0.  acc->dt must hold the time steps of the last force
+ * evaluation (run sph_density and sph_force with dt set for a cold start).
+ * dt_max must be finite and > 0.  No synchronisation.  Errors: as sph_step. */
+sph_status sph_step_adaptive(sph_ctx *ctx, sph_particles *p, const sph_batch *batch, sph_force_out *acc,
+                             double dt_max, double t_end, double *t_box, double *dt_box, void *stream);
+
+/* Time integration from t = 0 to t_end (Sec. 4.1 integrator, steps limited by
+ * Eq. (6)): the cells, orderings, density and force of the initial state
+ * (written to acc, which needs ax..dudt and dt), then sph_step_adaptive
+ * steps until every box has reached t_end or max_steps steps were taken.
+ * Synchronises `stream` once per step to read the box times.  *steps (may be
+ * NULL) receives the number of steps taken.  Errors: as sph_step_adaptive;
+ * SPH_E_CAPACITY when max_steps ends the run before t_end. */
+sph_status sph_integrate(sph_ctx *ctx, sph_particles *p, const sph_batch *batch, sph_force_out *acc,
+                         double t_end, double dt_max, int64_t max_steps, int64_t *steps, void *stream);
 
 /* Graph of one whole pass (the batched persistent form): optional copy of
  * h_init (device, n values; may be NULL) into p->h, then sph_build_cells,

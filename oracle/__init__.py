@@ -16,8 +16,11 @@ function names the part of Gonnet (2014) it evaluates:
 * :func:`force` -- Eqs. (4)-(5) plus the Monaghan-Balsara viscosity, Sec. 4.1.
 * :func:`full_pass` -- the two stages in the paper's order (Sec. 2.1:
   density for all particles first, then force).
+* :func:`signal_dt` -- the signal speed and time step of Eq. (6).
 * :func:`kdk_step` -- one kick-drift-kick velocity-Verlet step with a fixed
   time step (the integrator of Sec. 4.1).
+* :func:`integrate` -- kick-drift-kick steps to a final time, each step
+  limited by the smallest time step of Eq. (6).
 """
 from __future__ import annotations
 
@@ -34,6 +37,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 GAMMA = 5.0 / 3.0   # Sec. 4.2 constants
 ALPHA = 0.8
 N_NGB = 48.0
+CFL = 0.25
 
 ORA_OK, ORA_E_ARG, ORA_E_H_TOO_LARGE, ORA_E_NOT_CONVERGED, ORA_E_OOM = 0, 1, 2, 3, 4
 
@@ -78,7 +82,9 @@ def _load():
         lib.ora_density.restype = i32
         lib.ora_density.argtypes = [i64, P, P, P, P, P, P, P, P, P, i64, P] + [P] * 8
         lib.ora_ghost.restype = None
-        lib.ora_ghost.argtypes = [i64, P, P, P, P, P, P, d, P, P, P, P, P]
+        lib.ora_ghost.argtypes = [i64, P, P, P, P, P, P, d, i32, P, P, P, P, P]
+        lib.ora_signal.restype = i32
+        lib.ora_signal.argtypes = [i64, P, P, P, P, P, P, P, P, P, d, i64, P, P, P, P, P]
         lib.ora_force.restype = i32
         lib.ora_force.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, P, P, d, i64, P] + [P] * 8
         lib.ora_brute_count.restype = None
@@ -181,15 +187,19 @@ def density(pos, vel, m, h, box, sel=None):
     return out
 
 
-def ghost(dens, u, h, gamma=GAMMA):
-    """Omega, P, c, A, Balsara f from the density-stage sums (Sec. 2.1, Sec. 4.1)."""
+def ghost(dens, u, h, gamma=GAMMA, balsara_form=0):
+    """Omega, P, c, A, Balsara f from the density-stage sums (Sec. 2.1, Sec. 4.1).
+
+    balsara_form 0 puts |curl v| over the denominator, as Sec. 4.1 prints the
+    switch; 1 puts |div v| there, the switch of Balsara (1995) that it cites.
+    """
     lib = _load()
     rho = _c(dens["rho"])
     n = len(rho)
     u = _c(np.broadcast_to(np.asarray(u, dtype=np.float64), (n,)))
     out = {k: np.empty(n) for k in ("omega", "P", "c", "A", "f")}
     lib.ora_ghost(n, _p(rho), _p(_c(dens["drhodh"])), _p(_c(h)), _p(u), _p(_c(dens["div"])),
-                  _p(_c(dens["curl"])), float(gamma), _p(out["omega"]), _p(out["P"]),
+                  _p(_c(dens["curl"])), float(gamma), int(balsara_form), _p(out["omega"]), _p(out["P"]),
                   _p(out["c"]), _p(out["A"]), _p(out["f"]))
     return out
 
@@ -216,6 +226,22 @@ def force(pos, vel, m, h, rho, A, c, f, box, alpha=ALPHA, sel=None):
     return out
 
 
+def signal_dt(pos, vel, h, c, box, cfl=CFL, sel=None):
+    """Signal speed and time step of Eq. (6) (vsig, vsig_lo, vsig_hi, dt)."""
+    lib = _load()
+    x, y, z = _split(pos)
+    n = len(x)
+    vel = np.zeros((n, 3)) if vel is None else np.asarray(vel, dtype=np.float64)
+    vx, vy, vz = _c(vel[:, 0]), _c(vel[:, 1]), _c(vel[:, 2])
+    ns, s = _sel(sel, n)
+    out = {k: np.full(n, np.nan) for k in ("vsig", "vsig_lo", "vsig_hi", "dt")}
+    st = lib.ora_signal(n, _p(x), _p(y), _p(z), _p(vx), _p(vy), _p(vz), _p(_c(h)), _p(_c(c)),
+                        _p(_c(box)), float(cfl), ns, _p(s), _p(out["vsig"]), _p(out["vsig_lo"]),
+                        _p(out["vsig_hi"]), _p(out["dt"]))
+    _check(st, "signal_dt")
+    return out
+
+
 def brute_count(pos, R, box):
     """O(N^2) count of j != i with minimum-image r_ij < R_i."""
     lib = _load()
@@ -228,23 +254,25 @@ def brute_count(pos, R, box):
 
 
 def full_pass(pos, vel, m, u, h0, box, target=N_NGB, tol=1e-10, maxit=100,
-              gamma=GAMMA, alpha=ALPHA, force_sel=None):
+              gamma=GAMMA, alpha=ALPHA, force_sel=None, balsara_form=0, cfl=CFL):
     """Density stage for every particle (h solved), then the force stage.
 
     The two stages run in the order of Sec. 2.1: all densities (and the
     per-particle ghost quantities) before any force.  ``force_sel`` restricts
-    the force stage to a subset of particles (their neighbours' ghost
-    quantities are still computed for all particles).
+    the force stage and the time step of Eq. (6) to a subset of particles
+    (their neighbours' ghost quantities are still computed for all particles).
     """
     h, iters = solve_h(pos, h0, box, target=target, tol=tol, maxit=maxit)
     dens = density(pos, vel, m, h, box)
-    gh = ghost(dens, u, h, gamma=gamma)
+    gh = ghost(dens, u, h, gamma=gamma, balsara_form=balsara_form)
     frc = force(pos, vel, m, h, dens["rho"], gh["A"], gh["c"], gh["f"], box, alpha=alpha,
                 sel=force_sel)
-    return {"h": h, "iters": iters, "dens": dens, "ghost": gh, "force": frc}
+    sig = signal_dt(pos, vel, h, gh["c"], box, cfl=cfl, sel=force_sel)
+    return {"h": h, "iters": iters, "dens": dens, "ghost": gh, "force": frc, "signal": sig}
 
 
-def kdk_step(pos, vel, m, u, h, box, a_old, dudt_old, dt, target=N_NGB, tol=1e-10, gamma=GAMMA, alpha=ALPHA):
+def kdk_step(pos, vel, m, u, h, box, a_old, dudt_old, dt, target=N_NGB, tol=1e-10, gamma=GAMMA, alpha=ALPHA,
+             balsara_form=0, cfl=CFL):
     """One kick-drift-kick step (Sec. 4.1 names velocity Verlet with a fixed
     step).  The forces at the new positions need velocities and energies at
     the new time, which the kick has not produced yet; they are predicted
@@ -261,8 +289,35 @@ def kdk_step(pos, vel, m, u, h, box, a_old, dudt_old, dt, target=N_NGB, tol=1e-1
     x_new = np.where(x_new >= box, x_new - box, x_new)
     v_pred = v_half + hdt * np.asarray(a_old, dtype=np.float64)
     u_pred = u_half + hdt * np.asarray(dudt_old, dtype=np.float64)
-    out = full_pass(x_new, v_pred, m, u_pred, h, box, target=target, tol=tol, gamma=gamma, alpha=alpha)
+    out = full_pass(x_new, v_pred, m, u_pred, h, box, target=target, tol=tol, gamma=gamma, alpha=alpha,
+                    balsara_form=balsara_form, cfl=cfl)
     a_new = out["force"]["a"]
     du_new = out["force"]["dudt"]
     return {"pos": x_new, "vel": v_half + hdt * a_new, "u": u_half + hdt * du_new, "h": out["h"],
-            "a": a_new, "dudt": du_new}
+            "a": a_new, "dudt": du_new, "dt": out["signal"]["dt"]}
+
+
+def integrate(pos, vel, m, u, h, box, t_end, dt_max, max_steps=100000, **kw):
+    """Kick-drift-kick steps from t = 0 to t_end, each step as long as the
+    smallest time step of Eq. (6) of the previous force evaluation allows
+    (Sec. 4.2 runs its blast wave this way), capped by dt_max and clipped so
+    that the last step ends at t_end.  Starts with a full pass for the
+    initial accelerations.  Returns the final state and the steps taken.
+    """
+    box = np.asarray(box, dtype=np.float64)
+    f0 = full_pass(pos, vel, m, u, h, box, **kw)
+    st = {"pos": np.asarray(pos, dtype=np.float64), "vel": np.asarray(vel, dtype=np.float64),
+          "u": np.asarray(u, dtype=np.float64), "h": f0["h"], "a": f0["force"]["a"],
+          "dudt": f0["force"]["dudt"], "dt": f0["signal"]["dt"]}
+    t, steps = 0.0, []
+    while t < t_end and len(steps) < max_steps:
+        dt = min(float(np.min(st["dt"])), dt_max)
+        last = t + dt >= t_end
+        if last:
+            dt = t_end - t
+        st = kdk_step(st["pos"], st["vel"], m, st["u"], st["h"], box, st["a"], st["dudt"], dt, **kw)
+        t = t_end if last else t + dt
+        steps.append(dt)
+    st["t"] = t
+    st["steps"] = np.array(steps)
+    return st

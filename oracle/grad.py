@@ -51,8 +51,11 @@ def _dw(q):
     return torch.where(q <= 0.5, inner, outer) * (q < 1.0)
 
 
-def model(x, v, m, u, h, box, gamma=GAMMA, alpha=ALPHA, beps=BALSARA_EPS):
-    """Dense forward pass: returns dict with rho, N, dNdh, omega, div, curl, f, A, c, a, dudt."""
+def model(x, v, m, u, h, box, gamma=GAMMA, alpha=ALPHA, beps=BALSARA_EPS, balsara_form=0):
+    """Dense forward pass: returns dict with rho, N, dNdh, omega, div, curl, f, A, c, a, dudt.
+
+    balsara_form 0: f = |curl v| / (|div v| + |curl v| + eps c/h) as Sec. 4.1
+    prints it; 1: |div v| in the numerator (Balsara 1995)."""
     n = x.shape[0]
     box_t = torch.as_tensor(box, dtype=x.dtype)
     d = x[:, None, :] - x[None, :, :]                     # r_ij = x_i - x_j
@@ -88,7 +91,8 @@ def model(x, v, m, u, h, box, gamma=GAMMA, alpha=ALPHA, beps=BALSARA_EPS):
     # |curl|, with derivative 0 at curl = 0 (where the norm has none)
     cm = torch.where(c2 > 0, torch.sqrt(torch.where(c2 > 0, c2, torch.ones_like(c2))), torch.zeros_like(c2))
     den = div.abs() + cm + beps * c / h
-    f = torch.where(den > 0, cm / torch.where(den > 0, den, torch.ones_like(den)), torch.zeros_like(den))
+    num = div.abs() if balsara_form == 1 else cm
+    f = torch.where(den > 0, num / torch.where(den > 0, den, torch.ones_like(den)), torch.zeros_like(den))
     # force stage
     Gj = Gi.transpose(0, 1)                                 # grad W(r_ij, h_j) uses row j
     rng = (r < torch.maximum(hi, h[None, :])) * off
@@ -125,18 +129,18 @@ def _tensors(pos, vel, m, u):
     return x, v, mt, ut
 
 
-def _grad(pos, vel, m, u, h, box, loss, solve, target, tol):
+def _grad(pos, vel, m, u, h, box, loss, solve, target, tol, balsara_form=0):
     x, v, mt, ut = _tensors(pos, vel, m, u)
     if solve:
         hstar, _ = solve_h(pos, h, box, target=target, tol=tol)
         hs = torch.tensor(hstar)
-        nd = model(x, v, mt, ut, hs, box)
+        nd = model(x, v, mt, ut, hs, box, balsara_form=balsara_form)
         ht = hs - (nd["N"] - target) / nd["dNdh"].detach()
-        L = loss(model(x, v, mt, ut, ht, box))
+        L = loss(model(x, v, mt, ut, ht, box, balsara_form=balsara_form))
         L.backward()
         return x.grad.numpy().copy(), None, float(L.detach()), hstar
     ht = torch.tensor(np.asarray(h, dtype=np.float64), requires_grad=True)
-    L = loss(model(x, v, mt, ut, ht, box))
+    L = loss(model(x, v, mt, ut, ht, box, balsara_form=balsara_form))
     L.backward()
     return x.grad.numpy().copy(), ht.grad.numpy().copy(), float(L.detach()), np.asarray(h)
 
@@ -152,13 +156,14 @@ def gradients(pos, vel, m, u, h, box, rho_target, solve=True, target=N_NGB, tol=
     return _grad(pos, vel, m, u, h, box, lambda out: loss_of(out, rt), solve, target, tol)
 
 
-def vjp(pos, vel, m, u, h, box, g_rho, g_a, g_dudt, solve=True, target=N_NGB, tol=1e-13):
+def vjp(pos, vel, m, u, h, box, g_rho, g_a, g_dudt, solve=True, target=N_NGB, tol=1e-13, balsara_form=0):
     """dL/dx and (fixed h) dL/dh of linear_loss_of with weights g_rho (N,), g_a (N,3),
     g_dudt (N,): the vector-Jacobian product of (rho, a, du/dt) with respect to the
     positions (and h).  Same conventions as gradients()."""
     t = lambda a: torch.tensor(np.asarray(a, dtype=np.float64))
     gr, ga, gu = t(g_rho), t(g_a), t(g_dudt)
-    return _grad(pos, vel, m, u, h, box, lambda out: linear_loss_of(out, gr, ga, gu), solve, target, tol)
+    return _grad(pos, vel, m, u, h, box, lambda out: linear_loss_of(out, gr, ga, gu), solve, target, tol,
+                 balsara_form)
 
 
 # ---------------------------------------------------------------- finite differences through the C oracle

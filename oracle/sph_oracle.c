@@ -11,7 +11,8 @@
  *     Newton iteration on h that keeps it at a target value,
  *   - the correction term Omega and pressure P of Sec. 2.1,
  *   - the accelerations and internal-energy rates, Eqs. (4)-(5),
- *   - the Monaghan-Balsara viscosity and Balsara switch of Sec. 4.1.
+ *   - the Monaghan-Balsara viscosity and Balsara switch of Sec. 4.1,
+ *   - the per-particle time step of Eq. (6).
  *
  * Every sum is a one-sided gather over neighbours found by a plain periodic
  * cell list: no sorting, no symmetric updates, no blocking.  Only the tests,
@@ -415,7 +416,7 @@ int ora_density(int64_t np, const double *x, const double *y, const double *z,
  * f_i = 0 where its denominator vanishes.
  */
 void ora_ghost(int64_t n, const double *rho, const double *drhodh, const double *h, const double *u,
-               const double *div, const double *curl, double gamma,
+               const double *div, const double *curl, double gamma, int form,
                double *omega, double *P, double *c, double *A, double *f)
 {
     for (int64_t i = 0; i < n; i++) {
@@ -425,9 +426,74 @@ void ora_ghost(int64_t n, const double *rho, const double *drhodh, const double 
         double a = p / (om * rho[i] * rho[i]);
         double cm = sqrt(curl[3 * i] * curl[3 * i] + curl[3 * i + 1] * curl[3 * i + 1] + curl[3 * i + 2] * curl[3 * i + 2]);
         double den = fabs(div[i]) + cm + 1e-4 * cs / h[i];
+        /* form 0: |curl| on top, as Sec. 4.1 prints it; form 1: |div| on top,
+         * the switch of Balsara (1995) that Sec. 4.1 cites */
+        double num = form == 1 ? fabs(div[i]) : cm;
         omega[i] = om; P[i] = p; c[i] = cs; A[i] = a;
-        f[i] = den > 0.0 ? cm / den : 0.0;
+        f[i] = den > 0.0 ? num / den : 0.0;
     }
+}
+
+/*
+ * Signal speed of the time-step criterion, Eq. (6):
+ *   vsig_i = max_j (c_i + c_j + max(0, -3 v_ij . r_ij / r_ij)),
+ *   dt_i   = C_CFL 2 h_i / vsig_i,
+ * j running over the particles that interact with i in the force stage
+ * (r_ij < max(h_i, h_j)) and over i itself, whose term is 2 c_i (r_ii = 0, no
+ * approach speed).  vsig_lo and vsig_hi take the same maximum over the pairs
+ * with r_ij < (1 - band) max(h_i, h_j) and r_ij < (1 + band) max(h_i, h_j):
+ * a pair at the edge of the support may fall on either side in a lower
+ * precision.  dt_i is +inf where vsig_i = 0.
+ */
+int ora_signal(int64_t np, const double *x, const double *y, const double *z,
+               const double *vx, const double *vy, const double *vz, const double *h,
+               const double *c, const double L[3], double cfl, int64_t nsel, const int64_t *sel,
+               double *vsig, double *vsig_lo, double *vsig_hi, double *dt)
+{
+    if (np <= 0 || !x || !h || !c) return ORA_E_ARG;
+    double hmax = 0.0, hmin = INFINITY;
+    for (int64_t i = 0; i < np; i++) { if (h[i] > hmax) hmax = h[i]; if (h[i] < hmin) hmin = h[i]; }
+    ora_grid g;
+    int st = grid_build(&g, np, x, y, z, L, hmin);
+    if (st) return st;
+    int status = ORA_OK;
+#pragma omp parallel
+    {
+        ora_list l = {0};
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t k = 0; k < nsel; k++) {
+            int64_t i = sel_index(sel, k);
+            double R = fmax(h[i], hmax) * (1.0 + 2.0 * ORA_BAND);
+            int e = grid_gather(&g, x[i], y[i], z[i], R, &l);
+            if (e) {
+#pragma omp critical
+                { if (status == ORA_OK) status = e; }
+                continue;
+            }
+            double s = 2.0 * c[i], slo = s, shi = s;
+            for (int64_t t = 0; t < l.n; t++) {
+                ora_nb nb = l.v[t];
+                int64_t j = nb.j;
+                if (j == i) continue;
+                double r = sqrt(nb.r2);
+                double hij = fmax(h[i], h[j]);
+                if (!(r < hij * (1.0 + ORA_BAND))) continue;
+                double vdotr = (vx[i] - vx[j]) * nb.dx + (vy[i] - vy[j]) * nb.dy + (vz[i] - vz[j]) * nb.dz;
+                double approach = (r > 0.0) ? fmax(0.0, -3.0 * vdotr / r) : 0.0;
+                double v = c[i] + c[j] + approach;
+                if (v > shi) shi = v;
+                if (r < hij && v > s) s = v;
+                if (r < hij * (1.0 - ORA_BAND) && v > slo) slo = v;
+            }
+            if (vsig) vsig[i] = s;
+            if (vsig_lo) vsig_lo[i] = slo;
+            if (vsig_hi) vsig_hi[i] = shi;
+            if (dt) dt[i] = s > 0.0 ? cfl * 2.0 * h[i] / s : INFINITY;
+        }
+        free(l.v);
+    }
+    grid_free(&g);
+    return status;
 }
 
 /*

@@ -316,13 +316,15 @@ __global__ void k_adj_ghost(const CellData<R> cd, const GhostData<R> gd, AdjData
     const double Abar = fg.x, fbar = fg.z;
     double rhobar = fg.y + fg.w;
     double hbar = 0.0;
-    // Balsara f = |curl| / (|div| + |curl| + eps c / h)
+    // Balsara f = X / (|div| + |curl| + eps c / h), X = |curl| or |div|
     double divbar = 0.0, cbx = 0.0, cby = 0.0, cbz = 0.0;
     if (den > 0.0) {
-        const double id2 = 1.0 / (den * den);
-        const double cmbar = fbar * (den - cm) * id2;
-        const double adbar = -fbar * cm * id2;
-        hbar += fbar * cm * pc.beps * c / (h * h) * id2;
+        const double num = pc.balsara_div ? fabs(div) : cm;
+        const double denbar = -fbar * num / (den * den);   // through the denominator
+        const double numbar = fbar / den;                    // through the numerator
+        const double cmbar = denbar + (pc.balsara_div ? 0.0 : numbar);
+        const double adbar = denbar + (pc.balsara_div ? numbar : 0.0);
+        hbar -= denbar * pc.beps * c / (h * h);
         divbar = div > 0.0 ? adbar : (div < 0.0 ? -adbar : 0.0);
         if (cm > 0.0) { cbx = cmbar * cx / cm; cby = cmbar * cy / cm; cbz = cmbar * cz / cm; }
     }

@@ -61,6 +61,7 @@ struct sph_ctx {
     DBuf adj_ab, adj_sb0, adj_sb1, adj_x, adj_h, adj_fg;  // adjoint workspace
     DBuf qhead, status;
     DBuf step_tmp;                                   // predicted v, u; new a, du/dt
+    DBuf dt_box, dt_min, t_box;                      // per-box step length, minimum of Eq. (6), time
     uint32_t* status_host = nullptr;                 // pinned
     int32_t* ncells_host = nullptr;                  // pinned
     // state of the current decomposition
@@ -154,6 +155,8 @@ static PassConsts pass_consts(const sph_params& p)
     pc.beps = p.balsara_eps;
     pc.max_iter = p.max_iter;
     pc.h_margin = p.h_margin;
+    pc.cfl = p.cfl;
+    pc.balsara_div = p.balsara_form == SPH_BALSARA_DIV ? 1 : 0;
     return pc;
 }
 
@@ -215,6 +218,8 @@ void sph_default_params(sph_params* p)
     p->max_depth = 0;
     p->split_count = 64;
     p->split_frac = 0.875;
+    p->cfl = 0.25;
+    p->balsara_form = SPH_BALSARA_CURL;
 }
 
 const char* sph_status_string(sph_status s)
@@ -247,6 +252,8 @@ static bool params_ok(const sph_params& p)
     if (!(p.h_margin >= 0) || !(p.h_margin < 10)) return false;
     if (p.max_rebuilds < 0) return false;
     if (p.max_depth < 0 || p.split_count < 1 || !(p.split_frac >= 0.0) || !(p.split_frac <= 1.0)) return false;
+    if (!(p.cfl > 0.0) || !std::isfinite(p.cfl)) return false;
+    if (p.balsara_form != SPH_BALSARA_CURL && p.balsara_form != SPH_BALSARA_DIV) return false;
     return true;
 }
 
@@ -277,7 +284,7 @@ sph_status sph_destroy(sph_ctx* c)
     DBuf* all[] = {&c->boxes, &c->keys, &c->keys2, &c->vals, &c->vals2, &c->rs_scratch, &c->flag,
                    &c->cellx, &c->cell_of, &c->sc_scratch, &c->cells, &c->ncells, &c->cell_map,
                    &c->src, &c->src_count, &c->sidx, &c->srec, &c->rx, &c->ry, &c->rz, &c->h,
-                   &c->vm, &c->u, &c->g0, &c->g1, &c->cell_hmax, &c->qhead, &c->status, &c->step_tmp,
+                   &c->vm, &c->u, &c->g0, &c->g1, &c->cell_hmax, &c->qhead, &c->status, &c->step_tmp, &c->dt_box, &c->dt_min, &c->t_box,
                    &c->sd0, &c->sd1, &c->adj_ab, &c->adj_sb0, &c->adj_sb1, &c->adj_x, &c->adj_h, &c->adj_fg,
                    &c->src_off, &c->t_chg, &c->t_node_of, &c->t_node_start, &c->t_node_flag, &c->t_node_hmax,
                    &c->t_node_H, &c->t_node_leaf, &c->t_nnodes, &c->t_flag, &c->t_scan, &c->t_small,
@@ -666,6 +673,7 @@ sph_status sph_force(sph_ctx* c, const sph_particles* p, sph_force_out* o, void*
     if (c->n == 0) return SPH_OK;
     ForceOut out{};
     out.ax = o->ax; out.ay = o->ay; out.az = o->az; out.dudt = o->dudt; out.npairs = o->n_pairs;
+    out.dt = o->dt;
     int grid = force_occupancy_grid(c->prm.precision);
     ev_record(c, EV_FORCE0, st);
     if (c->prm.precision == SPH_FP64)
@@ -718,42 +726,119 @@ sph_status sph_backward(sph_ctx* c, const sph_particles* p, const sph_grad_in* g
     return hipGetLastError() == hipSuccess ? SPH_OK : SPH_E_HIP;
 }
 
-sph_status sph_step(sph_ctx* c, sph_particles* p, const sph_batch* batch, sph_force_out* acc, double dt,
-                    void* stream)
+// The step proper, with the step length of each box in c->dt_box (device).
+static sph_status step_core(sph_ctx* c, sph_particles* p, const sph_batch* batch, sph_force_out* acc,
+                            hipStream_t st)
 {
-    if (!c || !particles_ok(p) || !acc || !std::isfinite(dt)) return SPH_E_INVALID_ARG;
-    if (p->n > 0 && (!acc->ax || !acc->ay || !acc->az || !acc->dudt)) return SPH_E_INVALID_ARG;
-    hipStream_t st = (hipStream_t)stream;
     const int64_t n = p->n;
-    if (n == 0) return SPH_OK;
+    if (!c->step_tmp.ensure(sizeof(double) * 4 * (size_t)n)) return SPH_E_OOM;
+    double* vp = c->step_tmp.as<double>();
+    StepArrays sa;
+    sa.x = p->x; sa.y = p->y; sa.z = p->z; sa.vx = p->vx; sa.vy = p->vy; sa.vz = p->vz; sa.u = p->u;
+    sa.ax = acc->ax; sa.ay = acc->ay; sa.az = acc->az; sa.dudt = acc->dudt;
+    sa.pvx = vp; sa.pvy = vp + n; sa.pvz = vp + 2 * n; sa.pu = vp + 3 * n;
+    const double* dtb = c->dt_box.as<double>();
+    launch_step_open(sa, dtb, c->boxes.as<BoxInfo>(), c->nbox, n, st);
+    sph_particles q = *p;
+    q.vx = sa.pvx; q.vy = sa.pvy; q.vz = sa.pvz; q.u = sa.pu;
+    sph_status s = sph_build_cells(c, &q, batch, st);
+    if (s == SPH_OK) s = sph_sort(c, st);
+    if (s == SPH_OK) s = sph_density(c, &q, nullptr, st);
+    if (s != SPH_OK && s != SPH_E_NOT_CONVERGED) return s;
+    sph_status sd = s;
+    s = sph_force(c, &q, acc, st);
+    if (s != SPH_OK) return s;
+    launch_step_close(sa, dtb, c->boxes.as<BoxInfo>(), c->nbox, n, st);
+    if (hipGetLastError() != hipSuccess) return SPH_E_HIP;
+    return sd;
+}
+
+// box table and per-box step buffers for a step on p
+static sph_status step_setup(sph_ctx* c, const sph_particles* p, const sph_batch* batch, hipStream_t st)
+{
     if (hipSetDevice(c->device) != hipSuccess) return SPH_E_HIP;
-    // box table for the drift (the build below refreshes it)
-    sph_status s = setup_boxes(c, n, batch);
+    // box table for the opening half (the build in the step refreshes it)
+    sph_status s = setup_boxes(c, p->n, batch);
     if (s != SPH_OK) return s;
     if (!c->boxes.ensure(sizeof(BoxInfo) * c->nbox)) return SPH_E_OOM;
     if (!upload_boxes(c, st)) return SPH_E_HIP;
-    if (!c->step_tmp.ensure(sizeof(double) * 4 * (size_t)n)) return SPH_E_OOM;
-    double* vp = c->step_tmp.as<double>();
-    double *pvx = vp, *pvy = vp + n, *pvz = vp + 2 * n, *pu = vp + 3 * n;
-    const double hdt = 0.5 * dt;
-    launch_kick(p->vx, p->vy, p->vz, p->u, acc->ax, acc->ay, acc->az, acc->dudt, hdt, n, st);
-    launch_drift(p->x, p->y, p->z, p->vx, p->vy, p->vz, dt, nullptr, c->boxes.as<BoxInfo>(), c->nbox, n, st);
-    launch_predict(p->vx, acc->ax, hdt, pvx, n, st);
-    launch_predict(p->vy, acc->ay, hdt, pvy, n, st);
-    launch_predict(p->vz, acc->az, hdt, pvz, n, st);
-    launch_predict(p->u, acc->dudt, hdt, pu, n, st);
-    sph_particles q = *p;
-    q.vx = pvx; q.vy = pvy; q.vz = pvz; q.u = pu;
-    s = sph_build_cells(c, &q, batch, stream);
-    if (s == SPH_OK) s = sph_sort(c, stream);
-    if (s == SPH_OK) s = sph_density(c, &q, nullptr, stream);
-    if (s != SPH_OK && s != SPH_E_NOT_CONVERGED) return s;
-    sph_status sd = s;
-    s = sph_force(c, &q, acc, stream);
+    if (!c->dt_box.ensure(sizeof(double) * (size_t)c->nbox) || !c->dt_min.ensure(8 * (size_t)c->nbox))
+        return SPH_E_OOM;
+    return SPH_OK;
+}
+
+static bool acc_ok(const sph_force_out* acc, int64_t n, bool need_dt)
+{
+    if (!acc) return false;
+    if (n > 0 && (!acc->ax || !acc->ay || !acc->az || !acc->dudt)) return false;
+    return !(need_dt && n > 0 && !acc->dt);
+}
+
+sph_status sph_step(sph_ctx* c, sph_particles* p, const sph_batch* batch, sph_force_out* acc, double dt,
+                    void* stream)
+{
+    if (!c || !particles_ok(p) || !acc_ok(acc, p ? p->n : 0, false) || !std::isfinite(dt)) return SPH_E_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    if (p->n == 0) return SPH_OK;
+    sph_status s = step_setup(c, p, batch, st);
     if (s != SPH_OK) return s;
-    launch_kick(p->vx, p->vy, p->vz, p->u, acc->ax, acc->ay, acc->az, acc->dudt, hdt, n, st);
-    if (hipGetLastError() != hipSuccess) return SPH_E_HIP;
-    return sd;
+    launch_fill_f64(c->dt_box.as<double>(), dt, c->nbox, st);
+    return step_core(c, p, batch, acc, st);
+}
+
+sph_status sph_step_adaptive(sph_ctx* c, sph_particles* p, const sph_batch* batch, sph_force_out* acc,
+                             double dt_max, double t_end, double* t_box, double* dt_box, void* stream)
+{
+    if (!c || !particles_ok(p) || !acc_ok(acc, p ? p->n : 0, true) || !t_box) return SPH_E_INVALID_ARG;
+    if (!(dt_max > 0.0) || !std::isfinite(dt_max) || !std::isfinite(t_end)) return SPH_E_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    if (p->n == 0) return SPH_OK;
+    sph_status s = step_setup(c, p, batch, st);
+    if (s != SPH_OK) return s;
+    launch_dt_select(acc->dt, c->boxes.as<BoxInfo>(), c->nbox, p->n, c->dt_min.as<unsigned long long>(), dt_max,
+                     t_end, t_box, c->dt_box.as<double>(), dt_box, st);
+    return step_core(c, p, batch, acc, st);
+}
+
+sph_status sph_integrate(sph_ctx* c, sph_particles* p, const sph_batch* batch, sph_force_out* acc, double t_end,
+                         double dt_max, int64_t max_steps, int64_t* steps, void* stream)
+{
+    if (steps) *steps = 0;
+    if (!c || !particles_ok(p) || !acc_ok(acc, p ? p->n : 0, true) || max_steps < 0) return SPH_E_INVALID_ARG;
+    if (!(dt_max > 0.0) || !std::isfinite(dt_max) || !std::isfinite(t_end)) return SPH_E_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    if (p->n == 0) return SPH_OK;
+    if (hipSetDevice(c->device) != hipSuccess) return SPH_E_HIP;
+    // the initial state: accelerations and time steps for the first step
+    sph_status s = sph_build_cells(c, p, batch, st);
+    if (s == SPH_OK) s = sph_sort(c, st);
+    if (s == SPH_OK) s = sph_density(c, p, nullptr, st);
+    if (s != SPH_OK && s != SPH_E_NOT_CONVERGED) return s;
+    sph_status worst = s;
+    s = sph_force(c, p, acc, st);
+    if (s != SPH_OK) return s;
+    const int nb = c->nbox;
+    if (!c->t_box.ensure(sizeof(double) * (size_t)nb)) return SPH_E_OOM;
+    launch_fill_f64(c->t_box.as<double>(), 0.0, nb, st);
+    std::vector<double> tb((size_t)nb, 0.0);
+    int64_t k = 0;
+    for (; k < max_steps; k++) {
+        bool done = true;
+        for (double t : tb) done &= t >= t_end;
+        if (done) break;
+        s = sph_step_adaptive(c, p, batch, acc, dt_max, t_end, c->t_box.as<double>(), nullptr, stream);
+        if (s == SPH_E_NOT_CONVERGED) worst = s;
+        else if (s != SPH_OK) { if (steps) *steps = k; return s; }
+        if (hipMemcpyAsync(tb.data(), c->t_box.as<double>(), sizeof(double) * (size_t)nb, hipMemcpyDeviceToHost,
+                           st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+            if (steps) *steps = k + 1;
+            return SPH_E_HIP;
+        }
+    }
+    if (steps) *steps = k;
+    for (double t : tb)
+        if (t < t_end) return SPH_E_CAPACITY;
+    return worst;
 }
 
 __global__ void k_copy_f64(double* dst, const double* src, int64_t n)

@@ -76,6 +76,7 @@ struct DensityOut {
 struct ForceOut {
     double *ax, *ay, *az, *dudt;
     int32_t* npairs;
+    double* dt;                            // time step of Eq. (6)
     double *ax_c, *ay_c, *az_c, *dudt_c;   // optional cell-order copies (FP64)
 };
 
@@ -178,12 +179,17 @@ void launch_adjoint(const Decomp& dc, const CellData<R>& cd, const Sorted<R>& so
                     hipStream_t st);
 
 // step.hip
-void launch_kick(double* vx, double* vy, double* vz, double* u, const double* ax, const double* ay,
-                 const double* az, const double* dudt, double hdt, int64_t n, hipStream_t st);
-void launch_drift(double* x, double* y, double* z, const double* vx, const double* vy,
-                  const double* vz, double dt, const int64_t* box_of_dummy, const BoxInfo* boxes,
-                  int nbox, int64_t n, hipStream_t st);
-void launch_predict(const double* v, const double* a, double hdt, double* out, int64_t n,
-                    hipStream_t st);
+struct StepArrays {
+    double *x, *y, *z, *vx, *vy, *vz, *u;      // caller's state
+    const double *ax, *ay, *az, *dudt;         // accelerations of the last force evaluation
+    double *pvx, *pvy, *pvz, *pu;              // predicted v, u at the end of the step
+};
+void launch_step_open(const StepArrays& s, const double* dtb, const BoxInfo* boxes, int nbox, int64_t n,
+                      hipStream_t st);
+void launch_step_close(const StepArrays& s, const double* dtb, const BoxInfo* boxes, int nbox, int64_t n,
+                       hipStream_t st);
+void launch_fill_f64(double* a, double v, int n, hipStream_t st);
+void launch_dt_select(const double* dt, const BoxInfo* boxes, int nbox, int64_t n, unsigned long long* mn,
+                      double dt_max, double t_end, double* t_box, double* dtb, double* dt_out, hipStream_t st);
 
 }  // namespace sph

@@ -332,7 +332,7 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
                 const double A = P / (omega * rho * rho);
                 const double cm = sqrt(cx * cx + cy * cy + cz * cz);
                 const double den = fabs(div) + cm + pc.beps * c / h;
-                const double bal = den > 0.0 ? cm / den : 0.0;
+                const double bal = den > 0.0 ? (pc.balsara_div ? fabs(div) : cm) / den : 0.0;
                 cd.h[gi] = h;
                 R4 g0, g1;
                 g0.x = (R)(1.0 / h); g0.y = (R)k5; g0.z = (R)A; g0.w = (R)rho;
@@ -371,8 +371,10 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
 }
 
 // ---------------------------------------------------------------- force
+template <typename R>
 struct ForceAcc {
     double ax, ay, az, du;
+    R vsig;   // largest c_i + c_j - 3 w_ij over the pairs in range (Eq. (6))
     int n;
 };
 
@@ -385,7 +387,7 @@ struct ForceTarget {
 // (one-sided: the contribution of j to particle i).  Pairs outside both
 // supports contribute exactly zero (both kernel gradients vanish there).
 template <typename R>
-__device__ __forceinline__ void force_pair(ForceAcc& a, bool ok, const ForceTarget<R>& ti, R alpha,
+__device__ __forceinline__ void force_pair(ForceAcc<R>& a, bool ok, const ForceTarget<R>& ti, R alpha,
                                            typename Vec4T<R>::T e, typename Vec4T<R>::T vm,
                                            typename Vec4T<R>::T g0, typename Vec4T<R>::T g1)
 {
@@ -400,7 +402,8 @@ __device__ __forceinline__ void force_pair(ForceAcc& a, bool ok, const ForceTarg
     const R mj = ok ? vm.w : (R)0;  // masked pairs contribute nothing
     const R vr = (ti.vx - vm.x) * dx + (ti.vy - vm.y) * dy + (ti.vz - vm.z) * dz;
     const R wij = fmin(vr * rinv, (R)0);
-    const R Pi = -alpha * (ti.c + g1.x - (R)3 * wij) * wij * fast_rcp(ti.rho + g0.w);
+    const R vsig = ti.c + g1.x - (R)3 * wij;   // signal speed of Eq. (6), >= 0
+    const R Pi = -alpha * vsig * wij * fast_rcp(ti.rho + g0.w);
     const R T = Pi * (gwi + gwj) * (ti.f + g1.y);
     const R agi = ti.A * gwi;
     const R sc = -mj * (agi + g0.z * gwj + (R)0.25 * T);
@@ -409,6 +412,7 @@ __device__ __forceinline__ void force_pair(ForceAcc& a, bool ok, const ForceTarg
     a.ay += (double)(sc * dy);
     a.az += (double)(sc * dz);
     a.du += (double)pdu;
+    a.vsig = (ok && (qi < (R)1 || qj < (R)1)) ? fmax(a.vsig, vsig) : a.vsig;
     a.n += ok ? 1 : 0;
 }
 
@@ -452,7 +456,7 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
             const float fxi = (float)ti.x, fyi = (float)ti.y, fzi = (float)ti.z, fh = (float)ti.h;
             for (int a = w; a < NACC_F; a += NW) s.red[a][lane] = 0.0;
             __syncthreads();
-            ForceAcc acc = {};
+            ForceAcc<R> acc = {};
             auto process = [&](int n) {
                 for (int t = 0;; t += 2) {
                     const bool v0 = t < n, v1 = t + 1 < n;
@@ -489,6 +493,9 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
                 atomicAdd(&s.red[2][lane], acc.az);
                 atomicAdd(&s.red[3][lane], acc.du);
                 atomicAdd(&s.red[4][lane], (double)acc.n);
+                // signal speeds are >= 0, where the order of the bit patterns is the order of the values
+                atomicMax((unsigned long long*)&s.red[5][lane],
+                          (unsigned long long)__double_as_longlong((double)acc.vsig));
             }
             __syncthreads();
             if (w == 0 && valid) {
@@ -498,6 +505,11 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
                 if (out.az) out.az[pi] = s.red[2][lane];
                 if (out.dudt) out.dudt[pi] = s.red[3][lane];
                 if (out.npairs) out.npairs[pi] = (int32_t)s.red[4][lane];
+                if (out.dt) {
+                    // j = i contributes 2 c_i (no approach speed)
+                    const double vs = fmax(s.red[5][lane], 2.0 * (double)ti.c);
+                    out.dt[pi] = vs > 0.0 ? pc.cfl * 2.0 * (double)ti.h / vs : (double)INFINITY;
+                }
             }
             __syncthreads();
         }

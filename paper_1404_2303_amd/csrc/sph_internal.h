@@ -127,6 +127,8 @@ struct PassConsts {
     double n_ngb, tol, gamma, alpha, beps;
     int max_iter;
     double h_margin;
+    double cfl;         // C_CFL of Eq. (6)
+    int balsara_div;    // 1: |div v| over the Balsara denominator, 0: |curl v|
 };
 
 }  // namespace sph

@@ -1,73 +1,146 @@
-// step.hip -- kick-drift-kick velocity Verlet (Gonnet 2014, Sec. 4.1) with a
-// fixed step, on the caller's FP64 arrays.
+// step.hip -- kick-drift-kick velocity Verlet (Gonnet 2014, Sec. 4.1) on the
+// caller's FP64 arrays, with one step length per box: a fixed step, or the
+// smallest particle time step of Eq. (6) (Sec. 4.2 runs its blast wave so).
 #include "sph_internal.h"
 #include "kernels.h"
 
 namespace sph {
 
-// v += hdt a, u += hdt du/dt
-__global__ void k_kick(double* vx, double* vy, double* vz, double* u, const double* ax,
-                       const double* ay, const double* az, const double* dudt, double hdt, int64_t n)
+// box of caller-order particle i (boxes sorted by begin)
+__device__ __forceinline__ int box_of(const BoxInfo* boxes, int nbox, int64_t i)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    vx[i] += hdt * ax[i];
-    vy[i] += hdt * ay[i];
-    vz[i] += hdt * az[i];
-    u[i] += hdt * dudt[i];
-}
-
-// x += dt v, wrapped into [0, L) of the particle's box
-__global__ void k_drift(double* x, double* y, double* z, const double* vx, const double* vy,
-                        const double* vz, double dt, const BoxInfo* boxes, int nbox, int64_t n)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
     int lo = 0, hi = nbox - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
         if (boxes[mid].begin <= i) lo = mid; else hi = mid - 1;
     }
-    const BoxInfo& B = boxes[lo];
-    double p[3] = {x[i] + dt * vx[i], y[i] + dt * vy[i], z[i] + dt * vz[i]};
+    return lo;
+}
+
+// Opening half of the step, per particle with dt of its box:
+//   v += dt/2 a_old, u += dt/2 du_old, x += dt v (wrapped into [0, L)),
+//   predictions for the force evaluation at the new positions:
+//   pv = v + dt/2 a_old, pu = u + dt/2 du_old.
+__global__ void k_open(StepArrays s, const double* dtb, const BoxInfo* boxes, int nbox, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int b = box_of(boxes, nbox, i);
+    const double dt = dtb[b], hdt = 0.5 * dt;
+    const double ax = s.ax[i], ay = s.ay[i], az = s.az[i], du = s.dudt[i];
+    const double vx = s.vx[i] + hdt * ax, vy = s.vy[i] + hdt * ay, vz = s.vz[i] + hdt * az;
+    const double u = s.u[i] + hdt * du;
+    s.vx[i] = vx; s.vy[i] = vy; s.vz[i] = vz; s.u[i] = u;
+    s.pvx[i] = vx + hdt * ax; s.pvy[i] = vy + hdt * ay; s.pvz[i] = vz + hdt * az; s.pu[i] = u + hdt * du;
+    const BoxInfo& B = boxes[b];
+    double p[3] = {s.x[i] + dt * vx, s.y[i] + dt * vy, s.z[i] + dt * vz};
     for (int d = 0; d < 3; d++) {
         double w = fmod(p[d], B.L[d]);
         if (w < 0.0) w += B.L[d];
         if (w >= B.L[d]) w -= B.L[d];
         p[d] = w;
     }
-    x[i] = p[0]; y[i] = p[1]; z[i] = p[2];
+    s.x[i] = p[0]; s.y[i] = p[1]; s.z[i] = p[2];
 }
 
-// out = v + hdt a
-__global__ void k_predict(const double* v, const double* a, double hdt, double* out, int64_t n)
+// Closing kick with the new accelerations: v += dt/2 a, u += dt/2 du/dt.
+__global__ void k_close(StepArrays s, const double* dtb, const BoxInfo* boxes, int nbox, int64_t n)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = v[i] + hdt * a[i];
+    if (i >= n) return;
+    const double hdt = 0.5 * dtb[box_of(boxes, nbox, i)];
+    s.vx[i] += hdt * s.ax[i];
+    s.vy[i] += hdt * s.ay[i];
+    s.vz[i] += hdt * s.az[i];
+    s.u[i] += hdt * s.dudt[i];
 }
 
-void launch_kick(double* vx, double* vy, double* vz, double* u, const double* ax, const double* ay,
-                 const double* az, const double* dudt, double hdt, int64_t n, hipStream_t st)
+__global__ void k_fill_f64(double* a, double v, int n)
 {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_kick, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, vx, vy, vz, u, ax,
-                       ay, az, dudt, hdt, n);
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
 }
 
-void launch_drift(double* x, double* y, double* z, const double* vx, const double* vy,
-                  const double* vz, double dt, const int64_t*, const BoxInfo* boxes, int nbox,
-                  int64_t n, hipStream_t st)
+__global__ void k_fill_u64(unsigned long long* a, unsigned long long v, int n)
 {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_drift, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, y, z, vx, vy,
-                       vz, dt, boxes, nbox, n);
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
 }
 
-void launch_predict(const double* v, const double* a, double hdt, double* out, int64_t n,
-                    hipStream_t st)
+__device__ __forceinline__ double wave_min(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Per-box minimum of the particle time steps (values >= 0, so the order of
+// their bit patterns is their order).  A wavefront whose particles all lie in
+// one box reduces first and issues one atomic.
+__global__ void k_box_min(const double* dt, const BoxInfo* boxes, int nbox, int64_t n, unsigned long long* mn)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i - (int64_t)(threadIdx.x & 63) >= n) return;   // the whole wavefront is past the end
+    const bool valid = i < n;
+    const int b = valid ? box_of(boxes, nbox, i) : -1;
+    const double v = valid ? dt[i] : (double)INFINITY;
+    const int b0 = __builtin_amdgcn_readfirstlane(b);   // lane 0 is valid here
+    if (__all(!valid || b == b0)) {
+        const double m = wave_min(v);
+        if ((threadIdx.x & 63) == 0) atomicMin(&mn[b0], (unsigned long long)__double_as_longlong(m));
+    } else if (valid) {
+        atomicMin(&mn[b], (unsigned long long)__double_as_longlong(v));
+    }
+}
+
+// dt_b = min(smallest particle step, dt_max, t_end - t_b), and the box times
+__global__ void k_dt_select(const unsigned long long* mn, int nbox, double dt_max, double t_end, double* t_box,
+                            double* dtb, double* dt_out)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
+    double dt = fmin(__longlong_as_double((long long)mn[b]), dt_max);
+    const double rem = t_end - t_box[b];
+    if (!(rem > 0.0)) {
+        dt = 0.0;
+    } else if (dt >= rem) {
+        dt = rem;
+        t_box[b] = t_end;
+    } else {
+        t_box[b] += dt;
+    }
+    dtb[b] = dt;
+    if (dt_out) dt_out[b] = dt;
+}
+
+static unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+void launch_step_open(const StepArrays& s, const double* dtb, const BoxInfo* boxes, int nbox, int64_t n,
+                      hipStream_t st)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_predict, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v, a, hdt, out, n);
+    hipLaunchKernelGGL(k_open, dim3(blocks(n)), dim3(256), 0, st, s, dtb, boxes, nbox, n);
+}
+
+void launch_step_close(const StepArrays& s, const double* dtb, const BoxInfo* boxes, int nbox, int64_t n,
+                       hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_close, dim3(blocks(n)), dim3(256), 0, st, s, dtb, boxes, nbox, n);
+}
+
+void launch_fill_f64(double* a, double v, int n, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_f64, dim3(blocks(n)), dim3(256), 0, st, a, v, n);
+}
+
+void launch_dt_select(const double* dt, const BoxInfo* boxes, int nbox, int64_t n, unsigned long long* mn,
+                      double dt_max, double t_end, double* t_box, double* dtb, double* dt_out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill_u64, dim3(blocks(nbox)), dim3(256), 0, st, mn, 0x7FF0000000000000ull, nbox);
+    if (n > 0) hipLaunchKernelGGL(k_box_min, dim3(blocks(n)), dim3(256), 0, st, dt, boxes, nbox, n, mn);
+    hipLaunchKernelGGL(k_dt_select, dim3(blocks(nbox)), dim3(256), 0, st, mn, nbox, dt_max, t_end, t_box, dtb,
+                       dt_out);
 }
 
 }  // namespace sph

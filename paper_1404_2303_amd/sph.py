@@ -3,7 +3,8 @@
 Torch tensors provide device memory and the stream; every computation runs in
 the HIP kernels of libsph_mi355x.so.  The low-level functions carry the C
 names (``sph_create``, ``sph_build_cells``, ``sph_sort``, ``sph_density``,
-``sph_force``, ``sph_step``, ``sph_backward``); :class:`Context` wraps them
+``sph_force``, ``sph_step``, ``sph_step_adaptive``, ``sph_integrate``,
+``sph_backward``); :class:`Context` wraps them
 for tensors and :class:`SPHPass` exposes the pass to torch.autograd.
 There is no fallback: if the library is missing, loading raises.
 """
@@ -22,11 +23,13 @@ LIB_PATH = os.path.join(HERE, "libsph_mi355x.so")
 SPH_OK, SPH_E_INVALID_ARG, SPH_E_NONFINITE, SPH_E_H_TOO_LARGE, SPH_E_NOT_CONVERGED = 0, 1, 2, 3, 4
 SPH_E_CAPACITY, SPH_E_OOM, SPH_E_HIP, SPH_E_STATE = 5, 6, 7, 8
 SPH_FP64, SPH_FP32_ACC64 = 0, 1
+SPH_BALSARA_CURL, SPH_BALSARA_DIV = 0, 1
 
 EXPORTED = ["sph_default_params", "sph_create", "sph_destroy", "sph_build_cells", "sph_sort",
             "sph_density", "sph_force", "sph_step", "sph_get_stats", "sph_status_string",
             "sph_enable_timing", "sph_get_kernel_times", "sph_density_async", "sph_check",
-            "sph_graph_capture", "sph_graph_launch", "sph_backward", "sph_estimate_h"]
+            "sph_graph_capture", "sph_graph_launch", "sph_backward", "sph_estimate_h", "sph_step_adaptive",
+            "sph_integrate"]
 
 P = ctypes.c_void_p
 
@@ -37,7 +40,7 @@ class sph_params(ctypes.Structure):
                 ("balsara_eps", ctypes.c_double), ("precision", ctypes.c_int),
                 ("cell_target", ctypes.c_int), ("h_margin", ctypes.c_double),
                 ("max_rebuilds", ctypes.c_int), ("max_depth", ctypes.c_int), ("split_count", ctypes.c_int),
-                ("split_frac", ctypes.c_double)]
+                ("split_frac", ctypes.c_double), ("cfl", ctypes.c_double), ("balsara_form", ctypes.c_int)]
 
 
 class sph_particles(ctypes.Structure):
@@ -61,8 +64,11 @@ class sph_kernel_times(ctypes.Structure):
                 ("force_ms", ctypes.c_float), ("backward_ms", ctypes.c_float)]
 
 
+FORCE_FIELDS = ("ax", "ay", "az", "dudt", "n_pairs", "dt")
+
+
 class sph_force_out(ctypes.Structure):
-    _fields_ = [(k, P) for k in ("ax", "ay", "az", "dudt", "n_pairs")]
+    _fields_ = [(k, P) for k in FORCE_FIELDS]
 
 
 class sph_grad_in(ctypes.Structure):
@@ -107,6 +113,13 @@ def load_library():
         lib.sph_step.restype = st
         lib.sph_step.argtypes = [P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_batch),
                                  ctypes.POINTER(sph_force_out), ctypes.c_double, P]
+        lib.sph_step_adaptive.restype = st
+        lib.sph_step_adaptive.argtypes = [P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_batch),
+                                          ctypes.POINTER(sph_force_out), ctypes.c_double, ctypes.c_double, P, P, P]
+        lib.sph_integrate.restype = st
+        lib.sph_integrate.argtypes = [P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_batch),
+                                      ctypes.POINTER(sph_force_out), ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), P]
         lib.sph_get_stats.restype = st
         lib.sph_get_stats.argtypes = [P, ctypes.POINTER(sph_stats)]
         lib.sph_enable_timing.restype = st
@@ -197,6 +210,20 @@ def sph_force(ctx, parts: sph_particles, out: sph_force_out, stream):
 def sph_step(ctx, parts: sph_particles, batch: Optional[sph_batch], acc: sph_force_out, dt: float, stream):
     return load_library().sph_step(ctx, ctypes.byref(parts), ctypes.byref(batch) if batch is not None else None,
                                    ctypes.byref(acc), float(dt), stream)
+
+
+def sph_step_adaptive(ctx, parts: sph_particles, batch: Optional[sph_batch], acc: sph_force_out, dt_max: float,
+                      t_end: float, t_box, dt_box, stream):
+    return load_library().sph_step_adaptive(ctx, ctypes.byref(parts),
+                                            ctypes.byref(batch) if batch is not None else None, ctypes.byref(acc),
+                                            float(dt_max), float(t_end), t_box, dt_box, stream)
+
+
+def sph_integrate(ctx, parts: sph_particles, batch: Optional[sph_batch], acc: sph_force_out, t_end: float,
+                  dt_max: float, max_steps: int, steps, stream):
+    return load_library().sph_integrate(ctx, ctypes.byref(parts), ctypes.byref(batch) if batch is not None else None,
+                                        ctypes.byref(acc), float(t_end), float(dt_max), int(max_steps), steps,
+                                        stream)
 
 
 def sph_density_async(ctx, parts: sph_particles, out: Optional[sph_density_out], stream):
@@ -329,20 +356,51 @@ class Context:
                                           allow)
         return out
 
+    @staticmethod
+    def force_buffers(n, dev):
+        out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("ax", "ay", "az", "dudt", "dt")}
+        out["n_pairs"] = torch.empty(n, dtype=torch.int32, device=dev)
+        return out
+
     def force(self, parts: Particles, out=None):
-        n = parts.n
-        dev = parts.x.device
         if out is None:
-            out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("ax", "ay", "az", "dudt")}
-            out["n_pairs"] = torch.empty(n, dtype=torch.int32, device=dev)
-        c = sph_force_out(*[_ptr(out.get(k)) for k in ("ax", "ay", "az", "dudt", "n_pairs")])
+            out = self.force_buffers(parts.n, parts.x.device)
+        c = sph_force_out(*[_ptr(out.get(k)) for k in FORCE_FIELDS])
         _check(sph_force(self.ctx, parts.c_struct(), c, _stream()), "sph_force")
         return out
 
     def step(self, parts: Particles, acc: dict, dt: float, batch: Optional[Batch] = None):
-        c = sph_force_out(*[_ptr(acc.get(k)) for k in ("ax", "ay", "az", "dudt", "n_pairs")])
+        """One kick-drift-kick step of fixed length dt; acc (a, du/dt, optionally dt) is updated."""
+        c = sph_force_out(*[_ptr(acc.get(k)) for k in FORCE_FIELDS])
         return _check(sph_step(self.ctx, parts.c_struct(), batch.c if batch else None, c, dt, _stream()),
                       "sph_step", (SPH_E_NOT_CONVERGED,))
+
+    def step_adaptive(self, parts: Particles, acc: dict, t_box: torch.Tensor, t_end: float, dt_max: float,
+                      batch: Optional[Batch] = None, dt_box: Optional[torch.Tensor] = None):
+        """One step whose length per box is the smallest time step of Eq. (6) in acc["dt"]
+        (capped by dt_max, clipped at t_end); t_box (FP64, one per box) is advanced."""
+        nbox = batch.nbox if batch else 1
+        for t in (t_box, dt_box):
+            if t is not None and (t.dtype != torch.float64 or not t.is_cuda or t.numel() < nbox
+                                  or not t.is_contiguous()):
+                raise ValueError("t_box and dt_box must be contiguous float64 CUDA tensors of one value per box")
+        if acc.get("dt") is None:
+            raise ValueError("acc needs the time steps of the last force evaluation (key 'dt')")
+        c = sph_force_out(*[_ptr(acc.get(k)) for k in FORCE_FIELDS])
+        return _check(sph_step_adaptive(self.ctx, parts.c_struct(), batch.c if batch else None, c, dt_max, t_end,
+                                        _ptr(t_box), _ptr(dt_box), _stream()),
+                      "sph_step_adaptive", (SPH_E_NOT_CONVERGED,))
+
+    def integrate(self, parts: Particles, t_end: float, dt_max: float, max_steps: int = 1 << 30,
+                  batch: Optional[Batch] = None, acc: Optional[dict] = None):
+        """Integrate from t = 0 to t_end with steps limited by Eq. (6); returns (acc, steps)."""
+        if acc is None:
+            acc = self.force_buffers(parts.n, parts.x.device)
+        c = sph_force_out(*[_ptr(acc.get(k)) for k in FORCE_FIELDS])
+        steps = ctypes.c_int64(0)
+        _check(sph_integrate(self.ctx, parts.c_struct(), batch.c if batch else None, c, t_end, dt_max, max_steps,
+                             ctypes.byref(steps), _stream()), "sph_integrate", (SPH_E_NOT_CONVERGED,))
+        return acc, int(steps.value)
 
     def backward(self, parts: Particles, g_rho=None, g_a=None, g_dudt=None, implicit_h=True, want_h=False):
         """Gradients of L at the state of the last density(): dL/dx as (N,3) and, if want_h
@@ -389,7 +447,7 @@ class Context:
         dc = None
         if dout is not None:
             dc = sph_density_out(*[_ptr(dout.get(k)) for k in DENSITY_FIELDS])
-        fc = sph_force_out(*[_ptr(fout.get(k)) for k in ("ax", "ay", "az", "dudt", "n_pairs")])
+        fc = sph_force_out(*[_ptr(fout.get(k)) for k in FORCE_FIELDS])
         self._graph_keep = (parts, batch, h_init, dout, fout, dc, fc)
         pc = parts.c_struct()
         self._graph_pc = pc

@@ -19,6 +19,10 @@ Sets
                r = a (X^(-2/3) - 1)^(-1/2) with X ~ U(0,1), redrawn while
                r >= r_cut, isotropic directions, wrapped into the box.
 ``batch``      independent uniform boxes with log-uniform counts, seeded per box.
+``sod``        the shock tube of Sec. 4.2: a periodic 8 x 1 x 1 box, density 4
+               and pressure 1 on x < 4 (face-centred cubic lattice, 4 sites
+               per lattice cell), density 1 and pressure 0.1795 on x >= 4
+               (simple cubic lattice of the same cell), equal masses, at rest.
 """
 from __future__ import annotations
 
@@ -143,6 +147,45 @@ def batch(n_boxes: int = 256, n_min: int = 2048, n_max: int = 65536, seed: int =
                       box=np.ones(3), name=f"batch{n_boxes}")
     lens = np.ones((n_boxes, 3))
     return cat, offsets, lens
+
+
+SOD_LEFT = (4.0, 0.0, 1.0)       # (rho, v, P) on x < L/2
+SOD_RIGHT = (1.0, 0.0, 0.1795)   # (rho, v, P) on x >= L/2
+
+
+def sod(k: int = 16, length: float = 8.0, gamma: float = 5.0 / 3.0) -> ParticleSet:
+    """Sod shock tube of Sec. 4.2 in a periodic length x 1 x 1 box.
+
+    Lattice cells of edge 1/k: the dense half holds a face-centred cubic
+    lattice (4 sites per cell), the light half a simple cubic one (1 site per
+    cell), so that equal masses m = 1/k^3 give densities 4 and 1.  The
+    internal energy per unit mass is set from the pressure of each side,
+    u = P / ((gamma - 1) rho).  With k = 37 there are 810,448 + 202,612
+    particles (the paper uses 800,000 + 200,000).  The interfaces are at
+    x = length/2 and at x = 0 (periodic).
+    """
+    a = 1.0 / k
+    nx = int(round(length * k))
+    half = nx // 2
+    ii, jj, kk = np.meshgrid(np.arange(half), np.arange(k), np.arange(k), indexing="ij")
+    cell = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1).astype(np.float64)
+    fcc = np.array([[0.0, 0.0, 0.0], [0.5, 0.5, 0.0], [0.5, 0.0, 0.5], [0.0, 0.5, 0.5]]) + 0.25
+    dense = ((cell[:, None, :] + fcc[None, :, :]) * a).reshape(-1, 3)
+    light = (cell + np.array([half, 0.0, 0.0]) + 0.5) * a
+    pos = np.concatenate([dense, light])
+    n_d = dense.shape[0]
+    n = pos.shape[0]
+    box = np.array([nx * a, 1.0, 1.0])
+    rl, _, pl = SOD_LEFT
+    rr, _, pr = SOD_RIGHT
+    u = np.empty(n)
+    u[:n_d] = pl / ((gamma - 1.0) * rl)
+    u[n_d:] = pr / ((gamma - 1.0) * rr)
+    h0 = np.empty(n)
+    h0[:n_d] = mean_spacing_h(4.0 * k ** 3)
+    h0[n_d:] = mean_spacing_h(1.0 * k ** 3)
+    return ParticleSet(pos=np.ascontiguousarray(pos), vel=np.zeros((n, 3)), m=np.full(n, a ** 3), u=u, h0=h0,
+                       box=box, name=f"sod{n}", meta={"n_dense": n_d, "x0": box[0] / 2, "gamma": gamma})
 
 
 def density_target(pos: np.ndarray, mean_density: float, amp: float = 0.1) -> np.ndarray:
