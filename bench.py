@@ -405,6 +405,41 @@ def cpu_baseline(seed=0):
                       f"({ps.n} particles, same spacing/jitter/velocity law), {dt:.2f} s, P={P}"}
 
 
+def integrate_section(steps, warmup):
+    """Time integration of the Sod shock tube of Sec. 4.2 at the paper's size
+    (8 x 1 x 1 periodic box, 810,448 + 202,612 particles on FCC | simple cubic
+    lattices, density 4 | 1, pressure 1 | 0.1795), FP32 pair arithmetic,
+    Balsara switch of the |div v| form: kick-drift-kick steps of the length
+    Eq. (6) allows, each step a full rebuild, 13 orderings, density with the
+    Newton iteration, force with the time-step criterion, and the kicks."""
+    import torch
+    from paper_1404_2303_amd import sph, workloads
+    ps = workloads.sod(37)
+    parts = sph.Particles.from_numpy(ps, "cuda:0")
+    ctx = sph.Context(ps.box, precision="fp32", balsara_form=sph.SPH_BALSARA_DIV)
+    d, acc = ctx.run(parts)
+    t_box = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    dt_box = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    for _ in range(warmup):
+        ctx.step_adaptive(parts, acc, t_box, 1e30, 1.0, dt_box=dt_box)
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = float(t_box[0])
+    start.record()
+    for _ in range(steps):
+        ctx.step_adaptive(parts, acc, t_box, 1e30, 1.0, dt_box=dt_box)
+    end.record()
+    end.synchronize()
+    ms = start.elapsed_time(end) / steps
+    P = int(acc["n_pairs"].sum().item())
+    t1 = float(t_box[0])
+    ctx.close()
+    return {"workload": "Sod shock tube, 8x1x1 periodic box, FCC|simple-cubic lattices of cell 1/37 "
+                        f"({ps.n} particles), adaptive steps by Eq. (6), C_CFL 1/4",
+            "n": ps.n, "steps": steps, "ms_per_step": ms, "pairs_per_step": P,
+            "pairs_per_s": P / (ms * 1e-3), "mean_dt": (t1 - t0) / steps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -415,6 +450,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 256-box batched workload")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode timing")
     ap.add_argument("--no-multires", action="store_true", help="skip the 2M-particle Plummer mixture")
+    ap.add_argument("--no-integrate", action="store_true", help="skip the Sod time-integration timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -474,6 +510,9 @@ def main():
     if not args.no_multires:
         line["multires"] = multires_section(max(3, args.steps // 2), 1)
         log("multires:", json.dumps(line["multires"]))
+    if not args.no_integrate:
+        line["integrate"] = integrate_section(max(5, args.steps // 2), 2)
+        log("integrate:", json.dumps(line["integrate"]))
     if not args.no_adjoint:
         line["adjoint"] = adjoint_section(args.steps, args.warmup)
         log("adjoint:", json.dumps(line["adjoint"]))

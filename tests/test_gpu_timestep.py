@@ -276,3 +276,63 @@ def test_sod_shock_tube_matches_exact_solution():
         assert abs(np.mean(r_sph[m]) / rsr - 1) < 0.01
     for name, (er, ev, ep) in errs.items():
         assert er < 0.03 and ev < 0.04 and ep < 0.03, (name, er, ev, ep)
+
+
+def _front_radius(pos, rho, centre, dr=0.005, r_max=0.5):
+    r = np.linalg.norm(pos - centre, axis=1)
+    edges = np.arange(0.0, r_max + 1e-12, dr)
+    idx = np.digitize(r, edges) - 1
+    ok = (idx >= 0) & (idx < len(edges) - 1)
+    cnt = np.bincount(idx[ok], minlength=len(edges) - 1)
+    prof = np.bincount(idx[ok], weights=rho[ok], minlength=len(edges) - 1) / np.maximum(cnt, 1)
+    rc = 0.5 * (edges[1:] + edges[:-1])
+    k = int(np.argmax(np.where(cnt > 0, prof, 0.0)))
+    half = 1.0 + 0.5 * (prof[k] - 1.0)
+    out = np.where((np.arange(len(prof)) > k) & (prof < half) & (cnt > 0))[0]
+    return (rc[out[0]] if len(out) else rc[-1]), rc[k], prof[k]
+
+
+def test_sedov_blast_follows_the_similarity_solution():
+    """Sec. 4.2 blast wave: 55,296 particles on a face-centred cubic lattice at
+    density 1 and pressure 1e-6, energy 1 on the 28 central particles, gamma
+    5/3, C_CFL 1/4, alpha 0.8, every step as long as the smallest time step of
+    Eq. (6) allows, Balsara switch of the |div v| form.  The SPH shock is a
+    transition about one post-shock h wide (~0.04 at R ~ 0.3): between the
+    radius of the density peak of the radially binned SPH density and the
+    radius outside it where the density has fallen half way back to 1.  The
+    Sedov-Taylor radius R = xi0 (E t^2 / rho0)^(1/5), xi0 = 1.1517, must lie
+    inside that transition at two times, its midpoint within 3% of R (the
+    similarity solution assumes a point release and a cold gas), and the peak
+    radius must grow as t^(2/5) to within 0.04 in the exponent (bins of
+    0.005 move the measured exponent by ~0.015).  Energy sum m (v^2/2 + u)
+    is conserved to 1%."""
+    from oracle import sedov
+    ps = workloads.sedov(24)
+    g, E = ps.meta["gamma"], ps.meta["E"]
+    log(f"case sedov {ps.n}")
+    parts = sph.Particles.from_numpy(ps, "cuda:0")
+    ctx = sph.Context(ps.box, precision="fp32", balsara_form=sph.SPH_BALSARA_DIV)
+    e0 = float(np.sum(ps.m * ps.u))
+    xi0 = sedov.xi0(g)
+    radii = []
+    t_prev = 0.0
+    for t in (0.03, 0.06):
+        acc, steps = ctx.integrate(parts, t - t_prev, 1.0)
+        t_prev = t
+        d, _ = ctx.run(parts)
+        torch.cuda.synchronize()
+        pos, vel, u, h = _host(parts)
+        rho = d["rho"].cpu().numpy()
+        e1 = float(np.sum(ps.m * (0.5 * np.sum(vel ** 2, 1) + u)))
+        Rf, Rp, peak = _front_radius(pos, rho, ps.meta["centre"])
+        R = xi0 * (E * t * t / ps.meta["rho0"]) ** 0.2
+        log(f"  t {t}: steps {steps}, front {Rf:.4f} peak at {Rp:.4f} (rho {peak:.2f}), Sedov R {R:.4f}, "
+            f"energy drift {e1 / e0 - 1:.2e}")
+        radii.append(Rp)
+        assert Rp <= R <= Rf
+        assert abs(0.5 * (Rp + Rf) / R - 1.0) < 0.03
+        assert abs(e1 / e0 - 1.0) < 1e-2
+    slope = np.log(radii[1] / radii[0]) / np.log(2.0)
+    log(f"  d ln R / d ln t = {slope:.3f}")
+    assert abs(slope - 0.4) < 0.04
+    ctx.close()

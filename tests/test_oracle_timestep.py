@@ -166,3 +166,41 @@ def test_riemann_mirror_symmetry_and_trivial_case():
     np.testing.assert_allclose(r, 2.0, rtol=1e-12)
     np.testing.assert_allclose(u, 0.3, rtol=1e-10)
     np.testing.assert_allclose(p, 1.5, rtol=1e-12)
+
+
+# ---------------------------------------------------------------- Sedov-Taylor blast
+def test_sedov_constant_matches_textbook():
+    from oracle import sedov
+    # R = xi0 (E t^2/rho0)^(1/5): xi0 = 1.033 for gamma = 1.4 (Taylor 1950;
+    # Landau & Lifshitz, Fluid Mechanics, Sec. 106) and 1.1517 for gamma = 5/3
+    assert abs(sedov.xi0(1.4) - 1.033) < 1e-3
+    assert abs(sedov.xi0(5.0 / 3.0) - 1.1517) < 1e-3
+
+
+def test_sedov_profile_is_a_solution_with_rankine_hugoniot_front():
+    from oracle import sedov
+    g = 5.0 / 3.0
+    xs, psi, phi, pi = sedov.profile(g, xi_min=0.05, n=401)
+    # the front carries the strong-shock jump
+    assert abs(psi[0] - (g + 1) / (g - 1)) < 1e-12 and abs(phi[0] - 2 / (g + 1)) < 1e-12
+    # entropy p rho^-gamma of each shell grows inward (earlier, stronger shocks)
+    Q = pi * psi ** (-g)
+    assert np.all(np.diff(Q) > 0)
+    # mass conservation: the swept-up mass 4/3 pi R^3 rho0 sits inside the front
+    mass = -np.trapezoid(psi * xs * xs, xs) * 4 * np.pi
+    assert abs(mass - 4 * np.pi / 3) < 2e-3 * 4 * np.pi / 3 + 4 * np.pi * 0.05 ** 3
+    # the residual of the momentum equation along the solution is small
+    dphi = np.gradient(phi, xs)
+    dpi = np.gradient(pi, xs)
+    res = (phi - xs) * dphi - 1.5 * phi + dpi / psi
+    assert np.max(np.abs(res[5:-5])) < 1e-3
+
+
+def test_sedov_generator_energy():
+    ps = workloads.sedov(12)
+    e = np.sum(ps.m * ps.u)
+    assert abs(e - 1.0 - ps.m[0] * ps.u.min() * (ps.n - 28)) < 1e-12
+    r = np.linalg.norm(ps.pos - 0.5, axis=1)
+    hot = np.sort(r[ps.meta["hot"]])
+    # complete shells: the next particle lies strictly farther out
+    assert np.sort(r)[28] > hot[-1] + 1e-9
