@@ -86,6 +86,9 @@ typedef struct {
     double cfl;          /* C_CFL of the time-step criterion, Eq. (6); the paper uses 1/4 */
     int balsara_form;    /* numerator of the Balsara switch f_i of Sec. 4.1:
                             SPH_BALSARA_CURL as printed there, or SPH_BALSARA_DIV */
+    int reuse;           /* pseudo-Verlet reuse (Sec. 3.3): nonzero lets sph_step and
+                            sph_step_adaptive keep the cells and orderings of the last build
+                            (sph_refresh) while they stay valid, instead of rebuilding */
 } sph_params;
 
 /* Numerator of the Balsara switch f = X / (|div v| + |curl v| + eps c/h). */
@@ -98,7 +101,7 @@ enum {
 /* Default parameters: the paper's constants (48, 5/3, 0.8, 1e-4, C_CFL 1/4),
  * FP32_ACC64, cell_target 64, h_margin 0.1, max_iter 64, max_rebuilds 4, unit
  * box, max_depth 0 (single-level grid), split_count 64, split_frac 0.875,
- * balsara_form SPH_BALSARA_CURL. */
+ * balsara_form SPH_BALSARA_CURL, reuse 0. */
 void sph_default_params(sph_params *p);
 
 typedef struct {
@@ -171,6 +174,22 @@ sph_status sph_destroy(sph_ctx *ctx);
  * SPH_E_HIP. */
 sph_status sph_build_cells(sph_ctx *ctx, const sph_particles *p, const sph_batch *batch,
                            void *stream);
+
+/* Pseudo-Verlet reuse of the decomposition (Sec. 3.3 and Sec. 4.1: cells and
+ * orderings kept over several steps until particle motion invalidates them):
+ * refreshes the cell-ordered copies of x, v, u, m, h from p in the cell
+ * membership and orderings of the last sph_build_cells + sph_sort, and
+ * records per box twice the largest displacement since that build (the
+ * drift).  The next sph_density and sph_force widen every early-exit bound
+ * and every staging reach by the drift and require h_i + drift <= the
+ * h limit of the particle's cell, which keeps every pair in range in a listed
+ * cell pair and inside the swept prefix of every stored ordering; where that
+ * no longer holds (an h root beyond it, or a drift above half a cell's h
+ * limit), sph_density rebuilds the cells from p as it does when an h
+ * outgrows them.  Requires a build and sort on the same particle count and
+ * boxes.  Does not synchronise.  Errors: SPH_E_INVALID_ARG, SPH_E_STATE,
+ * SPH_E_HIP (non-finite data is reported by the next sph_density). */
+sph_status sph_refresh(sph_ctx *ctx, const sph_particles *p, void *stream);
 
 /* Initial smoothing lengths for particles without a usable guess: builds the
  * hierarchy of cells down to max_depth levels (params.max_depth >= 1) with
@@ -255,7 +274,9 @@ sph_status sph_backward(sph_ctx *ctx, const sph_particles *p, const sph_grad_in 
  *   predicted v + dt/2 a_old and u + dt/2 du_old,
  *   v += dt/2 a_new, u += dt/2 du_new, and `acc` overwritten with a_new, du_new.
  * acc->ax..dudt must hold the previous step's values (zeros for a cold start).
- * Errors: as sph_build_cells, sph_density. */
+ * With params.reuse the cells and orderings of the last build are refreshed
+ * (sph_refresh) instead of rebuilt when the particle count and boxes are
+ * unchanged.  Errors: as sph_build_cells, sph_density. */
 sph_status sph_step(sph_ctx *ctx, sph_particles *p, const sph_batch *batch, sph_force_out *acc,
                     double dt, void *stream);
 
@@ -310,6 +331,9 @@ typedef struct {
     int32_t max_iter_used;   /* largest Newton count of the last sph_density */
     int32_t unconverged;     /* particles left unconverged by the last sph_density */
     int32_t depth;           /* levels below the top grid in the keys of the last build */
+    int32_t refreshes;       /* sph_refresh calls since the last build */
+    double drift;            /* box 0: twice the largest displacement since the last build
+                                (as of the last sph_refresh) */
 } sph_stats;
 
 sph_status sph_get_stats(const sph_ctx *ctx, sph_stats *out);

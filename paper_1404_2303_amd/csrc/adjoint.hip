@@ -152,7 +152,7 @@ __global__ __launch_bounds__(WGS) void k_adj_sweep(Decomp dc, CellData<R> cd, So
         const CellInfo T = dc.cells[unit];
         const BoxInfo B = dc.boxes[T.box];
         const int nsrc = dc.src_count[unit];
-        const float margin = 1e-5f * (float)fmax(B.e[0], fmax(B.e[1], B.e[2]));
+        const float margin = 1e-5f * (float)fmax(B.e[0], fmax(B.e[1], B.e[2])) + (float)B.drift;
         const float Hst = gd.cell_hmax[unit];
         int k = 0, p = 0;
         stage_wave<R, true, NACC_ADJ>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, margin);

@@ -48,8 +48,9 @@ struct sph_ctx {
     int device = 0;
     // workspace
     DBuf boxes, keys, keys2, vals, vals2, rs_scratch, flag, cellx, cell_of, sc_scratch;
-    DBuf cells, ncells, cell_map, src, src_count, sidx, srec;
+    DBuf cells, ncells, cell_map, src, src_count, srec;
     DBuf rx, ry, rz, h, vm, u;                       // cell order
+    DBuf r0;                                         // cell-relative positions at the last build
     DBuf g0, g1, cell_hmax;                          // ghost quantities, cell order
     DBuf sd0, sd1;                                   // density sums kept for the adjoint
     DBuf src_off;                                    // first source of each cell
@@ -113,8 +114,7 @@ static Sorted<R> sorted_data(sph_ctx* c)
 {
     using R4 = typename Vec4T<R>::T;
     Sorted<R> so;
-    so.idx = c->sidx.as<uint16_t>();
-    so.rec = c->srec.as<R4>();
+    so.rec = c->srec.as<SortRec>();
     return so;
 }
 
@@ -187,8 +187,8 @@ static bool ensure_particles(sph_ctx* c, int64_t n)
         ok &= c->t_small.ensure(N * 4) && c->t_psmall.ensure(S * 4);
         ok &= c->t_group.ensure((27 * N + 1) * 4) && c->sc_scratch.ensure(scan_scratch_words((int64_t)(27 * N)) * 4 + 16);
     }
-    ok &= c->sidx.ensure(N * kSortDirs * 2) && c->srec.ensure(N * kSortDirs * 4 * R);
-    ok &= c->rx.ensure(N * R) && c->ry.ensure(N * R) && c->rz.ensure(N * R);
+    ok &= c->srec.ensure(N * kSortDirs * sizeof(SortRec));
+    ok &= c->rx.ensure(N * R) && c->ry.ensure(N * R) && c->rz.ensure(N * R) && c->r0.ensure(N * 4 * R);
     ok &= c->h.ensure(N * 8) && c->u.ensure(N * 8);
     ok &= c->vm.ensure(N * 4 * R);
     ok &= c->g0.ensure(N * 4 * R) && c->g1.ensure(N * 4 * R);
@@ -220,6 +220,7 @@ void sph_default_params(sph_params* p)
     p->split_frac = 0.875;
     p->cfl = 0.25;
     p->balsara_form = SPH_BALSARA_CURL;
+    p->reuse = 0;
 }
 
 const char* sph_status_string(sph_status s)
@@ -283,7 +284,7 @@ sph_status sph_destroy(sph_ctx* c)
     if (!c) return SPH_OK;
     DBuf* all[] = {&c->boxes, &c->keys, &c->keys2, &c->vals, &c->vals2, &c->rs_scratch, &c->flag,
                    &c->cellx, &c->cell_of, &c->sc_scratch, &c->cells, &c->ncells, &c->cell_map,
-                   &c->src, &c->src_count, &c->sidx, &c->srec, &c->rx, &c->ry, &c->rz, &c->h,
+                   &c->src, &c->src_count, &c->srec, &c->r0, &c->rx, &c->ry, &c->rz, &c->h,
                    &c->vm, &c->u, &c->g0, &c->g1, &c->cell_hmax, &c->qhead, &c->status, &c->step_tmp, &c->dt_box, &c->dt_min, &c->t_box,
                    &c->sd0, &c->sd1, &c->adj_ab, &c->adj_sb0, &c->adj_sb1, &c->adj_x, &c->adj_h, &c->adj_fg,
                    &c->src_off, &c->t_chg, &c->t_node_of, &c->t_node_start, &c->t_node_flag, &c->t_node_hmax,
@@ -450,7 +451,7 @@ static void build_launches(sph_ctx* c, const Particles& pv, hipStream_t st)
                           c->sc_scratch.as<uint32_t>(), st);
     }
     launch_gather<R>(pv, c->vals.as<uint32_t>(), c->cell_of.as<uint32_t>(), c->cells.as<CellInfo>(), boxes,
-                     n, cell_data<R>(c), st);
+                     n, cell_data<R>(c), c->r0.as<typename Vec4T<R>::T>(), st);
     if (c->depth == 0)
         launch_sources(c->cells.as<CellInfo>(), c->ncells.as<int32_t>(), boxes, c->cell_map.as<int32_t>(),
                        c->src.as<Source>(), c->src_off.as<int32_t>(), c->src_count.as<int32_t>(), n, st);
@@ -479,6 +480,7 @@ sph_status sph_build_cells(sph_ctx* c, const sph_particles* p, const sph_batch* 
     }
     c->n = p->n;
     c->built = c->sorted = c->have_density = false;
+    c->stats.refreshes = 0;
     if (!ensure_particles(c, p->n)) return SPH_E_OOM;
     if (!c->boxes.ensure(sizeof(BoxInfo) * c->nbox)) return SPH_E_OOM;
     if (!c->cell_map.ensure(sizeof(int32_t) * std::max<int64_t>(c->map_total, 1))) return SPH_E_OOM;
@@ -494,6 +496,42 @@ sph_status sph_build_cells(sph_ctx* c, const sph_particles* p, const sph_batch* 
     }
     if (hipGetLastError() != hipSuccess) return SPH_E_HIP;
     c->built = true;
+    return SPH_OK;
+}
+
+// The batch layout of the last build equals `batch` (NULL: one box of params.box).
+static bool same_layout(const sph_ctx* c, const sph_batch* batch)
+{
+    if (!batch) return c->batch_off.empty();
+    if ((int)c->batch_off.size() != batch->nbox + 1 || !batch->box_offsets || !batch->box_len) return false;
+    for (int b = 0; b <= batch->nbox; b++)
+        if (c->batch_off[(size_t)b] != batch->box_offsets[b]) return false;
+    for (int k = 0; k < 3 * batch->nbox; k++)
+        if (c->batch_len[(size_t)k] != batch->box_len[k]) return false;
+    return true;
+}
+
+sph_status sph_refresh(sph_ctx* c, const sph_particles* p, void* stream)
+{
+    if (!c || !particles_ok(p)) return SPH_E_INVALID_ARG;
+    if (!c->built || !c->sorted || p->n != c->n) return SPH_E_STATE;
+    hipStream_t st = (hipStream_t)stream;
+    if (hipSetDevice(c->device) != hipSuccess) return SPH_E_HIP;
+    c->have_density = false;
+    launch_fill_i32(c->status.as<int32_t>(), 4, 0, st);
+    if (p->n > 0) {
+        Particles pv = view(p);
+        if (c->prm.precision == SPH_FP64)
+            launch_refresh<double>(pv, c->vals.as<uint32_t>(), c->cell_of.as<uint32_t>(), c->cells.as<CellInfo>(),
+                                   c->boxes.as<BoxInfo>(), c->nbox, c->n, cell_data<double>(c),
+                                   c->r0.as<double4>(), c->status.as<uint32_t>(), st);
+        else
+            launch_refresh<float>(pv, c->vals.as<uint32_t>(), c->cell_of.as<uint32_t>(), c->cells.as<CellInfo>(),
+                                  c->boxes.as<BoxInfo>(), c->nbox, c->n, cell_data<float>(c), c->r0.as<float4>(),
+                                  c->status.as<uint32_t>(), st);
+    }
+    if (hipGetLastError() != hipSuccess) return SPH_E_HIP;
+    c->stats.refreshes++;
     return SPH_OK;
 }
 
@@ -728,7 +766,7 @@ sph_status sph_backward(sph_ctx* c, const sph_particles* p, const sph_grad_in* g
 
 // The step proper, with the step length of each box in c->dt_box (device).
 static sph_status step_core(sph_ctx* c, sph_particles* p, const sph_batch* batch, sph_force_out* acc,
-                            hipStream_t st)
+                            bool reuse, hipStream_t st)
 {
     const int64_t n = p->n;
     if (!c->step_tmp.ensure(sizeof(double) * 4 * (size_t)n)) return SPH_E_OOM;
@@ -741,8 +779,8 @@ static sph_status step_core(sph_ctx* c, sph_particles* p, const sph_batch* batch
     launch_step_open(sa, dtb, c->boxes.as<BoxInfo>(), c->nbox, n, st);
     sph_particles q = *p;
     q.vx = sa.pvx; q.vy = sa.pvy; q.vz = sa.pvz; q.u = sa.pu;
-    sph_status s = sph_build_cells(c, &q, batch, st);
-    if (s == SPH_OK) s = sph_sort(c, st);
+    sph_status s = reuse ? sph_refresh(c, &q, st) : sph_build_cells(c, &q, batch, st);
+    if (s == SPH_OK && !reuse) s = sph_sort(c, st);
     if (s == SPH_OK) s = sph_density(c, &q, nullptr, st);
     if (s != SPH_OK && s != SPH_E_NOT_CONVERGED) return s;
     sph_status sd = s;
@@ -753,15 +791,26 @@ static sph_status step_core(sph_ctx* c, sph_particles* p, const sph_batch* batch
     return sd;
 }
 
+// The decomposition of the last build can serve a step on p: reuse is on, the
+// cells and orderings exist, and the particle count and boxes are unchanged.
+static bool can_reuse(const sph_ctx* c, const sph_particles* p, const sph_batch* batch)
+{
+    return c->prm.reuse && c->built && c->sorted && p->n == c->n && same_layout(c, batch);
+}
+
 // box table and per-box step buffers for a step on p
-static sph_status step_setup(sph_ctx* c, const sph_particles* p, const sph_batch* batch, hipStream_t st)
+static sph_status step_setup(sph_ctx* c, const sph_particles* p, const sph_batch* batch, bool reuse,
+                             hipStream_t st)
 {
     if (hipSetDevice(c->device) != hipSuccess) return SPH_E_HIP;
-    // box table for the opening half (the build in the step refreshes it)
-    sph_status s = setup_boxes(c, p->n, batch);
-    if (s != SPH_OK) return s;
-    if (!c->boxes.ensure(sizeof(BoxInfo) * c->nbox)) return SPH_E_OOM;
-    if (!upload_boxes(c, st)) return SPH_E_HIP;
+    if (!reuse) {
+        // box table for the opening half (the build in the step refreshes it);
+        // a reused decomposition keeps the table of its build
+        sph_status s = setup_boxes(c, p->n, batch);
+        if (s != SPH_OK) return s;
+        if (!c->boxes.ensure(sizeof(BoxInfo) * c->nbox)) return SPH_E_OOM;
+        if (!upload_boxes(c, st)) return SPH_E_HIP;
+    }
     if (!c->dt_box.ensure(sizeof(double) * (size_t)c->nbox) || !c->dt_min.ensure(8 * (size_t)c->nbox))
         return SPH_E_OOM;
     return SPH_OK;
@@ -780,10 +829,11 @@ sph_status sph_step(sph_ctx* c, sph_particles* p, const sph_batch* batch, sph_fo
     if (!c || !particles_ok(p) || !acc_ok(acc, p ? p->n : 0, false) || !std::isfinite(dt)) return SPH_E_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
     if (p->n == 0) return SPH_OK;
-    sph_status s = step_setup(c, p, batch, st);
+    const bool reuse = can_reuse(c, p, batch);
+    sph_status s = step_setup(c, p, batch, reuse, st);
     if (s != SPH_OK) return s;
     launch_fill_f64(c->dt_box.as<double>(), dt, c->nbox, st);
-    return step_core(c, p, batch, acc, st);
+    return step_core(c, p, batch, acc, reuse, st);
 }
 
 sph_status sph_step_adaptive(sph_ctx* c, sph_particles* p, const sph_batch* batch, sph_force_out* acc,
@@ -793,11 +843,12 @@ sph_status sph_step_adaptive(sph_ctx* c, sph_particles* p, const sph_batch* batc
     if (!(dt_max > 0.0) || !std::isfinite(dt_max) || !std::isfinite(t_end)) return SPH_E_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
     if (p->n == 0) return SPH_OK;
-    sph_status s = step_setup(c, p, batch, st);
+    const bool reuse = can_reuse(c, p, batch);
+    sph_status s = step_setup(c, p, batch, reuse, st);
     if (s != SPH_OK) return s;
     launch_dt_select(acc->dt, c->boxes.as<BoxInfo>(), c->nbox, p->n, c->dt_min.as<unsigned long long>(), dt_max,
                      t_end, t_box, c->dt_box.as<double>(), dt_box, st);
-    return step_core(c, p, batch, acc, st);
+    return step_core(c, p, batch, acc, reuse, st);
 }
 
 sph_status sph_integrate(sph_ctx* c, sph_particles* p, const sph_batch* batch, sph_force_out* acc, double t_end,
@@ -938,6 +989,7 @@ sph_status sph_get_stats(const sph_ctx* c, sph_stats* out)
         BoxInfo b0;
         if (c->built && hipMemcpy(&b0, c->boxes.p, sizeof(BoxInfo), hipMemcpyDeviceToHost) == hipSuccess) {
             out->grid[0] = b0.nc[0]; out->grid[1] = b0.nc[1]; out->grid[2] = b0.nc[2];
+            out->drift = b0.drift;
         }
     }
     return SPH_OK;

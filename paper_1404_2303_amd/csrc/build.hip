@@ -352,9 +352,21 @@ __global__ void k_cell_counts(CellInfo* cells, const int32_t* ncells, const BoxI
 }
 
 // ---------------------------------------------------------------- gather (cell order)
+// Position of a particle relative to the lower corner of its cell: the
+// periodic image nearest the cell (a particle that moved across the box face
+// since the cells were built stays next to its cell).
+__device__ inline double cell_rel(double v, double o, double L)
+{
+    double r = wrap_coord(v, L) - o;
+    if (r > 0.5 * L) r -= L;
+    if (r < -0.5 * L) r += L;
+    return r;
+}
+
 template <typename R>
 __global__ void k_gather(Particles p, const uint32_t* perm, const uint32_t* cell_of,
-                         const CellInfo* cells, const BoxInfo* boxes, int64_t n, CellData<R> cd)
+                         const CellInfo* cells, const BoxInfo* boxes, int64_t n, CellData<R> cd,
+                         typename Vec4T<R>::T* r0)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -364,11 +376,9 @@ __global__ void k_gather(Particles p, const uint32_t* perm, const uint32_t* cell
     double pos[3] = {p.x[i], p.y[i], p.z[i]};
     R rel[3];
     for (int d = 0; d < 3; d++) {
-        double w = wrap_coord(pos[d], B.L[d]);
         double o = (double)C.c[d] * ldexp(B.e[d], -B.depth);
-        double r = w - o;
         // a coordinate that rounded onto the upper face belongs to this cell
-        rel[d] = (R)r;
+        rel[d] = (R)cell_rel(pos[d], o, B.L[d]);
     }
     cd.rx[k] = rel[0]; cd.ry[k] = rel[1]; cd.rz[k] = rel[2];
     cd.h[k] = p.h[i];
@@ -376,6 +386,72 @@ __global__ void k_gather(Particles p, const uint32_t* perm, const uint32_t* cell
     vm.x = (R)p.vx[i]; vm.y = (R)p.vy[i]; vm.z = (R)p.vz[i]; vm.w = (R)p.m[i];
     cd.vm[k] = vm;
     cd.u[k] = p.u[i];
+    if (r0) {
+        typename Vec4T<R>::T q;
+        q.x = rel[0]; q.y = rel[1]; q.z = rel[2]; q.w = (R)0;
+        r0[k] = q;
+    }
+}
+
+// Pseudo-Verlet reuse (Sec. 3.3 keeps orderings over several steps): the
+// cell-ordered copies of the particle data are refreshed from the caller's
+// arrays in the cell membership of the last build, and each box records twice
+// the largest displacement since that build (BoxInfo::drift).  A particle
+// has left its cell by at most its displacement and its projection on any
+// axis has moved by at most as much, so pairs in range still lie in listed
+// cell pairs, and the stored orderings still bound the sweeps, once every
+// range and every early-exit bound is widened by the drift.
+template <typename R>
+__global__ void k_refresh(Particles p, const uint32_t* perm, const uint32_t* cell_of, const CellInfo* cells,
+                          BoxInfo* boxes, int64_t n, CellData<R> cd, const typename Vec4T<R>::T* r0,
+                          uint32_t* status)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k - (int64_t)(threadIdx.x & 63) >= n) return;   // the whole wavefront is past the end
+    const bool valid = k < n;
+    int b = -1;
+    double dd = 0.0;
+    if (valid) {
+        const uint32_t i = perm[k];
+        const CellInfo& C = cells[cell_of[k]];
+        const BoxInfo& B = boxes[C.box];
+        b = C.box;
+        const double pos[3] = {p.x[i], p.y[i], p.z[i]};
+        const double h = p.h[i];
+        if (!isfinite(pos[0]) || !isfinite(pos[1]) || !isfinite(pos[2]) || !(h > 0.0) || !isfinite(h))
+            atomicOr(status, ST_NONFINITE);
+        R rel[3];
+        for (int d = 0; d < 3; d++) {
+            const double o = (double)C.c[d] * ldexp(B.e[d], -B.depth);
+            rel[d] = (R)cell_rel(pos[d], o, B.L[d]);
+        }
+        cd.rx[k] = rel[0]; cd.ry[k] = rel[1]; cd.rz[k] = rel[2];
+        cd.h[k] = h;
+        typename CellData<R>::R4 vm;
+        vm.x = (R)p.vx[i]; vm.y = (R)p.vy[i]; vm.z = (R)p.vz[i]; vm.w = (R)p.m[i];
+        cd.vm[k] = vm;
+        cd.u[k] = p.u[i];
+        const typename Vec4T<R>::T q = r0[k];
+        const double dx = (double)rel[0] - (double)q.x, dy = (double)rel[1] - (double)q.y,
+                     dz = (double)rel[2] - (double)q.z;
+        dd = 2.0 * sqrt(dx * dx + dy * dy + dz * dz);
+        if (!(dd == dd)) dd = (double)INFINITY;
+    }
+    const int b0 = __builtin_amdgcn_readfirstlane(b);   // lane 0 is valid here
+    if (__all(!valid || b == b0)) {
+        double m = dd;
+        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+        if ((threadIdx.x & 63) == 0)
+            atomicMax((unsigned long long*)&boxes[b0].drift, (unsigned long long)__double_as_longlong(m));
+    } else if (valid) {
+        atomicMax((unsigned long long*)&boxes[b].drift, (unsigned long long)__double_as_longlong(dd));
+    }
+}
+
+__global__ void k_zero_drift(BoxInfo* boxes, int nbox)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nbox) boxes[b].drift = 0.0;
 }
 
 // ---------------------------------------------------------------- sources
@@ -455,15 +531,9 @@ __global__ __launch_bounds__(kWave) void k_sort13_wave(const CellInfo* cells, co
                 }
             }
             // lane r now holds the element of rank r
-            const int t = (int)(v & 0xffffffffu);
-            const R xt = __shfl(x, in ? t : 0, kWave), yt = __shfl(y, in ? t : 0, kWave),
-                    zt = __shfl(z, in ? t : 0, kWave);
             if (in) {
                 const int64_t o = (int64_t)s * n + C.start + lane;
-                so.idx[o] = (uint16_t)t;
-                typename Sorted<R>::R4 r;
-                r.x = xt; r.y = yt; r.z = zt; r.w = (R)key_float((uint32_t)(v >> 32));
-                so.rec[o] = r;
+                so.rec[o] = SortRec{key_float((uint32_t)(v >> 32)), (uint32_t)(v & 0xffffffffu)};
             }
         }
     }
@@ -504,12 +574,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort13(const CellInfo* cells, 
                 rank += (kj < kt) || (kj == kt && j < t);
             }
             int64_t o = (int64_t)s * n + C.start + rank;
-            int64_t k = C.start + t;
-            so.idx[o] = (uint16_t)t;
             const uint32_t b = (kt & 0x80000000u) ? (kt & 0x7fffffffu) : ~kt;
-            typename Sorted<R>::R4 r;
-            r.x = cd.rx[k]; r.y = cd.ry[k]; r.z = cd.rz[k]; r.w = (R)__uint_as_float(b);
-            so.rec[o] = r;
+            so.rec[o] = SortRec{__uint_as_float(b), (uint32_t)t};
         }
     }
 }
@@ -608,18 +674,33 @@ void launch_cells(const uint64_t* keys, uint32_t* flag, uint32_t* cellx, int64_t
 }
 
 template <typename R>
-void launch_gather(const Particles& p, const uint32_t* perm, const uint32_t* cell_of,
-                   const CellInfo* cells, const BoxInfo* boxes, int64_t n, const CellData<R>& cd,
+void launch_gather(const Particles& p, const uint32_t* perm, const uint32_t* cell_of, const CellInfo* cells,
+                   const BoxInfo* boxes, int64_t n, const CellData<R>& cd, typename Vec4T<R>::T* r0,
                    hipStream_t st)
 {
     hipLaunchKernelGGL(k_gather<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, perm,
-                       cell_of, cells, boxes, n, cd);
+                       cell_of, cells, boxes, n, cd, r0);
 }
 template void launch_gather<float>(const Particles&, const uint32_t*, const uint32_t*, const CellInfo*,
-                                   const BoxInfo*, int64_t, const CellData<float>&, hipStream_t);
+                                   const BoxInfo*, int64_t, const CellData<float>&, float4*, hipStream_t);
 template void launch_gather<double>(const Particles&, const uint32_t*, const uint32_t*,
                                     const CellInfo*, const BoxInfo*, int64_t,
-                                    const CellData<double>&, hipStream_t);
+                                    const CellData<double>&, double4*, hipStream_t);
+
+template <typename R>
+void launch_refresh(const Particles& p, const uint32_t* perm, const uint32_t* cell_of, const CellInfo* cells,
+                    BoxInfo* boxes, int nbox, int64_t n, const CellData<R>& cd, const typename Vec4T<R>::T* r0,
+                    uint32_t* status, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zero_drift, dim3((unsigned)((nbox + 255) / 256)), dim3(256), 0, st, boxes, nbox);
+    if (n > 0)
+        hipLaunchKernelGGL(k_refresh<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, perm, cell_of,
+                           cells, boxes, n, cd, r0, status);
+}
+template void launch_refresh<float>(const Particles&, const uint32_t*, const uint32_t*, const CellInfo*, BoxInfo*,
+                                    int, int64_t, const CellData<float>&, const float4*, uint32_t*, hipStream_t);
+template void launch_refresh<double>(const Particles&, const uint32_t*, const uint32_t*, const CellInfo*, BoxInfo*,
+                                     int, int64_t, const CellData<double>&, const double4*, uint32_t*, hipStream_t);
 
 void launch_sources(const CellInfo* cells, const int32_t* ncells, const BoxInfo* boxes,
                     const int32_t* cell_map, Source* src, int32_t* src_off, int32_t* src_count,

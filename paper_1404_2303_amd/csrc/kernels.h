@@ -31,9 +31,7 @@ struct CellData {
 // (x, y, z relative to the cell, projection on the direction).
 template <typename R>
 struct Sorted {
-    using R4 = typename Vec4T<R>::T;
-    uint16_t* idx;
-    R4* rec;
+    SortRec* rec;   // [direction][cell-order slot]: the cell's particles by ascending projection
 };
 
 // Per-particle results of the density stage needed by the force stage, in
@@ -115,7 +113,11 @@ void launch_cells(const uint64_t* keys, uint32_t* flag, uint32_t* cellx, int64_t
 template <typename R>
 void launch_gather(const Particles& p, const uint32_t* perm, const uint32_t* cell_of,
                    const CellInfo* cells, const BoxInfo* boxes, int64_t n, const CellData<R>& cd,
-                   hipStream_t st);
+                   typename Vec4T<R>::T* r0, hipStream_t st);
+template <typename R>
+void launch_refresh(const Particles& p, const uint32_t* perm, const uint32_t* cell_of, const CellInfo* cells,
+                    BoxInfo* boxes, int nbox, int64_t n, const CellData<R>& cd, const typename Vec4T<R>::T* r0,
+                    uint32_t* status, hipStream_t st);
 void launch_sources(const CellInfo* cells, const int32_t* ncells, const BoxInfo* boxes,
                     const int32_t* cell_map, Source* src, int32_t* src_off, int32_t* src_count,
                     int64_t cell_cap, hipStream_t st);

@@ -106,12 +106,22 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
         const int unit = s.unit;
         __syncthreads();
         if (unit >= ncells) break;
-        const CellInfo T = dc.cells[unit];
+        CellInfo T = dc.cells[unit];
         const BoxInfo B = dc.boxes[T.box];
-        const int nsrc = dc.src_count[unit];
-        const double h_lim = (double)T.hlim;  // the interaction lists cover h up to this
+        // the interaction lists cover h up to this (less the drift of particles
+        // since the cells were built); a decomposition that has drifted by more
+        // than half of it is rebuilt rather than swept: the unit is then swept
+        // as an empty cell (no early exit from this loop, whose barriers every
+        // lane must reach together)
+        const double h_lim = (double)T.hlim - B.drift;
+        const bool stale = __builtin_amdgcn_readfirstlane(B.drift <= 0.5 * (double)T.hlim ? 0 : 1) != 0;
+        if (stale) {
+            if (tid == 0) atomicOr(dc.status, ST_REBUILD);
+            T.count = 0;
+        }
+        const int nsrc = stale ? 0 : dc.src_count[unit];
         const double h_box = fmin(B.L[0], fmin(B.L[1], B.L[2])) / 3.0;
-        const float margin = 1e-5f * (float)fmax(B.e[0], fmax(B.e[1], B.e[2]));
+        const float margin = 1e-5f * (float)fmax(B.e[0], fmax(B.e[1], B.e[2])) + (float)B.drift;
         double hc = 0.0;
         for (int t = lane; t < T.count; t += kWave) hc = fmax(hc, cd.h[T.start + t]);
         hc = wave_max(hc);
@@ -130,7 +140,7 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
             const R xi = cd.rx[gi], yi = cd.ry[gi], zi = cd.rz[gi];
             const R4 vmi = cd.vm[gi];
             const float fxi = (float)xi, fyi = (float)yi, fzi = (float)zi;
-            double h = cd.h[gi];
+            double h = fmin(cd.h[gi], h_lim);
             // Newton state (identical in every wavefront)
             double lo = 0.0, hi = INFINITY, h_rebuild = 0.0;
             int iters = 0;
@@ -438,7 +448,7 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
         const CellInfo T = dc.cells[unit];
         const BoxInfo B = dc.boxes[T.box];
         const int nsrc = dc.src_count[unit];
-        const float margin = 1e-5f * (float)fmax(B.e[0], fmax(B.e[1], B.e[2]));
+        const float margin = 1e-5f * (float)fmax(B.e[0], fmax(B.e[1], B.e[2])) + (float)B.drift;
         const float Hst = gd.cell_hmax[unit];
         int k = 0, p = 0;
         stage_wave<R, true, NACC_F>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, margin);

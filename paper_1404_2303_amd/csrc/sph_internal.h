@@ -44,6 +44,8 @@ struct BoxInfo {
     int32_t depth;        // levels below the top grid encoded in the keys (0: single level)
     double e[3];          // cell edges (device-written)
     double hmax;          // largest h in the box (device-written)
+    double drift;         // twice the largest displacement since the cells were built (device-written;
+                          // 0 after a build): the slack that the sweeps and the lists must allow
 };
 
 // ---------------------------------------------------------------- cells
@@ -123,6 +125,14 @@ __host__ __device__ inline uint64_t morton3(uint32_t x, uint32_t y, uint32_t z)
 }
 
 // ---------------------------------------------------------------- kernel parameters
+// One entry of a per-cell ordering (Sec. 3.3): the projection of the particle
+// on the ordering's axis when the ordering was made, and the particle's index
+// within its cell.
+struct SortRec {
+    float key;
+    uint32_t idx;
+};
+
 struct PassConsts {
     double n_ngb, tol, gamma, alpha, beps;
     int max_iter;

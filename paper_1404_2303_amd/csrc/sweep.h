@@ -176,21 +176,21 @@ __device__ void stage_wave(Smem<R, NACC, FORCE>& s, const int w, const Decomp& d
             while (p < S.count) {
                 const int pos = p + lane;
                 bool ok = false;
-                R4 r = {};
                 int l = 0;
                 if (pos < S.count) {
                     const int idx = flip ? (S.count - 1 - pos) : pos;
-                    r = so.rec[sbase + idx];
-                    l = so.idx[sbase + idx];
-                    const float proj = (flip ? -(float)r.w : (float)r.w) + udo;
+                    const SortRec r = so.rec[sbase + idx];
+                    l = (int)r.idx;
+                    const float proj = (flip ? -r.key : r.key) + udo;
                     ok = proj <= reach;
                 }
-                const int cnt = __popcll(__ballot(ok));  // projections are monotone: a prefix
+                const int cnt = __popcll(__ballot(ok));  // the keys are monotone: a prefix
                 const int take = min(cnt, CAPW - fill);
                 if (lane < take) {
+                    // positions now (they may have moved since the ordering was made)
                     const int g = S.start + l;
                     R4 e;
-                    e.x = r.x + dox; e.y = r.y + doy; e.z = r.z + doz;
+                    e.x = cd.rx[g] + dox; e.y = cd.ry[g] + doy; e.z = cd.rz[g] + doz;
                     // projection on the segment axis, recomputed from the shifted position
                     e.w = (R)(u[0] * (float)e.x + u[1] * (float)e.y + u[2] * (float)e.z);
                     s.st[w][fill + lane] = e;

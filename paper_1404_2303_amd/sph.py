@@ -29,7 +29,7 @@ EXPORTED = ["sph_default_params", "sph_create", "sph_destroy", "sph_build_cells"
             "sph_density", "sph_force", "sph_step", "sph_get_stats", "sph_status_string",
             "sph_enable_timing", "sph_get_kernel_times", "sph_density_async", "sph_check",
             "sph_graph_capture", "sph_graph_launch", "sph_backward", "sph_estimate_h", "sph_step_adaptive",
-            "sph_integrate"]
+            "sph_integrate", "sph_refresh"]
 
 P = ctypes.c_void_p
 
@@ -40,7 +40,8 @@ class sph_params(ctypes.Structure):
                 ("balsara_eps", ctypes.c_double), ("precision", ctypes.c_int),
                 ("cell_target", ctypes.c_int), ("h_margin", ctypes.c_double),
                 ("max_rebuilds", ctypes.c_int), ("max_depth", ctypes.c_int), ("split_count", ctypes.c_int),
-                ("split_frac", ctypes.c_double), ("cfl", ctypes.c_double), ("balsara_form", ctypes.c_int)]
+                ("split_frac", ctypes.c_double), ("cfl", ctypes.c_double), ("balsara_form", ctypes.c_int),
+                ("reuse", ctypes.c_int)]
 
 
 class sph_particles(ctypes.Structure):
@@ -82,7 +83,8 @@ class sph_grad_out(ctypes.Structure):
 class sph_stats(ctypes.Structure):
     _fields_ = [("n_cells", ctypes.c_int64), ("n_units", ctypes.c_int64), ("grid", ctypes.c_int32 * 3),
                 ("rebuilds", ctypes.c_int32), ("max_iter_used", ctypes.c_int32),
-                ("unconverged", ctypes.c_int32), ("depth", ctypes.c_int32)]
+                ("unconverged", ctypes.c_int32), ("depth", ctypes.c_int32), ("refreshes", ctypes.c_int32),
+                ("drift", ctypes.c_double)]
 
 
 _lib = None
@@ -120,6 +122,8 @@ def load_library():
         lib.sph_integrate.argtypes = [P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_batch),
                                       ctypes.POINTER(sph_force_out), ctypes.c_double, ctypes.c_double,
                                       ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), P]
+        lib.sph_refresh.restype = st
+        lib.sph_refresh.argtypes = [P, ctypes.POINTER(sph_particles), P]
         lib.sph_get_stats.restype = st
         lib.sph_get_stats.argtypes = [P, ctypes.POINTER(sph_stats)]
         lib.sph_enable_timing.restype = st
@@ -332,6 +336,10 @@ class Context:
         _check(sph_build_cells(self.ctx, parts.c_struct(), batch.c if batch else None, _stream()),
                "sph_build_cells")
 
+    def refresh(self, parts: Particles):
+        """Refresh the cell-ordered particle data in the cells and orderings of the last build."""
+        _check(load_library().sph_refresh(self.ctx, ctypes.byref(parts.c_struct()), _stream()), "sph_refresh")
+
     def sort(self):
         _check(sph_sort(self.ctx, _stream()), "sph_sort")
 
@@ -462,7 +470,7 @@ class Context:
         s = sph_stats()
         _check(load_library().sph_get_stats(self.ctx, ctypes.byref(s)), "sph_get_stats")
         return {"n_cells": s.n_cells, "n_units": s.n_units, "grid": tuple(s.grid), "rebuilds": s.rebuilds,
-                "depth": s.depth}
+                "depth": s.depth, "refreshes": s.refreshes, "drift": s.drift}
 
     def run(self, parts: Particles, batch: Optional[Batch] = None, allow_unconverged=False):
         """build -> sort -> density (h solved in place) -> force."""
