@@ -415,29 +415,54 @@ def integrate_section(steps, warmup):
     import torch
     from paper_1404_2303_amd import sph, workloads
     ps = workloads.sod(37)
-    parts = sph.Particles.from_numpy(ps, "cuda:0")
-    ctx = sph.Context(ps.box, precision="fp32", balsara_form=sph.SPH_BALSARA_DIV)
-    d, acc = ctx.run(parts)
-    t_box = torch.zeros(1, dtype=torch.float64, device="cuda:0")
-    dt_box = torch.zeros(1, dtype=torch.float64, device="cuda:0")
-    for _ in range(warmup):
-        ctx.step_adaptive(parts, acc, t_box, 1e30, 1.0, dt_box=dt_box)
-    torch.cuda.synchronize()
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = float(t_box[0])
-    start.record()
-    for _ in range(steps):
-        ctx.step_adaptive(parts, acc, t_box, 1e30, 1.0, dt_box=dt_box)
-    end.record()
-    end.synchronize()
-    ms = start.elapsed_time(end) / steps
-    P = int(acc["n_pairs"].sum().item())
-    t1 = float(t_box[0])
-    ctx.close()
+
+    def run(reuse):
+        parts = sph.Particles.from_numpy(ps, "cuda:0")
+        ctx = sph.Context(ps.box, precision="fp32", balsara_form=sph.SPH_BALSARA_DIV, reuse=reuse)
+        ctx.enable_timing(True)
+        d, acc = ctx.run(parts)
+        t_box = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        dt_box = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        for _ in range(warmup):
+            ctx.step_adaptive(parts, acc, t_box, 1e30, 1.0, dt_box=dt_box)
+        torch.cuda.synchronize()
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = float(t_box[0])
+        refreshed = 0
+        ms = 0.0
+        kt = {"density_ms": [], "force_ms": []}
+        for _ in range(steps):
+            start.record()
+            ctx.step_adaptive(parts, acc, t_box, 1e30, 1.0, dt_box=dt_box)
+            end.record()
+            end.synchronize()
+            ms += start.elapsed_time(end)
+            st = ctx.stats()
+            reused = st["refreshes"] > 0 and st["rebuilds"] == 0
+            refreshed += 1 if reused else 0
+            times = ctx.kernel_times()
+            for k in kt:
+                kt[k].append((reused, times[k]))
+        ms /= steps
+        kernel = {}
+        for k, v in kt.items():
+            a = [t for r, t in v if r]
+            b = [t for r, t in v if not r]
+            kernel[k] = {"reused_steps": float(np.mean(a)) if a else None,
+                         "rebuilt_steps": float(np.mean(b)) if b else None}
+        P = int(acc["n_pairs"].sum().item())
+        t1 = float(t_box[0])
+        ctx_drift = ctx.stats()["drift"]
+        ctx.close()
+        return {"ms_per_step": ms, "pairs_per_step": P, "pairs_per_s": P / (ms * 1e-3),
+                "mean_dt": (t1 - t0) / steps, "steps_reusing_cells": refreshed, "kernel_ms": kernel,
+                "drift_last": ctx_drift}
+
     return {"workload": "Sod shock tube, 8x1x1 periodic box, FCC|simple-cubic lattices of cell 1/37 "
                         f"({ps.n} particles), adaptive steps by Eq. (6), C_CFL 1/4",
-            "n": ps.n, "steps": steps, "ms_per_step": ms, "pairs_per_step": P,
-            "pairs_per_s": P / (ms * 1e-3), "mean_dt": (t1 - t0) / steps}
+            "n": ps.n, "steps": steps, "rebuild_every_step": run(sph.SPH_REUSE_OFF),
+            "reuse_cells_and_orderings": run(sph.SPH_REUSE_ORDERINGS),
+            "reuse_cells_resort": run(sph.SPH_REUSE_CELLS)}
 
 
 def main():

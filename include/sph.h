@@ -86,10 +86,22 @@ typedef struct {
     double cfl;          /* C_CFL of the time-step criterion, Eq. (6); the paper uses 1/4 */
     int balsara_form;    /* numerator of the Balsara switch f_i of Sec. 4.1:
                             SPH_BALSARA_CURL as printed there, or SPH_BALSARA_DIV */
-    int reuse;           /* pseudo-Verlet reuse (Sec. 3.3): nonzero lets sph_step and
-                            sph_step_adaptive keep the cells and orderings of the last build
-                            (sph_refresh) while they stay valid, instead of rebuilding */
+    int reuse;           /* reuse of the decomposition across steps by sph_step and
+                            sph_step_adaptive (SPH_REUSE_*) */
 } sph_params;
+
+/* Decomposition reuse across steps (the pseudo-Verlet scheme of Sec. 3.3 and
+ * Sec. 4.1).  While the particle count and boxes are unchanged and the
+ * refresh finds the cells still valid, a step calls sph_refresh instead of
+ * sph_build_cells + sph_sort; otherwise it rebuilds. */
+enum {
+    SPH_REUSE_OFF = 0,        /* rebuild cells and orderings every step */
+    SPH_REUSE_ORDERINGS = 1,  /* keep cells and orderings (the paper's scheme): the sweeps widen
+                                 by the displacement since the orderings were made */
+    SPH_REUSE_CELLS = 2       /* keep the cells, make the orderings again (sph_sort) every step:
+                                 exact orderings, only the staging reach and the h limit
+                                 carry the displacement */
+};
 
 /* Numerator of the Balsara switch f = X / (|div v| + |curl v| + eps c/h). */
 enum {
@@ -101,7 +113,7 @@ enum {
 /* Default parameters: the paper's constants (48, 5/3, 0.8, 1e-4, C_CFL 1/4),
  * FP32_ACC64, cell_target 64, h_margin 0.1, max_iter 64, max_rebuilds 4, unit
  * box, max_depth 0 (single-level grid), split_count 64, split_frac 0.875,
- * balsara_form SPH_BALSARA_CURL, reuse 0. */
+ * balsara_form SPH_BALSARA_CURL, reuse SPH_REUSE_OFF. */
 void sph_default_params(sph_params *p);
 
 typedef struct {
@@ -179,16 +191,20 @@ sph_status sph_build_cells(sph_ctx *ctx, const sph_particles *p, const sph_batch
  * orderings kept over several steps until particle motion invalidates them):
  * refreshes the cell-ordered copies of x, v, u, m, h from p in the cell
  * membership and orderings of the last sph_build_cells + sph_sort, and
- * records per box twice the largest displacement since that build (the
- * drift).  The next sph_density and sph_force widen every early-exit bound
- * and every staging reach by the drift and require h_i + drift <= the
- * h limit of the particle's cell, which keeps every pair in range in a listed
- * cell pair and inside the swept prefix of every stored ordering; where that
- * no longer holds (an h root beyond it, or a drift above half a cell's h
- * limit), sph_density rebuilds the cells from p as it does when an h
- * outgrows them.  Requires a build and sort on the same particle count and
- * boxes.  Does not synchronise.  Errors: SPH_E_INVALID_ARG, SPH_E_STATE,
- * SPH_E_HIP (non-finite data is reported by the next sph_density). */
+ * records the largest displacement since that build per cell, d(cell), and
+ * per box, d(box).  The next sph_density, sph_force and sph_backward keep
+ * h_i + d(T) + d(box) within the h limit of i's cell T (every pair in range
+ * then lies in a listed cell pair), widen the staging reach of every cell
+ * pair (T, S) by d(T) + d(S) and the early exit of a sweep over S by 2 d(S)
+ * (the stored order of projections that moved by up to d(S)); an sph_sort
+ * after the refresh makes the orderings exact again, which leaves d(T) in
+ * the reach and nothing in the early exit.  The refresh requests a rebuild
+ * when some h_i (1 + h_margin/2) exceeds that limit; sph_density then
+ * rebuilds the cells from p before sweeping (as it also does when a solved
+ * h outgrows its cell).  Requires a build and sort on the same particle
+ * count and boxes.  Does not synchronise.  Errors: SPH_E_INVALID_ARG,
+ * SPH_E_STATE, SPH_E_HIP (non-finite data is reported by the next
+ * sph_density). */
 sph_status sph_refresh(sph_ctx *ctx, const sph_particles *p, void *stream);
 
 /* Initial smoothing lengths for particles without a usable guess: builds the
@@ -274,9 +290,11 @@ sph_status sph_backward(sph_ctx *ctx, const sph_particles *p, const sph_grad_in 
  *   predicted v + dt/2 a_old and u + dt/2 du_old,
  *   v += dt/2 a_new, u += dt/2 du_new, and `acc` overwritten with a_new, du_new.
  * acc->ax..dudt must hold the previous step's values (zeros for a cold start).
- * With params.reuse the cells and orderings of the last build are refreshed
- * (sph_refresh) instead of rebuilt when the particle count and boxes are
- * unchanged.  Errors: as sph_build_cells, sph_density. */
+ * With params.reuse the cells (and orderings) of the last build are
+ * refreshed (sph_refresh, then sph_sort for SPH_REUSE_CELLS) instead of
+ * rebuilt, while the particle count and boxes are unchanged and the refresh
+ * finds them valid; the step then reads the device status once more.
+ * Errors: as sph_build_cells, sph_density. */
 sph_status sph_step(sph_ctx *ctx, sph_particles *p, const sph_batch *batch, sph_force_out *acc,
                     double dt, void *stream);
 
@@ -332,7 +350,7 @@ typedef struct {
     int32_t unconverged;     /* particles left unconverged by the last sph_density */
     int32_t depth;           /* levels below the top grid in the keys of the last build */
     int32_t refreshes;       /* sph_refresh calls since the last build */
-    double drift;            /* box 0: twice the largest displacement since the last build
+    double drift;            /* box 0: the largest displacement since the last build
                                 (as of the last sph_refresh) */
 } sph_stats;
 

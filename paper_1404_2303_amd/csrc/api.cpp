@@ -51,6 +51,11 @@ struct sph_ctx {
     DBuf cells, ncells, cell_map, src, src_count, srec;
     DBuf rx, ry, rz, h, vm, u;                       // cell order
     DBuf r0;                                         // cell-relative positions at the last build
+    DBuf cell_drift;                                 // largest displacement per cell since that build
+    bool refreshed = false;                          // a refresh followed the last build
+    bool keys_stale = false;                         // ... and the orderings predate it
+    bool refresh_checked = false;                    // its rebuild request was already acted on
+    int step_rebuilds = 0;                           // rebuilds a step did before its sph_density
     DBuf g0, g1, cell_hmax;                          // ghost quantities, cell order
     DBuf sd0, sd1;                                   // density sums kept for the adjoint
     DBuf src_off;                                    // first source of each cell
@@ -142,6 +147,8 @@ static Decomp decomp(sph_ctx* c)
     d.n = c->n;
     d.qhead = c->qhead.as<int32_t>();
     d.status = c->status.as<uint32_t>();
+    d.cell_drift = c->refreshed ? c->cell_drift.as<float>() : nullptr;
+    d.keys_stale = c->keys_stale ? 1 : 0;
     return d;
 }
 
@@ -189,6 +196,7 @@ static bool ensure_particles(sph_ctx* c, int64_t n)
     }
     ok &= c->srec.ensure(N * kSortDirs * sizeof(SortRec));
     ok &= c->rx.ensure(N * R) && c->ry.ensure(N * R) && c->rz.ensure(N * R) && c->r0.ensure(N * 4 * R);
+    ok &= c->cell_drift.ensure(N * sizeof(float));
     ok &= c->h.ensure(N * 8) && c->u.ensure(N * 8);
     ok &= c->vm.ensure(N * 4 * R);
     ok &= c->g0.ensure(N * 4 * R) && c->g1.ensure(N * 4 * R);
@@ -255,6 +263,7 @@ static bool params_ok(const sph_params& p)
     if (p.max_depth < 0 || p.split_count < 1 || !(p.split_frac >= 0.0) || !(p.split_frac <= 1.0)) return false;
     if (!(p.cfl > 0.0) || !std::isfinite(p.cfl)) return false;
     if (p.balsara_form != SPH_BALSARA_CURL && p.balsara_form != SPH_BALSARA_DIV) return false;
+    if (p.reuse != SPH_REUSE_OFF && p.reuse != SPH_REUSE_ORDERINGS && p.reuse != SPH_REUSE_CELLS) return false;
     return true;
 }
 
@@ -284,7 +293,7 @@ sph_status sph_destroy(sph_ctx* c)
     if (!c) return SPH_OK;
     DBuf* all[] = {&c->boxes, &c->keys, &c->keys2, &c->vals, &c->vals2, &c->rs_scratch, &c->flag,
                    &c->cellx, &c->cell_of, &c->sc_scratch, &c->cells, &c->ncells, &c->cell_map,
-                   &c->src, &c->src_count, &c->srec, &c->r0, &c->rx, &c->ry, &c->rz, &c->h,
+                   &c->src, &c->src_count, &c->srec, &c->r0, &c->cell_drift, &c->rx, &c->ry, &c->rz, &c->h,
                    &c->vm, &c->u, &c->g0, &c->g1, &c->cell_hmax, &c->qhead, &c->status, &c->step_tmp, &c->dt_box, &c->dt_min, &c->t_box,
                    &c->sd0, &c->sd1, &c->adj_ab, &c->adj_sb0, &c->adj_sb1, &c->adj_x, &c->adj_h, &c->adj_fg,
                    &c->src_off, &c->t_chg, &c->t_node_of, &c->t_node_start, &c->t_node_flag, &c->t_node_hmax,
@@ -481,6 +490,7 @@ sph_status sph_build_cells(sph_ctx* c, const sph_particles* p, const sph_batch* 
     c->n = p->n;
     c->built = c->sorted = c->have_density = false;
     c->stats.refreshes = 0;
+    c->refreshed = c->keys_stale = c->refresh_checked = false;
     if (!ensure_particles(c, p->n)) return SPH_E_OOM;
     if (!c->boxes.ensure(sizeof(BoxInfo) * c->nbox)) return SPH_E_OOM;
     if (!c->cell_map.ensure(sizeof(int32_t) * std::max<int64_t>(c->map_total, 1))) return SPH_E_OOM;
@@ -523,14 +533,19 @@ sph_status sph_refresh(sph_ctx* c, const sph_particles* p, void* stream)
         Particles pv = view(p);
         if (c->prm.precision == SPH_FP64)
             launch_refresh<double>(pv, c->vals.as<uint32_t>(), c->cell_of.as<uint32_t>(), c->cells.as<CellInfo>(),
-                                   c->boxes.as<BoxInfo>(), c->nbox, c->n, cell_data<double>(c),
-                                   c->r0.as<double4>(), c->status.as<uint32_t>(), st);
+                                   c->ncells.as<int32_t>(), c->boxes.as<BoxInfo>(), c->nbox, c->n,
+                                   cell_data<double>(c), c->r0.as<double4>(), c->cell_drift.as<float>(),
+                                   c->prm.h_margin, c->status.as<uint32_t>(), st);
         else
             launch_refresh<float>(pv, c->vals.as<uint32_t>(), c->cell_of.as<uint32_t>(), c->cells.as<CellInfo>(),
-                                  c->boxes.as<BoxInfo>(), c->nbox, c->n, cell_data<float>(c), c->r0.as<float4>(),
-                                  c->status.as<uint32_t>(), st);
+                                  c->ncells.as<int32_t>(), c->boxes.as<BoxInfo>(), c->nbox, c->n,
+                                  cell_data<float>(c), c->r0.as<float4>(), c->cell_drift.as<float>(),
+                                  c->prm.h_margin, c->status.as<uint32_t>(), st);
     }
     if (hipGetLastError() != hipSuccess) return SPH_E_HIP;
+    c->refreshed = true;
+    c->keys_stale = true;
+    c->refresh_checked = false;
     c->stats.refreshes++;
     return SPH_OK;
 }
@@ -578,6 +593,7 @@ sph_status sph_sort(sph_ctx* c, void* stream)
     }
     if (hipGetLastError() != hipSuccess) return SPH_E_HIP;
     c->sorted = true;
+    c->keys_stale = false;
     return SPH_OK;
 }
 
@@ -618,16 +634,47 @@ static void density_launch(sph_ctx* c, const sph_particles* p, const sph_density
 }
 }  // extern "C++"
 
+// Cells and orderings rebuilt for p with the boxes of the last build.
+static sph_status rebuild_same_boxes(sph_ctx* c, sph_particles* p, void* stream)
+{
+    sph_batch b{}, *bp = nullptr;
+    std::vector<int64_t> off = c->batch_off;
+    std::vector<double> len = c->batch_len;
+    if (!off.empty()) {
+        b.nbox = (int)off.size() - 1;
+        b.box_offsets = off.data();
+        b.box_len = len.data();
+        bp = &b;
+    }
+    sph_status s = sph_build_cells(c, p, bp, stream);
+    if (s == SPH_OK) s = sph_sort(c, stream);
+    return s;
+}
+
 sph_status sph_density(sph_ctx* c, sph_particles* p, sph_density_out* o, void* stream)
 {
     if (!c || !particles_ok(p)) return SPH_E_INVALID_ARG;
     if (!c->built || !c->sorted) return SPH_E_STATE;
     if (p->n != c->n) return SPH_E_STATE;
     hipStream_t st = (hipStream_t)stream;
-    c->stats.rebuilds = 0;
+    c->stats.rebuilds = c->step_rebuilds;   // a rebuild the step did just before
+    c->step_rebuilds = 0;
     c->have_density = false;
     c->dens_ms_acc = 0.0f;
     c->dens_async_timed = false;
+    if (c->refreshed && !c->refresh_checked && c->n > 0) {
+        // a refresh that found its decomposition no longer valid asked for a
+        // rebuild: do it before sweeping rather than after
+        uint32_t bits = 0;
+        sph_status s = read_status(c, st, &bits);
+        if (s == SPH_OK) s = status_error(bits);
+        if (s != SPH_OK) return s;
+        if (bits & ST_REBUILD) {
+            s = rebuild_same_boxes(c, p, stream);
+            if (s != SPH_OK) return s;
+            c->stats.rebuilds++;
+        }
+    }
     for (int attempt = 0;; attempt++) {
         uint32_t bits = 0;
         if (c->n > 0) {
@@ -647,18 +694,7 @@ sph_status sph_density(sph_ctx* c, sph_particles* p, sph_density_out* o, void* s
         if (s != SPH_OK) return s;
         if ((bits & ST_REBUILD) && attempt < c->prm.max_rebuilds) {
             // some smoothing length outgrew its cells: rebuild from the current h
-            sph_batch b{}, *bp = nullptr;
-            if (!c->batch_off.empty()) {
-                b.nbox = (int)c->batch_off.size() - 1;
-                b.box_offsets = c->batch_off.data();
-                b.box_len = c->batch_len.data();
-                bp = &b;
-            }
-            std::vector<int64_t> off = c->batch_off;
-            std::vector<double> len = c->batch_len;
-            if (bp) { b.box_offsets = off.data(); b.box_len = len.data(); }
-            s = sph_build_cells(c, p, bp, stream);
-            if (s == SPH_OK) s = sph_sort(c, stream);
+            s = rebuild_same_boxes(c, p, stream);
             if (s != SPH_OK) return s;
             c->stats.rebuilds++;
             continue;
@@ -779,8 +815,27 @@ static sph_status step_core(sph_ctx* c, sph_particles* p, const sph_batch* batch
     launch_step_open(sa, dtb, c->boxes.as<BoxInfo>(), c->nbox, n, st);
     sph_particles q = *p;
     q.vx = sa.pvx; q.vy = sa.pvy; q.vz = sa.pvz; q.u = sa.pu;
-    sph_status s = reuse ? sph_refresh(c, &q, st) : sph_build_cells(c, &q, batch, st);
-    if (s == SPH_OK && !reuse) s = sph_sort(c, st);
+    sph_status s;
+    if (reuse) {
+        // pseudo-Verlet: refresh, and rebuild only if the refresh finds the
+        // decomposition no longer valid (one status read)
+        s = sph_refresh(c, &q, st);
+        uint32_t bits = 0;
+        if (s == SPH_OK) s = read_status(c, st, &bits);
+        if (s == SPH_OK) s = status_error(bits);
+        if (s == SPH_OK) {
+            if (bits & ST_REBUILD) {
+                s = rebuild_same_boxes(c, &q, st);
+                c->step_rebuilds = 1;
+            } else {
+                c->refresh_checked = true;
+                if (c->prm.reuse == SPH_REUSE_CELLS) s = sph_sort(c, st);   // exact keys, no widening
+            }
+        }
+    } else {
+        s = sph_build_cells(c, &q, batch, st);
+        if (s == SPH_OK) s = sph_sort(c, st);
+    }
     if (s == SPH_OK) s = sph_density(c, &q, nullptr, st);
     if (s != SPH_OK && s != SPH_E_NOT_CONVERGED) return s;
     sph_status sd = s;

@@ -395,27 +395,30 @@ __global__ void k_gather(Particles p, const uint32_t* perm, const uint32_t* cell
 
 // Pseudo-Verlet reuse (Sec. 3.3 keeps orderings over several steps): the
 // cell-ordered copies of the particle data are refreshed from the caller's
-// arrays in the cell membership of the last build, and each box records twice
-// the largest displacement since that build (BoxInfo::drift).  A particle
-// has left its cell by at most its displacement and its projection on any
-// axis has moved by at most as much, so pairs in range still lie in listed
-// cell pairs, and the stored orderings still bound the sweeps, once every
-// range and every early-exit bound is widened by the drift.
+// arrays in the cell membership of the last build, and the largest
+// displacement since that build is recorded per cell (cell_drift) and per
+// box (BoxInfo::drift).  A particle has left its cell by at most its
+// displacement and its projection on any axis has moved by at most as much,
+// so for targets in cell T and sources in cell S every pair in range still
+// lies in a listed cell pair, and inside the swept prefix of every stored
+// ordering, once the ranges and early-exit bounds are widened by
+// drift(T) + drift(S) and every h_i + drift(T) + drift(box) stays within the
+// h limit of i's cell.
 template <typename R>
 __global__ void k_refresh(Particles p, const uint32_t* perm, const uint32_t* cell_of, const CellInfo* cells,
-                          BoxInfo* boxes, int64_t n, CellData<R> cd, const typename Vec4T<R>::T* r0,
-                          uint32_t* status)
+                          const BoxInfo* boxes, int64_t n, CellData<R> cd, const typename Vec4T<R>::T* r0,
+                          float* cell_drift, uint32_t* status)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k - (int64_t)(threadIdx.x & 63) >= n) return;   // the whole wavefront is past the end
     const bool valid = k < n;
-    int b = -1;
+    int c = -1;
     double dd = 0.0;
     if (valid) {
         const uint32_t i = perm[k];
-        const CellInfo& C = cells[cell_of[k]];
+        c = (int)cell_of[k];
+        const CellInfo& C = cells[c];
         const BoxInfo& B = boxes[C.box];
-        b = C.box;
         const double pos[3] = {p.x[i], p.y[i], p.z[i]};
         const double h = p.h[i];
         if (!isfinite(pos[0]) || !isfinite(pos[1]) || !isfinite(pos[2]) || !(h > 0.0) || !isfinite(h))
@@ -434,24 +437,76 @@ __global__ void k_refresh(Particles p, const uint32_t* perm, const uint32_t* cel
         const typename Vec4T<R>::T q = r0[k];
         const double dx = (double)rel[0] - (double)q.x, dy = (double)rel[1] - (double)q.y,
                      dz = (double)rel[2] - (double)q.z;
-        dd = 2.0 * sqrt(dx * dx + dy * dy + dz * dz);
+        // rounded up, so that the float allowance is never below the displacement
+        dd = sqrt(dx * dx + dy * dy + dz * dz) * (1.0 + 1e-6);
         if (!(dd == dd)) dd = (double)INFINITY;
     }
-    const int b0 = __builtin_amdgcn_readfirstlane(b);   // lane 0 is valid here
-    if (__all(!valid || b == b0)) {
-        double m = dd;
-        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-        if ((threadIdx.x & 63) == 0)
-            atomicMax((unsigned long long*)&boxes[b0].drift, (unsigned long long)__double_as_longlong(m));
-    } else if (valid) {
-        atomicMax((unsigned long long*)&boxes[b].drift, (unsigned long long)__double_as_longlong(dd));
+    const int lane = threadIdx.x & 63;
+    // per cell: the lanes of one cell are consecutive (cell order), so a
+    // segmented maximum over the wavefront leaves each cell's maximum in its
+    // last lane, which issues the one atomic of that cell
+    float m = (float)dd;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const float mo = __shfl_up(m, o, 64);
+        const int co = __shfl_up(c, o, 64);
+        if (lane >= o && co == c) m = fmaxf(m, mo);
+    }
+    const int cn = __shfl_down(c, 1, 64);
+    if (valid && (lane == 63 || cn != c)) atomicMax((unsigned int*)&cell_drift[c], __float_as_uint(m));
+}
+
+// Largest cell drift of each box (cells are ordered by box): a small grid
+// strides over the cells, each lane keeps the maximum of its current box and
+// hands it on with one atomic when its box changes and at the end.
+__global__ void k_box_drift(const CellInfo* cells, const int32_t* ncells, const float* cell_drift, BoxInfo* boxes)
+{
+    const int nc = *ncells;
+    int cb = -1;
+    float cm = 0.0f;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
+        const int b = cells[c].box;
+        if (b != cb) {
+            if (cb >= 0) atomicMax((unsigned long long*)&boxes[cb].drift,
+                                   (unsigned long long)__double_as_longlong((double)cm));
+            cb = b;
+            cm = 0.0f;
+        }
+        cm = fmaxf(cm, cell_drift[c]);
+    }
+    const int b0 = __builtin_amdgcn_readfirstlane(cb);
+    if (__all(cb == b0)) {
+        for (int o = 32; o > 0; o >>= 1) cm = fmaxf(cm, __shfl_xor(cm, o, 64));
+        if ((threadIdx.x & 63) == 0 && b0 >= 0)
+            atomicMax((unsigned long long*)&boxes[b0].drift, (unsigned long long)__double_as_longlong((double)cm));
+    } else if (cb >= 0) {
+        atomicMax((unsigned long long*)&boxes[cb].drift, (unsigned long long)__double_as_longlong((double)cm));
     }
 }
 
-__global__ void k_zero_drift(BoxInfo* boxes, int nbox)
+// After a refresh: the decomposition still serves the particles whose h,
+// with room for a growth of half the build slack, stays within the h limit
+// of their cell less the allowances; otherwise a rebuild is requested.
+template <typename R>
+__global__ void k_refresh_check(const uint32_t* cell_of, const CellInfo* cells, const BoxInfo* boxes, int64_t n,
+                                CellData<R> cd, const float* cell_drift, double h_margin, uint32_t* status)
 {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < nbox) boxes[b].drift = 0.0;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false;
+    if (k < n) {
+        const int c = (int)cell_of[k];
+        const CellInfo& C = cells[c];
+        const double lim = (double)C.hlim - (double)cell_drift[c] - boxes[C.box].drift;
+        bad = !(cd.h[k] * (1.0 + 0.5 * h_margin) <= lim);
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(status, ST_REBUILD);
+}
+
+__global__ void k_zero_drift(BoxInfo* boxes, int nbox, float* cell_drift, const int32_t* ncells)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nbox) boxes[i].drift = 0.0;
+    if (i < *ncells) cell_drift[i] = 0.0f;
 }
 
 // ---------------------------------------------------------------- sources
@@ -492,6 +547,7 @@ __global__ void k_sources(const CellInfo* cells, const int32_t* ncells, const Bo
 // the ordering is a permutation and stable.
 constexpr int SORT_THREADS = 64;
 constexpr int SORT_MAX = 4096;
+constexpr int kWaveSortMax = 4 * kWave;   // cells up to this size are sorted by one wavefront
 
 // order-preserving integer image of a float (a total order, NaN included)
 __device__ inline uint32_t float_key(float f)
@@ -501,9 +557,79 @@ __device__ inline uint32_t float_key(float f)
 }
 __device__ inline float key_float(uint32_t k) { return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k); }
 
-// Cells of at most one wavefront of particles: one wavefront per cell, the
-// particle of lane t loaded once, and for each of the 13 directions a bitonic
-// sort across the lanes of (key, t), so ties keep the cell order.
+// Bitonic sort across one wavefront of 64 E keys, key i held by lane i % 64
+// in slot i / 64: exchanges at distances below 64 go through lane shuffles,
+// longer ones between the slots of a lane.  Ascending on return.
+template <int E>
+__device__ __forceinline__ void wave_bitonic(uint64_t (&v)[E], const int lane)
+{
+#pragma unroll
+    for (int kk = 2; kk <= kWave * E; kk <<= 1) {
+#pragma unroll
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            if (j >= kWave) {
+                const int js = j / kWave;
+#pragma unroll
+                for (int e = 0; e < E; e++) {
+                    const int f = e ^ js;
+                    if (f > e) {
+                        const bool up = (((e * kWave + lane) & kk) == 0);
+                        const uint64_t a = v[e], b = v[f];
+                        const bool sw = up ? (a > b) : (a < b);
+                        v[e] = sw ? b : a;
+                        v[f] = sw ? a : b;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < E; e++) {
+                    const uint64_t o = __shfl_xor(v[e], j, kWave);
+                    const bool keep_min = ((lane & j) == 0) == (((e * kWave + lane) & kk) == 0);
+                    v[e] = keep_min ? (o < v[e] ? o : v[e]) : (o > v[e] ? o : v[e]);
+                }
+            }
+        }
+    }
+}
+
+// The 13 orderings of one cell of at most 64 E particles by one wavefront:
+// every particle's position is loaded once, and for each direction the keys
+// (projection, cell index) are sorted with a bitonic network (ties keep the
+// cell order).
+template <typename R, int E>
+__device__ __forceinline__ void sort13_cell(const CellInfo& C, const CellData<R>& cd, int64_t n,
+                                            const Sorted<R>& so, const int lane)
+{
+    R x[E], y[E], z[E];
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+        const int t = e * kWave + lane;
+        const int64_t k = C.start + (t < C.count ? t : 0);
+        x[e] = cd.rx[k]; y[e] = cd.ry[k]; z[e] = cd.rz[k];
+    }
+    for (int s = 0; s < kSortDirs; s++) {
+        float su[3];
+        dir_unit(s + 13, su);
+        uint64_t v[E];
+#pragma unroll
+        for (int e = 0; e < E; e++) {
+            const int t = e * kWave + lane;
+            const float f = su[0] * (float)x[e] + su[1] * (float)y[e] + su[2] * (float)z[e];
+            v[e] = t < C.count ? (((uint64_t)float_key(f) << 32) | (uint32_t)t) : ~0ull;
+        }
+        wave_bitonic<E>(v, lane);
+        // slot e of this lane now holds the element of rank e * 64 + lane
+#pragma unroll
+        for (int e = 0; e < E; e++) {
+            const int r = e * kWave + lane;
+            if (r < C.count)
+                so.rec[(int64_t)s * n + C.start + r] = SortRec{key_float((uint32_t)(v[e] >> 32)),
+                                                               (uint32_t)(v[e] & 0xffffffffu)};
+        }
+    }
+}
+
+// Cells of at most kWaveSortMax particles: one wavefront per cell.
 template <typename R>
 __global__ __launch_bounds__(kWave) void k_sort13_wave(const CellInfo* cells, const int32_t* ncells, CellData<R> cd,
                                                        int64_t n, Sorted<R> so)
@@ -512,30 +638,9 @@ __global__ __launch_bounds__(kWave) void k_sort13_wave(const CellInfo* cells, co
     const int nc = *ncells;
     for (int c = blockIdx.x; c < nc; c += gridDim.x) {
         const CellInfo C = cells[c];
-        if (C.count > kWave) continue;
-        const bool in = lane < C.count;
-        const int64_t k = C.start + (in ? lane : 0);
-        const R x = cd.rx[k], y = cd.ry[k], z = cd.rz[k];
-        for (int s = 0; s < kSortDirs; s++) {
-            float su[3];
-            dir_unit(s + 13, su);
-            const float f = su[0] * (float)x + su[1] * (float)y + su[2] * (float)z;
-            uint64_t v = in ? (((uint64_t)float_key(f) << 32) | (uint32_t)lane) : ~0ull;
-#pragma unroll
-            for (int kk = 2; kk <= kWave; kk <<= 1) {
-#pragma unroll
-                for (int j = kk >> 1; j > 0; j >>= 1) {
-                    const uint64_t o = __shfl_xor(v, j, kWave);
-                    const bool keep_min = ((lane & j) == 0) == ((lane & kk) == 0);
-                    v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
-                }
-            }
-            // lane r now holds the element of rank r
-            if (in) {
-                const int64_t o = (int64_t)s * n + C.start + lane;
-                so.rec[o] = SortRec{key_float((uint32_t)(v >> 32)), (uint32_t)(v & 0xffffffffu)};
-            }
-        }
+        if (C.count <= kWave) sort13_cell<R, 1>(C, cd, n, so, lane);
+        else if (C.count <= 2 * kWave) sort13_cell<R, 2>(C, cd, n, so, lane);
+        else if (C.count <= kWaveSortMax) sort13_cell<R, 4>(C, cd, n, so, lane);
     }
 }
 
@@ -552,7 +657,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort13(const CellInfo* cells, 
         const int c = (int)(unit / kSortDirs);
         const int s = (int)(unit % kSortDirs);
         const CellInfo C = cells[c];
-        if (C.count <= kWave) continue;  // sorted by k_sort13_wave
+        if (C.count <= kWaveSortMax) continue;  // sorted by k_sort13_wave
         if (C.count > SORT_MAX) { if (threadIdx.x == 0) atomicOr(status, ST_CAPACITY); continue; }
         float su[3];
         dir_unit(s + 13, su);
@@ -689,18 +794,28 @@ template void launch_gather<double>(const Particles&, const uint32_t*, const uin
 
 template <typename R>
 void launch_refresh(const Particles& p, const uint32_t* perm, const uint32_t* cell_of, const CellInfo* cells,
-                    BoxInfo* boxes, int nbox, int64_t n, const CellData<R>& cd, const typename Vec4T<R>::T* r0,
-                    uint32_t* status, hipStream_t st)
+                    const int32_t* ncells, BoxInfo* boxes, int nbox, int64_t n, const CellData<R>& cd,
+                    const typename Vec4T<R>::T* r0, float* cell_drift, double h_margin, uint32_t* status,
+                    hipStream_t st)
 {
-    hipLaunchKernelGGL(k_zero_drift, dim3((unsigned)((nbox + 255) / 256)), dim3(256), 0, st, boxes, nbox);
-    if (n > 0)
+    // cells number at most n (and at least one per box)
+    const int64_t zn = n > nbox ? n : nbox;
+    hipLaunchKernelGGL(k_zero_drift, dim3((unsigned)((zn + 255) / 256)), dim3(256), 0, st, boxes, nbox, cell_drift,
+                       ncells);
+    if (n > 0) {
         hipLaunchKernelGGL(k_refresh<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, perm, cell_of,
-                           cells, boxes, n, cd, r0, status);
+                           cells, (const BoxInfo*)boxes, n, cd, r0, cell_drift, status);
+        hipLaunchKernelGGL(k_box_drift, dim3(64), dim3(256), 0, st, cells, ncells, (const float*)cell_drift, boxes);
+        hipLaunchKernelGGL(k_refresh_check<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, cell_of, cells,
+                           (const BoxInfo*)boxes, n, cd, (const float*)cell_drift, h_margin, status);
+    }
 }
-template void launch_refresh<float>(const Particles&, const uint32_t*, const uint32_t*, const CellInfo*, BoxInfo*,
-                                    int, int64_t, const CellData<float>&, const float4*, uint32_t*, hipStream_t);
-template void launch_refresh<double>(const Particles&, const uint32_t*, const uint32_t*, const CellInfo*, BoxInfo*,
-                                     int, int64_t, const CellData<double>&, const double4*, uint32_t*, hipStream_t);
+template void launch_refresh<float>(const Particles&, const uint32_t*, const uint32_t*, const CellInfo*,
+                                    const int32_t*, BoxInfo*, int, int64_t, const CellData<float>&, const float4*,
+                                    float*, double, uint32_t*, hipStream_t);
+template void launch_refresh<double>(const Particles&, const uint32_t*, const uint32_t*, const CellInfo*,
+                                     const int32_t*, BoxInfo*, int, int64_t, const CellData<double>&,
+                                     const double4*, float*, double, uint32_t*, hipStream_t);
 
 void launch_sources(const CellInfo* cells, const int32_t* ncells, const BoxInfo* boxes,
                     const int32_t* cell_map, Source* src, int32_t* src_off, int32_t* src_count,

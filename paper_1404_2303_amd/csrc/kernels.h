@@ -90,7 +90,17 @@ struct Decomp {
     int64_t n;
     int32_t* qhead;         // work counter of the persistent launches
     uint32_t* status;
+    const float* cell_drift;  // largest displacement in each cell since the build (null: none)
+    int keys_stale;           // the orderings predate that displacement (made before it)
 };
+
+// displacement of cell c's particles since the cells were built
+__device__ __forceinline__ float cell_dr(const Decomp& dc, int c) { return dc.cell_drift ? dc.cell_drift[c] : 0.0f; }
+// how far the stored projections of cell c may be from the current ones
+__device__ __forceinline__ float key_dr(const Decomp& dc, int c)
+{
+    return (dc.cell_drift && dc.keys_stale) ? dc.cell_drift[c] : 0.0f;
+}
 
 // build.hip
 void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t st);
@@ -116,8 +126,9 @@ void launch_gather(const Particles& p, const uint32_t* perm, const uint32_t* cel
                    typename Vec4T<R>::T* r0, hipStream_t st);
 template <typename R>
 void launch_refresh(const Particles& p, const uint32_t* perm, const uint32_t* cell_of, const CellInfo* cells,
-                    BoxInfo* boxes, int nbox, int64_t n, const CellData<R>& cd, const typename Vec4T<R>::T* r0,
-                    uint32_t* status, hipStream_t st);
+                    const int32_t* ncells, BoxInfo* boxes, int nbox, int64_t n, const CellData<R>& cd,
+                    const typename Vec4T<R>::T* r0, float* cell_drift, double h_margin, uint32_t* status,
+                    hipStream_t st);
 void launch_sources(const CellInfo* cells, const int32_t* ncells, const BoxInfo* boxes,
                     const int32_t* cell_map, Source* src, int32_t* src_off, int32_t* src_count,
                     int64_t cell_cap, hipStream_t st);

@@ -108,20 +108,25 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
         if (unit >= ncells) break;
         CellInfo T = dc.cells[unit];
         const BoxInfo B = dc.boxes[T.box];
-        // the interaction lists cover h up to this (less the drift of particles
-        // since the cells were built); a decomposition that has drifted by more
-        // than half of it is rebuilt rather than swept: the unit is then swept
-        // as an empty cell (no early exit from this loop, whose barriers every
-        // lane must reach together)
-        const double h_lim = (double)T.hlim - B.drift;
-        const bool stale = __builtin_amdgcn_readfirstlane(B.drift <= 0.5 * (double)T.hlim ? 0 : 1) != 0;
+        // the interaction lists cover h up to this, less the displacement
+        // allowances of this cell and of the box since the cells were built; a
+        // decomposition that has drifted by more than half of it is rebuilt
+        // rather than swept: the unit is then swept as an empty cell (no early
+        // exit from this loop, whose barriers every lane must reach together)
+        const float dT = cell_dr(dc, unit);
+        const double h_lim = (double)T.hlim - (double)dT - B.drift;
+        const bool stale =
+            __builtin_amdgcn_readfirstlane((double)dT + B.drift <= 0.5 * (double)T.hlim ? 0 : 1) != 0;
         if (stale) {
             if (tid == 0) atomicOr(dc.status, ST_REBUILD);
             T.count = 0;
         }
         const int nsrc = stale ? 0 : dc.src_count[unit];
         const double h_box = fmin(B.L[0], fmin(B.L[1], B.L[2])) / 3.0;
-        const float margin = 1e-5f * (float)fmax(B.e[0], fmax(B.e[1], B.e[2])) + (float)B.drift;
+        // rounding margin of the sweeps; staging also covers targets that left
+        // the cell by up to dT
+        const float margin = 1e-5f * (float)fmax(B.e[0], fmax(B.e[1], B.e[2]));
+        const float mstage = margin + dT;
         double hc = 0.0;
         for (int t = lane; t < T.count; t += kWave) hc = fmax(hc, cd.h[T.start + t]);
         hc = wave_max(hc);
@@ -130,7 +135,7 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
 
         // staging of the first batch, kept while it holds every source of the wavefront
         int k = 0, p = 0;
-        stage_wave<R, false, NACC_D>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, margin);
+        stage_wave<R, false, NACC_D>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, mstage);
         bool single = k >= nsrc;
 
         for (int c0 = 0; c0 < T.count; c0 += kWave) {
@@ -195,7 +200,7 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
                 bool flushed = false;
                 int kk = 0, pp = 0;
                 do {
-                    if (!single) stage_wave<R, false, NACC_D>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, kk, pp, Hst, margin);
+                    if (!single) stage_wave<R, false, NACC_D>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, kk, pp, Hst, mstage);
                     else kk = nsrc;
                     const int selfj = self_index(s, w, ti);
                     int seg = 0, jj = s.nseg[w] > 0 ? s.seg_b[w][0] : 0;
@@ -314,7 +319,7 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
                     const double hm = wave_max(conv ? 0.0 : h);
                     Hst = (float)fmin(fmax((double)Hst, hm * (1.0 + pc.h_margin)), h_lim);
                     k = 0; p = 0;
-                    stage_wave<R, false, NACC_D>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, margin);
+                    stage_wave<R, false, NACC_D>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, mstage);
                     single = k >= nsrc;
                     cached = false;
                 }
@@ -448,10 +453,11 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
         const CellInfo T = dc.cells[unit];
         const BoxInfo B = dc.boxes[T.box];
         const int nsrc = dc.src_count[unit];
-        const float margin = 1e-5f * (float)fmax(B.e[0], fmax(B.e[1], B.e[2])) + (float)B.drift;
+        const float margin = 1e-5f * (float)fmax(B.e[0], fmax(B.e[1], B.e[2]));
+        const float mstage = margin + cell_dr(dc, unit);   // targets may have left the cell by this
         const float Hst = gd.cell_hmax[unit];
         int k = 0, p = 0;
-        stage_wave<R, true, NACC_F>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, margin);
+        stage_wave<R, true, NACC_F>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, mstage);
         const bool single = k >= nsrc;
         for (int c0 = 0; c0 < T.count; c0 += kWave) {
             const int ti_ = c0 + lane;
@@ -484,7 +490,7 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
             };
             int kk = 0, pp = 0;
             do {
-                if (!single) stage_wave<R, true, NACC_F>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, kk, pp, Hst, margin);
+                if (!single) stage_wave<R, true, NACC_F>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, kk, pp, Hst, mstage);
                 else kk = nsrc;
                 const int selfj = self_index(s, w, ti_);
                 int seg = 0, jj = s.nseg[w] > 0 ? s.seg_b[w][0] : 0;

@@ -44,8 +44,8 @@ struct BoxInfo {
     int32_t depth;        // levels below the top grid encoded in the keys (0: single level)
     double e[3];          // cell edges (device-written)
     double hmax;          // largest h in the box (device-written)
-    double drift;         // twice the largest displacement since the cells were built (device-written;
-                          // 0 after a build): the slack that the sweeps and the lists must allow
+    double drift;         // largest displacement of a particle since the cells were built
+                          // (device-written by a refresh; 0 after a build)
 };
 
 // ---------------------------------------------------------------- cells

@@ -74,21 +74,31 @@ __device__ __forceinline__ double wave_min(double v)
 }
 
 // Per-box minimum of the particle time steps (values >= 0, so the order of
-// their bit patterns is their order).  A wavefront whose particles all lie in
-// one box reduces first and issues one atomic.
+// their bit patterns is their order).  A small grid strides over the
+// particles (ordered by box); each lane keeps the minimum of its current box
+// and hands it on with one atomic when its box changes and at the end.
 __global__ void k_box_min(const double* dt, const BoxInfo* boxes, int nbox, int64_t n, unsigned long long* mn)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i - (int64_t)(threadIdx.x & 63) >= n) return;   // the whole wavefront is past the end
-    const bool valid = i < n;
-    const int b = valid ? box_of(boxes, nbox, i) : -1;
-    const double v = valid ? dt[i] : (double)INFINITY;
-    const int b0 = __builtin_amdgcn_readfirstlane(b);   // lane 0 is valid here
-    if (__all(!valid || b == b0)) {
-        const double m = wave_min(v);
-        if ((threadIdx.x & 63) == 0) atomicMin(&mn[b0], (unsigned long long)__double_as_longlong(m));
-    } else if (valid) {
-        atomicMin(&mn[b], (unsigned long long)__double_as_longlong(v));
+    int cb = -1;
+    double cm = (double)INFINITY;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int b = i < n ? box_of(boxes, nbox, i) : -1;
+    for (; i < n; i += stride) {
+        while (b + 1 < nbox && boxes[b + 1].begin <= i) b++;
+        if (b != cb) {
+            if (cb >= 0) atomicMin(&mn[cb], (unsigned long long)__double_as_longlong(cm));
+            cb = b;
+            cm = (double)INFINITY;
+        }
+        cm = fmin(cm, dt[i]);
+    }
+    const int b0 = __builtin_amdgcn_readfirstlane(cb);
+    if (__all(cb == b0)) {
+        const double m = wave_min(cm);
+        if ((threadIdx.x & 63) == 0 && b0 >= 0) atomicMin(&mn[b0], (unsigned long long)__double_as_longlong(m));
+    } else if (cb >= 0) {
+        atomicMin(&mn[cb], (unsigned long long)__double_as_longlong(cm));
     }
 }
 
@@ -138,7 +148,10 @@ void launch_dt_select(const double* dt, const BoxInfo* boxes, int nbox, int64_t 
                       double dt_max, double t_end, double* t_box, double* dtb, double* dt_out, hipStream_t st)
 {
     hipLaunchKernelGGL(k_fill_u64, dim3(blocks(nbox)), dim3(256), 0, st, mn, 0x7FF0000000000000ull, nbox);
-    if (n > 0) hipLaunchKernelGGL(k_box_min, dim3(blocks(n)), dim3(256), 0, st, dt, boxes, nbox, n, mn);
+    if (n > 0) {
+        const unsigned g = blocks(n) < 256 ? blocks(n) : 256;
+        hipLaunchKernelGGL(k_box_min, dim3(g), dim3(256), 0, st, dt, boxes, nbox, n, mn);
+    }
     hipLaunchKernelGGL(k_dt_select, dim3(blocks(nbox)), dim3(256), 0, st, mn, nbox, dt_max, t_end, t_box, dtb,
                        dt_out);
 }

@@ -94,6 +94,7 @@ struct Smem {
     int seg_b[NW][kMaxSegW], seg_e[NW][kMaxSegW];
     float seg_u[NW][kMaxSegW][3];
     float seg_hx[NW][kMaxSegW];       // force: largest h of the source cell
+    float seg_dr[NW][kMaxSegW];       // staleness of the source cell's stored projections
     int nseg[NW];
     int self_b[NW], self_t0[NW], self_n[NW];  // self segment: staged start, first cell index, count
     int unit;
@@ -143,7 +144,7 @@ __device__ void stage_wave(Smem<R, NACC, FORCE>& s, const int w, const Decomp& d
         const int segb = fill;
         bool complete = true;
         float u[3] = {0.f, 0.f, 0.f};
-        float hx = 0.f;
+        float hx = 0.f, ds = 0.f;
         if (self) {
             const int q0 = (S.count * w) / NW, q1 = (S.count * (w + 1)) / NW;
             const int n = q1 - q0 - p;
@@ -170,8 +171,9 @@ __device__ void stage_wave(Smem<R, NACC, FORCE>& s, const int w, const Decomp& d
             const float udo = u[0] * (float)dxo + u[1] * (float)dyo + u[2] * (float)dzo;
             float hs = Hst;
             if (FORCE) { hx = gd.cell_hmax[scell]; hs = fmaxf(Hst, hx); }
+            ds = key_dr(dc, scell);
             const float reach = fmaxf(u[0], 0.f) * et[0] + fmaxf(u[1], 0.f) * et[1] + fmaxf(u[2], 0.f) * et[2] +
-                                hs + margin;
+                                hs + margin + ds;
             const int64_t sbase = (int64_t)sd * dc.n + S.start;
             while (p < S.count) {
                 const int pos = p + lane;
@@ -208,6 +210,7 @@ __device__ void stage_wave(Smem<R, NACC, FORCE>& s, const int w, const Decomp& d
             s.seg_e[w][nseg] = fill;
             s.seg_u[w][nseg][0] = u[0]; s.seg_u[w][nseg][1] = u[1]; s.seg_u[w][nseg][2] = u[2];
             s.seg_hx[w][nseg] = hx;
+            s.seg_dr[w][nseg] = ds;
         }
         nseg++;
         if (!complete) break;
@@ -281,7 +284,10 @@ __device__ __forceinline__ int walk(Smem<R, NACC, FORCE>& s, int w, int lane, bo
                 jj += STEP;
             }
         } else {
-            const float bound = !act ? -INFINITY : ux * fxi + uy * fyi + uz * fzi + fmaxf(fh, hx) + margin;
+            // stored order of projections that moved by up to d since: an entry
+            // beyond bound + 2d leaves every later one beyond bound
+            const float bound =
+                !act ? -INFINITY : ux * fxi + uy * fyi + uz * fzi + fmaxf(fh, hx) + margin + 2.0f * s.seg_dr[w][seg];
             while (jj < je) {
                 if (wave_any(cnt > LISTW - STEP)) { full = true; break; }
                 bool in_last = false;

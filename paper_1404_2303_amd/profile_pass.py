@@ -2,9 +2,12 @@
 profilers (rocprofv3 --kernel-trace / --pmc) to record.
 
     python -m paper_1404_2303_amd.profile_pass --workload lattice --passes 2 --copy-mib 512
+    python -m paper_1404_2303_amd.profile_pass --workload sod --steps 20 --reuse 1
 
 --copy-mib adds device-to-device copies of that size after the passes, a
-kernel of known traffic that calibrates the memory counters.
+kernel of known traffic that calibrates the memory counters.  The sod
+workload (the shock tube at 1,013,060 particles) runs --steps adaptive
+kick-drift-kick steps instead, with the decomposition reuse mode --reuse.
 """
 from __future__ import annotations
 
@@ -13,13 +16,32 @@ import argparse
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=("lattice", "mixture", "lattice64"), default="lattice")
+    ap.add_argument("--workload", choices=("lattice", "mixture", "lattice64", "sod"), default="lattice")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--reuse", type=int, default=0)
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
     ap.add_argument("--passes", type=int, default=2)
     ap.add_argument("--copy-mib", type=int, default=0)
     args = ap.parse_args()
+    import time
+
     import torch
     from . import sph, workloads
+    if args.workload == "sod":
+        ps = workloads.sod(37)
+        parts = sph.Particles.from_numpy(ps, "cuda:0")
+        ctx = sph.Context(ps.box, precision=args.precision, balsara_form=sph.SPH_BALSARA_DIV, reuse=args.reuse)
+        d, acc = ctx.run(parts)
+        t_box = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.step_adaptive(parts, acc, t_box, 1e30, 1.0)
+        torch.cuda.synchronize()
+        print(f"{args.steps} steps, {1e3 * (time.perf_counter() - t0) / args.steps:.3f} ms per step", flush=True)
+        ctx.close()
+        print("passes done", flush=True)
+        return
     if args.workload == "lattice":
         ps, params = workloads.config1(), {}
     elif args.workload == "lattice64":

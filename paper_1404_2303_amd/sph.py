@@ -24,6 +24,7 @@ SPH_OK, SPH_E_INVALID_ARG, SPH_E_NONFINITE, SPH_E_H_TOO_LARGE, SPH_E_NOT_CONVERG
 SPH_E_CAPACITY, SPH_E_OOM, SPH_E_HIP, SPH_E_STATE = 5, 6, 7, 8
 SPH_FP64, SPH_FP32_ACC64 = 0, 1
 SPH_BALSARA_CURL, SPH_BALSARA_DIV = 0, 1
+SPH_REUSE_OFF, SPH_REUSE_ORDERINGS, SPH_REUSE_CELLS = 0, 1, 2
 
 EXPORTED = ["sph_default_params", "sph_create", "sph_destroy", "sph_build_cells", "sph_sort",
             "sph_density", "sph_force", "sph_step", "sph_get_stats", "sph_status_string",

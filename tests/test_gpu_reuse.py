@@ -103,6 +103,34 @@ def test_refresh_across_the_periodic_face(precision):
     compare(g, ref, precision, label="refresh-periodic")
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("resort", [False, True])
+def test_refresh_moving_next_to_resting(precision, resort):
+    # the half x > 0.5 is scrambled by random displacements (its stored orderings
+    # go stale), the other half is at rest: sweeps of resting targets over moving
+    # sources need the full allowance of the sources' stale orderings
+    ps = _state(6000, 95)
+    rng = np.random.default_rng(5)
+    shift = rng.normal(0.0, 0.006, ps.pos.shape) * (ps.pos[:, :1] > 0.5)
+    q = _moved(ps, shift)
+    log(f"case refresh moving|resting {ps.n} {precision} resort={resort}")
+    parts = sph.Particles.from_numpy(ps, "cuda:0")
+    ctx = sph.Context(ps.box, precision=precision)
+    ctx.run(parts)
+    _to_dev(parts, q)
+    ctx.refresh(parts)
+    if resort:
+        ctx.sort()
+    d = ctx.density(parts)
+    f = ctx.force(parts)
+    g = _collect(ctx, parts, d, f)
+    ctx.close()
+    log(f"  stats {g['stats']}")
+    assert g["stats"]["refreshes"] == 1 and g["stats"]["rebuilds"] == 0
+    ref = oracle.full_pass(q.pos, q.vel, q.m, q.u, ps.h0, q.box)
+    compare(g, ref, precision, label="refresh-half")
+
+
 def test_refresh_on_the_hierarchy():
     rng = np.random.default_rng(7)
     clump = 0.5 + 0.04 * rng.normal(size=(3000, 3))
@@ -150,11 +178,12 @@ def _steps(ps, precision, dt, nsteps, reuse, batch=None):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_steps_with_reuse_match_oracle(precision):
+@pytest.mark.parametrize("mode", [sph.SPH_REUSE_ORDERINGS, sph.SPH_REUSE_CELLS])
+def test_steps_with_reuse_match_oracle(precision, mode):
     ps = _state(2000, 94, sigma_v=0.4)
     dt, nsteps = 0.002, 4
-    log(f"case kdk with reuse {ps.n} {precision}")
-    g, reused = _steps(ps, precision, dt, nsteps, True)
+    log(f"case kdk with reuse mode {mode} {ps.n} {precision}")
+    g, reused = _steps(ps, precision, dt, nsteps, mode)
     f = oracle.full_pass(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box)
     pos, vel, u, h, a, du = ps.pos, ps.vel, ps.u, f["h"], f["force"]["a"], f["force"]["dudt"]
     kap = f["force"]["kappa_a"]
@@ -182,8 +211,8 @@ def test_batched_steps_with_reuse_match_plain_steps():
                                 h0=np.concatenate([s_.h0 for s_ in sets]), box=np.ones(3))
     lens = np.asarray(boxes, dtype=np.float64)
     log(f"case batched kdk with reuse {cat.n} in 3 boxes")
-    a, reused = _steps(cat, "fp64", 0.003, 3, True, batch=(offsets, lens))
-    b, _ = _steps(cat, "fp64", 0.003, 3, False, batch=(offsets, lens))
+    a, reused = _steps(cat, "fp64", 0.003, 3, sph.SPH_REUSE_ORDERINGS, batch=(offsets, lens))
+    b, _ = _steps(cat, "fp64", 0.003, 3, sph.SPH_REUSE_OFF, batch=(offsets, lens))
     assert reused >= 2
     for k in range(3):
         for key in ("vel", "u", "h"):
