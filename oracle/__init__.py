@@ -21,6 +21,8 @@ function names the part of Gonnet (2014) it evaluates:
   time step (the integrator of Sec. 4.1).
 * :func:`integrate` -- kick-drift-kick steps to a final time, each step
   limited by the smallest time step of Eq. (6).
+* :func:`time_bin`, :func:`mts_integrate` -- multiple time-stepping: power-of-two
+  time bins, only the particles at the end of their own step active.
 """
 from __future__ import annotations
 
@@ -321,3 +323,85 @@ def integrate(pos, vel, m, u, h, box, t_end, dt_max, max_steps=100000, **kw):
     st["t"] = t
     st["steps"] = np.array(steps)
     return st
+
+
+def time_bin(dt, dt_base, max_bin, n_next):
+    """Time bin of each particle for multiple time-stepping (Sec. 4.1): the
+    largest k with 2^k dt_base <= dt (k >= 0; the bin whose step does not
+    exceed the particle's own step of Eq. (6)), at most max_bin, and lowered
+    until the particle's next step starts on a multiple of its length:
+    n_next % 2^k == 0, n_next the index of the next base step."""
+    dt = np.asarray(dt, dtype=np.float64)
+    with np.errstate(divide="ignore"):
+        r = np.log2(np.where(dt > 0, dt / dt_base, 1.0))
+    k = np.clip(np.floor(r), 0, max_bin).astype(np.int64)
+    k = np.where(np.isinf(dt), max_bin, k)
+    while True:
+        bad = (k > 0) & ((n_next % (1 << k)) != 0)
+        if not bad.any():
+            return k
+        k = np.where(bad, k - 1, k)
+
+
+def mts_integrate(pos, vel, m, u, h, box, dt_base, max_bin, nsteps, target=N_NGB, tol=1e-10, gamma=GAMMA,
+                  alpha=ALPHA, balsara_form=0, cfl=CFL):
+    """Multiple time-stepping (Sec. 4.1): particle i sits in time bin k_i
+    (time_bin) and takes kick-drift-kick steps of 2^k_i dt_base; it is active,
+    i.e. included in the density and force calculations as a target, only at
+    the ends of its own steps.  One base step n:
+
+      1. particles starting a step (n % 2^k == 0) take the opening half kick
+         v += T/2 a, u += T/2 du/dt with their own T = 2^k dt_base;
+      2. every particle drifts, x += dt_base v;
+      3. particles ending a step ((n+1) % 2^k == 0) are active: their h is
+         solved and their density-stage quantities (rho, A, c, f) recomputed at
+         the new positions; the other particles keep the values of their last
+         active step.  Velocities and energies enter at the end of the base
+         step, predicted from each particle's last kick with its stored
+         acceleration;
+      4. the active particles' forces (every particle a source), the closing
+         half kick with the new accelerations, their new time step of Eq. (6)
+         and their new bin.
+
+    The initial state is one full pass with every particle active.  Returns
+    the final state (pos, vel, u, h, a, dudt, dt, bins) and the number of
+    active particles of each base step.
+    """
+    box = np.asarray(box, dtype=np.float64)
+    kw = dict(target=target, tol=tol, gamma=gamma, alpha=alpha, balsara_form=balsara_form, cfl=cfl)
+    f0 = full_pass(pos, vel, m, u, h, box, **kw)
+    x = np.asarray(pos, dtype=np.float64).copy()
+    v = np.asarray(vel, dtype=np.float64).copy()
+    uu = np.broadcast_to(np.asarray(u, dtype=np.float64), (len(x),)).copy()
+    h = f0["h"].copy()
+    rho, A, c, f = f0["dens"]["rho"].copy(), f0["ghost"]["A"].copy(), f0["ghost"]["c"].copy(), f0["ghost"]["f"].copy()
+    a, du, dt = f0["force"]["a"].copy(), f0["force"]["dudt"].copy(), f0["signal"]["dt"].copy()
+    bins = time_bin(dt, dt_base, max_bin, 0)
+    counts = []
+    for n in range(nsteps):
+        span = np.left_shift(1, bins)
+        T = span * dt_base
+        start = (n % span) == 0
+        v += (start * 0.5 * T)[:, None] * a
+        uu += start * 0.5 * T * du
+        x = np.mod(x + dt_base * v, box)
+        x = np.where(x >= box, x - box, x)
+        tau = ((n % span) + 1) * dt_base - 0.5 * T
+        pv = v + tau[:, None] * a
+        pu = uu + tau * du
+        sel = np.where(((n + 1) % span) == 0)[0]
+        counts.append(len(sel))
+        if len(sel) == 0:
+            continue
+        h, _ = solve_h(x, h, box, target=target, tol=tol, sel=sel)
+        d = density(x, pv, m, h, box, sel=sel)
+        g = ghost(d, pu, h, gamma=gamma, balsara_form=balsara_form)
+        rho[sel], A[sel], c[sel], f[sel] = d["rho"][sel], g["A"][sel], g["c"][sel], g["f"][sel]
+        fr = force(x, pv, m, h, rho, A, c, f, box, alpha=alpha, sel=sel)
+        sig = signal_dt(x, pv, h, c, box, cfl=cfl, sel=sel)
+        a[sel], du[sel], dt[sel] = fr["a"][sel], fr["dudt"][sel], sig["dt"][sel]
+        v[sel] += (0.5 * T[sel])[:, None] * a[sel]
+        uu[sel] += 0.5 * T[sel] * du[sel]
+        bins[sel] = time_bin(dt[sel], dt_base, max_bin, n + 1)
+    return {"pos": x, "vel": v, "u": uu, "h": h, "a": a, "dudt": du, "dt": dt, "bins": bins,
+            "active": np.array(counts), "rho": rho, "A": A, "c": c, "f": f}

@@ -74,3 +74,63 @@ def test_energy_error_is_second_order():
         errs.append(abs(E(s["vel"], s["u"]) - E0))
     ratio = errs[0] / errs[1]
     assert errs[0] > 0 and 3.0 < ratio < 5.5, (errs, ratio)
+
+
+# ---------------------------------------------------------------- multiple time-stepping
+def test_time_bins():
+    dtb = 0.01
+    dt = np.array([0.005, 0.01, 0.0199, 0.02, 0.05, 1.0, np.inf])
+    np.testing.assert_array_equal(oracle.time_bin(dt, dtb, 4, 0), [0, 0, 0, 1, 2, 4, 4])
+    # a step must start on a multiple of its length: at base step 6, bin 2 (4 steps) is not allowed
+    np.testing.assert_array_equal(oracle.time_bin(np.array([0.05, 0.02]), dtb, 4, 6), [1, 1])
+    np.testing.assert_array_equal(oracle.time_bin(np.array([0.05]), dtb, 4, 8), [2])
+
+
+def test_mts_with_one_bin_is_the_fixed_step():
+    ps = workloads.uniform(700, seed=21, sigma_v=0.3)
+    ps.u[:] = np.random.default_rng(21).uniform(0.5, 1.5, ps.n)
+    dtb = 0.002
+    r = oracle.mts_integrate(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box, dtb, 0, 3)
+    assert list(r["active"]) == [ps.n] * 3
+    f = oracle.full_pass(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box)
+    pos, vel, u, h, a, du = ps.pos, ps.vel, ps.u, f["h"], f["force"]["a"], f["force"]["dudt"]
+    for _ in range(3):
+        s = oracle.kdk_step(pos, vel, ps.m, u, h, ps.box, a, du, dtb)
+        pos, vel, u, h, a, du = s["pos"], s["vel"], s["u"], s["h"], s["a"], s["dudt"]
+    np.testing.assert_allclose(r["vel"], vel, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(r["u"], u, rtol=1e-12)
+    np.testing.assert_allclose(r["h"], h, rtol=1e-12)
+
+
+def test_mts_with_every_particle_in_bin_one_is_the_double_step():
+    # every time step of Eq. (6) is far above 2 dt_base: with at most one bin all
+    # particles take steps of 2 dt_base, which is one kick-drift-kick step of that length
+    ps = workloads.uniform(700, seed=22, sigma_v=0.1)
+    dtb = 1e-4
+    r = oracle.mts_integrate(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box, dtb, 1, 2)
+    assert list(r["active"]) == [0, ps.n]
+    f = oracle.full_pass(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box)
+    s = oracle.kdk_step(ps.pos, ps.vel, ps.m, ps.u, f["h"], ps.box, f["force"]["a"], f["force"]["dudt"], 2 * dtb)
+    d = r["pos"] - s["pos"]
+    d -= ps.box * np.rint(d / ps.box)
+    assert np.max(np.abs(d)) < 1e-15
+    np.testing.assert_allclose(r["vel"], s["vel"], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(r["h"], s["h"], rtol=1e-12)
+
+
+def test_mts_inactive_particles_only_drift():
+    # two regions: hot particles (small steps) in a slab, cold ones (large steps) elsewhere
+    ps = workloads.uniform(900, seed=23, sigma_v=0.05)
+    ps.u[:] = np.where(ps.pos[:, 0] < 0.3, 20.0, 0.05)
+    f = oracle.full_pass(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box)
+    dtb = float(np.min(f["signal"]["dt"]))
+    r1 = oracle.mts_integrate(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box, dtb, 3, 1)
+    bins0 = oracle.time_bin(f["signal"]["dt"], dtb, 3, 0)
+    assert bins0.max() >= 2 and bins0.min() == 0
+    idle = bins0 >= 1   # not at the end of a step after one base step
+    # their velocities carry only the opening half kick, their energies too
+    span = 2.0 ** bins0[idle] * dtb
+    np.testing.assert_allclose(r1["vel"][idle], ps.vel[idle] + 0.5 * span[:, None] * f["force"]["a"][idle],
+                               rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(r1["h"][idle], f["h"][idle], rtol=0, atol=0)
+    assert r1["active"][0] == np.sum(bins0 == 0)
