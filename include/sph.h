@@ -323,6 +323,34 @@ sph_status sph_step_adaptive(sph_ctx *ctx, sph_particles *p, const sph_batch *ba
 sph_status sph_integrate(sph_ctx *ctx, sph_particles *p, const sph_batch *batch, sph_force_out *acc,
                          double t_end, double dt_max, int64_t max_steps, int64_t *steps, void *stream);
 
+/* Multiple time-stepping (Sec. 4.1), one box (batch NULL).  Particle i sits
+ * in time bin k_i: the largest k with 2^k dt_base <= its time step of
+ * Eq. (6) (k >= 0, at most max_bin, infinite steps in max_bin), lowered until
+ * its step starts on a multiple of its length; it takes kick-drift-kick steps
+ * of 2^k_i dt_base and is active, a target of the density and force stages,
+ * only at the end of each of them.  The other particles are sources with the
+ * rho, A, c and f of their last active step (kept by the context).
+ *
+ * sph_mts_init: a full pass with every particle active (cells, orderings,
+ * density, force with dt into acc), the stored quantities of every particle,
+ * and bin[i] (device, n values, written) from acc->dt; the base step counter
+ * is set to 0.  acc needs ax..dudt and dt.  dt_base > 0, 0 <= max_bin <= 30.
+ *
+ * sph_mts_step: base step n -> n+1: particles starting a step take the
+ * opening half kick v += T_i/2 a_i, u += T_i/2 du_i; every particle drifts
+ * by dt_base; velocities and energies are predicted at the end of the base
+ * step from each particle's last kick; cells (params.reuse applies),
+ * orderings, then density and force for the particles ending their step
+ * there (acc, including dt, is written for them only); their closing half
+ * kick and their new bin.  *n_active (may be NULL; it costs one stream
+ * synchronisation) receives the number of active particles.  Errors: as
+ * sph_step; SPH_E_STATE without sph_mts_init on the same particle count, or
+ * after a batched build. */
+sph_status sph_mts_init(sph_ctx *ctx, sph_particles *p, sph_force_out *acc, int32_t *bin, double dt_base,
+                        int max_bin, void *stream);
+sph_status sph_mts_step(sph_ctx *ctx, sph_particles *p, sph_force_out *acc, int32_t *bin, int64_t *n_active,
+                        void *stream);
+
 /* Graph of one whole pass (the batched persistent form): optional copy of
  * h_init (device, n values; may be NULL) into p->h, then sph_build_cells,
  * sph_sort, sph_density_async and sph_force, captured once into a HIP graph

@@ -68,6 +68,13 @@ struct sph_ctx {
     DBuf qhead, status;
     DBuf step_tmp;                                   // predicted v, u; new a, du/dt
     DBuf dt_box, dt_min, t_box;                      // per-box step length, minimum of Eq. (6), time
+    // multiple time-stepping: activity of the current base step, the density-stage
+    // quantities of every particle's last active step (caller order), counters
+    DBuf mts_active, mts_rho, mts_A, mts_c, mts_f, mts_count;
+    bool mts_ready = false, mts_masked = false, mts_store = false;
+    int64_t mts_n = 0, mts_np = 0;
+    double mts_dtb = 0.0;
+    int mts_max_bin = 0;
     uint32_t* status_host = nullptr;                 // pinned
     int32_t* ncells_host = nullptr;                  // pinned
     // state of the current decomposition
@@ -131,6 +138,12 @@ static GhostData<R> ghost_data(sph_ctx* c)
     g.g0 = c->g0.as<R4>(); g.g1 = c->g1.as<R4>();
     g.cell_hmax = c->cell_hmax.as<float>();
     g.sd0 = c->sd0.as<double4>(); g.sd1 = c->sd1.as<double4>();
+    g.active = c->mts_masked ? c->mts_active.as<uint8_t>() : nullptr;
+    const bool st = c->mts_masked || c->mts_store;
+    g.s_rho = st ? c->mts_rho.as<double>() : nullptr;
+    g.s_A = st ? c->mts_A.as<double>() : nullptr;
+    g.s_c = st ? c->mts_c.as<double>() : nullptr;
+    g.s_f = st ? c->mts_f.as<double>() : nullptr;
     return g;
 }
 
@@ -294,7 +307,8 @@ sph_status sph_destroy(sph_ctx* c)
     DBuf* all[] = {&c->boxes, &c->keys, &c->keys2, &c->vals, &c->vals2, &c->rs_scratch, &c->flag,
                    &c->cellx, &c->cell_of, &c->sc_scratch, &c->cells, &c->ncells, &c->cell_map,
                    &c->src, &c->src_count, &c->srec, &c->r0, &c->cell_drift, &c->rx, &c->ry, &c->rz, &c->h,
-                   &c->vm, &c->u, &c->g0, &c->g1, &c->cell_hmax, &c->qhead, &c->status, &c->step_tmp, &c->dt_box, &c->dt_min, &c->t_box,
+                   &c->vm, &c->u, &c->g0, &c->g1, &c->cell_hmax, &c->qhead, &c->status, &c->step_tmp, &c->dt_box, &c->dt_min, &c->t_box, &c->mts_active, &c->mts_rho, &c->mts_A,
+                   &c->mts_c, &c->mts_f, &c->mts_count,
                    &c->sd0, &c->sd1, &c->adj_ab, &c->adj_sb0, &c->adj_sb1, &c->adj_x, &c->adj_h, &c->adj_fg,
                    &c->src_off, &c->t_chg, &c->t_node_of, &c->t_node_start, &c->t_node_flag, &c->t_node_hmax,
                    &c->t_node_H, &c->t_node_leaf, &c->t_nnodes, &c->t_flag, &c->t_scan, &c->t_small,
@@ -945,6 +959,113 @@ sph_status sph_integrate(sph_ctx* c, sph_particles* p, const sph_batch* batch, s
     for (double t : tb)
         if (t < t_end) return SPH_E_CAPACITY;
     return worst;
+}
+
+// ---------------------------------------------------------------- multiple time-stepping
+static MtsStep mts_view(sph_ctx* c, int32_t* bin)
+{
+    MtsStep m;
+    m.n = c->mts_n;
+    m.dtb = c->mts_dtb;
+    m.max_bin = c->mts_max_bin;
+    m.bin = bin;
+    m.active = c->mts_active.as<uint8_t>();
+    m.n_active = c->mts_count.as<int32_t>();
+    return m;
+}
+
+sph_status sph_mts_init(sph_ctx* c, sph_particles* p, sph_force_out* acc, int32_t* bin, double dt_base, int max_bin,
+                        void* stream)
+{
+    if (!c || !particles_ok(p) || !acc_ok(acc, p ? p->n : 0, true) || (!bin && p->n > 0)) return SPH_E_INVALID_ARG;
+    if (!(dt_base > 0.0) || !std::isfinite(dt_base) || max_bin < 0 || max_bin > 30) return SPH_E_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    if (hipSetDevice(c->device) != hipSuccess) return SPH_E_HIP;
+    c->mts_ready = false;
+    const size_t N = (size_t)std::max<int64_t>(p->n, 1);
+    if (!c->mts_active.ensure(N) || !c->mts_rho.ensure(N * 8) || !c->mts_A.ensure(N * 8) || !c->mts_c.ensure(N * 8) ||
+        !c->mts_f.ensure(N * 8) || !c->mts_count.ensure(16))
+        return SPH_E_OOM;
+    if (p->n == 0) return SPH_OK;
+    // every particle active: the density-stage quantities of all are stored
+    c->mts_store = true;
+    sph_status s = sph_build_cells(c, p, nullptr, st);
+    if (s == SPH_OK) s = sph_sort(c, st);
+    if (s == SPH_OK) s = sph_density(c, p, nullptr, st);
+    c->mts_store = false;
+    if (s != SPH_OK && s != SPH_E_NOT_CONVERGED) return s;
+    sph_status sd = s;
+    s = sph_force(c, p, acc, st);
+    if (s != SPH_OK) return s;
+    c->mts_dtb = dt_base;
+    c->mts_max_bin = max_bin;
+    c->mts_n = 0;
+    c->mts_np = p->n;
+    launch_mts_bins(acc->dt, mts_view(c, bin), 0, p->n, st);
+    if (hipGetLastError() != hipSuccess) return SPH_E_HIP;
+    c->mts_ready = true;
+    return sd;
+}
+
+sph_status sph_mts_step(sph_ctx* c, sph_particles* p, sph_force_out* acc, int32_t* bin, int64_t* n_active,
+                        void* stream)
+{
+    if (n_active) *n_active = 0;
+    if (!c || !particles_ok(p) || !acc_ok(acc, p ? p->n : 0, true) || (!bin && p->n > 0)) return SPH_E_INVALID_ARG;
+    if (!c->mts_ready || p->n != c->mts_np || !c->batch_off.empty()) return SPH_E_STATE;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = p->n;
+    if (n == 0) return SPH_OK;
+    if (hipSetDevice(c->device) != hipSuccess) return SPH_E_HIP;
+    if (!c->step_tmp.ensure(sizeof(double) * 4 * (size_t)n)) return SPH_E_OOM;
+    double* vp = c->step_tmp.as<double>();
+    StepArrays sa;
+    sa.x = p->x; sa.y = p->y; sa.z = p->z; sa.vx = p->vx; sa.vy = p->vy; sa.vz = p->vz; sa.u = p->u;
+    sa.ax = acc->ax; sa.ay = acc->ay; sa.az = acc->az; sa.dudt = acc->dudt;
+    sa.pvx = vp; sa.pvy = vp + n; sa.pvz = vp + 2 * n; sa.pu = vp + 3 * n;
+    const MtsStep m = mts_view(c, bin);
+    // the box table of the last build (one box) gives the drift its box
+    launch_mts_open(sa, m, c->boxes.as<BoxInfo>(), n, st);
+    sph_particles q = *p;
+    q.vx = sa.pvx; q.vy = sa.pvy; q.vz = sa.pvz; q.u = sa.pu;
+    const bool reuse = can_reuse(c, p, nullptr);
+    sph_status s = SPH_OK;
+    if (reuse) {
+        s = sph_refresh(c, &q, st);
+        uint32_t bits = 0;
+        if (s == SPH_OK) s = read_status(c, st, &bits);
+        if (s == SPH_OK) s = status_error(bits);
+        if (s == SPH_OK) {
+            if (bits & ST_REBUILD) {
+                s = rebuild_same_boxes(c, &q, st);
+                c->step_rebuilds = 1;
+            } else {
+                c->refresh_checked = true;
+                if (c->prm.reuse == SPH_REUSE_CELLS) s = sph_sort(c, st);
+            }
+        }
+    } else {
+        s = sph_build_cells(c, &q, nullptr, st);
+        if (s == SPH_OK) s = sph_sort(c, st);
+    }
+    // only the active particles are targets; the others pass on their stored quantities
+    c->mts_masked = true;
+    if (s == SPH_OK) s = sph_density(c, &q, nullptr, st);
+    sph_status sd = s;
+    if (s == SPH_OK || s == SPH_E_NOT_CONVERGED) s = sph_force(c, &q, acc, st);
+    c->mts_masked = false;
+    if (s != SPH_OK) return s;
+    launch_mts_close(sa, m, acc->dt, n, st);
+    if (hipGetLastError() != hipSuccess) return SPH_E_HIP;
+    c->mts_n++;
+    if (n_active) {
+        int32_t h = 0;
+        if (hipMemcpyAsync(&h, m.n_active, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return SPH_E_HIP;
+        *n_active = h;
+    }
+    return sd;
 }
 
 __global__ void k_copy_f64(double* dst, const double* src, int64_t n)

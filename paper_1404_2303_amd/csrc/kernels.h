@@ -45,6 +45,11 @@ struct GhostData {
     // sums kept for the adjoint (FP64, cell order; may be null):
     // sd0 = (sum m w incl. self, sum m q w', dN/dh, sum m g dv.r), sd1 = (sum m g dv x r, 0)
     double4 *sd0, *sd1;
+    // multiple time-stepping (caller order; null when every particle is active):
+    // a particle is a target of the density and force stages only where active[i] != 0;
+    // the others enter as sources with the rho, A, c, f of their last active step
+    const uint8_t* active;
+    double *s_rho, *s_A, *s_c, *s_f;
 };
 
 // Per-particle adjoint data (cell order).
@@ -202,6 +207,17 @@ void launch_step_open(const StepArrays& s, const double* dtb, const BoxInfo* box
 void launch_step_close(const StepArrays& s, const double* dtb, const BoxInfo* boxes, int nbox, int64_t n,
                        hipStream_t st);
 void launch_fill_f64(double* a, double v, int n, hipStream_t st);
+struct MtsStep {
+    int64_t n;          // index of the base step
+    double dtb;         // base step
+    int max_bin;
+    int32_t* bin;       // time bin per particle (caller order)
+    uint8_t* active;    // active at the end of base step n
+    int32_t* n_active;  // count of active particles (device)
+};
+void launch_mts_open(const StepArrays& s, const MtsStep& m, const BoxInfo* boxes, int64_t n, hipStream_t st);
+void launch_mts_close(const StepArrays& s, const MtsStep& m, const double* dt, int64_t n, hipStream_t st);
+void launch_mts_bins(const double* dt, const MtsStep& m, int64_t n_next, int64_t n, hipStream_t st);
 void launch_dt_select(const double* dt, const BoxInfo* boxes, int nbox, int64_t n, unsigned long long* mn,
                       double dt_max, double t_end, double* t_box, double* dtb, double* dt_out, hipStream_t st);
 

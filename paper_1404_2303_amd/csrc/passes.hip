@@ -121,7 +121,13 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
             if (tid == 0) atomicOr(dc.status, ST_REBUILD);
             T.count = 0;
         }
-        const int nsrc = stale ? 0 : dc.src_count[unit];
+        // with multiple time-stepping, a cell without active particles stages
+        // nothing and only passes its particles' stored quantities on
+        bool any_on = !gd.active;
+        if (gd.active)
+            for (int t = lane; t < T.count; t += kWave) any_on |= gd.active[dc.perm[T.start + t]] != 0;
+        const bool cell_on = __builtin_amdgcn_readfirstlane(__any(any_on) ? 1 : 0) != 0;
+        const int nsrc = (stale || !cell_on) ? 0 : dc.src_count[unit];
         const double h_box = fmin(B.L[0], fmin(B.L[1], B.L[2])) / 3.0;
         // rounding margin of the sweeps; staging also covers targets that left
         // the cell by up to dT
@@ -142,6 +148,8 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
             const int ti = c0 + lane;
             const bool valid = ti < T.count;
             const uint32_t gi = (uint32_t)(T.start + (valid ? ti : 0));
+            const uint32_t pi = dc.perm[gi];
+            const bool on = valid && (!gd.active || gd.active[pi] != 0);   // a target of this pass
             const R xi = cd.rx[gi], yi = cd.ry[gi], zi = cd.rz[gi];
             const R4 vmi = cd.vm[gi];
             const float fxi = (float)xi, fyi = (float)yi, fzi = (float)zi;
@@ -150,7 +158,7 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
             double lo = 0.0, hi = INFINITY, h_rebuild = 0.0;
             int iters = 0;
             bool failed = false;
-            bool conv = !valid;
+            bool conv = !on;
             // neighbour lists of this wavefront: valid while every lane's h <= hcache
             bool cached = false;
             bool cached_all = false;  // the lists were built with every valid lane active
@@ -217,7 +225,7 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
                 } while (kk < nsrc);
                 if (single) process(cnt);
                 cached = single && !flushed;
-                cached_all = __all(act || !valid);
+                cached_all = __all(act || !on);
             };
 
             // ---- Newton iteration on h (Eq. (3)) in FP64, safeguarded by a bracket.
@@ -243,8 +251,8 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
                     __syncthreads();  // every wavefront has read the last step's sums
                     for (int a = w; a < NACC_D; a += NW) s.red[a][lane] = 0.0;
                     __syncthreads();
-                    evaluate(valid, true);
-                    if (valid) {
+                    evaluate(on, true);
+                    if (on) {
                         atomicAdd(&s.red[0][lane], acc.w);
                         atomicAdd(&s.red[1][lane], acc.qdw);
                         atomicAdd(&s.red[2][lane], acc.mw);
@@ -327,7 +335,18 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
             }
 
             // ---- per-particle quantities between the stages (wavefront 0)
-            if (w == 0 && valid) {
+            if (w == 0 && valid && !on) {
+                // not a target this time: its quantities of the last active step
+                const double hh = cd.h[gi];
+                const double k5 = kNorm / (hh * hh * hh * hh * hh);
+                R4 g0, g1;
+                g0.x = (R)(1.0 / hh); g0.y = (R)k5; g0.z = (R)gd.s_A[pi]; g0.w = (R)gd.s_rho[pi];
+                g1.x = (R)gd.s_c[pi]; g1.y = (R)gd.s_f[pi]; g1.z = (R)hh; g1.w = (R)0;
+                gd.g0[gi] = g0;
+                gd.g1[gi] = g1;
+                cell_hmax = fmaxf(cell_hmax, (float)hh * (1.0f + 1e-6f));
+            }
+            if (w == 0 && on) {
                 DensAcc tot;
                 tot.w = s.red[0][lane]; tot.qdw = s.red[1][lane]; tot.mw = s.red[2][lane];
                 tot.mqdw = s.red[3][lane]; tot.div = s.red[4][lane]; tot.cx = s.red[5][lane];
@@ -358,7 +377,7 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
                     gd.sd0[gi] = make_double4(tot.mw + m, tot.mqdw, -32.0 / 3.0 / h * tot.qdw, tot.div);
                     gd.sd1[gi] = make_double4(tot.cx, tot.cy, tot.cz, 0.0);
                 }
-                const uint32_t pi = dc.perm[gi];
+                if (gd.s_rho) { gd.s_rho[pi] = rho; gd.s_A[pi] = A; gd.s_c[pi] = c; gd.s_f[pi] = bal; }
                 if (out.h) out.h[pi] = h_rebuild > 0.0 ? h_rebuild : h;
                 if (out.rho) out.rho[pi] = rho;
                 if (out.omega) out.omega[pi] = omega;
@@ -452,10 +471,15 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
         if (unit >= ncells) break;
         const CellInfo T = dc.cells[unit];
         const BoxInfo B = dc.boxes[T.box];
-        const int nsrc = dc.src_count[unit];
+        int nsrc = dc.src_count[unit];
         const float margin = 1e-5f * (float)fmax(B.e[0], fmax(B.e[1], B.e[2]));
         const float mstage = margin + cell_dr(dc, unit);   // targets may have left the cell by this
         const float Hst = gd.cell_hmax[unit];
+        bool any_on = !gd.active;
+        if (gd.active)
+            for (int t = lane; t < T.count; t += kWave) any_on |= gd.active[dc.perm[T.start + t]] != 0;
+        const bool cell_on = __builtin_amdgcn_readfirstlane(__any(any_on) ? 1 : 0) != 0;
+        if (!cell_on) nsrc = 0;   // no target here: nothing to stage or sweep
         int k = 0, p = 0;
         stage_wave<R, true, NACC_F>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, mstage);
         const bool single = k >= nsrc;
@@ -463,6 +487,7 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
             const int ti_ = c0 + lane;
             const bool valid = ti_ < T.count;
             const uint32_t gi = (uint32_t)(T.start + (valid ? ti_ : 0));
+            const bool on = valid && (!gd.active || gd.active[dc.perm[gi]] != 0);   // a target of this pass
             ForceTarget<R> ti;
             ti.x = cd.rx[gi]; ti.y = cd.ry[gi]; ti.z = cd.rz[gi];
             const R4 vmi = cd.vm[gi], g0i = gd.g0[gi], g1i = gd.g1[gi];
@@ -496,14 +521,14 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
                 int seg = 0, jj = s.nseg[w] > 0 ? s.seg_b[w][0] : 0;
                 int cnt = 0;
                 while (true) {
-                    cnt = walk<R, true, NACC_F>(s, w, lane, valid, ti.x, ti.y, ti.z, fxi, fyi, fzi, ti.h, fh, margin,
+                    cnt = walk<R, true, NACC_F>(s, w, lane, on, ti.x, ti.y, ti.z, fxi, fyi, fzi, ti.h, fh, margin,
                                                 selfj, seg, jj, cnt);
                     process(cnt);
                     cnt = 0;
                     if (seg >= s.nseg[w]) break;
                 }
             } while (kk < nsrc);
-            if (valid) {
+            if (on) {
                 atomicAdd(&s.red[0][lane], acc.ax);
                 atomicAdd(&s.red[1][lane], acc.ay);
                 atomicAdd(&s.red[2][lane], acc.az);
@@ -514,7 +539,7 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
                           (unsigned long long)__double_as_longlong((double)acc.vsig));
             }
             __syncthreads();
-            if (w == 0 && valid) {
+            if (w == 0 && on) {
                 const uint32_t pi = dc.perm[gi];
                 if (out.ax) out.ax[pi] = s.red[0][lane];
                 if (out.ay) out.ay[pi] = s.red[1][lane];

@@ -30,7 +30,7 @@ EXPORTED = ["sph_default_params", "sph_create", "sph_destroy", "sph_build_cells"
             "sph_density", "sph_force", "sph_step", "sph_get_stats", "sph_status_string",
             "sph_enable_timing", "sph_get_kernel_times", "sph_density_async", "sph_check",
             "sph_graph_capture", "sph_graph_launch", "sph_backward", "sph_estimate_h", "sph_step_adaptive",
-            "sph_integrate", "sph_refresh"]
+            "sph_integrate", "sph_refresh", "sph_mts_init", "sph_mts_step"]
 
 P = ctypes.c_void_p
 
@@ -123,6 +123,12 @@ def load_library():
         lib.sph_integrate.argtypes = [P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_batch),
                                       ctypes.POINTER(sph_force_out), ctypes.c_double, ctypes.c_double,
                                       ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), P]
+        lib.sph_mts_init.restype = st
+        lib.sph_mts_init.argtypes = [P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_force_out), P,
+                                     ctypes.c_double, ctypes.c_int, P]
+        lib.sph_mts_step.restype = st
+        lib.sph_mts_step.argtypes = [P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_force_out), P,
+                                     ctypes.POINTER(ctypes.c_int64), P]
         lib.sph_refresh.restype = st
         lib.sph_refresh.argtypes = [P, ctypes.POINTER(sph_particles), P]
         lib.sph_get_stats.restype = st
@@ -336,6 +342,29 @@ class Context:
     def build_cells(self, parts: Particles, batch: Optional[Batch] = None):
         _check(sph_build_cells(self.ctx, parts.c_struct(), batch.c if batch else None, _stream()),
                "sph_build_cells")
+
+    def mts_init(self, parts: Particles, dt_base: float, max_bin: int, acc: Optional[dict] = None):
+        """Multiple time-stepping: full pass and time bins; returns (acc, bins)."""
+        if acc is None:
+            acc = self.force_buffers(parts.n, parts.x.device)
+        bins = torch.zeros(parts.n, dtype=torch.int32, device=parts.x.device)
+        c = sph_force_out(*[_ptr(acc.get(k)) for k in FORCE_FIELDS])
+        _check(load_library().sph_mts_init(self.ctx, ctypes.byref(parts.c_struct()), ctypes.byref(c), _ptr(bins),
+                                           float(dt_base), int(max_bin), _stream()), "sph_mts_init",
+               (SPH_E_NOT_CONVERGED,))
+        return acc, bins
+
+    def mts_step(self, parts: Particles, acc: dict, bins: torch.Tensor, count: bool = False):
+        """One base step of multiple time-stepping; returns the number of active particles
+        (with count=True, which synchronises) or None."""
+        if bins.dtype != torch.int32 or bins.numel() != parts.n or not bins.is_cuda:
+            raise ValueError("bins must be an int32 CUDA tensor with one value per particle")
+        c = sph_force_out(*[_ptr(acc.get(k)) for k in FORCE_FIELDS])
+        na = ctypes.c_int64(0)
+        _check(load_library().sph_mts_step(self.ctx, ctypes.byref(parts.c_struct()), ctypes.byref(c), _ptr(bins),
+                                           ctypes.byref(na) if count else None, _stream()), "sph_mts_step",
+               (SPH_E_NOT_CONVERGED,))
+        return int(na.value) if count else None
 
     def refresh(self, parts: Particles):
         """Refresh the cell-ordered particle data in the cells and orderings of the last build."""
