@@ -465,6 +465,69 @@ def integrate_section(steps, warmup):
             "reuse_cells_resort": run(sph.SPH_REUSE_CELLS)}
 
 
+def mts_section(base_steps):
+    """Multiple time-stepping on the blast wave of Sec. 4.2 at about the
+    paper's size (face-centred cubic lattice of 1,000,188 particles, energy 1
+    on the 28 central particles, background pressure 1e-6, Balsara switch of
+    the |div v| form): the same simulated interval, base_steps times the
+    smallest initial time step of Eq. (6), advanced (a) with every particle
+    stepping at the smallest current time step (sph_step_adaptive) and (b) with
+    power-of-two time bins on that base step, up to 2^10 (sph_mts_step), with
+    and without reuse of the cells."""
+    import torch
+    from paper_1404_2303_amd import sph, workloads
+    ps = workloads.sedov(63)
+    ev = lambda: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+
+    def global_steps(t_end):
+        parts = sph.Particles.from_numpy(ps, "cuda:0")
+        ctx = sph.Context(ps.box, precision="fp32", balsara_form=sph.SPH_BALSARA_DIV)
+        d, acc = ctx.run(parts)
+        t_box = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        a, b = ev()
+        torch.cuda.synchronize()
+        a.record()
+        nst = 0
+        while float(t_box[0]) < t_end and nst < 100000:
+            ctx.step_adaptive(parts, acc, t_box, t_end, 1.0)
+            nst += 1
+        b.record()
+        b.synchronize()
+        ctx.close()
+        return {"ms": a.elapsed_time(b), "steps": nst}
+
+    def mts(dtb, reuse):
+        parts = sph.Particles.from_numpy(ps, "cuda:0")
+        ctx = sph.Context(ps.box, precision="fp32", balsara_form=sph.SPH_BALSARA_DIV, reuse=reuse)
+        acc, bins = ctx.mts_init(parts, dtb, 10)
+        a, b = ev()
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(base_steps):
+            ctx.mts_step(parts, acc, bins)
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        # the active fractions of one more cycle of base steps, counted (untimed)
+        counts = [ctx.mts_step(parts, acc, bins, count=True) for _ in range(16)]
+        ctx.close()
+        return {"ms": ms, "base_steps": base_steps, "active_fraction_next_16": float(np.mean(counts)) / ps.n}
+
+    parts = sph.Particles.from_numpy(ps, "cuda:0")
+    ctx = sph.Context(ps.box, precision="fp32", balsara_form=sph.SPH_BALSARA_DIV)
+    d, f = ctx.run(parts)
+    dtb = float(f["dt"].min().item())
+    ctx.close()
+    t_end = base_steps * dtb
+    g = global_steps(t_end)
+    m0 = mts(dtb, sph.SPH_REUSE_OFF)
+    m1 = mts(dtb, sph.SPH_REUSE_ORDERINGS)
+    return {"workload": f"Sedov blast, FCC lattice of {ps.n} particles, E = 1 on 28 central particles, "
+                        "background P = 1e-6, unit periodic box",
+            "t_end": t_end, "dt_base": dtb, "global_smallest_step": g, "mts": m0, "mts_reuse": m1,
+            "speedup_mts": g["ms"] / m0["ms"], "speedup_mts_reuse": g["ms"] / m1["ms"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -476,6 +539,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode timing")
     ap.add_argument("--no-multires", action="store_true", help="skip the 2M-particle Plummer mixture")
     ap.add_argument("--no-integrate", action="store_true", help="skip the Sod time-integration timing")
+    ap.add_argument("--no-mts", action="store_true", help="skip the multiple time-stepping timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -538,6 +602,9 @@ def main():
     if not args.no_integrate:
         line["integrate"] = integrate_section(max(5, args.steps // 2), 2)
         log("integrate:", json.dumps(line["integrate"]))
+    if not args.no_mts:
+        line["mts"] = mts_section(64)
+        log("mts:", json.dumps(line["mts"]))
     if not args.no_adjoint:
         line["adjoint"] = adjoint_section(args.steps, args.warmup)
         log("adjoint:", json.dumps(line["adjoint"]))

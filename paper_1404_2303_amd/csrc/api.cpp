@@ -70,7 +70,7 @@ struct sph_ctx {
     DBuf dt_box, dt_min, t_box;                      // per-box step length, minimum of Eq. (6), time
     // multiple time-stepping: activity of the current base step, the density-stage
     // quantities of every particle's last active step (caller order), counters
-    DBuf mts_active, mts_rho, mts_A, mts_c, mts_f, mts_count;
+    DBuf mts_active, mts_rho, mts_A, mts_c, mts_f, mts_count, mts_units, mts_flag;
     bool mts_ready = false, mts_masked = false, mts_store = false;
     int64_t mts_n = 0, mts_np = 0;
     double mts_dtb = 0.0;
@@ -162,6 +162,8 @@ static Decomp decomp(sph_ctx* c)
     d.status = c->status.as<uint32_t>();
     d.cell_drift = c->refreshed ? c->cell_drift.as<float>() : nullptr;
     d.keys_stale = c->keys_stale ? 1 : 0;
+    d.units = c->mts_masked ? c->mts_units.as<int32_t>() : nullptr;
+    d.nunits = c->mts_masked ? c->mts_count.as<int32_t>() + 1 : nullptr;
     return d;
 }
 
@@ -308,7 +310,7 @@ sph_status sph_destroy(sph_ctx* c)
                    &c->cellx, &c->cell_of, &c->sc_scratch, &c->cells, &c->ncells, &c->cell_map,
                    &c->src, &c->src_count, &c->srec, &c->r0, &c->cell_drift, &c->rx, &c->ry, &c->rz, &c->h,
                    &c->vm, &c->u, &c->g0, &c->g1, &c->cell_hmax, &c->qhead, &c->status, &c->step_tmp, &c->dt_box, &c->dt_min, &c->t_box, &c->mts_active, &c->mts_rho, &c->mts_A,
-                   &c->mts_c, &c->mts_f, &c->mts_count,
+                   &c->mts_c, &c->mts_f, &c->mts_count, &c->mts_units, &c->mts_flag,
                    &c->sd0, &c->sd1, &c->adj_ab, &c->adj_sb0, &c->adj_sb1, &c->adj_x, &c->adj_h, &c->adj_fg,
                    &c->src_off, &c->t_chg, &c->t_node_of, &c->t_node_start, &c->t_node_flag, &c->t_node_hmax,
                    &c->t_node_H, &c->t_node_leaf, &c->t_nnodes, &c->t_flag, &c->t_scan, &c->t_small,
@@ -665,6 +667,20 @@ static sph_status rebuild_same_boxes(sph_ctx* c, sph_particles* p, void* stream)
     return s;
 }
 
+// Multiple time-stepping: the active cells and the inactive particles' records
+// for the decomposition as it stands (again after any rebuild).
+static void mts_prepare(sph_ctx* c, hipStream_t st)
+{
+    if (c->prm.precision == SPH_FP64)
+        launch_mts_prepare<double>(decomp(c), cell_data<double>(c), ghost_data<double>(c), c->mts_units.as<int32_t>(),
+                                   c->mts_count.as<int32_t>() + 1, c->mts_flag.as<uint32_t>(),
+                                   c->cell_of.as<uint32_t>(), c->n, st);
+    else
+        launch_mts_prepare<float>(decomp(c), cell_data<float>(c), ghost_data<float>(c), c->mts_units.as<int32_t>(),
+                                  c->mts_count.as<int32_t>() + 1, c->mts_flag.as<uint32_t>(),
+                                  c->cell_of.as<uint32_t>(), c->n, st);
+}
+
 sph_status sph_density(sph_ctx* c, sph_particles* p, sph_density_out* o, void* stream)
 {
     if (!c || !particles_ok(p)) return SPH_E_INVALID_ARG;
@@ -689,6 +705,7 @@ sph_status sph_density(sph_ctx* c, sph_particles* p, sph_density_out* o, void* s
             c->stats.rebuilds++;
         }
     }
+    if (c->mts_masked) mts_prepare(c, st);
     for (int attempt = 0;; attempt++) {
         uint32_t bits = 0;
         if (c->n > 0) {
@@ -711,6 +728,7 @@ sph_status sph_density(sph_ctx* c, sph_particles* p, sph_density_out* o, void* s
             s = rebuild_same_boxes(c, p, stream);
             if (s != SPH_OK) return s;
             c->stats.rebuilds++;
+            if (c->mts_masked) mts_prepare(c, st);
             continue;
         }
         if (bits & ST_REBUILD) return SPH_E_H_TOO_LARGE;
@@ -984,7 +1002,8 @@ sph_status sph_mts_init(sph_ctx* c, sph_particles* p, sph_force_out* acc, int32_
     c->mts_ready = false;
     const size_t N = (size_t)std::max<int64_t>(p->n, 1);
     if (!c->mts_active.ensure(N) || !c->mts_rho.ensure(N * 8) || !c->mts_A.ensure(N * 8) || !c->mts_c.ensure(N * 8) ||
-        !c->mts_f.ensure(N * 8) || !c->mts_count.ensure(16))
+        !c->mts_f.ensure(N * 8) || !c->mts_count.ensure(16) || !c->mts_units.ensure(N * 4) ||
+        !c->mts_flag.ensure(N * 4))
         return SPH_E_OOM;
     if (p->n == 0) return SPH_OK;
     // every particle active: the density-stage quantities of all are stored

@@ -97,6 +97,8 @@ struct Decomp {
     uint32_t* status;
     const float* cell_drift;  // largest displacement in each cell since the build (null: none)
     int keys_stale;           // the orderings predate that displacement (made before it)
+    const int32_t* units;     // the cells to process (null: every cell)
+    const int32_t* nunits;    // their number (device)
 };
 
 // displacement of cell c's particles since the cells were built
@@ -188,6 +190,9 @@ template <typename R>
 void launch_force(const Decomp& dc, const CellData<R>& cd, const Sorted<R>& so, const GhostData<R>& gd,
                   const ForceOut& out, const PassConsts& pc, int grid, hipStream_t st);
 int density_occupancy_grid(int precision);
+template <typename R>
+void launch_mts_prepare(const Decomp& dc, const CellData<R>& cd, const GhostData<R>& gd, int32_t* units,
+                        int32_t* nunits, uint32_t* cell_flag, const uint32_t* cell_of, int64_t n, hipStream_t st);
 int force_occupancy_grid(int precision);
 
 // adjoint.hip

@@ -100,12 +100,14 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
     // a decomposition flagged by the build (non-finite data, capacity, h too
     // large for the box) is not swept: its orderings need not be complete
     if (*dc.status & (ST_NONFINITE | ST_H_TOO_LARGE | ST_CAPACITY)) return;
+    const int nunits = dc.nunits ? *dc.nunits : ncells;
     while (true) {
         if (tid == 0) s.unit = atomicAdd(dc.qhead, 1);
         __syncthreads();
-        const int unit = s.unit;
+        const int uidx = s.unit;
         __syncthreads();
-        if (unit >= ncells) break;
+        if (uidx >= nunits) break;
+        const int unit = dc.units ? dc.units[uidx] : uidx;
         CellInfo T = dc.cells[unit];
         const BoxInfo B = dc.boxes[T.box];
         // the interaction lists cover h up to this, less the displacement
@@ -463,12 +465,14 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
     const int ncells = *dc.ncells;
     const R alpha = (R)pc.alpha;
     if (*dc.status & (ST_NONFINITE | ST_H_TOO_LARGE | ST_CAPACITY)) return;
+    const int nunits = dc.nunits ? *dc.nunits : ncells;
     while (true) {
         if (tid == 0) s.unit = atomicAdd(dc.qhead, 1);
         __syncthreads();
-        const int unit = s.unit;
+        const int uidx = s.unit;
         __syncthreads();
-        if (unit >= ncells) break;
+        if (uidx >= nunits) break;
+        const int unit = dc.units ? dc.units[uidx] : uidx;
         const CellInfo T = dc.cells[unit];
         const BoxInfo B = dc.boxes[T.box];
         int nsrc = dc.src_count[unit];
@@ -556,6 +560,95 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
         }
     }
 }
+
+// ---------------------------------------------------------------- multiple time-stepping
+// Before the density stage of a base step: the force-stage records of the
+// inactive particles from their last active step, and per cell whether it
+// holds an active particle (flag) and its largest h (the sweeps of active
+// cells read those of their sources).  Particle-parallel in cell order: the
+// lanes of one cell are consecutive, so a segmented wavefront reduction
+// leaves each cell's values in its last lane, which issues the atomics.
+template <typename R>
+__global__ void k_ghost_stash(const uint32_t* perm, const uint32_t* cell_of, CellData<R> cd, GhostData<R> gd,
+                              uint32_t* cell_flag, int64_t n)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k - (int64_t)(threadIdx.x & 63) >= n) return;   // the whole wavefront is past the end
+    const bool valid = k < n;
+    int c = -1;
+    float hm = 0.0f;
+    uint32_t on = 0;
+    if (valid) {
+        const uint32_t pi = perm[k];
+        c = (int)cell_of[k];
+        const double h = cd.h[k];
+        hm = (float)h * (1.0f + 1e-6f);
+        on = gd.active[pi] ? 1u : 0u;
+        if (!on) {
+            const double kNorm = 8.0 / kPi;
+            typename Vec4T<R>::T g0, g1;
+            g0.x = (R)(1.0 / h); g0.y = (R)(kNorm / (h * h * h * h * h)); g0.z = (R)gd.s_A[pi];
+            g0.w = (R)gd.s_rho[pi];
+            g1.x = (R)gd.s_c[pi]; g1.y = (R)gd.s_f[pi]; g1.z = (R)h; g1.w = (R)0;
+            gd.g0[k] = g0;
+            gd.g1[k] = g1;
+        }
+    }
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const float ho = __shfl_up(hm, o, 64);
+        const uint32_t oo = __shfl_up(on, o, 64);
+        const int co = __shfl_up(c, o, 64);
+        if (lane >= o && co == c) { hm = fmaxf(hm, ho); on |= oo; }
+    }
+    const int cn = __shfl_down(c, 1, 64);
+    if (valid && (lane == 63 || cn != c)) {
+        atomicMax((unsigned int*)&gd.cell_hmax[c], __float_as_uint(hm));
+        if (on) atomicOr(&cell_flag[c], 1u);
+    }
+}
+
+// The flagged cells appended to the unit list (order is irrelevant: each
+// unit's result does not depend on the others); flags and maxima cleared for
+// the next base step are done by the caller's fills.
+__global__ void k_mts_units(const int32_t* ncells, const uint32_t* cell_flag, int32_t* units, int32_t* nunits)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool f = c < *ncells && cell_flag[c] != 0;
+    const unsigned long long b = __ballot(f);
+    if (!b) return;
+    const int lane = threadIdx.x & 63;
+    int base = 0;
+    if (lane == __ffsll((long long)b) - 1) base = atomicAdd(nunits, __popcll(b));
+    base = __shfl(base, __ffsll((long long)b) - 1, 64);
+    if (f) units[base + __popcll(b & ((1ull << lane) - 1))] = c;
+}
+
+__global__ void k_clear_cells(const int32_t* ncells, float* cell_hmax, uint32_t* cell_flag)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < *ncells) { cell_hmax[c] = 0.0f; cell_flag[c] = 0u; }
+}
+
+__global__ void k_zero_i32(int32_t* a) { *a = 0; }
+
+template <typename R>
+void launch_mts_prepare(const Decomp& dc, const CellData<R>& cd, const GhostData<R>& gd, int32_t* units,
+                        int32_t* nunits, uint32_t* cell_flag, const uint32_t* cell_of, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, st, nunits);
+    if (n <= 0) return;
+    // cells number at most n
+    const unsigned g = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_clear_cells, dim3(g), dim3(256), 0, st, dc.ncells, gd.cell_hmax, cell_flag);
+    hipLaunchKernelGGL(k_ghost_stash<R>, dim3(g), dim3(256), 0, st, dc.perm, cell_of, cd, gd, cell_flag, n);
+    hipLaunchKernelGGL(k_mts_units, dim3(g), dim3(256), 0, st, dc.ncells, (const uint32_t*)cell_flag, units, nunits);
+}
+template void launch_mts_prepare<float>(const Decomp&, const CellData<float>&, const GhostData<float>&, int32_t*,
+                                        int32_t*, uint32_t*, const uint32_t*, int64_t, hipStream_t);
+template void launch_mts_prepare<double>(const Decomp&, const CellData<double>&, const GhostData<double>&, int32_t*,
+                                         int32_t*, uint32_t*, const uint32_t*, int64_t, hipStream_t);
 
 // ---------------------------------------------------------------- launchers
 __global__ void k_reset_counter(int32_t* c) { *c = 0; }

@@ -3,11 +3,15 @@ profilers (rocprofv3 --kernel-trace / --pmc) to record.
 
     python -m paper_1404_2303_amd.profile_pass --workload lattice --passes 2 --copy-mib 512
     python -m paper_1404_2303_amd.profile_pass --workload sod --steps 20 --reuse 1
+    python -m paper_1404_2303_amd.profile_pass --workload sedov --steps 64 --reuse 1
 
 --copy-mib adds device-to-device copies of that size after the passes, a
 kernel of known traffic that calibrates the memory counters.  The sod
 workload (the shock tube at 1,013,060 particles) runs --steps adaptive
-kick-drift-kick steps instead, with the decomposition reuse mode --reuse.
+kick-drift-kick steps instead, with the decomposition reuse mode --reuse;
+the sedov workload (the blast wave at 1,000,188 particles) runs --steps base
+steps of multiple time-stepping (bins up to 2^10 of the smallest initial
+time step).
 """
 from __future__ import annotations
 
@@ -16,7 +20,7 @@ import argparse
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=("lattice", "mixture", "lattice64", "sod"), default="lattice")
+    ap.add_argument("--workload", choices=("lattice", "mixture", "lattice64", "sod", "sedov"), default="lattice")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--reuse", type=int, default=0)
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
@@ -39,6 +43,23 @@ def main():
             ctx.step_adaptive(parts, acc, t_box, 1e30, 1.0)
         torch.cuda.synchronize()
         print(f"{args.steps} steps, {1e3 * (time.perf_counter() - t0) / args.steps:.3f} ms per step", flush=True)
+        ctx.close()
+        print("passes done", flush=True)
+        return
+    if args.workload == "sedov":
+        ps = workloads.sedov(63)
+        parts = sph.Particles.from_numpy(ps, "cuda:0")
+        ctx = sph.Context(ps.box, precision=args.precision, balsara_form=sph.SPH_BALSARA_DIV, reuse=args.reuse)
+        d, f = ctx.run(parts)
+        dtb = float(f["dt"].min().item())
+        acc, bins = ctx.mts_init(parts, dtb, 10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.mts_step(parts, acc, bins)
+        torch.cuda.synchronize()
+        print(f"{args.steps} base steps, {1e3 * (time.perf_counter() - t0) / args.steps:.3f} ms per base step",
+              flush=True)
         ctx.close()
         print("passes done", flush=True)
         return
