@@ -230,6 +230,17 @@ __device__ __forceinline__ int self_index(const Smem<R, NACC, F>& s, int w, int 
 }
 
 __device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
+
+// max of two squares (>= 0, no NaN): their bit patterns order like their values
+__device__ __forceinline__ float sq_max(float a, float b)
+{
+    return __uint_as_float(max(__float_as_uint(a), __float_as_uint(b)));
+}
+__device__ __forceinline__ double sq_max(double a, double b)
+{
+    return __longlong_as_double((long long)max((unsigned long long)__double_as_longlong(a),
+                                               (unsigned long long)__double_as_longlong(b)));
+}
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Walk of wavefront w over its staged segments, one segment at a time for
@@ -252,7 +263,12 @@ __device__ __forceinline__ int walk(Smem<R, NACC, FORCE>& s, int w, int lane, bo
     const R rad2 = rad * rad;
     int seg = uniform(seg_io);
     int jj = uniform(jj_io);
-    uint16_t* lst = &s.list[w][0][lane];
+    // list slots of this lane, kWave entries apart; wp is the next free one
+    // (an LDS pointer: 32-bit arithmetic, no address recomputation per entry)
+    using lds_u16 = __attribute__((address_space(3))) uint16_t;
+    lds_u16* const lst = (lds_u16*)&s.list[w][0][lane];
+    lds_u16* wp = lst + cnt * kWave;
+    lds_u16* const wfull = lst + (LISTW - STEP) * kWave;
     bool full = false;
     while (seg < nseg) {
         const int je = uniform(s.seg_e[w][seg]);
@@ -260,26 +276,28 @@ __device__ __forceinline__ int walk(Smem<R, NACC, FORCE>& s, int w, int lane, bo
         const float hx = s.seg_hx[w][seg];
         // the self segment has u = 0; a uniform flag
         const bool self = uniform((ux == 0.0f) & (uy == 0.0f) & (uz == 0.0f)) != 0;
-        auto test = [&](int j, R& r2, R& lim) {
+        // in range: r^2 < h_i^2, or (force) r^2 < max(h_i^2, h_j^2); both squares are
+        // >= 0, whose bit patterns order like their values (one integer max)
+        auto test = [&](int j, bool& in) {
             const auto e = s.st[w][j];  // past the segment end: any value, masked by the caller
             const R dx = xi - e.x, dy = yi - e.y, dz = zi - e.z;
-            r2 = dx * dx + dy * dy + dz * dz;
-            lim = rad2;
-            if constexpr (FORCE) lim = fmax(rad2, s.sh[w][j]);
+            const R r2 = dx * dx + dy * dy + dz * dz;
+            if constexpr (FORCE) in = r2 < sq_max(rad2, s.sh[w][j]);
+            else in = r2 < rad2;
             return (float)e.w;
         };
         if (self) {
             // the whole self segment is within every bound; skip the target itself
             while (jj < je) {
-                if (wave_any(cnt > LISTW - STEP)) { full = true; break; }
+                if (wave_any(wp > wfull)) { full = true; break; }
 #pragma unroll
                 for (int k = 0; k < STEP; k++) {
                     const int j = jj + k;
-                    R r2, lim;
-                    (void)test(j, r2, lim);
-                    const bool hit = (j < je) & act & (r2 < lim) & (j != selfj);
-                    lst[cnt * kWave] = (uint16_t)j;  // slot cnt is free; kept only on a hit
-                    cnt += hit ? 1 : 0;
+                    bool in;
+                    (void)test(j, in);
+                    const bool hit = (j < je) & act & in & (j != selfj);
+                    *wp = (uint16_t)j;  // the free slot; kept only on a hit
+                    wp += hit ? kWave : 0;
                 }
                 jj += STEP;
             }
@@ -289,17 +307,16 @@ __device__ __forceinline__ int walk(Smem<R, NACC, FORCE>& s, int w, int lane, bo
             const float bound =
                 !act ? -INFINITY : ux * fxi + uy * fyi + uz * fzi + fmaxf(fh, hx) + margin + 2.0f * s.seg_dr[w][seg];
             while (jj < je) {
-                if (wave_any(cnt > LISTW - STEP)) { full = true; break; }
+                if (wave_any(wp > wfull)) { full = true; break; }
                 bool in_last = false;
 #pragma unroll
                 for (int k = 0; k < STEP; k++) {
                     const int j = jj + k;
-                    R r2, lim;
-                    const float p = test(j, r2, lim);
+                    bool in;
+                    const float p = test(j, in);
                     const bool inb = (j < je) & (p <= bound);
-                    const bool hit = inb & (r2 < lim);
-                    lst[cnt * kWave] = (uint16_t)j;
-                    cnt += hit ? 1 : 0;
+                    *wp = (uint16_t)j;
+                    wp += (inb & in) ? kWave : 0;
                     if (k == STEP - 1) in_last = inb;
                 }
                 jj += STEP;
@@ -312,6 +329,7 @@ __device__ __forceinline__ int walk(Smem<R, NACC, FORCE>& s, int w, int lane, bo
         seg++;
         jj = seg < nseg ? uniform(s.seg_b[w][seg]) : 0;
     }
+    cnt = (int)(wp - lst) / kWave;
     seg_io = seg;
     jj_io = jj;
     return cnt;
