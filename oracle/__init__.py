@@ -332,9 +332,9 @@ def time_bin(dt, dt_base, max_bin, n_next):
     until the particle's next step starts on a multiple of its length:
     n_next % 2^k == 0, n_next the index of the next base step."""
     dt = np.asarray(dt, dtype=np.float64)
-    with np.errstate(divide="ignore"):
-        r = np.log2(np.where(dt > 0, dt / dt_base, 1.0))
-    k = np.clip(np.floor(r), 0, max_bin).astype(np.int64)
+    # floor(log2(dt / dt_base)) exactly: dt / dt_base = mant 2^e with mant in [1/2, 1)
+    _, e = np.frexp(np.where(np.isfinite(dt) & (dt > 0), dt / dt_base, 1.0))
+    k = np.clip(e.astype(np.int64) - 1, 0, max_bin)
     k = np.where(np.isinf(dt), max_bin, k)
     while True:
         bad = (k > 0) & ((n_next % (1 << k)) != 0)
