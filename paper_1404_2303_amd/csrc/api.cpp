@@ -91,6 +91,7 @@ struct sph_ctx {
     std::vector<int64_t> batch_off;
     std::vector<double> batch_len;
     bool built = false, sorted = false, have_density = false;
+    unsigned ev_recorded = 0;                        // events recorded at least once (bit per event)
     sph_stats stats{};
     // optional kernel timing
     bool timing = false;
@@ -104,7 +105,21 @@ enum { EV_BUILD0, EV_BUILD1, EV_SORT0, EV_SORT1, EV_DENS0, EV_DENS1, EV_FORCE0, 
 
 static void ev_record(sph_ctx* c, int k, hipStream_t st)
 {
-    if (c->timing) (void)hipEventRecord(c->ev[k], st);
+    if (c->timing && hipEventRecord(c->ev[k], st) == hipSuccess) c->ev_recorded |= 1u << k;
+}
+
+// Elapsed milliseconds between two recorded events (0 when either was never
+// recorded: querying such a pair would leave a HIP error behind).
+static float ev_elapsed(sph_ctx* c, int a, int b)
+{
+    const unsigned need = (1u << a) | (1u << b);
+    float ms = 0.0f;
+    if ((c->ev_recorded & need) != need) return 0.0f;
+    if (hipEventSynchronize(c->ev[b]) != hipSuccess || hipEventElapsedTime(&ms, c->ev[a], c->ev[b]) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0.0f;
+    }
+    return ms;
 }
 
 static sph_status hip_status(hipError_t e) { return e == hipSuccess ? SPH_OK : SPH_E_HIP; }
@@ -718,7 +733,8 @@ sph_status sph_density(sph_ctx* c, sph_particles* p, sph_density_out* o, void* s
         sph_status s = read_status(c, st, &bits);
         if (c->timing && c->n > 0) {
             float ms = 0.0f;
-            if (hipEventElapsedTime(&ms, c->ev[EV_DENS0], c->ev[EV_DENS1]) == hipSuccess) c->dens_ms_acc += ms;
+            ms = ev_elapsed(c, EV_DENS0, EV_DENS1);
+            c->dens_ms_acc += ms;
         }
         if (s != SPH_OK) return s;
         s = status_error(bits);
@@ -1159,19 +1175,15 @@ sph_status sph_get_kernel_times(sph_ctx* c, sph_kernel_times* out)
     if (!c || !out) return SPH_E_INVALID_ARG;
     std::memset(out, 0, sizeof(*out));
     if (!c->timing) return SPH_OK;
-    if (hipEventSynchronize(c->ev[EV_FORCE1]) != hipSuccess) return SPH_E_HIP;
-    (void)hipEventElapsedTime(&out->build_ms, c->ev[EV_BUILD0], c->ev[EV_BUILD1]);
-    (void)hipEventElapsedTime(&out->sort_ms, c->ev[EV_SORT0], c->ev[EV_SORT1]);
-    (void)hipEventElapsedTime(&out->force_ms, c->ev[EV_FORCE0], c->ev[EV_FORCE1]);
+    out->build_ms = ev_elapsed(c, EV_BUILD0, EV_BUILD1);
+    out->sort_ms = ev_elapsed(c, EV_SORT0, EV_SORT1);
+    out->force_ms = ev_elapsed(c, EV_FORCE0, EV_FORCE1);
     if (c->dens_async_timed) {
-        (void)hipEventElapsedTime(&c->dens_ms_acc, c->ev[EV_DENS0], c->ev[EV_DENS1]);
+        c->dens_ms_acc = ev_elapsed(c, EV_DENS0, EV_DENS1);
         c->dens_async_timed = false;
     }
     out->density_ms = c->dens_ms_acc;
-    if (c->adj_timed) {
-        if (hipEventSynchronize(c->ev[EV_ADJ1]) != hipSuccess) return SPH_E_HIP;
-        (void)hipEventElapsedTime(&out->backward_ms, c->ev[EV_ADJ0], c->ev[EV_ADJ1]);
-    }
+    if (c->adj_timed) out->backward_ms = ev_elapsed(c, EV_ADJ0, EV_ADJ1);
     return SPH_OK;
 }
 

@@ -198,3 +198,21 @@ def test_rebuild_when_h_outgrows_the_cells():
     g = gpu_run(ps, "fp64", cell_target=8, h_margin=0.0)
     assert g["stats"]["rebuilds"] >= 1
     compare(g, ref, "fp64", label="rebuild")
+
+
+def test_kernel_times_before_any_force_leave_no_error():
+    # timing enabled, density only: the force events were never recorded; asking for
+    # the times must not leave a HIP error behind for the next launch to report
+    ps = workloads.uniform(3000, seed=12)
+    log("case kernel times without a force call")
+    parts = sph.Particles.from_numpy(ps, "cuda:0")
+    ctx = sph.Context(ps.box, precision="fp32")
+    ctx.enable_timing(True)
+    ctx.build_cells(parts)
+    ctx.sort()
+    ctx.density(parts, want=("rho",))
+    t = ctx.kernel_times()
+    assert t["force_ms"] == 0.0 and t["density_ms"] > 0.0 and t["build_ms"] > 0.0
+    parts.h.add_(0.0)   # a torch launch after the query
+    torch.cuda.synchronize()
+    ctx.close()
