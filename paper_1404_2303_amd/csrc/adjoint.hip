@@ -238,7 +238,7 @@ __global__ __launch_bounds__(WGS) void k_adj_sweep(Decomp dc, CellData<R> cd, So
                 for (int t = 0;; t++) {
                     const bool v0 = t < n;
                     if (!__any(v0)) break;
-                    pair(v0, v0 ? (int)s.list[w][t][lane] : 0);
+                    pair(v0, v0 ? (int)s.list[w][lane][t] : 0);
                 }
             };
             int kk = 0, pp = 0;

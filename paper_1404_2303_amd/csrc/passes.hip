@@ -85,8 +85,12 @@ __device__ __forceinline__ void density_pair(DensAcc& a, bool ok, R xi, R yi, R 
     a.n += ok ? 1 : 0;
 }
 
+// waves per SIMD the register budget is held to: three work-groups of four
+// wavefronts per CU in FP32 (at most 168 VGPRs); FP64 is held to two by its LDS
+template <typename R> constexpr int kDensWaves = sizeof(R) == 4 ? 3 : 2;
+
 template <typename R>
-__global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sorted<R> so, GhostData<R> gd,
+__global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<R>))) void k_density(Decomp dc, CellData<R> cd, Sorted<R> so, GhostData<R> gd,
                                                  DensityOut out, PassConsts pc)
 {
     using R4 = typename Vec4T<R>::T;
@@ -178,8 +182,8 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
                         for (int t = 0;; t += 2) {
                             const bool v0 = act && t < n, v1 = act && t + 1 < n;
                             if (!__any(v0)) break;
-                            const int j0 = v0 ? (int)s.list[w][t][lane] : 0;
-                            const int j1 = v1 ? (int)s.list[w][t + 1][lane] : 0;
+                            const int j0 = v0 ? (int)s.list[w][lane][t] : 0;
+                            const int j1 = v1 ? (int)s.list[w][lane][t + 1] : 0;
                             const R4 e0 = s.st[w][j0], e1 = s.st[w][j1];
                             const uint32_t g0 = s.sg[w][j0], g1 = s.sg[w][j1];
                             const R4 q0 = cd.vm[g0], q1 = cd.vm[g1];
@@ -190,8 +194,8 @@ __global__ __launch_bounds__(WGS) void k_density(Decomp dc, CellData<R> cd, Sort
                         for (int t = 0;; t += 2) {
                             const bool v0 = act && t < n, v1 = act && t + 1 < n;
                             if (!__any(v0)) break;
-                            const int j0 = v0 ? (int)s.list[w][t][lane] : 0;
-                            const int j1 = v1 ? (int)s.list[w][t + 1][lane] : 0;
+                            const int j0 = v0 ? (int)s.list[w][lane][t] : 0;
+                            const int j1 = v1 ? (int)s.list[w][lane][t + 1] : 0;
                             const R4 e0 = s.st[w][j0], e1 = s.st[w][j1];
                             count_pair<R>(acc, v0, xi, yi, zi, hinv, h2, e0);
                             count_pair<R>(acc, v1, xi, yi, zi, hinv, h2, e1);
@@ -448,8 +452,11 @@ __device__ __forceinline__ void force_pair(ForceAcc<R>& a, bool ok, const ForceT
     a.ay += (double)(sc * dy);
     a.az += (double)(sc * dz);
     a.du += (double)pdu;
-    a.vsig = (ok && (qi < (R)1 || qj < (R)1)) ? fmax(a.vsig, vsig) : a.vsig;
-    a.n += ok ? 1 : 0;
+    // lists may hold a few pairs just outside both supports: they add nothing
+    // above (zero gradients) and are neither counted nor signal pairs
+    const bool in = ok && (qi < (R)1 || qj < (R)1);
+    a.vsig = in ? fmax(a.vsig, vsig) : a.vsig;
+    a.n += in ? 1 : 0;
 }
 
 template <typename R>
@@ -506,8 +513,8 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
                 for (int t = 0;; t += 2) {
                     const bool v0 = t < n, v1 = t + 1 < n;
                     if (!__any(v0)) break;
-                    const int j0 = v0 ? (int)s.list[w][t][lane] : 0;
-                    const int j1 = v1 ? (int)s.list[w][t + 1][lane] : 0;
+                    const int j0 = v0 ? (int)s.list[w][lane][t] : 0;
+                    const int j1 = v1 ? (int)s.list[w][lane][t + 1] : 0;
                     const uint32_t q0 = s.sg[w][j0], q1 = s.sg[w][j1];
                     const R4 e0 = s.st[w][j0], e1 = s.st[w][j1];
                     const R4 v0m = cd.vm[q0], v1m = cd.vm[q1];

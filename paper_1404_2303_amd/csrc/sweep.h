@@ -3,6 +3,8 @@
 // for the description of the work unit, the staging and the walk.
 #pragma once
 
+#include <limits>
+
 #include "sph_internal.h"
 #include "kernels.h"
 
@@ -22,7 +24,7 @@ constexpr int WALK_PAD = WALK_STEP - 1;
 // serve the Newton iteration, so they are longer)
 template <typename R, bool FORCE> struct PCfg;
 template <> struct PCfg<float, false> { static constexpr int CAPW = 256, LISTW = 48; };
-template <> struct PCfg<float, true> { static constexpr int CAPW = 256, LISTW = 32; };
+template <> struct PCfg<float, true> { static constexpr int CAPW = 224, LISTW = 32; };
 template <> struct PCfg<double, false> { static constexpr int CAPW = 256, LISTW = 48; };
 template <> struct PCfg<double, true> { static constexpr int CAPW = 256, LISTW = 32; };
 
@@ -78,18 +80,36 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// |x|^2 / 2 reduced by 32 units of rounding, for the in-range test of the walk:
+// with a_j and K_i from this, a_j + K_i - x_i . x_j evaluated by fused
+// multiply-adds stays below r_ij^2 / 2 (the three roundings of the dot product
+// and those of the two norms add up to less than the reduction), so the test
+// never drops a pair in range; the pair arithmetic then decides exactly.
+template <typename R> __device__ __forceinline__ R half_sq_lo(R x, R y, R z)
+{
+    constexpr R lo = (R)0.5 * ((R)1 - (R)32 * std::numeric_limits<R>::epsilon() / (R)2);
+    return (x * x + y * y + z * z) * lo;
+}
+
 // ---------------------------------------------------------------- LDS layout
 template <typename R, int NACC, bool STAGE_H>
 struct Smem {
     using R4 = typename Vec4T<R>::T;
     static constexpr int CAPW = PCfg<R, STAGE_H>::CAPW;
     static constexpr int LISTW = PCfg<R, STAGE_H>::LISTW;
-    // staged (x, y, z in T's frame, projection on the segment axis); the walk
-    // reads up to WALK_PAD entries past a segment's end (masked off)
+    // staged (x, y, z in T's frame, |x|^2 / 2 less its rounding allowance); the
+    // walk reads up to WALK_PAD entries past a segment's end (masked off)
     R4 st[NW][CAPW + WALK_PAD];
-    R sh[NW][STAGE_H ? CAPW + WALK_PAD : 1];  // pair range max(h_i, h_j): h^2 of each staged particle
+    R sh[NW][STAGE_H ? CAPW + WALK_PAD : 1];  // pair range max(h_i, h_j): h^2 / 2 of each staged particle
+    float sp[NW][CAPW + WALK_PAD];    // projection on the segment axis (the early exit)
     uint32_t sg[NW][CAPW];            // cell-order index of each staged particle
-    uint16_t list[NW][LISTW][kWave];  // per-lane neighbour lists (staged indices)
+    // per-lane neighbour lists (staged indices), each lane's slots contiguous;
+    // the row pitch is an odd number of dwords, so that the 64 lanes of a
+    // wavefront reading or writing slot t of their rows meet 64 distinct banks
+    static constexpr int LISTP = LISTW + 4;
+    static_assert(CAPW <= 256, "list entries are bytes");
+    static_assert(LISTW % 8 == 0, "odd dword pitch");
+    uint8_t list[NW][kWave][LISTP];
     double red[NACC][kWave];          // partial sums of the four wavefronts
     int seg_b[NW][kMaxSegW], seg_e[NW][kMaxSegW];
     float seg_u[NW][kMaxSegW][3];
@@ -153,9 +173,9 @@ __device__ void stage_wave(Smem<R, NACC, FORCE>& s, const int w, const Decomp& d
                 const int g = S.start + q0 + p + t;
                 R4 e;
                 e.x = cd.rx[g]; e.y = cd.ry[g]; e.z = cd.rz[g];
-                e.w = (R)0;
+                e.w = half_sq_lo(e.x, e.y, e.z);
                 s.st[w][fill + t] = e;
-                if constexpr (FORCE) { const R hj = gd.g1[g].z; s.sh[w][fill + t] = hj * hj; }
+                if constexpr (FORCE) { const R hj = gd.g1[g].z; s.sh[w][fill + t] = (R)0.5 * hj * hj; }
                 s.sg[w][fill + t] = (uint32_t)g;
             }
             if (lane == 0) { s.self_b[w] = fill; s.self_t0[w] = q0 + p; s.self_n[w] = take; }
@@ -193,10 +213,11 @@ __device__ void stage_wave(Smem<R, NACC, FORCE>& s, const int w, const Decomp& d
                     const int g = S.start + l;
                     R4 e;
                     e.x = cd.rx[g] + dox; e.y = cd.ry[g] + doy; e.z = cd.rz[g] + doz;
-                    // projection on the segment axis, recomputed from the shifted position
-                    e.w = (R)(u[0] * (float)e.x + u[1] * (float)e.y + u[2] * (float)e.z);
+                    e.w = half_sq_lo(e.x, e.y, e.z);
                     s.st[w][fill + lane] = e;
-                    if constexpr (FORCE) { const R hj = gd.g1[g].z; s.sh[w][fill + lane] = hj * hj; }
+                    // projection on the segment axis, recomputed from the shifted position
+                    s.sp[w][fill + lane] = u[0] * (float)e.x + u[1] * (float)e.y + u[2] * (float)e.z;
+                    if constexpr (FORCE) { const R hj = gd.g1[g].z; s.sh[w][fill + lane] = (R)0.5 * hj * hj; }
                     s.sg[w][fill + lane] = (uint32_t)g;
                 }
                 fill += take;
@@ -243,15 +264,31 @@ __device__ __forceinline__ double sq_max(double a, double b)
 }
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// p += 1 in the lanes of mask m, as one add with m as its carry-in (the
+// compiler otherwise selects 0 or 1 into a register and adds that)
+template <typename P> __device__ __forceinline__ void append(P& p, uint64_t m)
+{
+    uint64_t carry_out;
+    asm volatile("v_addc_co_u32_e64 %0, %1, 0, %0, %2" : "+v"(p), "=s"(carry_out) : "s"(m));
+}
+__device__ __forceinline__ uint64_t lanes(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
 // Walk of wavefront w over its staged segments, one segment at a time for
 // all lanes together: every lane reads the same staged particle (an LDS
-// broadcast), tests it against its own bound and radius, and appends it to
-// its list when in range.  The segment is left as soon as no lane is still
-// within its projected bound (the early exit of the sorted sweep).  The
-// walk state (seg, jj) is uniform and kept in scalar registers; four staged
-// particles are tested per step.  The call returns early when some lane's
-// list might overflow in the next step (lists hold at most LISTW entries),
-// and resumes from (seg, jj).
+// broadcast), tests it against its own radius, and appends it to its list
+// when in range.  The segment is left as soon as no lane is still within its
+// projected bound (the early exit of the sorted sweep).  The walk state
+// (seg, jj) is uniform and kept in scalar registers; four staged particles
+// are tested per step.  The call returns early when some lane's list might
+// overflow in the next step (lists hold at most LISTW entries), and resumes
+// from (seg, jj).
+//
+// The in-range test takes r^2 / 2 = K_i + a_j - x_i . x_j, with the halved
+// squared norms a_j (staged) and K_i (per lane) reduced by their rounding
+// allowance (half_sq_lo): three fused multiply-adds per candidate, never
+// below the exact r^2 / 2 by more than the allowance, so a list holds every
+// pair in range and possibly a few just outside, which the pair arithmetic
+// (its own tests of r against h) discards.
 template <typename R, bool FORCE, int NACC>
 __device__ __forceinline__ int walk(Smem<R, NACC, FORCE>& s, int w, int lane, bool act, R xi, R yi, R zi, float fxi,
                                     float fyi, float fzi, R rad, float fh, float margin, int selfj, int& seg_io,
@@ -260,76 +297,94 @@ __device__ __forceinline__ int walk(Smem<R, NACC, FORCE>& s, int w, int lane, bo
     constexpr int LISTW = Smem<R, NACC, FORCE>::LISTW;
     constexpr int STEP = WALK_STEP;
     const int nseg = uniform(s.nseg[w]);
-    const R rad2 = rad * rad;
+    // lane constants of the test: K_i, and the range (rad^2 / 2, rounded up)
+    const R ki = half_sq_lo(xi, yi, zi);
+    const R c_half = (R)0.5 * rad * rad * ((R)1 + (R)8 * std::numeric_limits<R>::epsilon());
+    const R d_half = c_half - ki;   // density: a_j - x_i . x_j < d_half
+    const uint64_t mact = lanes(act);
     int seg = uniform(seg_io);
     int jj = uniform(jj_io);
-    // list slots of this lane, kWave entries apart; wp is the next free one
-    // (an LDS pointer: 32-bit arithmetic, no address recomputation per entry)
-    using lds_u16 = __attribute__((address_space(3))) uint16_t;
-    lds_u16* const lst = (lds_u16*)&s.list[w][0][lane];
-    lds_u16* wp = lst + cnt * kWave;
-    lds_u16* const wfull = lst + (LISTW - STEP) * kWave;
+    // list slots of this lane; wp is the next free one (an LDS pointer: the
+    // append is one add of the hit flag, the pointer is the store address)
+    using lds_u8 = __attribute__((address_space(3))) uint8_t;
+    lds_u8* const lst = (lds_u8*)&s.list[w][lane][0];
+    lds_u8* wp = lst + cnt;
+    lds_u8* const wfull = lst + (LISTW - STEP);
     bool full = false;
+    // in range: r^2 < h_i^2, or (force) r^2 < max(h_i^2, h_j^2); both halved
+    // squares are >= 0, whose bit patterns order like their values (one integer max).
+    // A step reads its STEP staged particles before it writes any list slot:
+    // list entries are bytes, which may alias anything, so the reads could not
+    // be moved ahead of the writes by the compiler.
+    using R4 = typename Vec4T<R>::T;
+    auto test = [&](const R4& e, R hj2) {
+        if constexpr (FORCE) {
+            const R t = fma(-zi, e.z, fma(-yi, e.y, fma(-xi, e.x, e.w + ki)));
+            return t < sq_max(c_half, hj2);
+        } else {
+            const R t = fma(-zi, e.z, fma(-yi, e.y, fma(-xi, e.x, e.w)));
+            return t < d_half;
+        }
+    };
+    // one step over staged entries jj .. jj + STEP - 1 (past the segment end:
+    // any value, masked by j < je)
+    auto step = [&](int je, int jj, bool self) {
+        R4 e[STEP];
+        R hj2[STEP];
+#pragma unroll
+        for (int k = 0; k < STEP; k++) {
+            e[k] = s.st[w][jj + k];
+            hj2[k] = FORCE ? s.sh[w][FORCE ? jj + k : 0] : (R)0;
+        }
+        // hits as lane masks, combined in scalar registers
+        uint64_t hit[STEP];
+#pragma unroll
+        for (int k = 0; k < STEP; k++) {
+            const int j = jj + k;
+            hit[k] = lanes(test(e[k], hj2[k])) & (j < je ? mact : 0ull);
+            if (self) hit[k] &= lanes(j != selfj);
+        }
+#pragma unroll
+        for (int k = 0; k < STEP; k++) {
+            *wp = (uint8_t)(jj + k);  // the free slot; kept only on a hit
+            append(wp, hit[k]);
+        }
+    };
     while (seg < nseg) {
         const int je = uniform(s.seg_e[w][seg]);
         const float ux = s.seg_u[w][seg][0], uy = s.seg_u[w][seg][1], uz = s.seg_u[w][seg][2];
         const float hx = s.seg_hx[w][seg];
         // the self segment has u = 0; a uniform flag
         const bool self = uniform((ux == 0.0f) & (uy == 0.0f) & (uz == 0.0f)) != 0;
-        // in range: r^2 < h_i^2, or (force) r^2 < max(h_i^2, h_j^2); both squares are
-        // >= 0, whose bit patterns order like their values (one integer max)
-        auto test = [&](int j, bool& in) {
-            const auto e = s.st[w][j];  // past the segment end: any value, masked by the caller
-            const R dx = xi - e.x, dy = yi - e.y, dz = zi - e.z;
-            const R r2 = dx * dx + dy * dy + dz * dz;
-            if constexpr (FORCE) in = r2 < sq_max(rad2, s.sh[w][j]);
-            else in = r2 < rad2;
-            return (float)e.w;
-        };
         if (self) {
             // the whole self segment is within every bound; skip the target itself
             while (jj < je) {
                 if (wave_any(wp > wfull)) { full = true; break; }
-#pragma unroll
-                for (int k = 0; k < STEP; k++) {
-                    const int j = jj + k;
-                    bool in;
-                    (void)test(j, in);
-                    const bool hit = (j < je) & act & in & (j != selfj);
-                    *wp = (uint16_t)j;  // the free slot; kept only on a hit
-                    wp += hit ? kWave : 0;
-                }
+                step(je, jj, true);
                 jj += STEP;
             }
         } else {
             // stored order of projections that moved by up to d since: an entry
-            // beyond bound + 2d leaves every later one beyond bound
+            // beyond bound + 2d leaves every later one beyond bound.  A pair in
+            // range is within the bound, so only the exit reads projections.
             const float bound =
                 !act ? -INFINITY : ux * fxi + uy * fyi + uz * fzi + fmaxf(fh, hx) + margin + 2.0f * s.seg_dr[w][seg];
             while (jj < je) {
                 if (wave_any(wp > wfull)) { full = true; break; }
-                bool in_last = false;
-#pragma unroll
-                for (int k = 0; k < STEP; k++) {
-                    const int j = jj + k;
-                    bool in;
-                    const float p = test(j, in);
-                    const bool inb = (j < je) & (p <= bound);
-                    *wp = (uint16_t)j;
-                    wp += (inb & in) ? kWave : 0;
-                    if (k == STEP - 1) in_last = inb;
-                }
+                const int jl = jj + STEP - 1;
+                const uint64_t in_last = jl < je ? lanes(s.sp[w][jl] <= bound) : 0ull;
+                step(je, jj, false);
                 jj += STEP;
                 // projections grow along the segment: once the last entry of a step
                 // is beyond every lane's bound, so is the rest of the segment
-                if (!wave_any(in_last)) break;
+                if (in_last == 0) break;
             }
         }
         if (full) break;
         seg++;
         jj = seg < nseg ? uniform(s.seg_b[w][seg]) : 0;
     }
-    cnt = (int)(wp - lst) / kWave;
+    cnt = (int)(wp - lst);
     seg_io = seg;
     jj_io = jj;
     return cnt;
