@@ -91,6 +91,14 @@ template <typename R> __device__ __forceinline__ R half_sq_lo(R x, R y, R z)
     return (x * x + y * y + z * z) * lo;
 }
 
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// the value of lane l (uniform) of v
+__device__ __forceinline__ int lane_of(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ float lane_of(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
 // ---------------------------------------------------------------- LDS layout
 template <typename R, int NACC, bool STAGE_H>
 struct Smem {
@@ -141,6 +149,11 @@ __device__ void stage_wave(Smem<R, NACC, FORCE>& s, const int w, const Decomp& d
     int chunk = -1;
     Source my = {};
     uint64_t mask = 0;
+    // per lane, for its source of the chunk: the cell's range, staleness and
+    // (force) largest h, loaded for the whole chunk at once and broadcast
+    // from the source's lane when it is staged
+    int my_start = 0, my_count = 0;
+    float my_ds = 0.f, my_hx = 0.f;
     if (lane == 0) s.self_n[w] = 0;
     while (true) {
         if (k >= nsrc) { k = nsrc; p = 0; break; }
@@ -148,19 +161,25 @@ __device__ void stage_wave(Smem<R, NACC, FORCE>& s, const int w, const Decomp& d
             chunk = k & ~(kWave - 1);
             const bool in = chunk + lane < nsrc;
             my = in ? dc.src[soff + chunk + lane] : Source{};
-            mask = __ballot(in && (my.wave == w || my.wave == kAllWaves));
+            const bool mine = in && (my.wave == w || my.wave == kAllWaves);
+            mask = __ballot(mine);
+            if (mine) {
+                const CellInfo S = dc.cells[my.cell];
+                my_start = S.start;
+                my_count = S.count;
+                my_ds = key_dr(dc, my.cell);
+                if constexpr (FORCE) my_hx = gd.cell_hmax[my.cell];
+            }
         }
         const uint64_t m = mask & (~0ull << (k - chunk));
         if (m == 0) { k = chunk + kWave; p = 0; continue; }
         k = chunk + __builtin_ctzll(m);
         if (nseg == kMaxSegW || fill >= CAPW) break;
-        const int sl = k - chunk;
-        const int scell = __shfl(my.cell, sl, 64);
-        const int sdir = __shfl((int)my.dir, sl, 64);
-        const int sox = __shfl((int)my.ox, sl, 64), soy = __shfl((int)my.oy, sl, 64),
-                  soz = __shfl((int)my.oz, sl, 64);
+        const int sl = uniform(k - chunk);
+        const int sdir = lane_of((int)my.dir, sl);
+        const int sox = lane_of((int)my.ox, sl), soy = lane_of((int)my.oy, sl), soz = lane_of((int)my.oz, sl);
         const bool self = sdir == kSelfDir;
-        const CellInfo S = dc.cells[scell];
+        struct { int start, count; } S = {lane_of(my_start, sl), lane_of(my_count, sl)};
         const int segb = fill;
         bool complete = true;
         float u[3] = {0.f, 0.f, 0.f};
@@ -190,8 +209,8 @@ __device__ void stage_wave(Smem<R, NACC, FORCE>& s, const int w, const Decomp& d
             const R dox = (R)dxo, doy = (R)dyo, doz = (R)dzo;
             const float udo = u[0] * (float)dxo + u[1] * (float)dyo + u[2] * (float)dzo;
             float hs = Hst;
-            if (FORCE) { hx = gd.cell_hmax[scell]; hs = fmaxf(Hst, hx); }
-            ds = key_dr(dc, scell);
+            if (FORCE) { hx = lane_of(my_hx, sl); hs = fmaxf(Hst, hx); }
+            ds = lane_of(my_ds, sl);
             const float reach = fmaxf(u[0], 0.f) * et[0] + fmaxf(u[1], 0.f) * et[1] + fmaxf(u[2], 0.f) * et[2] +
                                 hs + margin + ds;
             const int64_t sbase = (int64_t)sd * dc.n + S.start;
@@ -262,8 +281,6 @@ __device__ __forceinline__ double sq_max(double a, double b)
     return __longlong_as_double((long long)max((unsigned long long)__double_as_longlong(a),
                                                (unsigned long long)__double_as_longlong(b)));
 }
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
 // p += 1 in the lanes of mask m, as one add with m as its carry-in (the
 // compiler otherwise selects 0 or 1 into a register and adds that)
 template <typename P> __device__ __forceinline__ void append(P& p, uint64_t m)
