@@ -40,8 +40,14 @@
 namespace sph {
 // ---------------------------------------------------------------- density
 struct DensAcc {
-    double w, qdw, mw, mqdw, div, cx, cy, cz;
+    double w, qdw;
     int n;
+};
+// the mass-weighted sums of one pass over a list, in the pair precision:
+// added to the FP64 totals once per list (at most LISTW pairs)
+template <typename R>
+struct DensPart {
+    R mw, mqdw, div, cx, cy, cz;
 };
 
 // Newton evaluation: the two sums of Eq. (3) (N and dN/dh need w and q w')
@@ -61,7 +67,7 @@ __device__ __forceinline__ void count_pair(DensAcc& a, bool ok, R xi, R yi, R zi
 // All density-stage terms of one pair: Eq. (2), Eq. (3), d rho/dh and the
 // velocity divergence and curl of Sec. 4.1 (gradient prefactor applied later)
 template <typename R>
-__device__ __forceinline__ void density_pair(DensAcc& a, bool ok, R xi, R yi, R zi, R vxi, R vyi, R vzi, R h,
+__device__ __forceinline__ void density_pair(DensAcc& a, DensPart<R>& b, bool ok, R xi, R yi, R zi, R vxi, R vyi, R vzi, R h,
                                              R hinv, R h2, typename Vec4T<R>::T e, typename Vec4T<R>::T vm)
 {
     const R dx = xi - e.x, dy = yi - e.y, dz = zi - e.z;
@@ -76,18 +82,19 @@ __device__ __forceinline__ void density_pair(DensAcc& a, bool ok, R xi, R yi, R 
     const R qdw = q * dw;
     a.w += (double)(ok ? w : (R)0);
     a.qdw += (double)(ok ? qdw : (R)0);
-    a.mw += (double)(mj * w);
-    a.mqdw += (double)(mj * qdw);
-    a.div += (double)(mg * (dvx * dx + dvy * dy + dvz * dz));
-    a.cx += (double)(mg * (dvy * dz - dvz * dy));
-    a.cy += (double)(mg * (dvz * dx - dvx * dz));
-    a.cz += (double)(mg * (dvx * dy - dvy * dx));
+    b.mw += mj * w;
+    b.mqdw += mj * qdw;
+    b.div += mg * (dvx * dx + dvy * dy + dvz * dz);
+    b.cx += mg * (dvy * dz - dvz * dy);
+    b.cy += mg * (dvz * dx - dvx * dz);
+    b.cz += mg * (dvx * dy - dvy * dx);
     a.n += ok ? 1 : 0;
 }
 
-// waves per SIMD the register budget is held to: three work-groups of four
-// wavefronts per CU in FP32 (at most 168 VGPRs); FP64 is held to two by its LDS
-template <typename R> constexpr int kDensWaves = sizeof(R) == 4 ? 3 : 2;
+// waves per SIMD the register budget is held to: four work-groups of four
+// wavefronts per CU in FP32 (at most 128 VGPRs, with the LDS of a work-group
+// under 40 KiB); FP64 is held to two by its LDS
+template <typename R> constexpr int kDensWaves = sizeof(R) == 4 ? 4 : 2;
 
 template <typename R>
 __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<R>))) void k_density(Decomp dc, CellData<R> cd, Sorted<R> so, GhostData<R> gd,
@@ -179,16 +186,26 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
                 const R hr = (R)h, hinv = (R)(1.0 / h), h2 = hr * hr;
                 auto process = [&](int n) {
                     if (full) {
+                        DensPart<R> b = {};
                         for (int t = 0;; t += 2) {
                             const bool v0 = act && t < n, v1 = act && t + 1 < n;
                             if (!__any(v0)) break;
                             const int j0 = v0 ? (int)s.list[w][lane][t] : 0;
                             const int j1 = v1 ? (int)s.list[w][lane][t + 1] : 0;
                             const R4 e0 = s.st[w][j0], e1 = s.st[w][j1];
-                            const uint32_t g0 = s.sg[w][j0], g1 = s.sg[w][j1];
-                            const R4 q0 = cd.vm[g0], q1 = cd.vm[g1];
-                            density_pair<R>(acc, v0, xi, yi, zi, vmi.x, vmi.y, vmi.z, hr, hinv, h2, e0, q0);
-                            density_pair<R>(acc, v1, xi, yi, zi, vmi.x, vmi.y, vmi.z, hr, hinv, h2, e1, q1);
+                            const R4 q0 = cd.vm[s.sg[w][j0]], q1 = cd.vm[s.sg[w][j1]];
+                            density_pair<R>(acc, b, v0, xi, yi, zi, vmi.x, vmi.y, vmi.z, hr, hinv, h2, e0, q0);
+                            density_pair<R>(acc, b, v1, xi, yi, zi, vmi.x, vmi.y, vmi.z, hr, hinv, h2, e1, q1);
+                        }
+                        // into the FP64 totals of the four wavefronts (cleared before
+                        // the evaluation); nothing of them stays in registers
+                        if (act) {
+                            atomicAdd(&s.red[2][lane], (double)b.mw);
+                            atomicAdd(&s.red[3][lane], (double)b.mqdw);
+                            atomicAdd(&s.red[4][lane], (double)b.div);
+                            atomicAdd(&s.red[5][lane], (double)b.cx);
+                            atomicAdd(&s.red[6][lane], (double)b.cy);
+                            atomicAdd(&s.red[7][lane], (double)b.cz);
                         }
                     } else {
                         for (int t = 0;; t += 2) {
@@ -261,12 +278,6 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
                     if (on) {
                         atomicAdd(&s.red[0][lane], acc.w);
                         atomicAdd(&s.red[1][lane], acc.qdw);
-                        atomicAdd(&s.red[2][lane], acc.mw);
-                        atomicAdd(&s.red[3][lane], acc.mqdw);
-                        atomicAdd(&s.red[4][lane], acc.div);
-                        atomicAdd(&s.red[5][lane], acc.cx);
-                        atomicAdd(&s.red[6][lane], acc.cy);
-                        atomicAdd(&s.red[7][lane], acc.cz);
                         atomicAdd(&s.red[8][lane], (double)acc.n);
                     }
                     __syncthreads();
@@ -353,7 +364,7 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
                 cell_hmax = fmaxf(cell_hmax, (float)hh * (1.0f + 1e-6f));
             }
             if (w == 0 && on) {
-                DensAcc tot;
+                struct { double w, qdw, mw, mqdw, div, cx, cy, cz, n; } tot;
                 tot.w = s.red[0][lane]; tot.qdw = s.red[1][lane]; tot.mw = s.red[2][lane];
                 tot.mqdw = s.red[3][lane]; tot.div = s.red[4][lane]; tot.cx = s.red[5][lane];
                 tot.cy = s.red[6][lane]; tot.cz = s.red[7][lane]; tot.n = s.red[8][lane];
