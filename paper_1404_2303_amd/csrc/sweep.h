@@ -24,7 +24,7 @@ constexpr int WALK_PAD = WALK_STEP - 1;
 // serve the Newton iteration, so they are longer)
 template <typename R, bool FORCE> struct PCfg;
 template <> struct PCfg<float, false> { static constexpr int CAPW = 192, LISTW = 48; };
-template <> struct PCfg<float, true> { static constexpr int CAPW = 224, LISTW = 32; };
+template <> struct PCfg<float, true> { static constexpr int CAPW = 216, LISTW = 32; };
 template <> struct PCfg<double, false> { static constexpr int CAPW = 256, LISTW = 48; };
 template <> struct PCfg<double, true> { static constexpr int CAPW = 256, LISTW = 32; };
 
