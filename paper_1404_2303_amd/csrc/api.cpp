@@ -49,6 +49,7 @@ struct sph_ctx {
     // workspace
     DBuf boxes, keys, keys2, vals, vals2, rs_scratch, flag, cellx, cell_of, sc_scratch;
     DBuf cells, ncells, cell_map, src, src_count, srec;
+    DBuf big_cells;                                  // count, then the cells the wavefront sort leaves
     DBuf rx, ry, rz, h, vm, u;                       // cell order
     DBuf r0;                                         // cell-relative positions at the last build
     DBuf cell_drift;                                 // largest displacement per cell since that build
@@ -209,6 +210,7 @@ static bool ensure_particles(sph_ctx* c, int64_t n)
     ok &= c->flag.ensure(N * 4) && c->cellx.ensure(N * 4) && c->cell_of.ensure(N * 4);
     ok &= c->sc_scratch.ensure(scan_scratch_words((int64_t)N) * 4 + 16);
     ok &= c->cells.ensure(N * sizeof(CellInfo)) && c->ncells.ensure(16);
+    ok &= c->big_cells.ensure((N / 256 + 2) * 4);
     // interaction lists: 27 per cell on the single-level grid; on the hierarchy
     // a bound per particle (exceeding it sets SPH_E_CAPACITY)
     c->src_cap = (int64_t)N * (c->depth > 0 ? kTreeSourcesPerParticle : kMaxSources);
@@ -322,7 +324,7 @@ sph_status sph_destroy(sph_ctx* c)
 {
     if (!c) return SPH_OK;
     DBuf* all[] = {&c->boxes, &c->keys, &c->keys2, &c->vals, &c->vals2, &c->rs_scratch, &c->flag,
-                   &c->cellx, &c->cell_of, &c->sc_scratch, &c->cells, &c->ncells, &c->cell_map,
+                   &c->cellx, &c->cell_of, &c->sc_scratch, &c->cells, &c->ncells, &c->big_cells, &c->cell_map,
                    &c->src, &c->src_count, &c->srec, &c->r0, &c->cell_drift, &c->rx, &c->ry, &c->rz, &c->h,
                    &c->vm, &c->u, &c->g0, &c->g1, &c->cell_hmax, &c->qhead, &c->status, &c->step_tmp, &c->dt_box, &c->dt_min, &c->t_box, &c->mts_active, &c->mts_rho, &c->mts_A,
                    &c->mts_c, &c->mts_f, &c->mts_count, &c->mts_units, &c->mts_flag,
@@ -616,10 +618,12 @@ sph_status sph_sort(sph_ctx* c, void* stream)
         ev_record(c, EV_SORT0, st);
         if (c->prm.precision == SPH_FP64)
             launch_sort13<double>(c->cells.as<CellInfo>(), c->ncells.as<int32_t>(), cell_data<double>(c), c->n,
-                                  sorted_data<double>(c), c->status.as<uint32_t>(), c->n, st);
+                                  sorted_data<double>(c), c->big_cells.as<int32_t>(), c->status.as<uint32_t>(),
+                                  c->n, st);
         else
             launch_sort13<float>(c->cells.as<CellInfo>(), c->ncells.as<int32_t>(), cell_data<float>(c), c->n,
-                                 sorted_data<float>(c), c->status.as<uint32_t>(), c->n, st);
+                                 sorted_data<float>(c), c->big_cells.as<int32_t>(), c->status.as<uint32_t>(),
+                                 c->n, st);
         ev_record(c, EV_SORT1, st);
     }
     if (hipGetLastError() != hipSuccess) return SPH_E_HIP;

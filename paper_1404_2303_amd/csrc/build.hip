@@ -71,7 +71,8 @@ __global__ __launch_bounds__(BS_THREADS) void k_box_scan(Particles p, BoxInfo* b
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < BS_THREADS / kWave; w++) hm = fmax(hm, red[w]);
-        if (hm > 0.0)
+        // most blocks of a box find no larger h than one already merged
+        if (hm > 0.0 && hm > *(volatile double*)&boxes[b0].hmax)
             atomicMax((unsigned long long*)&boxes[b0].hmax, (unsigned long long)__double_as_longlong(hm));
     }
 }
@@ -629,10 +630,14 @@ __device__ __forceinline__ void sort13_cell(const CellInfo& C, const CellData<R>
     }
 }
 
-// Cells of at most kWaveSortMax particles: one wavefront per cell.
+__global__ void k_zero_first(int32_t* a) { a[0] = 0; }
+
+// Cells of at most kWaveSortMax particles: one wavefront per cell.  The
+// larger ones are listed for k_sort13: big[0] counts them (zero on entry),
+// big[1..] holds them.
 template <typename R>
 __global__ __launch_bounds__(kWave) void k_sort13_wave(const CellInfo* cells, const int32_t* ncells, CellData<R> cd,
-                                                       int64_t n, Sorted<R> so)
+                                                       int64_t n, Sorted<R> so, int32_t* big)
 {
     const int lane = threadIdx.x;
     const int nc = *ncells;
@@ -641,23 +646,23 @@ __global__ __launch_bounds__(kWave) void k_sort13_wave(const CellInfo* cells, co
         if (C.count <= kWave) sort13_cell<R, 1>(C, cd, n, so, lane);
         else if (C.count <= 2 * kWave) sort13_cell<R, 2>(C, cd, n, so, lane);
         else if (C.count <= kWaveSortMax) sort13_cell<R, 4>(C, cd, n, so, lane);
+        else if (lane == 0) big[1 + atomicAdd(&big[0], 1)] = c;
     }
 }
 
 // Larger cells: one workgroup per (cell, direction); each particle's rank is
 // the number of particles with a smaller key, ties broken by cell order.
 template <typename R>
-__global__ __launch_bounds__(SORT_THREADS) void k_sort13(const CellInfo* cells, const int32_t* ncells,
+__global__ __launch_bounds__(SORT_THREADS) void k_sort13(const CellInfo* cells, const int32_t* big,
                                                          CellData<R> cd, int64_t n, Sorted<R> so,
                                                          uint32_t* status)
 {
     __shared__ uint32_t key[SORT_MAX];
-    const int64_t units = (int64_t)(*ncells) * kSortDirs;
+    const int64_t units = (int64_t)big[0] * kSortDirs;  // the cells k_sort13_wave left
     for (int64_t unit = blockIdx.x; unit < units; unit += gridDim.x) {
-        const int c = (int)(unit / kSortDirs);
+        const int c = big[1 + (int)(unit / kSortDirs)];
         const int s = (int)(unit % kSortDirs);
         const CellInfo C = cells[c];
-        if (C.count <= kWaveSortMax) continue;  // sorted by k_sort13_wave
         if (C.count > SORT_MAX) { if (threadIdx.x == 0) atomicOr(status, ST_CAPACITY); continue; }
         float su[3];
         dir_unit(s + 13, su);
@@ -692,7 +697,7 @@ void launch_box_scan(const Particles& p, BoxInfo* boxes, int nbox, int64_t n, ui
     hipLaunchKernelGGL(k_clear_boxes, dim3((nbox + 255) / 256), dim3(256), 0, st, boxes, nbox);
     if (n > 0) {
         int64_t nb = (n + BS_THREADS - 1) / BS_THREADS;
-        if (nb > 1024) nb = 1024;
+        if (nb > 4096) nb = 4096;
         int64_t chunk = (n + nb - 1) / nb;
         nb = (n + chunk - 1) / chunk;
         hipLaunchKernelGGL(k_box_scan, dim3((unsigned)nb), dim3(BS_THREADS), 0, st, p, boxes, nbox, n, chunk,
@@ -827,19 +832,20 @@ void launch_sources(const CellInfo* cells, const int32_t* ncells, const BoxInfo*
 
 template <typename R>
 void launch_sort13(const CellInfo* cells, const int32_t* ncells, const CellData<R>& cd, int64_t n,
-                   const Sorted<R>& so, uint32_t* status, int64_t cell_cap, hipStream_t st)
+                   const Sorted<R>& so, int32_t* big, uint32_t* status, int64_t cell_cap, hipStream_t st)
 {
+    hipLaunchKernelGGL(k_zero_first, dim3(1), dim3(1), 0, st, big);
     unsigned gw = (unsigned)(cell_cap < 65536 ? cell_cap : 65536);
     if (gw < 1) gw = 1;
-    hipLaunchKernelGGL(k_sort13_wave<R>, dim3(gw), dim3(kWave), 0, st, cells, ncells, cd, n, so);
-    int64_t units = cell_cap * kSortDirs;
-    unsigned grid = (unsigned)(units < 65536 ? units : 65536);
-    if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_sort13<R>, dim3(grid), dim3(SORT_THREADS), 0, st, cells, ncells, cd, n, so, status);
+    hipLaunchKernelGGL(k_sort13_wave<R>, dim3(gw), dim3(kWave), 0, st, cells, ncells, cd, n, so, big);
+    // at most n / (kWaveSortMax + 1) cells are left; the grid strides over them
+    const int64_t units = (cell_cap / (kWaveSortMax + 1) + 1) * kSortDirs;
+    const unsigned grid = (unsigned)(units < 2048 ? units : 2048);
+    hipLaunchKernelGGL(k_sort13<R>, dim3(grid), dim3(SORT_THREADS), 0, st, cells, big, cd, n, so, status);
 }
 template void launch_sort13<float>(const CellInfo*, const int32_t*, const CellData<float>&, int64_t,
-                                   const Sorted<float>&, uint32_t*, int64_t, hipStream_t);
+                                   const Sorted<float>&, int32_t*, uint32_t*, int64_t, hipStream_t);
 template void launch_sort13<double>(const CellInfo*, const int32_t*, const CellData<double>&, int64_t,
-                                    const Sorted<double>&, uint32_t*, int64_t, hipStream_t);
+                                    const Sorted<double>&, int32_t*, uint32_t*, int64_t, hipStream_t);
 
 }  // namespace sph

@@ -141,7 +141,7 @@ void launch_sources(const CellInfo* cells, const int32_t* ncells, const BoxInfo*
                     int64_t cell_cap, hipStream_t st);
 template <typename R>
 void launch_sort13(const CellInfo* cells, const int32_t* ncells, const CellData<R>& cd, int64_t n,
-                   const Sorted<R>& so, uint32_t* status, int64_t cell_cap, hipStream_t st);
+                   const Sorted<R>& so, int32_t* big, uint32_t* status, int64_t cell_cap, hipStream_t st);
 
 // tree.hip -- hierarchical decomposition below the top grid
 struct TreeView {
