@@ -558,49 +558,93 @@ __device__ inline uint32_t float_key(float f)
 }
 __device__ inline float key_float(uint32_t k) { return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k); }
 
-// Bitonic sort across one wavefront of 64 E keys, key i held by lane i % 64
-// in slot i / 64: exchanges at distances below 64 go through lane shuffles,
-// longer ones between the slots of a lane.  Ascending on return.
-template <int E>
-__device__ __forceinline__ void wave_bitonic(uint64_t (&v)[E], const int lane)
+// Bitonic sort across one wavefront of 64 E 32-bit words, word i held by
+// lane i % 64 in slot i / 64, ascending on return.  The network is the form
+// whose first stage of every merge of size kk pairs i with i ^ (kk - 1) (the
+// mirror image in its block) and whose later stages pair i with i ^ j; every
+// comparator leaves the smaller word at the lower index, so a lane's choice
+// depends on one bit of its index only.
+
+// the value held by lane (lane ^ M), M < 64: data-parallel-primitive moves
+// inside a row of 16 lanes where the pattern allows (xor 1, 2, 3 by quad
+// permutes, 7 and 15 by the row half-mirror and mirror, 4 and 8 by two
+// shifts, each writing the banks of four lanes that read in its direction),
+// a lane permute otherwise
+template <int M>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v)
 {
+    const int x = (int)v;
+    if constexpr (M == 0) return v;
+    else if constexpr (M == 1) return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false);   // quad [1,0,3,2]
+    else if constexpr (M == 2) return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false);   // quad [2,3,0,1]
+    else if constexpr (M == 3) return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x1B, 0xF, 0xF, false);   // quad [3,2,1,0]
+    else if constexpr (M == 7) return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, false);  // row half-mirror
+    else if constexpr (M == 15) return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, false); // row mirror
+    else if constexpr (M == 4 || M == 8) {
+        // banks whose lanes have bit M clear read lane + M (row shift left),
+        // the others lane - M (row shift right)
+        constexpr int lo = M == 4 ? 0x5 : 0x3;
+        const int t = __builtin_amdgcn_update_dpp(x, x, 0x100 + M, 0xF, lo, false);
+        return (uint32_t)__builtin_amdgcn_update_dpp(t, x, 0x110 + M, 0xF, 0xF ^ lo, false);
+    } else {
+        return (uint32_t)__shfl_xor(x, M, kWave);
+    }
+}
+
+// stage I of the network over 64 E words: its partner mask m and the index
+// bit hb that marks the upper element of a pair
+__host__ __device__ constexpr int net_size(int E) { int n = 0; for (int kk = 2; kk <= 64 * E; kk <<= 1) for (int j = kk; j > 1; j >>= 1) n++; return n; }
+__host__ __device__ constexpr int net_stage(int E, int I, bool want_hb)
+{
+    int i = 0;
+    for (int kk = 2; kk <= 64 * E; kk <<= 1) {
+        if (i++ == I) return want_hb ? kk / 2 : kk - 1;
+        for (int j = kk / 4; j >= 1; j >>= 1)
+            if (i++ == I) return j;
+    }
+    return 0;
+}
+
+template <int E, int M, int HB>
+__device__ __forceinline__ void net_step(uint32_t (&v)[E], const int lane)
+{
+    if constexpr (HB >= kWave) {
+        // pairs across slots (e, e ^ (M >> 6)), lanes mirrored when M's low bits are set
+        uint32_t q[E];
 #pragma unroll
-    for (int kk = 2; kk <= kWave * E; kk <<= 1) {
+        for (int e = 0; e < E; e++) q[e] = lane_xor<(M & (kWave - 1))>(v[e ^ (M >> 6)]);
 #pragma unroll
-        for (int j = kk >> 1; j > 0; j >>= 1) {
-            if (j >= kWave) {
-                const int js = j / kWave;
+        for (int e = 0; e < E; e++) v[e] = ((e * kWave) & HB) == 0 ? min(v[e], q[e]) : max(v[e], q[e]);
+    } else {
+        const bool low = (lane & HB) == 0;
 #pragma unroll
-                for (int e = 0; e < E; e++) {
-                    const int f = e ^ js;
-                    if (f > e) {
-                        const bool up = (((e * kWave + lane) & kk) == 0);
-                        const uint64_t a = v[e], b = v[f];
-                        const bool sw = up ? (a > b) : (a < b);
-                        v[e] = sw ? b : a;
-                        v[f] = sw ? a : b;
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int e = 0; e < E; e++) {
-                    const uint64_t o = __shfl_xor(v[e], j, kWave);
-                    const bool keep_min = ((lane & j) == 0) == (((e * kWave + lane) & kk) == 0);
-                    v[e] = keep_min ? (o < v[e] ? o : v[e]) : (o > v[e] ? o : v[e]);
-                }
-            }
+        for (int e = 0; e < E; e++) {
+            const uint32_t q = lane_xor<M>(v[e]);
+            v[e] = low ? min(v[e], q) : max(v[e], q);
         }
     }
 }
 
+template <int E, int I = 0>
+__device__ __forceinline__ void wave_bitonic(uint32_t (&v)[E], const int lane)
+{
+    if constexpr (I < net_size(E)) {
+        net_step<E, net_stage(E, I, false), net_stage(E, I, true)>(v, lane);
+        wave_bitonic<E, I + 1>(v, lane);
+    }
+}
+
 // The 13 orderings of one cell of at most 64 E particles by one wavefront:
-// every particle's position is loaded once, and for each direction the keys
-// (projection, cell index) are sorted with a bitonic network (ties keep the
-// cell order).
+// every particle's position is loaded once, and for each direction the
+// order-preserving image of the projection, with its low bits replaced by the
+// particle's index in the cell, is sorted.  The stored key is that image with
+// the index bits cleared: the projection rounded down by less than 2^-15 of
+// its magnitude, and monotone along the ordering (ties keep the cell order).
 template <typename R, int E>
 __device__ __forceinline__ void sort13_cell(const CellInfo& C, const CellData<R>& cd, int64_t n,
                                             const Sorted<R>& so, const int lane)
 {
+    constexpr uint32_t IDX = 64u * E - 1u;  // index bits
     R x[E], y[E], z[E];
 #pragma unroll
     for (int e = 0; e < E; e++) {
@@ -611,21 +655,20 @@ __device__ __forceinline__ void sort13_cell(const CellInfo& C, const CellData<R>
     for (int s = 0; s < kSortDirs; s++) {
         float su[3];
         dir_unit(s + 13, su);
-        uint64_t v[E];
+        uint32_t v[E];
 #pragma unroll
         for (int e = 0; e < E; e++) {
             const int t = e * kWave + lane;
             const float f = su[0] * (float)x[e] + su[1] * (float)y[e] + su[2] * (float)z[e];
-            v[e] = t < C.count ? (((uint64_t)float_key(f) << 32) | (uint32_t)t) : ~0ull;
+            v[e] = t < C.count ? ((float_key(f) & ~IDX) | (uint32_t)t) : ~0u;
         }
         wave_bitonic<E>(v, lane);
-        // slot e of this lane now holds the element of rank e * 64 + lane
+        // slot e of this lane now holds the word of rank e * 64 + lane
 #pragma unroll
         for (int e = 0; e < E; e++) {
             const int r = e * kWave + lane;
             if (r < C.count)
-                so.rec[(int64_t)s * n + C.start + r] = SortRec{key_float((uint32_t)(v[e] >> 32)),
-                                                               (uint32_t)(v[e] & 0xffffffffu)};
+                so.rec[(int64_t)s * n + C.start + r] = SortRec{key_float(v[e] & ~IDX), v[e] & IDX};
         }
     }
 }

@@ -223,7 +223,9 @@ __device__ void stage_wave(Smem<R, NACC, FORCE>& s, const int w, const Decomp& d
                     const SortRec r = so.rec[sbase + idx];
                     l = (int)r.idx;
                     const float proj = (flip ? -r.key : r.key) + udo;
-                    ok = proj <= reach;
+                    // a stored key may be its projection rounded down by less
+                    // than 2^-15 of its magnitude (flipped: rounded up)
+                    ok = proj <= reach + 0x1p-14f * fabsf(r.key);
                 }
                 const int cnt = __popcll(__ballot(ok));  // the keys are monotone: a prefix
                 const int take = min(cnt, CAPW - fill);

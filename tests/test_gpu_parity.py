@@ -90,7 +90,7 @@ def test_tiny_three_cells_per_dimension():
     compare(g, ref, "fp64", label="tiny")
 
 
-@pytest.mark.parametrize("cell_target", [16, 200, 1000])
+@pytest.mark.parametrize("cell_target", [16, 100, 200, 1000])
 def test_decomposition_invariance(cell_target):
     """Cell size changes which loop finds a pair, never the result."""
     ps = workloads.uniform(6000, seed=9, sigma_v=0.3)
@@ -102,6 +102,19 @@ def test_decomposition_invariance(cell_target):
     assert np.allclose(base["rho"], other["rho"], rtol=1e-11, atol=0)
     ka = np.max(np.abs(base["a"]))
     assert np.max(np.abs(base["a"] - other["a"])) <= 1e-9 * ka
+
+
+@pytest.mark.parametrize("n,cell_target,lo,hi", [(40000, 100, 64, 128), (6000, 200, 128, 256)])
+def test_large_cells_fp32(n, cell_target, lo, hi):
+    """Cells of 65..128 and 129..256 particles on average: the orderings of two
+    and four words per lane of the wavefront sort (keys rounded down below
+    their index bits)."""
+    ps = workloads.uniform(n, seed=10, sigma_v=0.3)
+    g = gpu_run(ps, "fp32", cell_target=cell_target)
+    mean = ps.n / g["stats"]["n_cells"]
+    log(f"case large cells fp32 n={n} cell_target={cell_target}: {g['stats']['n_cells']} cells, mean {mean:.0f}")
+    assert lo < mean <= hi
+    compare(g, oracle_run(ps), "fp32", label=f"cells {cell_target}")
 
 
 def test_momentum_and_energy_conservation_gpu():
