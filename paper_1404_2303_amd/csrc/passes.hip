@@ -50,18 +50,32 @@ struct DensPart {
     R mw, mqdw, div, cx, cy, cz;
 };
 
-// Newton evaluation: the two sums of Eq. (3) (N and dN/dh need w and q w')
+// w(q) and q w'(q) of the kernel of Sec. 2.1 from shared terms, t = 1 - q:
+// w = 1 - 6 q^2 t and q w' = 6 q^2 (3q - 2) for q <= 1/2, w = 2 t^3 and
+// q w' = -6 q t^2 above (callers mask q >= 1)
 template <typename R>
-__device__ __forceinline__ void count_pair(DensAcc& a, bool ok, R xi, R yi, R zi, R hinv, R h2,
+__device__ __forceinline__ void kern_w_qdw(R q, R& w, R& qdw)
+{
+    const R t = (R)1 - q, q2 = q * q, t2 = t * t;
+    const bool in = q <= (R)0.5;
+    w = in ? fma((R)-6 * q2, t, (R)1) : (R)2 * t2 * t;
+    qdw = in ? (R)6 * q2 * fma((R)3, q, (R)-2) : (R)-6 * q * t2;
+}
+
+// Newton evaluation: the two sums of Eq. (3) (N and dN/dh need w and q w'),
+// into partial sums of one list in the pair precision
+template <typename R>
+__device__ __forceinline__ void count_pair(R& sw, R& sq, bool ok, R xi, R yi, R zi, R hinv, R h2,
                                            typename Vec4T<R>::T e)
 {
     const R dx = xi - e.x, dy = yi - e.y, dz = zi - e.z;
     const R r2 = dx * dx + dy * dy + dz * dz;
     ok = ok && r2 < h2;
     const R q = fast_sqrt(r2) * hinv;
-    const R w = ok ? kern_w(q) : (R)0, qdw = ok ? q * kern_dw(q) : (R)0;
-    a.w += (double)w;
-    a.qdw += (double)qdw;
+    R w, qdw;
+    kern_w_qdw(q, w, qdw);
+    sw += ok ? w : (R)0;
+    sq += ok ? qdw : (R)0;
 }
 
 // All density-stage terms of one pair: Eq. (2), Eq. (3), d rho/dh and the
@@ -75,11 +89,16 @@ __device__ __forceinline__ void density_pair(DensAcc& a, DensPart<R>& b, bool ok
     ok = ok && r2 < h2;
     const R rinv = r2 > (R)0 ? fast_rsqrt(r2) : (R)0;
     const R q = r2 * rinv * hinv;
-    const R w = kern_w(q), dw = kern_dw(q), gq = kern_g(q, h * rinv);
+    // the kernel without branches, t = 1 - q, u = max(1 - 2q, 0): w = 2 t^3 - u^3,
+    // g = w'/q = -6 (u + t) min(1, t/q), which is 18q - 12 for q <= 1/2 and
+    // -6 t^2 / q above (zero at r = 0, where the pair adds nothing anyway)
+    const R t = (R)1 - q, u = fmax(fma((R)-2, q, (R)1), (R)0);
+    const R w = fma((R)2 * t * t, t, -(u * u * u));
+    const R gq = (R)-6 * (u + t) * fmin((R)1, t * (h * rinv));
+    const R qdw = gq * q * q;
     const R mj = ok ? vm.w : (R)0;  // masked pairs contribute nothing
     const R dvx = vm.x - vxi, dvy = vm.y - vyi, dvz = vm.z - vzi;
     const R mg = mj * gq;
-    const R qdw = q * dw;
     a.w += (double)(ok ? w : (R)0);
     a.qdw += (double)(ok ? qdw : (R)0);
     b.mw += mj * w;
@@ -208,15 +227,19 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
                             atomicAdd(&s.red[7][lane], (double)b.cz);
                         }
                     } else {
+                        // partial sums of this list (at most LISTW terms), then FP64
+                        R sw = (R)0, sq = (R)0;
                         for (int t = 0;; t += 2) {
                             const bool v0 = act && t < n, v1 = act && t + 1 < n;
-                            if (!__any(v0)) break;
-                            const int j0 = v0 ? (int)s.list[w][lane][t] : 0;
-                            const int j1 = v1 ? (int)s.list[w][lane][t + 1] : 0;
-                            const R4 e0 = s.st[w][j0], e1 = s.st[w][j1];
-                            count_pair<R>(acc, v0, xi, yi, zi, hinv, h2, e0);
-                            count_pair<R>(acc, v1, xi, yi, zi, hinv, h2, e1);
+                            if (lanes(v0) == 0) break;
+                            // slots t, t + 1 <= LISTW lie in the row; past the list: masked
+                            const int r0 = s.list[w][lane][t], r1 = s.list[w][lane][t + 1];
+                            const R4 e0 = s.st[w][v0 ? r0 : 0], e1 = s.st[w][v1 ? r1 : 0];
+                            count_pair<R>(sw, sq, v0, xi, yi, zi, hinv, h2, e0);
+                            count_pair<R>(sw, sq, v1, xi, yi, zi, hinv, h2, e1);
                         }
+                        acc.w += (double)sw;
+                        acc.qdw += (double)sq;
                     }
                 };
                 const bool reuse = cached && (!full || cached_all) && __all(!act || (float)h <= hcache);
