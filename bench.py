@@ -411,14 +411,17 @@ def integrate_section(steps, warmup):
     lattices, density 4 | 1, pressure 1 | 0.1795), FP32 pair arithmetic,
     Balsara switch of the |div v| form: kick-drift-kick steps of the length
     Eq. (6) allows, each step a full rebuild, 13 orderings, density with the
-    Newton iteration, force with the time-step criterion, and the kicks."""
+    Newton iteration, force with the time-step criterion, and the kicks.  The
+    dense side's cells hold ~110 particles (cells are sized by the light
+    side's h): wide staging of the density stage."""
     import torch
     from paper_1404_2303_amd import sph, workloads
     ps = workloads.sod(37)
 
     def run(reuse):
         parts = sph.Particles.from_numpy(ps, "cuda:0")
-        ctx = sph.Context(ps.box, precision="fp32", balsara_form=sph.SPH_BALSARA_DIV, reuse=reuse)
+        ctx = sph.Context(ps.box, precision="fp32", balsara_form=sph.SPH_BALSARA_DIV, reuse=reuse,
+                          staging=sph.SPH_STAGING_WIDE)
         ctx.enable_timing(True)
         d, acc = ctx.run(parts)
         t_box = torch.zeros(1, dtype=torch.float64, device="cuda:0")

@@ -90,7 +90,22 @@ typedef struct {
                             SPH_BALSARA_CURL as printed there, or SPH_BALSARA_DIV */
     int reuse;           /* reuse of the decomposition across steps by sph_step and
                             sph_step_adaptive (SPH_REUSE_*) */
+    int staging;         /* FP32 density stage: sources staged per wavefront and work-groups
+                            per compute unit (SPH_STAGING_*); FP64 has one form */
 } sph_params;
+
+/* Staging of the FP32 density stage.  A target cell's sources are copied into
+ * LDS per wavefront; when they do not fit, every Newton step stages and walks
+ * them again.  Compact staging keeps four work-groups per compute unit and
+ * suits cells of up to ~80 particles at the usual h / edge (the lattice and
+ * hierarchy workloads); wide staging holds a third more at three work-groups
+ * per compute unit, for single-level grids whose cells hold ~80-110 (a dense
+ * region under cells sized for the largest h, as in the Sod tube).  Both
+ * give the same results up to summation order. */
+enum {
+    SPH_STAGING_COMPACT = 0,  /* 192 sources per wavefront, 4 work-groups per CU */
+    SPH_STAGING_WIDE = 1      /* 256 sources per wavefront, 3 work-groups per CU */
+};
 
 /* Decomposition reuse across steps (the pseudo-Verlet scheme of Sec. 3.3 and
  * Sec. 4.1).  While the particle count and boxes are unchanged and the
@@ -115,7 +130,7 @@ enum {
 /* Default parameters: the paper's constants (48, 5/3, 0.8, 1e-4, C_CFL 1/4),
  * FP32_ACC64, cell_target 64, h_margin 0.1, max_iter 64, max_rebuilds 4, unit
  * box, max_depth 0 (single-level grid), split_count 64, split_frac 0.875,
- * balsara_form SPH_BALSARA_CURL, reuse SPH_REUSE_OFF. */
+ * balsara_form SPH_BALSARA_CURL, reuse SPH_REUSE_OFF, staging SPH_STAGING_COMPACT. */
 void sph_default_params(sph_params *p);
 
 typedef struct {

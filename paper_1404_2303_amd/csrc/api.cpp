@@ -210,7 +210,7 @@ static bool ensure_particles(sph_ctx* c, int64_t n)
     ok &= c->flag.ensure(N * 4) && c->cellx.ensure(N * 4) && c->cell_of.ensure(N * 4);
     ok &= c->sc_scratch.ensure(scan_scratch_words((int64_t)N) * 4 + 16);
     ok &= c->cells.ensure(N * sizeof(CellInfo)) && c->ncells.ensure(16);
-    ok &= c->big_cells.ensure((N / 256 + 2) * 4);
+    ok &= c->big_cells.ensure((N / 256 + 1 + kBigHeader) * 4);
     // interaction lists: 27 per cell on the single-level grid; on the hierarchy
     // a bound per particle (exceeding it sets SPH_E_CAPACITY)
     c->src_cap = (int64_t)N * (c->depth > 0 ? kTreeSourcesPerParticle : kMaxSources);
@@ -261,6 +261,7 @@ void sph_default_params(sph_params* p)
     p->cfl = 0.25;
     p->balsara_form = SPH_BALSARA_CURL;
     p->reuse = 0;
+    p->staging = SPH_STAGING_COMPACT;
 }
 
 const char* sph_status_string(sph_status s)
@@ -296,6 +297,7 @@ static bool params_ok(const sph_params& p)
     if (!(p.cfl > 0.0) || !std::isfinite(p.cfl)) return false;
     if (p.balsara_form != SPH_BALSARA_CURL && p.balsara_form != SPH_BALSARA_DIV) return false;
     if (p.reuse != SPH_REUSE_OFF && p.reuse != SPH_REUSE_ORDERINGS && p.reuse != SPH_REUSE_CELLS) return false;
+    if (p.staging != SPH_STAGING_COMPACT && p.staging != SPH_STAGING_WIDE) return false;
     return true;
 }
 
@@ -663,9 +665,8 @@ static void density_launch(sph_ctx* c, const sph_particles* p, const sph_density
         out.iters = o->n_iter;
         out.ndens = o->n_dens;
     }
-    int grid = density_occupancy_grid(c->prm.precision);
     launch_density<R>(decomp(c), cell_data<R>(c), sorted_data<R>(c), ghost_data<R>(c), out, pass_consts(c->prm),
-                      grid, st);
+                      c->prm.staging, st);
 }
 }  // extern "C++"
 

@@ -673,11 +673,14 @@ __device__ __forceinline__ void sort13_cell(const CellInfo& C, const CellData<R>
     }
 }
 
-__global__ void k_zero_first(int32_t* a) { a[0] = 0; }
+__global__ void k_zero_header(int32_t* a)
+{
+    for (int i = 0; i < kBigHeader; i++) a[i] = 0;
+}
 
 // Cells of at most kWaveSortMax particles: one wavefront per cell.  The
 // larger ones are listed for k_sort13: big[0] counts them (zero on entry),
-// big[1..] holds them.
+// big[kBigHeader..] holds them.
 template <typename R>
 __global__ __launch_bounds__(kWave) void k_sort13_wave(const CellInfo* cells, const int32_t* ncells, CellData<R> cd,
                                                        int64_t n, Sorted<R> so, int32_t* big)
@@ -689,7 +692,7 @@ __global__ __launch_bounds__(kWave) void k_sort13_wave(const CellInfo* cells, co
         if (C.count <= kWave) sort13_cell<R, 1>(C, cd, n, so, lane);
         else if (C.count <= 2 * kWave) sort13_cell<R, 2>(C, cd, n, so, lane);
         else if (C.count <= kWaveSortMax) sort13_cell<R, 4>(C, cd, n, so, lane);
-        else if (lane == 0) big[1 + atomicAdd(&big[0], 1)] = c;
+        else if (lane == 0) big[kBigHeader + atomicAdd(&big[0], 1)] = c;
     }
 }
 
@@ -703,7 +706,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort13(const CellInfo* cells, 
     __shared__ uint32_t key[SORT_MAX];
     const int64_t units = (int64_t)big[0] * kSortDirs;  // the cells k_sort13_wave left
     for (int64_t unit = blockIdx.x; unit < units; unit += gridDim.x) {
-        const int c = big[1 + (int)(unit / kSortDirs)];
+        const int c = big[kBigHeader + (int)(unit / kSortDirs)];
         const int s = (int)(unit % kSortDirs);
         const CellInfo C = cells[c];
         if (C.count > SORT_MAX) { if (threadIdx.x == 0) atomicOr(status, ST_CAPACITY); continue; }
@@ -877,7 +880,7 @@ template <typename R>
 void launch_sort13(const CellInfo* cells, const int32_t* ncells, const CellData<R>& cd, int64_t n,
                    const Sorted<R>& so, int32_t* big, uint32_t* status, int64_t cell_cap, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_zero_first, dim3(1), dim3(1), 0, st, big);
+    hipLaunchKernelGGL(k_zero_header, dim3(1), dim3(1), 0, st, big);
     unsigned gw = (unsigned)(cell_cap < 65536 ? cell_cap : 65536);
     if (gw < 1) gw = 1;
     hipLaunchKernelGGL(k_sort13_wave<R>, dim3(gw), dim3(kWave), 0, st, cells, ncells, cd, n, so, big);

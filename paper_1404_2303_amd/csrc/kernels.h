@@ -142,6 +142,8 @@ void launch_sources(const CellInfo* cells, const int32_t* ncells, const BoxInfo*
 template <typename R>
 void launch_sort13(const CellInfo* cells, const int32_t* ncells, const CellData<R>& cd, int64_t n,
                    const Sorted<R>& so, int32_t* big, uint32_t* status, int64_t cell_cap, hipStream_t st);
+// big[0]: the number of cells left to the rank sort, big[kBigHeader..]: those cells
+constexpr int kBigHeader = 1;
 
 // tree.hip -- hierarchical decomposition below the top grid
 struct TreeView {
@@ -185,11 +187,10 @@ void launch_estimate_h(const TreeView& tv, const BoxInfo* boxes, double n_ngb, d
 void launch_reset_counter(int32_t* c, hipStream_t st);
 template <typename R>
 void launch_density(const Decomp& dc, const CellData<R>& cd, const Sorted<R>& so, const GhostData<R>& gd,
-                    const DensityOut& out, const PassConsts& pc, int grid, hipStream_t st);
+                    const DensityOut& out, const PassConsts& pc, int staging, hipStream_t st);
 template <typename R>
 void launch_force(const Decomp& dc, const CellData<R>& cd, const Sorted<R>& so, const GhostData<R>& gd,
                   const ForceOut& out, const PassConsts& pc, int grid, hipStream_t st);
-int density_occupancy_grid(int precision);
 template <typename R>
 void launch_mts_prepare(const Decomp& dc, const CellData<R>& cd, const GhostData<R>& gd, int32_t* units,
                         int32_t* nunits, uint32_t* cell_flag, const uint32_t* cell_of, int64_t n, hipStream_t st);

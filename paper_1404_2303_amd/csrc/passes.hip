@@ -110,17 +110,18 @@ __device__ __forceinline__ void density_pair(DensAcc& a, DensPart<R>& b, bool ok
     a.n += ok ? 1 : 0;
 }
 
-// waves per SIMD the register budget is held to: four work-groups of four
-// wavefronts per CU in FP32 (at most 128 VGPRs, with the LDS of a work-group
-// under 40 KiB); FP64 is held to two by its LDS
-template <typename R> constexpr int kDensWaves = sizeof(R) == 4 ? 4 : 2;
+// waves per SIMD the register budget is held to: in FP32, four work-groups of
+// four wavefronts per CU for configuration 0 (at most 128 VGPRs, the LDS of a
+// work-group under 40 KiB), three for configuration 1 (its larger staging);
+// FP64 is held to two by its LDS
+template <typename R, int CFG> constexpr int kDensWaves = sizeof(R) == 4 ? (CFG == 0 ? 4 : 3) : 2;
 
-template <typename R>
-__global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<R>))) void k_density(Decomp dc, CellData<R> cd, Sorted<R> so, GhostData<R> gd,
+template <typename R, int CFG>
+__global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<R, CFG>))) void k_density(Decomp dc, CellData<R> cd, Sorted<R> so, GhostData<R> gd,
                                                  DensityOut out, PassConsts pc)
 {
     using R4 = typename Vec4T<R>::T;
-    using SM = Smem<R, NACC_D, false>;
+    using SM = Smem<R, NACC_D, false, CFG>;
     __shared__ SM s;
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: the wavefront index
@@ -173,7 +174,7 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
 
         // staging of the first batch, kept while it holds every source of the wavefront
         int k = 0, p = 0;
-        stage_wave<R, false, NACC_D>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, mstage);
+        stage_wave<R, false, NACC_D, CFG>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, mstage);
         bool single = k >= nsrc;
 
         for (int c0 = 0; c0 < T.count; c0 += kWave) {
@@ -254,13 +255,13 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
                 bool flushed = false;
                 int kk = 0, pp = 0;
                 do {
-                    if (!single) stage_wave<R, false, NACC_D>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, kk, pp, Hst, mstage);
+                    if (!single) stage_wave<R, false, NACC_D, CFG>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, kk, pp, Hst, mstage);
                     else kk = nsrc;
                     const int selfj = self_index(s, w, ti);
                     int seg = 0, jj = s.nseg[w] > 0 ? s.seg_b[w][0] : 0;
                     cnt = 0;
                     while (true) {
-                        cnt = walk<R, false, NACC_D>(s, w, lane, act, xi, yi, zi, fxi, fyi, fzi, rad, fh, margin,
+                        cnt = walk<R, false, NACC_D, CFG>(s, w, lane, act, xi, yi, zi, fxi, fyi, fzi, rad, fh, margin,
                                                      selfj, seg, jj, cnt);
                         if (seg >= s.nseg[w]) break;
                         process(cnt);  // a list is full: evaluate it and continue the walk
@@ -367,7 +368,7 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
                     const double hm = wave_max(conv ? 0.0 : h);
                     Hst = (float)fmin(fmax((double)Hst, hm * (1.0 + pc.h_margin)), h_lim);
                     k = 0; p = 0;
-                    stage_wave<R, false, NACC_D>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, mstage);
+                    stage_wave<R, false, NACC_D, CFG>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, mstage);
                     single = k >= nsrc;
                     cached = false;
                 }
@@ -699,12 +700,33 @@ void launch_reset_counter(int32_t* c, hipStream_t st)
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, c);
 }
 
+static int occupancy_grid(const void* fn)
+{
+    int dev = 0, ncu = 0, per = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, WGS, 0) != hipSuccess || per < 1) per = 1;
+    if (ncu < 1) ncu = 1;
+    return ncu * per;
+}
+
 template <typename R>
 void launch_density(const Decomp& dc, const CellData<R>& cd, const Sorted<R>& so, const GhostData<R>& gd,
-                    const DensityOut& out, const PassConsts& pc, int grid, hipStream_t st)
+                    const DensityOut& out, const PassConsts& pc, int staging, hipStream_t st)
 {
     launch_reset_counter(dc.qhead, st);
-    hipLaunchKernelGGL(k_density<R>, dim3(grid), dim3(WGS), 0, st, dc, cd, so, gd, out, pc);
+    bool wide = false;
+    if constexpr (sizeof(R) == 4) {
+        // FP64 has one staging form
+        wide = staging == SPH_STAGING_WIDE;
+        if (wide)
+            hipLaunchKernelGGL((k_density<R, 1>), dim3(occupancy_grid((const void*)k_density<R, 1>)), dim3(WGS), 0,
+                               st, dc, cd, so, gd, out, pc);
+    }
+    if (!wide) {
+        hipLaunchKernelGGL((k_density<R, 0>), dim3(occupancy_grid((const void*)k_density<R, 0>)), dim3(WGS), 0, st,
+                           dc, cd, so, gd, out, pc);
+    }
 }
 
 template <typename R>
@@ -724,21 +746,6 @@ template void launch_force<float>(const Decomp&, const CellData<float>&, const S
 template void launch_force<double>(const Decomp&, const CellData<double>&, const Sorted<double>&,
                                    const GhostData<double>&, const ForceOut&, const PassConsts&, int, hipStream_t);
 
-static int occupancy_grid(const void* fn)
-{
-    int dev = 0, ncu = 0, per = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, WGS, 0) != hipSuccess || per < 1) per = 1;
-    if (ncu < 1) ncu = 1;
-    return ncu * per;
-}
-
-int density_occupancy_grid(int precision)
-{
-    return precision == SPH_FP64 ? occupancy_grid((const void*)k_density<double>)
-                                 : occupancy_grid((const void*)k_density<float>);
-}
 
 int force_occupancy_grid(int precision)
 {

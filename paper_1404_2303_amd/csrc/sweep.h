@@ -22,11 +22,15 @@ constexpr int WALK_PAD = WALK_STEP - 1;
 
 // staged particles per wavefront and list slots per lane (density lists also
 // serve the Newton iteration, so they are longer)
-template <typename R, bool FORCE> struct PCfg;
-template <> struct PCfg<float, false> { static constexpr int CAPW = 192, LISTW = 48; };
-template <> struct PCfg<float, true> { static constexpr int CAPW = 216, LISTW = 32; };
-template <> struct PCfg<double, false> { static constexpr int CAPW = 256, LISTW = 48; };
-template <> struct PCfg<double, true> { static constexpr int CAPW = 256, LISTW = 32; };
+// The FP32 density stage has two (SPH_STAGING_COMPACT and _WIDE): CFG 0 for
+// cells of up to ~80 particles (four work-groups per CU), CFG 1 with room for
+// cells of ~80-110 (three).
+template <typename R, bool FORCE, int CFG = 0> struct PCfg;
+template <> struct PCfg<float, false, 0> { static constexpr int CAPW = 192, LISTW = 48; };
+template <> struct PCfg<float, false, 1> { static constexpr int CAPW = 256, LISTW = 48; };
+template <> struct PCfg<float, true, 0> { static constexpr int CAPW = 216, LISTW = 32; };
+template <int CFG> struct PCfg<double, false, CFG> { static constexpr int CAPW = 256, LISTW = 48; };
+template <> struct PCfg<double, true, 0> { static constexpr int CAPW = 256, LISTW = 32; };
 
 // square root, reciprocal square root and reciprocal of the pair arithmetic:
 // the hardware instructions in FP32 (about 1 ulp), correctly rounded in FP64
@@ -100,11 +104,11 @@ __device__ __forceinline__ float lane_of(float v, int l)
 }
 
 // ---------------------------------------------------------------- LDS layout
-template <typename R, int NACC, bool STAGE_H>
+template <typename R, int NACC, bool STAGE_H, int CFG = 0>
 struct Smem {
     using R4 = typename Vec4T<R>::T;
-    static constexpr int CAPW = PCfg<R, STAGE_H>::CAPW;
-    static constexpr int LISTW = PCfg<R, STAGE_H>::LISTW;
+    static constexpr int CAPW = PCfg<R, STAGE_H, CFG>::CAPW;
+    static constexpr int LISTW = PCfg<R, STAGE_H, CFG>::LISTW;
     // staged (x, y, z in T's frame, |x|^2 / 2 less its rounding allowance); the
     // walk reads up to WALK_PAD entries past a segment's end (masked off)
     R4 st[NW][CAPW + WALK_PAD];
@@ -131,14 +135,14 @@ struct Smem {
 // Stage, for wavefront w, its sources from cursor (k, p) on; advance the
 // cursor past what was staged (k == nsrc when every source is staged).  The
 // sources of the target cell are read 64 at a time, one per lane.
-template <typename R, bool FORCE, int NACC>
-__device__ void stage_wave(Smem<R, NACC, FORCE>& s, const int w, const Decomp& dc, const CellData<R>& cd,
+template <typename R, bool FORCE, int NACC, int CFG = 0>
+__device__ void stage_wave(Smem<R, NACC, FORCE, CFG>& s, const int w, const Decomp& dc, const CellData<R>& cd,
                            const Sorted<R>& so, const GhostData<R>& gd, const BoxInfo& B, const int tcell,
                            const int tlevel, const int nsrc, int& k, int& p, const float Hst, const float margin)
 {
     using R4 = typename Vec4T<R>::T;
     const int lane = threadIdx.x & (kWave - 1);
-    const int CAPW = Smem<R, NACC, FORCE>::CAPW;
+    const int CAPW = Smem<R, NACC, FORCE, CFG>::CAPW;
     // edges of the target cell and the finest-level unit of the source offsets
     const float et[3] = {(float)ldexp(B.e[0], -tlevel), (float)ldexp(B.e[1], -tlevel),
                          (float)ldexp(B.e[2], -tlevel)};
@@ -264,8 +268,8 @@ __device__ void stage_wave(Smem<R, NACC, FORCE>& s, const int w, const Decomp& d
 }
 
 // Staged index of the lane's own particle in wavefront w's self segment, or -1.
-template <typename R, int NACC, bool F>
-__device__ __forceinline__ int self_index(const Smem<R, NACC, F>& s, int w, int ti)
+template <typename R, int NACC, bool F, int CFG>
+__device__ __forceinline__ int self_index(const Smem<R, NACC, F, CFG>& s, int w, int ti)
 {
     const int d = ti - s.self_t0[w];
     return (d >= 0 && d < s.self_n[w]) ? s.self_b[w] + d : -1;
@@ -308,12 +312,12 @@ __device__ __forceinline__ uint64_t lanes(bool p) { return __builtin_amdgcn_ball
 // below the exact r^2 / 2 by more than the allowance, so a list holds every
 // pair in range and possibly a few just outside, which the pair arithmetic
 // (its own tests of r against h) discards.
-template <typename R, bool FORCE, int NACC>
-__device__ __forceinline__ int walk(Smem<R, NACC, FORCE>& s, int w, int lane, bool act, R xi, R yi, R zi, float fxi,
+template <typename R, bool FORCE, int NACC, int CFG = 0>
+__device__ __forceinline__ int walk(Smem<R, NACC, FORCE, CFG>& s, int w, int lane, bool act, R xi, R yi, R zi, float fxi,
                                     float fyi, float fzi, R rad, float fh, float margin, int selfj, int& seg_io,
                                     int& jj_io, int cnt)
 {
-    constexpr int LISTW = Smem<R, NACC, FORCE>::LISTW;
+    constexpr int LISTW = Smem<R, NACC, FORCE, CFG>::LISTW;
     constexpr int STEP = WALK_STEP;
     const int nseg = uniform(s.nseg[w]);
     // lane constants of the test: K_i, and the range (rad^2 / 2, rounded up)

@@ -34,7 +34,8 @@ def main():
     if args.workload == "sod":
         ps = workloads.sod(37)
         parts = sph.Particles.from_numpy(ps, "cuda:0")
-        ctx = sph.Context(ps.box, precision=args.precision, balsara_form=sph.SPH_BALSARA_DIV, reuse=args.reuse)
+        ctx = sph.Context(ps.box, precision=args.precision, balsara_form=sph.SPH_BALSARA_DIV, reuse=args.reuse,
+                          staging=sph.SPH_STAGING_WIDE)
         d, acc = ctx.run(parts)
         t_box = torch.zeros(1, dtype=torch.float64, device="cuda:0")
         torch.cuda.synchronize()

@@ -25,6 +25,7 @@ SPH_E_CAPACITY, SPH_E_OOM, SPH_E_HIP, SPH_E_STATE = 5, 6, 7, 8
 SPH_FP64, SPH_FP32_ACC64 = 0, 1
 SPH_BALSARA_CURL, SPH_BALSARA_DIV = 0, 1
 SPH_REUSE_OFF, SPH_REUSE_ORDERINGS, SPH_REUSE_CELLS = 0, 1, 2
+SPH_STAGING_COMPACT, SPH_STAGING_WIDE = 0, 1
 
 EXPORTED = ["sph_default_params", "sph_create", "sph_destroy", "sph_build_cells", "sph_sort",
             "sph_density", "sph_force", "sph_step", "sph_get_stats", "sph_status_string",
@@ -42,7 +43,7 @@ class sph_params(ctypes.Structure):
                 ("cell_target", ctypes.c_int), ("h_margin", ctypes.c_double),
                 ("max_rebuilds", ctypes.c_int), ("max_depth", ctypes.c_int), ("split_count", ctypes.c_int),
                 ("split_frac", ctypes.c_double), ("cfl", ctypes.c_double), ("balsara_form", ctypes.c_int),
-                ("reuse", ctypes.c_int)]
+                ("reuse", ctypes.c_int), ("staging", ctypes.c_int)]
 
 
 class sph_particles(ctypes.Structure):

@@ -104,13 +104,15 @@ def test_decomposition_invariance(cell_target):
     assert np.max(np.abs(base["a"] - other["a"])) <= 1e-9 * ka
 
 
+@pytest.mark.parametrize("staging", [sph.SPH_STAGING_COMPACT, sph.SPH_STAGING_WIDE])
 @pytest.mark.parametrize("n,cell_target,lo,hi", [(40000, 100, 64, 128), (6000, 200, 128, 256)])
-def test_large_cells_fp32(n, cell_target, lo, hi):
+def test_large_cells_fp32(n, cell_target, lo, hi, staging):
     """Cells of 65..128 and 129..256 particles on average: the orderings of two
     and four words per lane of the wavefront sort (keys rounded down below
-    their index bits)."""
+    their index bits), under both stagings of the density stage (sources that
+    overflow the compact one take several batches)."""
     ps = workloads.uniform(n, seed=10, sigma_v=0.3)
-    g = gpu_run(ps, "fp32", cell_target=cell_target)
+    g = gpu_run(ps, "fp32", cell_target=cell_target, staging=staging)
     mean = ps.n / g["stats"]["n_cells"]
     log(f"case large cells fp32 n={n} cell_target={cell_target}: {g['stats']['n_cells']} cells, mean {mean:.0f}")
     assert lo < mean <= hi

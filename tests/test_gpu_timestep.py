@@ -237,7 +237,7 @@ def test_sod_shock_tube_matches_exact_solution():
     t_end = 1.5
     log(f"case sod {ps.n} t_end {t_end}")
     parts = sph.Particles.from_numpy(ps, "cuda:0")
-    ctx = sph.Context(ps.box, precision="fp32", balsara_form=sph.SPH_BALSARA_DIV)
+    ctx = sph.Context(ps.box, precision="fp32", balsara_form=sph.SPH_BALSARA_DIV, staging=sph.SPH_STAGING_WIDE)
     e0 = float(np.sum(ps.m * ps.u))
     acc, steps = ctx.integrate(parts, t_end, 1.0)
     d, _ = ctx.run(parts)
@@ -311,7 +311,7 @@ def test_sedov_blast_follows_the_similarity_solution():
     g, E = ps.meta["gamma"], ps.meta["E"]
     log(f"case sedov {ps.n}")
     parts = sph.Particles.from_numpy(ps, "cuda:0")
-    ctx = sph.Context(ps.box, precision="fp32", balsara_form=sph.SPH_BALSARA_DIV)
+    ctx = sph.Context(ps.box, precision="fp32", balsara_form=sph.SPH_BALSARA_DIV, staging=sph.SPH_STAGING_WIDE)
     e0 = float(np.sum(ps.m * ps.u))
     xi0 = sedov.xi0(g)
     radii = []
