@@ -58,9 +58,9 @@ typedef enum {
 enum {
     SPH_FP64 = 0,        /* every pair term and every sum in FP64 ("plain" form) */
     SPH_FP32_ACC64 = 1   /* pair terms in FP32 on cell-relative coordinates; per-particle
-                            sums and the Newton step on h in FP64 (the mass-weighted
-                            density-stage sums reach FP64 through FP32 partial sums
-                            over one neighbour list of at most 48 pairs) */
+                            sums and the Newton step on h in FP64 (the sums reach FP64
+                            through FP32 partial sums over one neighbour list, of at
+                            most 48 pairs in the density stage and 32 in the force stage) */
 };
 
 typedef struct {

@@ -452,6 +452,11 @@ struct ForceAcc {
     R vsig;   // largest c_i + c_j - 3 w_ij over the pairs in range (Eq. (6))
     int n;
 };
+// the sums of one pass over a list (at most LISTW pairs) in the pair precision
+template <typename R>
+struct ForcePart {
+    R ax, ay, az, du;
+};
 
 template <typename R>
 struct ForceTarget {
@@ -462,7 +467,7 @@ struct ForceTarget {
 // (one-sided: the contribution of j to particle i).  Pairs outside both
 // supports contribute exactly zero (both kernel gradients vanish there).
 template <typename R>
-__device__ __forceinline__ void force_pair(ForceAcc<R>& a, bool ok, const ForceTarget<R>& ti, R alpha,
+__device__ __forceinline__ void force_pair(ForceAcc<R>& a, ForcePart<R>& b, bool ok, const ForceTarget<R>& ti, R alpha,
                                            typename Vec4T<R>::T e, typename Vec4T<R>::T vm,
                                            typename Vec4T<R>::T g0, typename Vec4T<R>::T g1)
 {
@@ -471,9 +476,15 @@ __device__ __forceinline__ void force_pair(ForceAcc<R>& a, bool ok, const ForceT
     const R rinv = r2 > (R)0 ? fast_rsqrt(r2) : (R)0;
     const R r = r2 * rinv;
     const R qi = r * ti.hinv, qj = r * g0.x;
-    // grad W(r, h) = 8/(pi h^5) g(q) r_vec, zero outside the support and at r = 0
-    const R gwi = (qi < (R)1 && r > (R)0) ? ti.gk * kern_g(qi, ti.h * rinv) : (R)0;
-    const R gwj = (qj < (R)1 && r > (R)0) ? g0.y * kern_g(qj, g1.z * rinv) : (R)0;
+    // grad W(r, h) = 8/(pi h^5) g(q) r_vec with g = w'/q = -6 (u + t) min(1, t/q),
+    // t = max(1 - q, 0), u = max(1 - 2q, 0): 18q - 12 for q <= 1/2, -6 t^2/q
+    // up to q = 1, zero beyond and (rinv = 0) at r = 0, without branches
+    auto grad = [&](R q, R h, R gk) {
+        const R t = fmax((R)1 - q, (R)0), u = fmax(fma((R)-2, q, (R)1), (R)0);
+        return gk * (R)-6 * (u + t) * fmin((R)1, t * (h * rinv));
+    };
+    const R gwi = grad(qi, ti.h, ti.gk);
+    const R gwj = grad(qj, g1.z, g0.y);
     const R mj = ok ? vm.w : (R)0;  // masked pairs contribute nothing
     const R vr = (ti.vx - vm.x) * dx + (ti.vy - vm.y) * dy + (ti.vz - vm.z) * dz;
     const R wij = fmin(vr * rinv, (R)0);
@@ -483,10 +494,10 @@ __device__ __forceinline__ void force_pair(ForceAcc<R>& a, bool ok, const ForceT
     const R agi = ti.A * gwi;
     const R sc = -mj * (agi + g0.z * gwj + (R)0.25 * T);
     const R pdu = mj * vr * (agi + (R)0.125 * T);
-    a.ax += (double)(sc * dx);
-    a.ay += (double)(sc * dy);
-    a.az += (double)(sc * dz);
-    a.du += (double)pdu;
+    b.ax += sc * dx;
+    b.ay += sc * dy;
+    b.az += sc * dz;
+    b.du += pdu;
     // lists may hold a few pairs just outside both supports: they add nothing
     // above (zero gradients) and are neither counted nor signal pairs
     const bool in = ok && (qi < (R)1 || qj < (R)1);
@@ -545,19 +556,25 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
             __syncthreads();
             ForceAcc<R> acc = {};
             auto process = [&](int n) {
+                ForcePart<R> b = {};
                 for (int t = 0;; t += 2) {
                     const bool v0 = t < n, v1 = t + 1 < n;
-                    if (!__any(v0)) break;
-                    const int j0 = v0 ? (int)s.list[w][lane][t] : 0;
-                    const int j1 = v1 ? (int)s.list[w][lane][t + 1] : 0;
+                    if (lanes(v0) == 0) break;
+                    // slots t, t + 1 <= LISTW lie in the row; past the list: masked
+                    const int r0 = s.list[w][lane][t], r1 = s.list[w][lane][t + 1];
+                    const int j0 = v0 ? r0 : 0, j1 = v1 ? r1 : 0;
                     const uint32_t q0 = s.sg[w][j0], q1 = s.sg[w][j1];
                     const R4 e0 = s.st[w][j0], e1 = s.st[w][j1];
                     const R4 v0m = cd.vm[q0], v1m = cd.vm[q1];
                     const R4 a0 = gd.g0[q0], a1 = gd.g0[q1];
                     const R4 b0 = gd.g1[q0], b1 = gd.g1[q1];
-                    force_pair<R>(acc, v0, ti, alpha, e0, v0m, a0, b0);
-                    force_pair<R>(acc, v1, ti, alpha, e1, v1m, a1, b1);
+                    force_pair<R>(acc, b, v0, ti, alpha, e0, v0m, a0, b0);
+                    force_pair<R>(acc, b, v1, ti, alpha, e1, v1m, a1, b1);
                 }
+                acc.ax += (double)b.ax;
+                acc.ay += (double)b.ay;
+                acc.az += (double)b.az;
+                acc.du += (double)b.du;
             };
             int kk = 0, pp = 0;
             do {

@@ -9,10 +9,12 @@ div, curl 1e-9 of their RMS; a, du/dt 1e-9 of kappa (the sum of the
 magnitudes of the pair contributions, the natural scale of a cancelling sum).
 
 FP32 form -- pair terms in FP32 (unit roundoff 6e-8, ~10 roundings per term,
-so about 1e-6 per term), sums in FP64 (the density stage's mass-weighted sums
-in FP32 over one neighbour list of at most 48 pairs first: at most
-48 x 6e-8 ~ 3e-6 of the summed magnitudes, the size of the per-term error
-already allowed), and the Newton iteration stops at
+so about 1e-6 per term), sums in FP64 (each reached through FP32 partial sums
+over one neighbour list, of at most 48 pairs in the density stage and 32 in
+the force stage: at most 48 x 6e-8 ~ 3e-6 of the summed magnitudes, the size
+of the per-term error already allowed; the Newton decision sees at most
+~3e-5 in N, inside its 1e-4 stopping band and the 2e-4 band below), and the
+Newton iteration stops at
 |N - 48| <= 1e-4, which moves h by at most ~1e-4/(h dN/dh) ~ 1e-4/144 ~ 7e-7
 relative (more where h dN/dh is small, so h is also allowed the band
 ngb/(h |dN/dh|) of each particle, ngb the tolerance on N).  Hence: h relative 2e-6;
