@@ -585,7 +585,7 @@ def main():
         "config": {"workload": "jittered cubic lattice 128x128x64 (2^20 particles), spacing 1/128, "
                                "periodic 1x1x0.5 box, v~N(0,0.1), u=1; build+sort+density(h-Newton)+force",
                    "n": ps.n, "form": ("graph-captured pass, " if use_graph else "eager calls, ") +
-                                       "fp32 pair arithmetic, fp64 sums and Newton step",
+                                       "fp32 pair arithmetic and per-list partial sums, fp64 totals and Newton step",
                    "eager_ms_per_step": fast["ms_per_step"], "graph_ms_per_step": graph["ms_per_step"],
                    "pairs_per_step": fast["P"], "kernel_ms": fast["kernel_ms"],
                    "newton_mean": fast["newton_mean"], "newton_max": fast["newton_max"],
