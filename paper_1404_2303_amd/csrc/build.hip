@@ -344,12 +344,13 @@ __global__ void k_cell_fill(const uint64_t* keys, const uint32_t* flag, const ui
 
 __global__ void k_cell_counts(CellInfo* cells, const int32_t* ncells, const BoxInfo* boxes)
 {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= *ncells) return;
-    cells[c].count -= cells[c].start;
-    cells[c].level = 0;
-    const BoxInfo& B = boxes[cells[c].box];
-    cells[c].hlim = (float)fmin(B.e[0], fmin(B.e[1], B.e[2]));
+    const int nc_all = *ncells;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc_all; c += gridDim.x * blockDim.x) {
+        cells[c].count -= cells[c].start;
+        cells[c].level = 0;
+        const BoxInfo& B = boxes[cells[c].box];
+        cells[c].hlim = (float)fmin(B.e[0], fmin(B.e[1], B.e[2]));
+    }
 }
 
 // ---------------------------------------------------------------- gather (cell order)
@@ -522,32 +523,57 @@ __global__ void k_zero_drift(BoxInfo* boxes, int nbox, float* cell_drift, const 
 // before (the loops shorten by a fifth).
 constexpr uint64_t kDirWavePacked = 0x5e2d6c533acdaull;
 
-__global__ void k_sources(const CellInfo* cells, const int32_t* ncells, const BoxInfo* boxes,
-                          const int32_t* cell_map, Source* src, int32_t* src_off, int32_t* src_count)
+// The self source and the existing neighbours of each cell, in direction
+// order: 32 lanes per cell, lane 0 the cell itself and lane 1 + d direction
+// d; a ballot over the half-wavefront compacts them.
+__global__ __launch_bounds__(256) void k_sources(const CellInfo* cells, const int32_t* ncells,
+                                                 const BoxInfo* boxes, const int32_t* cell_map, Source* src,
+                                                 int32_t* src_off, int32_t* src_count)
 {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= *ncells) return;
-    const CellInfo C = cells[c];
-    const BoxInfo& B = boxes[C.box];
-    Source* out = src + (int64_t)c * kMaxSources;
-    int k = 0;
-    out[k++] = Source{c, (int8_t)kSelfDir, (int8_t)kAllWaves, 0, 0, 0};
-    for (int d = 0; d < kDirs; d++) {
-        int o[3];
-        dir_off(d, o);
-        int nc[3];
-        for (int a = 0; a < 3; a++) {
-            int v = C.c[a] + o[a];
-            nc[a] = v < 0 ? v + B.nc[a] : (v >= B.nc[a] ? v - B.nc[a] : v);
+    const int nc_all = *ncells;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int j = lane & 31;                 // slot within the cell's half-wavefront
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x / 32;
+    for (int64_t base = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 32; ; base += stride) {
+        // every lane of a wavefront takes the loop's last step together (ballot below)
+        const int64_t first = base - (lane >> 5);   // the wavefront's first cell
+        if (first >= nc_all) break;
+        const int c = (int)base;
+        bool have = false;
+        Source sv{};
+        if (c < nc_all && j <= kDirs) {
+            const CellInfo C = cells[c];
+            if (j == 0) {
+                sv = Source{c, (int8_t)kSelfDir, (int8_t)kAllWaves, 0, 0, 0};
+                have = true;
+            } else {
+                const int d = j - 1;
+                const BoxInfo& B = boxes[C.box];
+                int o[3];
+                dir_off(d, o);
+                int nc[3];
+                for (int a = 0; a < 3; a++) {
+                    const int v = C.c[a] + o[a];
+                    nc[a] = v < 0 ? v + B.nc[a] : (v >= B.nc[a] ? v - B.nc[a] : v);
+                }
+                const int32_t sc = cell_map[B.map_off + ((int64_t)nc[0] * B.nc[1] + nc[1]) * B.nc[2] + nc[2]];
+                if (sc >= 0) {
+                    sv = Source{sc, (int8_t)d, (int8_t)((kDirWavePacked >> (2 * d)) & 3u), (int16_t)o[0],
+                                (int16_t)o[1], (int16_t)o[2]};
+                    have = true;
+                }
+            }
         }
-        int32_t s = cell_map[B.map_off + ((int64_t)nc[0] * B.nc[1] + nc[1]) * B.nc[2] + nc[2]];
-        if (s >= 0)
-            out[k++] = Source{s, (int8_t)d, (int8_t)((kDirWavePacked >> (2 * d)) & 3u), (int16_t)o[0],
-                              (int16_t)o[1], (int16_t)o[2]};
+        const uint64_t m = __ballot(have);
+        const uint32_t half = (uint32_t)(m >> (lane & 32));
+        if (have) src[(int64_t)c * kMaxSources + __popc(half & ((1u << j) - 1u))] = sv;
+        if (c < nc_all && j == 0) {
+            src_off[c] = c * kMaxSources;
+            src_count[c] = __popc(half);
+        }
     }
-    src_off[c] = c * kMaxSources;
-    src_count[c] = k;
 }
+
 
 // ---------------------------------------------------------------- 13-direction orderings
 // One workgroup per (cell, direction).  Each particle's rank is the number of
@@ -832,7 +858,8 @@ void launch_cells(const uint64_t* keys, uint32_t* flag, uint32_t* cellx, int64_t
     exclusive_scan(flag, cellx, n, scan_scratch, nullptr, st);
     hipLaunchKernelGGL(k_cell_fill, dim3(g), dim3(256), 0, st, keys, flag, cellx, n, top_bits, boxes,
                        cells, cell_map, cell_of, ncells);
-    hipLaunchKernelGGL(k_cell_counts, dim3((unsigned)((cell_cap + 255) / 256)), dim3(256), 0, st,
+    const int64_t cb = (cell_cap + 255) / 256;   // cells number at most cell_cap: the grid strides
+    hipLaunchKernelGGL(k_cell_counts, dim3((unsigned)(cb < 1024 ? cb : 1024)), dim3(256), 0, st,
                        cells, ncells, boxes);
 }
 
@@ -879,7 +906,9 @@ void launch_sources(const CellInfo* cells, const int32_t* ncells, const BoxInfo*
                     const int32_t* cell_map, Source* src, int32_t* src_off, int32_t* src_count,
                     int64_t cell_cap, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_sources, dim3((unsigned)((cell_cap + 127) / 128)), dim3(128), 0, st, cells,
+    // cells number at most cell_cap (not known here); 8 cells per block, the grid strides over them
+    const int64_t blocks = (cell_cap + 7) / 8;
+    hipLaunchKernelGGL(k_sources, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, st, cells,
                        ncells, boxes, cell_map, src, src_off, src_count);
 }
 
