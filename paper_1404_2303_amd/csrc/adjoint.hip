@@ -162,7 +162,8 @@ __global__ __launch_bounds__(WGS) void k_adj_sweep(Decomp dc, CellData<R> cd, So
             const int ti = c0 + lane;
             const bool valid = ti < T.count;
             const uint32_t gi = (uint32_t)(T.start + (valid ? ti : 0));
-            const R xi = cd.rx[gi], yi = cd.ry[gi], zi = cd.rz[gi];
+            const R4 ri = cd.rp[gi];
+            const R xi = ri.x, yi = ri.y, zi = ri.z;
             const R4 vmi = cd.vm[gi], g0i = gd.g0[gi], g1i = gd.g1[gi];
             const R hi = g1i.z, hinvi = g0i.x;
             R4 abi = {}, sb0i = {}, sb1i = {};

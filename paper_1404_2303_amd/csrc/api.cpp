@@ -50,7 +50,7 @@ struct sph_ctx {
     DBuf boxes, keys, keys2, vals, vals2, rs_scratch, flag, cellx, cell_of, sc_scratch;
     DBuf cells, ncells, cell_map, src, src_count, srec;
     DBuf big_cells;                                  // count, then the cells the wavefront sort leaves
-    DBuf rx, ry, rz, h, vm, u;                       // cell order
+    DBuf rp, h, vm, u;                               // cell order
     DBuf r0;                                         // cell-relative positions at the last build
     DBuf cell_drift;                                 // largest displacement per cell since that build
     bool refreshed = false;                          // a refresh followed the last build
@@ -130,7 +130,7 @@ static CellData<R> cell_data(sph_ctx* c)
 {
     using R4 = typename Vec4T<R>::T;
     CellData<R> d;
-    d.rx = c->rx.as<R>(); d.ry = c->ry.as<R>(); d.rz = c->rz.as<R>();
+    d.rp = c->rp.as<R4>();
     d.h = c->h.as<double>();
     d.vm = c->vm.as<R4>();
     d.u = c->u.as<double>();
@@ -227,7 +227,7 @@ static bool ensure_particles(sph_ctx* c, int64_t n)
         ok &= c->t_group.ensure((27 * N + 1) * 4) && c->sc_scratch.ensure(scan_scratch_words((int64_t)(27 * N)) * 4 + 16);
     }
     ok &= c->srec.ensure(N * kSortDirs * sizeof(SortRec));
-    ok &= c->rx.ensure(N * R) && c->ry.ensure(N * R) && c->rz.ensure(N * R) && c->r0.ensure(N * 4 * R);
+    ok &= c->rp.ensure(N * 4 * R) && c->r0.ensure(N * 4 * R);
     ok &= c->cell_drift.ensure(N * sizeof(float));
     ok &= c->h.ensure(N * 8) && c->u.ensure(N * 8);
     ok &= c->vm.ensure(N * 4 * R);
@@ -327,7 +327,7 @@ sph_status sph_destroy(sph_ctx* c)
     if (!c) return SPH_OK;
     DBuf* all[] = {&c->boxes, &c->keys, &c->keys2, &c->vals, &c->vals2, &c->rs_scratch, &c->flag,
                    &c->cellx, &c->cell_of, &c->sc_scratch, &c->cells, &c->ncells, &c->big_cells, &c->cell_map,
-                   &c->src, &c->src_count, &c->srec, &c->r0, &c->cell_drift, &c->rx, &c->ry, &c->rz, &c->h,
+                   &c->src, &c->src_count, &c->srec, &c->r0, &c->cell_drift, &c->rp, &c->h,
                    &c->vm, &c->u, &c->g0, &c->g1, &c->cell_hmax, &c->qhead, &c->status, &c->step_tmp, &c->dt_box, &c->dt_min, &c->t_box, &c->mts_active, &c->mts_rho, &c->mts_A,
                    &c->mts_c, &c->mts_f, &c->mts_count, &c->mts_units, &c->mts_flag,
                    &c->sd0, &c->sd1, &c->adj_ab, &c->adj_sb0, &c->adj_sb1, &c->adj_x, &c->adj_h, &c->adj_fg,

@@ -382,7 +382,7 @@ __global__ void k_gather(Particles p, const uint32_t* perm, const uint32_t* cell
         // a coordinate that rounded onto the upper face belongs to this cell
         rel[d] = (R)cell_rel(pos[d], o, B.L[d]);
     }
-    cd.rx[k] = rel[0]; cd.ry[k] = rel[1]; cd.rz[k] = rel[2];
+    cd.rp[k] = typename CellData<R>::R4{rel[0], rel[1], rel[2], (R)0};
     cd.h[k] = p.h[i];
     typename CellData<R>::R4 vm;
     vm.x = (R)p.vx[i]; vm.y = (R)p.vy[i]; vm.z = (R)p.vz[i]; vm.w = (R)p.m[i];
@@ -430,7 +430,7 @@ __global__ void k_refresh(Particles p, const uint32_t* perm, const uint32_t* cel
             const double o = (double)C.c[d] * ldexp(B.e[d], -B.depth);
             rel[d] = (R)cell_rel(pos[d], o, B.L[d]);
         }
-        cd.rx[k] = rel[0]; cd.ry[k] = rel[1]; cd.rz[k] = rel[2];
+        cd.rp[k] = typename CellData<R>::R4{rel[0], rel[1], rel[2], (R)0};
         cd.h[k] = h;
         typename CellData<R>::R4 vm;
         vm.x = (R)p.vx[i]; vm.y = (R)p.vy[i]; vm.z = (R)p.vz[i]; vm.w = (R)p.m[i];
@@ -683,7 +683,8 @@ __device__ __forceinline__ void sort13_cell(const CellInfo& C, const CellData<R>
     for (int e = 0; e < E; e++) {
         const int t = e * kWave + lane;
         const int64_t k = C.start + (t < C.count ? t : 0);
-        x[e] = cd.rx[k]; y[e] = cd.ry[k]; z[e] = cd.rz[k];
+        const typename CellData<R>::R4 q = cd.rp[k];
+        x[e] = q.x; y[e] = q.y; z[e] = q.z;
     }
     for (int s = 0; s < kSortDirs; s++) {
         float su[3];
@@ -750,7 +751,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort13(const CellInfo* cells, 
         // a total order (NaN included), so every cell's ordering is a permutation
         for (int t = threadIdx.x; t < C.count; t += SORT_THREADS) {
             int64_t k = C.start + t;
-            const float f = su[0] * (float)cd.rx[k] + su[1] * (float)cd.ry[k] + su[2] * (float)cd.rz[k];
+            const typename CellData<R>::R4 q = cd.rp[k];
+            const float f = su[0] * (float)q.x + su[1] * (float)q.y + su[2] * (float)q.z;
             const uint32_t b = __float_as_uint(f);
             key[t] = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
         }

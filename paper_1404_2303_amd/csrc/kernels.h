@@ -20,15 +20,15 @@ template <> struct Vec4T<double> { using T = double4; };
 template <typename R>
 struct CellData {
     using R4 = typename Vec4T<R>::T;
-    R *rx, *ry, *rz;
+    R4* rp;              // (x, y, z, 0) relative to the cell's lower corner: one load
     double* h;           // smoothing length (FP64 master copy)
     R4* vm;              // (vx, vy, vz, m)
     double* u;
 };
 
 // The 13 orderings of every cell: for stored direction s and rank k within
-// cell C, entry s*n + C.start + k holds the particle's cell-local index and
-// (x, y, z relative to the cell, projection on the direction).
+// cell C, entry s*n + C.start + k holds the projection on the direction (the
+// sort key) and the particle's cell-local index.
 template <typename R>
 struct Sorted {
     SortRec* rec;   // [direction][cell-order slot]: the cell's particles by ascending projection

@@ -183,7 +183,8 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
             const uint32_t gi = (uint32_t)(T.start + (valid ? ti : 0));
             const uint32_t pi = dc.perm[gi];
             const bool on = valid && (!gd.active || gd.active[pi] != 0);   // a target of this pass
-            const R xi = cd.rx[gi], yi = cd.ry[gi], zi = cd.rz[gi];
+            const R4 ri = cd.rp[gi];
+            const R xi = ri.x, yi = ri.y, zi = ri.z;
             const R4 vmi = cd.vm[gi];
             const float fxi = (float)xi, fyi = (float)yi, fzi = (float)zi;
             double h = fmin(cd.h[gi], h_lim);
@@ -546,7 +547,8 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
             const uint32_t gi = (uint32_t)(T.start + (valid ? ti_ : 0));
             const bool on = valid && (!gd.active || gd.active[dc.perm[gi]] != 0);   // a target of this pass
             ForceTarget<R> ti;
-            ti.x = cd.rx[gi]; ti.y = cd.ry[gi]; ti.z = cd.rz[gi];
+            const R4 ri = cd.rp[gi];
+            ti.x = ri.x; ti.y = ri.y; ti.z = ri.z;
             const R4 vmi = cd.vm[gi], g0i = gd.g0[gi], g1i = gd.g1[gi];
             ti.vx = vmi.x; ti.vy = vmi.y; ti.vz = vmi.z;
             ti.hinv = g0i.x; ti.gk = g0i.y; ti.A = g0i.z; ti.rho = g0i.w;

@@ -195,7 +195,7 @@ __device__ void stage_wave(Smem<R, NACC, FORCE, CFG>& s, const int w, const Deco
             for (int t = lane; t < take; t += kWave) {
                 const int g = S.start + q0 + p + t;
                 R4 e;
-                e.x = cd.rx[g]; e.y = cd.ry[g]; e.z = cd.rz[g];
+                e = cd.rp[g];
                 e.w = half_sq_lo(e.x, e.y, e.z);
                 s.st[w][fill + t] = e;
                 if constexpr (FORCE) { const R hj = gd.g1[g].z; s.sh[w][fill + t] = (R)0.5 * hj * hj; }
@@ -237,7 +237,8 @@ __device__ void stage_wave(Smem<R, NACC, FORCE, CFG>& s, const int w, const Deco
                     // positions now (they may have moved since the ordering was made)
                     const int g = S.start + l;
                     R4 e;
-                    e.x = cd.rx[g] + dox; e.y = cd.ry[g] + doy; e.z = cd.rz[g] + doz;
+                    e = cd.rp[g];
+                    e.x += dox; e.y += doy; e.z += doz;
                     e.w = half_sq_lo(e.x, e.y, e.z);
                     s.st[w][fill + lane] = e;
                     // projection on the segment axis, recomputed from the shifted position
