@@ -50,16 +50,16 @@ struct DensPart {
     R mw, mqdw, div, cx, cy, cz;
 };
 
-// w(q) and q w'(q) of the kernel of Sec. 2.1 from shared terms, t = 1 - q:
-// w = 1 - 6 q^2 t and q w' = 6 q^2 (3q - 2) for q <= 1/2, w = 2 t^3 and
-// q w' = -6 q t^2 above (callers mask q >= 1)
+// w(q) and q w'(q) of the kernel of Sec. 2.1 without branches, t = 1 - q and
+// u = max(1 - 2q, 0): w = 2 t^3 - u^3 and q w' = 6 q (u^2 - t^2), which are
+// 1 - 6q^2 + 6q^3 and q (18q^2 - 12q) for q <= 1/2 (callers mask q >= 1)
 template <typename R>
 __device__ __forceinline__ void kern_w_qdw(R q, R& w, R& qdw)
 {
-    const R t = (R)1 - q, q2 = q * q, t2 = t * t;
-    const bool in = q <= (R)0.5;
-    w = in ? fma((R)-6 * q2, t, (R)1) : (R)2 * t2 * t;
-    qdw = in ? (R)6 * q2 * fma((R)3, q, (R)-2) : (R)-6 * q * t2;
+    const R t = (R)1 - q, u = fmax(fma((R)-2, q, (R)1), (R)0);
+    const R t2 = t * t, u2 = u * u;
+    w = fma((R)2 * t2, t, -(u2 * u));
+    qdw = (R)6 * q * (u2 - t2);
 }
 
 // Newton evaluation: the two sums of Eq. (3) (N and dN/dh need w and q w'),
