@@ -314,24 +314,45 @@ __global__ void k_tree_sources(TreeView tv, const CellInfo* cells, const int32_t
 }
 
 // Per leaf: its list's offset and length, and the wavefront of each source,
-// greedily to the least loaded (cost: source count by direction type).
-__global__ void k_src_finish(const CellInfo* cells, const int32_t* ncells, const uint32_t* group, Source* src,
-                             int64_t src_cap, int32_t* src_off, int32_t* src_count)
+// greedily to the least loaded (cost: source count by direction type).  One
+// wavefront per leaf: its lanes load the costs of 64 sources at once, then
+// the greedy pass walks them in order from registers (readlane).
+constexpr int FIN_THREADS = 256;
+__global__ __launch_bounds__(FIN_THREADS) void k_src_finish(const CellInfo* cells, const int32_t* ncells,
+                                                           const uint32_t* group, Source* src, int64_t src_cap,
+                                                           int32_t* src_off, int32_t* src_count)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= *ncells) return;
-    const int64_t b = group[27 * t], e = group[27 * t + 27];
-    src_off[t] = (int32_t)b;
-    src_count[t] = (int32_t)(e - b);
-    float cost[kSweepWaves] = {0.f, 0.f, 0.f, 0.f};
-    const int64_t end = e < src_cap ? e : src_cap;
-    for (int64_t k = b; k < end; k++) {
-        Source s = src[k];
-        if (s.dir == kSelfDir) continue;
-        int wv = 0;
-        for (int w = 1; w < kSweepWaves; w++) if (cost[w] < cost[wv]) wv = w;
-        cost[wv] += (float)cells[s.cell].count * dir_weight(s.dir);
-        src[k].wave = (int8_t)wv;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nwaves = (int64_t)gridDim.x * (FIN_THREADS / kWave);
+    const int64_t nc = *ncells;
+    for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; t < nc; t += nwaves) {
+        const int64_t b = group[27 * t], e = group[27 * t + 27];
+        if (lane == 0) {
+            src_off[t] = (int32_t)b;
+            src_count[t] = (int32_t)(e - b);
+        }
+        float cost[kSweepWaves] = {0.f, 0.f, 0.f, 0.f};   // the same in every lane
+        const int64_t end = e < src_cap ? e : src_cap;
+        for (int64_t c0 = b; c0 < end; c0 += kWave) {
+            const int64_t k = c0 + lane;
+            int dir = kSelfDir;
+            float my = 0.f;
+            if (k < end) {
+                const Source sk = src[k];
+                dir = sk.dir;
+                if (dir != kSelfDir) my = (float)cells[sk.cell].count * dir_weight(dir);
+            }
+            const int m = (int)(end - c0 < kWave ? end - c0 : kWave);
+            int mine = 0;
+            for (int i = 0; i < m; i++) {
+                if (__builtin_amdgcn_readlane(dir, i) == kSelfDir) continue;
+                int wv = 0;
+                for (int w = 1; w < kSweepWaves; w++) if (cost[w] < cost[wv]) wv = w;
+                cost[wv] += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(my), i));
+                if (lane == i) mine = wv;
+            }
+            if (k < end && dir != kSelfDir) src[k].wave = (int8_t)mine;
+        }
     }
 }
 
@@ -409,8 +430,10 @@ void launch_tree_sources(const TreeView& tv, const CellInfo* cells, const int32_
     exclusive_scan(group, group, ng, scan_scratch, group + ng, st);
     hipLaunchKernelGGL(k_tree_sources<true>, grid_for(ng), dim3(256), 0, st, tv, cells, ncells, boxes, cell_map,
                        src, src_cap, group, status);
-    hipLaunchKernelGGL(k_src_finish, grid_for(cell_cap), dim3(256), 0, st, cells, ncells, group, src, src_cap,
-                       src_off, src_count);
+    // one wavefront per leaf; leaves number at most cell_cap, the grid strides over them
+    const int64_t fb = (cell_cap + FIN_THREADS / kWave - 1) / (FIN_THREADS / kWave);
+    hipLaunchKernelGGL(k_src_finish, dim3((unsigned)(fb < 2048 ? fb : 2048)), dim3(FIN_THREADS), 0, st, cells,
+                       ncells, group, src, src_cap, src_off, src_count);
 }
 
 void launch_estimate_h(const TreeView& tv, const BoxInfo* boxes, double n_ngb, double* h, int64_t n,
