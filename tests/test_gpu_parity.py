@@ -3,15 +3,18 @@
 Every input is a seeded synthetic set from paper_1404_2303_amd.workloads;
 tolerances are derived in tests/parity_util.py.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
 
 import oracle
 from paper_1404_2303_amd import sph, workloads
-from parity_util import compare, gpu_run, log, oracle_run
+from parity_util import TOL, compare, gpu_run, log, oracle_run
 
 pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 @pytest.fixture(scope="module")
@@ -231,3 +234,67 @@ def test_kernel_times_before_any_force_leave_no_error():
     parts.h.add_(0.0)   # a torch launch after the query
     torch.cuda.synchronize()
     ctx.close()
+
+
+def _config1_graph(ps):
+    """The pass as the bench line times it: captured once with h restored from the
+    initial guess inside the graph, then replayed (twice here)."""
+    parts = sph.Particles.from_numpy(ps, "cuda:0")
+    h0 = parts.h.clone()
+    n = ps.n
+    dout = {k: torch.empty(n, dtype=torch.float64, device="cuda:0") for k in ("rho", "omega", "div_v", "balsara")}
+    dout["curl_v"] = torch.empty((n, 3), dtype=torch.float64, device="cuda:0")
+    ctx = sph.Context(ps.box, precision="fp32")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        _, fout = ctx.graph_capture(parts, None, h_init=h0, dout=dout)
+        ctx.check()
+        ctx.graph_launch()
+        ctx.graph_launch()
+        torch.cuda.synchronize()
+        ctx.check()
+    out = {k: v.cpu().numpy() for k, v in dout.items()}
+    out.update({k: v.cpu().numpy() for k, v in fout.items()})
+    out["h"] = parts.h.cpu().numpy()
+    out["a"] = np.stack([out["ax"], out["ay"], out["az"]], axis=1)
+    out["stats"] = ctx.stats()
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("mode", ["eager", "graph"])
+def test_config1_sampled_fp32(mode):
+    """The 2^20-particle jittered lattice of the bench line, in its launch
+    configuration (FP32 form, default parameters; eager calls, or the captured
+    pass replayed as the bench times it), checked at the oracle's sample
+    (tests/golden/config1_sample.txt, written by make_config1_sample.py from the
+    oracle alone)."""
+    path = os.path.join(HERE, "golden", "config1_sample.txt")
+    ref = np.loadtxt(path)
+    cols = open(path).readline().lstrip("# ").split()
+    R = {c: ref[:, k] for k, c in enumerate(cols)}
+    idx = R["index"].astype(np.int64)
+    ps = workloads.config1()
+    log(f"case config1 {ps.n} fp32 {mode}")
+    g = gpu_run(ps, "fp32") if mode == "eager" else _config1_graph(ps)
+    log(f"  cells {g['stats']['n_cells']} grid {g['stats']['grid']}")
+    t = TOL["fp32"]
+    e = {}
+    h_band = np.maximum(t["h"], t["ngb"] / (R["h"] * np.abs(R["dndh"])))
+    e["h"] = np.max(np.abs(g["h"][idx] / R["h"] - 1) / h_band) * t["h"]
+    e["rho"] = np.max(np.abs(g["rho"][idx] / R["rho"] - 1))
+    e["omega"] = np.max(np.abs(g["omega"][idx] - R["omega"]))
+    e["f"] = np.max(np.abs(g["balsara"][idx] - R["f"]))
+    rd = np.sqrt(np.mean(R["div"] ** 2))
+    e["div"] = np.max(np.abs(g["div_v"][idx] - R["div"]) / (rd + np.abs(R["div"])))
+    curl = np.stack([R["curl_x"], R["curl_y"], R["curl_z"]], 1)
+    rc = np.sqrt(np.mean(np.sum(curl ** 2, 1)))
+    e["curl"] = np.max(np.linalg.norm(g["curl_v"][idx] - curl, axis=1) / (rc + np.linalg.norm(curl, axis=1)))
+    a = np.stack([R["ax"], R["ay"], R["az"]], 1)
+    e["a"] = np.max(np.linalg.norm(g["a"][idx] - a, axis=1) / R["kappa_a"])
+    e["dudt"] = np.max(np.abs(g["dudt"][idx] - R["dudt"]) / R["kappa_u"])
+    e["count"] = int(np.max(np.abs(g["n_pairs"][idx] - R["count"]) - R["band"]))
+    log("  " + " ".join(f"{k}={v:.2e}" if isinstance(v, float) else f"{k}={v}" for k, v in e.items()))
+    assert e["h"] <= t["h"] and e["rho"] <= t["rho"] and e["omega"] <= t["omega"] and e["f"] <= t["f"]
+    assert e["div"] <= t["vec"] and e["curl"] <= t["vec"] and e["a"] <= t["a"] and e["dudt"] <= t["a"]
+    assert e["count"] <= 0

@@ -123,18 +123,20 @@ def test_adjoint_on_the_hierarchy():
     assert e <= 1e-8
 
 
-def test_config2_sampled_fp32():
+@pytest.mark.parametrize("split_count", [64, 256])
+def test_config2_sampled_fp32(split_count):
     """The 2,097,152-particle Plummer mixture through the hierarchy, checked at
     the oracle's sample (tests/golden/config2_sample.txt, written by
-    make_config2_sample.py from the oracle alone)."""
+    make_config2_sample.py from the oracle alone); split count 256 is the
+    bench's autotuned launch configuration."""
     path = os.path.join(HERE, "golden", "config2_sample.txt")
     ref = np.loadtxt(path)
     cols = open(path).readline().lstrip("# ").split()
     R = {c: ref[:, k] for k, c in enumerate(cols)}
     idx = R["index"].astype(np.int64)
     ps = workloads.config2()
-    log(f"case tree config2 {ps.n} fp32")
-    g = gpu_run(ps, "fp32", estimate=True, max_depth=10, split_count=64)
+    log(f"case tree config2 {ps.n} fp32 split_count {split_count}")
+    g = gpu_run(ps, "fp32", estimate=True, max_depth=10, split_count=split_count)
     st = g["stats"]
     log(f"  leaves {st['n_cells']} depth {st['depth']} top grid {st['grid']} rebuilds {st['rebuilds']}")
     t = TOL["fp32"]
