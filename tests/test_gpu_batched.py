@@ -115,3 +115,42 @@ def test_density_async_and_check():
     ref = oracle.full_pass(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box)
     assert np.allclose(d["rho"].cpu().numpy(), ref["dens"]["rho"], rtol=1e-9)
     ctx.close()
+
+
+@pytest.mark.parametrize("cell_target", [32, 64])
+def test_full_batch_as_the_bench_runs_it(cell_target):
+    """The 256-box set of the bench (5.36M particles, log-uniform counts in
+    [2048, 65536]) as one captured pass, replayed; the smallest and largest box
+    and two others checked whole against the oracle.  Cell size 32 is the one
+    the autotuner picks on this set, 64 the default."""
+    cat, offsets, lens = workloads.batch()
+    counts = np.diff(offsets)
+    rng = np.random.default_rng(4)
+    boxes = sorted({int(np.argmin(counts)), int(np.argmax(counts))} | set(int(b) for b in rng.choice(256, 2)))
+    log(f"case full batch {cat.n} particles, cell_target {cell_target}, boxes {boxes}")
+    parts = sph.Particles.from_numpy(cat, "cuda:0")
+    h0 = parts.h.clone()
+    n = cat.n
+    dout = {k: torch.empty(n, dtype=torch.float64, device="cuda:0") for k in ("rho", "omega", "div_v", "balsara",
+                                                                            "pressure", "sound", "n_ngb")}
+    dout["curl_v"] = torch.empty((n, 3), dtype=torch.float64, device="cuda:0")
+    ctx = sph.Context((1, 1, 1), precision="fp32", cell_target=cell_target)
+    batch = sph.Batch(offsets, lens)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        _, fout = ctx.graph_capture(parts, batch, h_init=h0, dout=dout)
+        ctx.check()
+        ctx.graph_launch()
+        ctx.graph_launch()
+        torch.cuda.synchronize()
+        ctx.check()
+    for b in boxes:
+        sl = slice(offsets[b], offsets[b + 1])
+        ps = workloads.uniform(int(counts[b]), seed=b)
+        ref = oracle.full_pass(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box)
+        g = {k: v[sl].cpu().numpy() for k, v in dout.items()}
+        g.update({k: v[sl].cpu().numpy() for k, v in fout.items()})
+        g["h"] = parts.h[sl].cpu().numpy()
+        g["a"] = np.stack([g["ax"], g["ay"], g["az"]], 1)
+        compare(g, ref, "fp32", label=f"box{b} n={counts[b]}")
+    ctx.close()
