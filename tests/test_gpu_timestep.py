@@ -336,3 +336,44 @@ def test_sedov_blast_follows_the_similarity_solution():
     log(f"  d ln R / d ln t = {slope:.3f}")
     assert abs(slope - 0.4) < 0.04
     ctx.close()
+
+
+def test_sod_at_the_bench_size_sampled():
+    """The first pass of the Sod tube the bench steps (1,013,060 particles, wide
+    staging, |div v| Balsara form), checked at the oracle's sample
+    (tests/golden/sod_sample.txt, written by make_sod_sample.py from the oracle
+    alone: half the sample within 0.1 of the density jumps), Eq. (6) included."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sod_sample.txt")
+    ref = np.loadtxt(path)
+    cols = open(path).readline().lstrip("# ").split()
+    R = {c: ref[:, k] for k, c in enumerate(cols)}
+    idx = R["index"].astype(np.int64)
+    ps = workloads.sod(37)
+    log(f"case sod bench size {ps.n} fp32, wide staging")
+    g = gpu_run(ps, "fp32", balsara_form=sph.SPH_BALSARA_DIV, staging=sph.SPH_STAGING_WIDE)
+    from parity_util import TOL
+    t = TOL["fp32"]
+    e = {}
+    h_band = np.maximum(t["h"], t["ngb"] / (R["h"] * np.abs(R["dndh"])))
+    e["h"] = np.max(np.abs(g["h"][idx] / R["h"] - 1) / h_band) * t["h"]
+    e["rho"] = np.max(np.abs(g["rho"][idx] / R["rho"] - 1))
+    e["P"] = np.max(np.abs(g["pressure"][idx] / R["P"] - 1))
+    e["c"] = np.max(np.abs(g["sound"][idx] / R["c"] - 1))
+    e["omega"] = np.max(np.abs(g["omega"][idx] - R["omega"]))
+    e["f"] = np.max(np.abs(g["balsara"][idx] - R["f"]))
+    rd = np.sqrt(np.mean(R["div"] ** 2)) + 1e-300
+    e["div"] = np.max(np.abs(g["div_v"][idx] - R["div"]) / (rd + np.abs(R["div"])))
+    a = np.stack([R["ax"], R["ay"], R["az"]], 1)
+    e["a"] = np.max(np.linalg.norm(g["a"][idx] - a, axis=1) / R["kappa_a"])
+    e["dudt"] = np.max(np.abs(g["dudt"][idx] - R["dudt"]) / (R["kappa_u"] + 1e-300))
+    e["count"] = int(np.max(np.abs(g["n_pairs"][idx] - R["count"]) - R["band"]))
+    vs = CFL * 2.0 * g["h"][idx] / g["dt"][idx]
+    tv = T_VSIG["fp32"] + T_H["fp32"]
+    e["vsig_below"] = float(-np.min(vs / R["vsig_lo"] - 1.0))
+    e["vsig_above"] = float(np.max(vs / R["vsig_hi"] - 1.0))
+    log("  " + " ".join(f"{k}={v:.2e}" if isinstance(v, float) else f"{k}={v}" for k, v in e.items()))
+    assert e["h"] <= t["h"] and e["rho"] <= t["rho"] and e["P"] <= t["rho"] and e["c"] <= t["rho"]
+    assert e["omega"] <= t["omega"] and e["f"] <= t["f"] and e["div"] <= t["vec"]
+    assert e["a"] <= t["a"] and e["dudt"] <= t["a"] and e["count"] <= 0
+    assert e["vsig_below"] <= tv and e["vsig_above"] <= tv
