@@ -8,7 +8,8 @@ The arithmetic lives in ``sph_oracle.c`` (plain C, FP64, one-sided gathers
 over a periodic cell list); this module only marshals numpy arrays.  Each
 function names the part of Gonnet (2014) it evaluates:
 
-* :func:`kernel_w`, :func:`kernel_dw` -- cubic spline w(q), w'(q), Sec. 2.1.
+* :func:`kernel_w`, :func:`kernel_dw`, :func:`kernel_d2w` -- cubic spline w(q) and
+  its first two derivatives, Sec. 2.1.
 * :func:`solve_h` -- Newton iteration of Eq. (3) for N_i(h_i) = N_ngb.
 * :func:`density` -- Eq. (2), Eq. (3) and dN/dh, drho/dh (for Omega), and the
   velocity divergence and curl of Sec. 4.1.
@@ -77,6 +78,10 @@ def _load():
         lib.ora_W.argtypes = [d, d]
         lib.ora_dWdr.restype = d
         lib.ora_dWdr.argtypes = [d, d]
+        lib.ora_d2w.restype = d
+        lib.ora_d2w.argtypes = [d]
+        lib.ora_dWdr_dlnh.restype = d
+        lib.ora_dWdr_dlnh.argtypes = [d, d]
         lib.ora_dWdh.restype = d
         lib.ora_dWdh.argtypes = [d, d]
         lib.ora_solve_h.restype = i32
@@ -88,7 +93,7 @@ def _load():
         lib.ora_signal.restype = i32
         lib.ora_signal.argtypes = [i64, P, P, P, P, P, P, P, P, P, d, i64, P, P, P, P, P]
         lib.ora_force.restype = i32
-        lib.ora_force.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, P, P, d, i64, P] + [P] * 8
+        lib.ora_force.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, P, P, d, i64, P] + [P] * 10
         lib.ora_brute_count.restype = None
         lib.ora_brute_count.argtypes = [i64, P, P, P, P, P, P]
         lib.ora_num_threads.restype = i32
@@ -124,6 +129,11 @@ def kernel_w(q):
 def kernel_dw(q):
     lib = _load()
     return np.array([lib.ora_dw(float(v)) for v in np.atleast_1d(q)])
+
+
+def kernel_d2w(q):
+    lib = _load()
+    return np.array([lib.ora_d2w(float(v)) for v in np.atleast_1d(q)])
 
 
 def kernel_W(r, h):
@@ -207,7 +217,11 @@ def ghost(dens, u, h, gamma=GAMMA, balsara_form=0):
 
 
 def force(pos, vel, m, h, rho, A, c, f, box, alpha=ALPHA, sel=None):
-    """Eqs. (4)-(5) with Monaghan-Balsara viscosity (Sec. 4.1)."""
+    """Eqs. (4)-(5) with Monaghan-Balsara viscosity (Sec. 4.1).  Besides a and
+    du/dt: kappa_a, kappa_u (sums of the magnitudes of the pair terms) and
+    sens_a, sens_u (sums of the magnitudes of each pair term's derivatives with
+    respect to ln h_i and ln h_j, the other inputs held fixed): the scales of
+    the rounding and of the h tolerance in a and du/dt."""
     lib = _load()
     x, y, z = _split(pos)
     n = len(x)
@@ -216,13 +230,14 @@ def force(pos, vel, m, h, rho, A, c, f, box, alpha=ALPHA, sel=None):
     m = _c(np.broadcast_to(np.asarray(m, dtype=np.float64), (n,)))
     L = _c(box)
     ns, s = _sel(sel, n)
-    out = {k: np.full(n, np.nan) for k in ("ax", "ay", "az", "dudt", "kappa_a", "kappa_u")}
+    out = {k: np.full(n, np.nan) for k in ("ax", "ay", "az", "dudt", "kappa_a", "kappa_u", "sens_a", "sens_u")}
     out["count"] = np.full(n, -1, dtype=np.int32)
     out["band"] = np.full(n, -1, dtype=np.int32)
     st = lib.ora_force(n, _p(x), _p(y), _p(z), _p(vx), _p(vy), _p(vz), _p(m), _p(_c(h)),
                        _p(_c(rho)), _p(_c(A)), _p(_c(c)), _p(_c(f)), _p(L), float(alpha), ns, _p(s),
                        _p(out["ax"]), _p(out["ay"]), _p(out["az"]), _p(out["dudt"]),
-                       _p(out["kappa_a"]), _p(out["kappa_u"]), _p(out["count"]), _p(out["band"]))
+                       _p(out["kappa_a"]), _p(out["kappa_u"]), _p(out["count"]), _p(out["band"]),
+                       _p(out["sens_a"]), _p(out["sens_u"]))
     _check(st, "force")
     out["a"] = np.stack([out["ax"], out["ay"], out["az"]], axis=1)
     return out

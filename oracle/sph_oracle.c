@@ -62,10 +62,26 @@ double ora_dw(double q)
     return 0.0;
 }
 
+/* d^2w/dq^2 */
+double ora_d2w(double q)
+{
+    if (q < 0.0) q = -q;
+    if (q <= 0.5) return -12.0 + 36.0 * q;
+    if (q <= 1.0) return 12.0 * (1.0 - q);
+    return 0.0;
+}
+
 double ora_W(double r, double h) { return 8.0 / (ORA_PI * h * h * h) * ora_w(r / h); }
 
 /* dW/dr */
 double ora_dWdr(double r, double h) { return 8.0 / (ORA_PI * h * h * h * h) * ora_dw(r / h); }
+
+/* d(dW/dr)/d(ln h) at fixed r: dW/dr = 8/(pi h^4) w'(r/h) */
+double ora_dWdr_dlnh(double r, double h)
+{
+    double q = r / h;
+    return -8.0 / (ORA_PI * h * h * h * h) * (4.0 * ora_dw(q) + q * ora_d2w(q));
+}
 
 /* dW/dh at fixed r: W = 8/(pi h^3) w(r/h) */
 double ora_dWdh(double r, double h)
@@ -509,13 +525,19 @@ int ora_signal(int64_t np, const double *x, const double *y, const double *z,
  * of du only has support r < h_i, which the kernel gradient enforces.
  * kappa_a / kappa_u: sum over j of the magnitudes of the individual pair
  * contributions (a scale for the cancellation in a_i and du_i).
+ * sens_a / sens_u: sum over j of the magnitudes of the derivatives of each
+ * pair contribution with respect to ln h_i and to ln h_j, rho, A, c and f
+ * held fixed (how far a relative change of the smoothing lengths moves the
+ * sums; near the edge of the support w' vanishes like (1-q)^2, so a term there
+ * moves by up to 2q/(1-q) times that change).  Either may be NULL.
  */
 int ora_force(int64_t np, const double *x, const double *y, const double *z,
               const double *vx, const double *vy, const double *vz, const double *m,
               const double *h, const double *rho, const double *A, const double *c,
               const double *f, const double L[3], double alpha, int64_t nsel, const int64_t *sel,
               double *ax, double *ay, double *az, double *dudt,
-              double *kappa_a, double *kappa_u, int32_t *count, int32_t *band)
+              double *kappa_a, double *kappa_u, int32_t *count, int32_t *band,
+              double *sens_a, double *sens_u)
 {
     if (np <= 0 || !x || !h || !m || !rho || !A || !c || !f) return ORA_E_ARG;
     double hmax = 0.0, hmin = INFINITY;
@@ -537,7 +559,7 @@ int ora_force(int64_t np, const double *x, const double *y, const double *z,
                 { if (status == ORA_OK) status = e; }
                 continue;
             }
-            double sax = 0, say = 0, saz = 0, sdu = 0, ka = 0, ku = 0;
+            double sax = 0, say = 0, saz = 0, sdu = 0, ka = 0, ku = 0, sa = 0, su = 0;
             int32_t cnt = 0, b = 0;
             for (int64_t t = 0; t < l.n; t++) {
                 ora_nb nb = l.v[t];
@@ -563,10 +585,17 @@ int ora_force(int64_t np, const double *x, const double *y, const double *z,
                 sax += pax; say += pay; saz += paz; sdu += pdu;
                 ka += sqrt(pax * pax + pay * pay + paz * paz);
                 ku += fabs(pdu);
+                /* derivatives of gi, gj with respect to ln h_i, ln h_j */
+                double di = (r > 0.0) ? ora_dWdr_dlnh(r, h[i]) / r : 0.0;
+                double dj = (r > 0.0) ? ora_dWdr_dlnh(r, h[j]) / r : 0.0;
+                sa += (fabs(m[j] * di * (A[i] + 0.25 * Pi * fij)) + fabs(m[j] * dj * (A[j] + 0.25 * Pi * fij))) * r;
+                su += fabs(m[j] * vdotr * di * (A[i] + 0.125 * Pi * fij)) + fabs(0.125 * m[j] * Pi * vdotr * dj * fij);
             }
             ax[i] = sax; ay[i] = say; az[i] = saz; dudt[i] = sdu;
             if (kappa_a) kappa_a[i] = ka;
             if (kappa_u) kappa_u[i] = ku;
+            if (sens_a) sens_a[i] = sa;
+            if (sens_u) sens_u[i] = su;
             if (count) count[i] = cnt;
             if (band) band[i] = b;
         }

@@ -19,7 +19,7 @@ import oracle  # noqa: E402
 from paper_1404_2303_amd import workloads  # noqa: E402
 
 COLUMNS = ["index", "h", "rho", "omega", "div", "f", "P", "c", "ax", "ay", "az", "dudt", "kappa_a", "kappa_u",
-           "count", "band", "dndh", "dt", "vsig_lo", "vsig_hi"]
+           "count", "band", "dndh", "dt", "vsig_lo", "vsig_hi", "sens_a", "sens_u"]
 
 
 def sample_indices(ps, k=64, seed=4):
@@ -40,7 +40,7 @@ def main():
     rows = np.column_stack([sel, out["h"][sel], d["rho"][sel], g["omega"][sel], d["div"][sel], g["f"][sel],
                             g["P"][sel], g["c"][sel], f["a"][sel], f["dudt"][sel], f["kappa_a"][sel],
                             f["kappa_u"][sel], f["count"][sel], f["band"][sel], d["dndh"][sel], s["dt"][sel],
-                            s["vsig_lo"][sel], s["vsig_hi"][sel]])
+                            s["vsig_lo"][sel], s["vsig_hi"][sel], f["sens_a"][sel], f["sens_u"][sel]])
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "sod_sample.txt")
     np.savetxt(path, rows, fmt="%.17g", header=" ".join(COLUMNS))
     print("wrote", path, rows.shape)

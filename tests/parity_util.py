@@ -29,6 +29,14 @@ The Balsara switch f = |curl| / (|div| + |curl| + eps c/h) moves by at most
 tolerance it is allowed the div and curl tolerance scaled that way:
 vec (rms_div + rms_curl + |div| + |curl|) / den.
 
+The h tolerance also reaches a and du/dt through the kernel gradients, most
+where a pair sits near the edge of a support: w' vanishes there like (1-q)^2,
+so the pair term moves by up to 2q/(1-q) times the relative change of h (a
+particle whose force comes from one neighbour at q = 0.994 has a sensitivity
+of ~300).  a and du/dt are therefore measured against kappa + (h tolerance /
+a tolerance) sens, sens the oracle's sum of the magnitudes of the derivatives
+of the pair terms with respect to ln h_i and ln h_j.
+
 Neighbour counts (pairs with r < max(h_i, h_j)) must match exactly except
 for pairs within 1e-6 relative of the support radius, which the oracle counts
 per particle ("band").
@@ -106,8 +114,8 @@ def compare(g, ref, precision, sel=None, force_sel=None, label=""):
     err["div"] = np.max(np.abs(g["div_v"][sel] - dens["div"][sel]) / (rms_div + np.abs(dens["div"][sel])))
     err["curl"] = np.max(np.linalg.norm(g["curl_v"][sel] - dens["curl"][sel], axis=1) /
                          (rms_curl + np.linalg.norm(dens["curl"][sel], axis=1)))
-    ka = frc["kappa_a"][fsel] + 1e-300
-    ku = frc["kappa_u"][fsel] + 1e-300
+    ka = frc["kappa_a"][fsel] + t["h"] / t["a"] * frc["sens_a"][fsel] + 1e-300
+    ku = frc["kappa_u"][fsel] + t["h"] / t["a"] * frc["sens_u"][fsel] + 1e-300
     err["a"] = np.max(np.linalg.norm(g["a"][fsel] - frc["a"][fsel], axis=1) / ka)
     err["dudt"] = np.max(np.abs(g["dudt"][fsel] - frc["dudt"][fsel]) / ku)
     dc = np.abs(g["n_pairs"][fsel].astype(np.int64) - frc["count"][fsel])

@@ -338,21 +338,20 @@ def test_sedov_blast_follows_the_similarity_solution():
     ctx.close()
 
 
-def test_sod_at_the_bench_size_sampled():
-    """The first pass of the Sod tube the bench steps (1,013,060 particles, wide
-    staging, |div v| Balsara form), checked at the oracle's sample
-    (tests/golden/sod_sample.txt, written by make_sod_sample.py from the oracle
-    alone: half the sample within 0.1 of the density jumps), Eq. (6) included."""
+def _load_sample(name):
     import os
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sod_sample.txt")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
     ref = np.loadtxt(path)
     cols = open(path).readline().lstrip("# ").split()
-    R = {c: ref[:, k] for k, c in enumerate(cols)}
-    idx = R["index"].astype(np.int64)
-    ps = workloads.sod(37)
-    log(f"case sod bench size {ps.n} fp32, wide staging")
-    g = gpu_run(ps, "fp32", balsara_form=sph.SPH_BALSARA_DIV, staging=sph.SPH_STAGING_WIDE)
+    return {c: ref[:, k] for k, c in enumerate(cols)}
+
+
+def _check_sample(g, R):
+    """First-pass outputs of the FP32 form at the oracle's sampled particles,
+    with Eq. (6)'s signal velocity inside the oracle's band; a and du/dt
+    against kappa plus the h tolerance's reach through sens."""
     from parity_util import TOL
+    idx = R["index"].astype(np.int64)
     t = TOL["fp32"]
     e = {}
     h_band = np.maximum(t["h"], t["ngb"] / (R["h"] * np.abs(R["dndh"])))
@@ -365,8 +364,10 @@ def test_sod_at_the_bench_size_sampled():
     rd = np.sqrt(np.mean(R["div"] ** 2)) + 1e-300
     e["div"] = np.max(np.abs(g["div_v"][idx] - R["div"]) / (rd + np.abs(R["div"])))
     a = np.stack([R["ax"], R["ay"], R["az"]], 1)
-    e["a"] = np.max(np.linalg.norm(g["a"][idx] - a, axis=1) / R["kappa_a"])
-    e["dudt"] = np.max(np.abs(g["dudt"][idx] - R["dudt"]) / (R["kappa_u"] + 1e-300))
+    ka = R["kappa_a"] + t["h"] / t["a"] * R["sens_a"]
+    ku = R["kappa_u"] + t["h"] / t["a"] * R["sens_u"] + 1e-300
+    e["a"] = np.max(np.linalg.norm(g["a"][idx] - a, axis=1) / ka)
+    e["dudt"] = np.max(np.abs(g["dudt"][idx] - R["dudt"]) / ku)
     e["count"] = int(np.max(np.abs(g["n_pairs"][idx] - R["count"]) - R["band"]))
     vs = CFL * 2.0 * g["h"][idx] / g["dt"][idx]
     tv = T_VSIG["fp32"] + T_H["fp32"]
@@ -377,3 +378,47 @@ def test_sod_at_the_bench_size_sampled():
     assert e["omega"] <= t["omega"] and e["f"] <= t["f"] and e["div"] <= t["vec"]
     assert e["a"] <= t["a"] and e["dudt"] <= t["a"] and e["count"] <= 0
     assert e["vsig_below"] <= tv and e["vsig_above"] <= tv
+
+
+def test_sod_at_the_bench_size_sampled():
+    """The first pass of the Sod tube the bench steps (1,013,060 particles, wide
+    staging, |div v| Balsara form), checked at the oracle's sample
+    (tests/golden/sod_sample.txt, written by make_sod_sample.py from the oracle
+    alone: half the sample within 0.1 of the density jumps), Eq. (6) included."""
+    R = _load_sample("sod_sample.txt")
+    ps = workloads.sod(37)
+    log(f"case sod bench size {ps.n} fp32, wide staging")
+    g = gpu_run(ps, "fp32", balsara_form=sph.SPH_BALSARA_DIV, staging=sph.SPH_STAGING_WIDE)
+    _check_sample(g, R)
+
+
+def test_sedov_at_the_bench_size_sampled():
+    """The first pass of the Sedov blast the bench steps with time bins
+    (1,000,188 particles, compact staging, |div v| Balsara form), checked at the
+    oracle's sample (tests/golden/sedov_sample.txt, written by
+    make_sedov_sample.py from the oracle alone: half the sample within 0.05 of
+    the centre, where the energy sits), Eq. (6) included; then the time bins of
+    sph_mts_init (Sec. 4.1) at the sample, against the oracle's bin of every
+    step inside Eq. (6)'s tolerance band, on a base step of 0.7 times the
+    sample's smallest step (every ratio at least 0.2 away from a power of two)."""
+    R = _load_sample("sedov_sample.txt")
+    idx = R["index"].astype(np.int64)
+    ps = workloads.sedov(63)
+    log(f"case sedov bench size {ps.n} fp32, compact staging")
+    g = gpu_run(ps, "fp32", balsara_form=sph.SPH_BALSARA_DIV)
+    _check_sample(g, R)
+    dtb = 0.7 * float(R["dt"].min())
+    tv = T_VSIG["fp32"] + T_H["fp32"]
+    dt_lo = CFL * 2.0 * R["h"] / R["vsig_hi"] / (1.0 + tv)
+    dt_hi = CFL * 2.0 * R["h"] / R["vsig_lo"] / (1.0 - tv)
+    k_lo = oracle.time_bin(dt_lo, dtb, 10, 0)
+    k_hi = oracle.time_bin(dt_hi, dtb, 10, 0)
+    parts = sph.Particles.from_numpy(ps, "cuda:0")
+    ctx = sph.Context(ps.box, precision="fp32", balsara_form=sph.SPH_BALSARA_DIV)
+    acc, bins = ctx.mts_init(parts, dtb, 10)
+    torch.cuda.synchronize()
+    kb = bins.cpu().numpy()[idx]
+    ctx.close()
+    log(f"  bins {np.bincount(kb, minlength=11).tolist()}, oracle band differs at {int(np.sum(k_lo != k_hi))}")
+    assert np.all((kb >= k_lo) & (kb <= k_hi))
+    assert len(set(kb.tolist())) >= 3

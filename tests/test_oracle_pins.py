@@ -70,6 +70,8 @@ def test_kernel_derivatives_match_finite_differences(q):
     assert oracle.kernel_dWdr(r, h) == pytest.approx(fdr, rel=1e-7)
     fdh = (oracle.kernel_W(r, h + d) - oracle.kernel_W(r, h - d)) / (2 * d)
     assert oracle.kernel_dWdh(r, h) == pytest.approx(fdh, rel=1e-7)
+    fd2 = (oracle.kernel_dw(q + d)[0] - oracle.kernel_dw(q - d)[0]) / (2 * d)
+    assert oracle.kernel_d2w(q)[0] == pytest.approx(fd2, rel=1e-7, abs=1e-8)
 
 
 # ---------------------------------------------------------------- perfect lattice
@@ -257,6 +259,40 @@ def test_pressure_force_is_repulsive_for_two_particles():
     assert np.dot(f["a"][0], r12) > 0 and np.dot(f["a"][1], r12) < 0
     assert np.allclose(np.cross(f["a"][0], r12), 0, atol=1e-12 * np.linalg.norm(f["a"][0]))
     assert np.allclose(m[0] * f["a"][0], -m[1] * f["a"][1], rtol=1e-13)
+
+
+@pytest.mark.parametrize("sep, A, f", [(0.05, (1.0, 0.5), (0.0, 0.0)), (0.097, (1.0, 0.5), (0.3, 0.9)),
+                                       (0.066, (1e-6, 1e-6), (1.0, 1.0)), (0.0695, (2.0, 1e-3), (0.5, 0.2))])
+def test_h_sensitivity_of_the_force_matches_finite_differences(sep, A, f):
+    # one approaching pair isolated in a large box, h_1 = 0.1, h_2 = 0.07 (the
+    # pair inside one or both supports, near the edge of one in the second and
+    # fourth cases, viscosity dominant in the third): sens_a and sens_u of
+    # particle 1 must equal the magnitudes of the central differences of its a
+    # and du/dt over ln h_1 plus those over ln h_2, rho, A, c and f held fixed.
+    e = np.array([0.6, 0.64, -0.48])
+    pos = np.array([[0.5, 0.5, 0.5], 0.5 + sep * e])
+    vel = np.array([[0.3, -0.1, 0.2], [-0.4, 0.3, -0.5]])
+    m = np.array([1.0, 2.0])
+    h = np.array([0.1, 0.07])
+    rho, A, c, f = np.array([3.0, 2.5]), np.array(A), np.array([1.0, 1.3]), np.array(f)
+    box = np.ones(3)
+    run = lambda hh: oracle.force(pos, vel, m, hh, rho, A, c, f, box, alpha=1.5, sel=[0])
+    ref = run(h)
+    assert ref["count"][0] == 1
+    eps = 1e-6
+    fd_a, fd_u = 0.0, 0.0
+    for k in range(2):
+        up, dn = h.copy(), h.copy()
+        up[k] *= math.exp(eps)
+        dn[k] *= math.exp(-eps)
+        p, q = run(up), run(dn)
+        fd_a += np.linalg.norm(p["a"][0] - q["a"][0]) / (2 * eps)
+        fd_u += abs(p["dudt"][0] - q["dudt"][0]) / (2 * eps)
+    assert ref["sens_a"][0] == pytest.approx(fd_a, rel=1e-6)
+    assert ref["sens_u"][0] == pytest.approx(fd_u, rel=1e-6)
+    # near the edge of a support the sensitivity far exceeds the term itself
+    if abs(sep / 0.1 - 1) < 0.05:
+        assert ref["sens_a"][0] > 10 * ref["kappa_a"][0]
 
 
 # ---------------------------------------------------------------- div / curl, Sec. 4.1
