@@ -92,6 +92,11 @@ typedef struct {
                             sph_step_adaptive (SPH_REUSE_*) */
     int staging;         /* FP32 density stage: sources staged per wavefront and work-groups
                             per compute unit (SPH_STAGING_*); FP64 has one form */
+    int shared_min;      /* force stage: cells of more than this many particles are swept
+                            shared (each wavefront takes 64 targets and walks the sources
+                            staged by all four, so that a batch of sources is staged once
+                            per 256 targets rather than per 64); >= 64; results agree
+                            with the other sweep up to summation order */
 } sph_params;
 
 /* Staging of the FP32 density stage.  A target cell's sources are copied into
@@ -130,7 +135,8 @@ enum {
 /* Default parameters: the paper's constants (48, 5/3, 0.8, 1e-4, C_CFL 1/4),
  * FP32_ACC64, cell_target 64, h_margin 0.1, max_iter 64, max_rebuilds 4, unit
  * box, max_depth 0 (single-level grid), split_count 64, split_frac 0.875,
- * balsara_form SPH_BALSARA_CURL, reuse SPH_REUSE_OFF, staging SPH_STAGING_COMPACT. */
+ * balsara_form SPH_BALSARA_CURL, reuse SPH_REUSE_OFF, staging SPH_STAGING_COMPACT,
+ * shared_min 128. */
 void sph_default_params(sph_params *p);
 
 typedef struct {

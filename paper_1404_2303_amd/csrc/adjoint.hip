@@ -250,7 +250,7 @@ __global__ __launch_bounds__(WGS) void k_adj_sweep(Decomp dc, CellData<R> cd, So
                 int seg = 0, jj = s.nseg[w] > 0 ? s.seg_b[w][0] : 0;
                 int cnt = 0;
                 while (true) {
-                    cnt = walk<R, true, NACC_ADJ>(s, w, lane, valid, xi, yi, zi, fxi, fyi, fzi, hi, fh, margin, selfj,
+                    cnt = walk<R, true, NACC_ADJ>(s, w, w, lane, valid, xi, yi, zi, fxi, fyi, fzi, hi, fh, margin, selfj,
                                                   seg, jj, cnt);
                     process(cnt);
                     cnt = 0;

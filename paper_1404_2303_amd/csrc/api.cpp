@@ -195,6 +195,7 @@ static PassConsts pass_consts(const sph_params& p)
     pc.h_margin = p.h_margin;
     pc.cfl = p.cfl;
     pc.balsara_div = p.balsara_form == SPH_BALSARA_DIV ? 1 : 0;
+    pc.shared_min = p.shared_min;
     return pc;
 }
 
@@ -262,6 +263,7 @@ void sph_default_params(sph_params* p)
     p->balsara_form = SPH_BALSARA_CURL;
     p->reuse = 0;
     p->staging = SPH_STAGING_COMPACT;
+    p->shared_min = 128;
 }
 
 const char* sph_status_string(sph_status s)
@@ -298,6 +300,7 @@ static bool params_ok(const sph_params& p)
     if (p.balsara_form != SPH_BALSARA_CURL && p.balsara_form != SPH_BALSARA_DIV) return false;
     if (p.reuse != SPH_REUSE_OFF && p.reuse != SPH_REUSE_ORDERINGS && p.reuse != SPH_REUSE_CELLS) return false;
     if (p.staging != SPH_STAGING_COMPACT && p.staging != SPH_STAGING_WIDE) return false;
+    if (p.shared_min < 64) return false;
     return true;
 }
 

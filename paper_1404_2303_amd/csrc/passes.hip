@@ -32,6 +32,12 @@
 // per-particle quantities of the force stage (Omega, P, c, A = P/(Omega rho^2),
 // the Balsara switch of Sec. 4.1) are formed at the end.
 // Force (Eqs. (4)-(5) + Sec. 4.1 viscosity): one sweep over r < max(h_i, h_j).
+// A cell of more than shared_min particles is swept shared instead: each
+// wavefront takes its own 64 targets and walks the sources staged by all four,
+// so that a batch of sources is staged once per 256 targets rather than per 64.
+// (The density stage keeps one layout: shared, its four wavefronts would run
+// their Newton iterations in lockstep rounds, and on leaves of up to 256
+// particles the waiting cost more than the staging it saves.)
 //
 // Arithmetic: pair terms in R (float or double); every per-particle sum and
 // the Newton step in double.
@@ -262,7 +268,7 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
                     int seg = 0, jj = s.nseg[w] > 0 ? s.seg_b[w][0] : 0;
                     cnt = 0;
                     while (true) {
-                        cnt = walk<R, false, NACC_D, CFG>(s, w, lane, act, xi, yi, zi, fxi, fyi, fzi, rad, fh, margin,
+                        cnt = walk<R, false, NACC_D, CFG>(s, w, w, lane, act, xi, yi, zi, fxi, fyi, fzi, rad, fh, margin,
                                                      selfj, seg, jj, cnt);
                         if (seg >= s.nseg[w]) break;
                         process(cnt);  // a list is full: evaluate it and continue the walk
@@ -541,8 +547,22 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
         int k = 0, p = 0;
         stage_wave<R, true, NACC_F>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, mstage);
         const bool single = k >= nsrc;
-        for (int c0 = 0; c0 < T.count; c0 += kWave) {
-            const int ti_ = c0 + lane;
+        // Cells of more than shared_min particles are swept shared: each
+        // wavefront takes its own 64 targets and walks the staged sources of all
+        // four, so that a batch of sources is staged once for up to 256 targets
+        // rather than once per 64.  Otherwise the four wavefronts hold the same
+        // 64 targets, each walking its own sources, and add their sums in LDS.
+        const bool shared = T.count > pc.shared_min;
+        bool all_single = single;
+        if (shared) {
+            if (lane == 0) s.done[w] = single ? 1 : 0;
+            __syncthreads();
+            all_single = (s.done[0] & s.done[1] & s.done[2] & s.done[3]) != 0;
+            __syncthreads();   // read before the sweeps write done[] again
+        }
+        const int gstep = shared ? NW * kWave : kWave;
+        for (int c0 = 0; c0 < T.count; c0 += gstep) {
+            const int ti_ = c0 + (shared ? w * kWave : 0) + lane;
             const bool valid = ti_ < T.count;
             const uint32_t gi = (uint32_t)(T.start + (valid ? ti_ : 0));
             const bool on = valid && (!gd.active || gd.active[dc.perm[gi]] != 0);   // a target of this pass
@@ -554,10 +574,12 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
             ti.hinv = g0i.x; ti.gk = g0i.y; ti.A = g0i.z; ti.rho = g0i.w;
             ti.c = g1i.x; ti.f = g1i.y; ti.h = g1i.z;
             const float fxi = (float)ti.x, fyi = (float)ti.y, fzi = (float)ti.z, fh = (float)ti.h;
-            for (int a = w; a < NACC_F; a += NW) s.red[a][lane] = 0.0;
+            if (!shared)
+                for (int a = w; a < NACC_F; a += NW) s.red[a][lane] = 0.0;
             __syncthreads();
             ForceAcc<R> acc = {};
-            auto process = [&](int n) {
+            // the pairs of a list of staged indices of region r
+            auto process = [&](int n, int r) {
                 ForcePart<R> b = {};
                 for (int t = 0;; t += 2) {
                     const bool v0 = t < n, v1 = t + 1 < n;
@@ -565,8 +587,8 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
                     // slots t, t + 1 <= LISTW lie in the row; past the list: masked
                     const int r0 = s.list[w][lane][t], r1 = s.list[w][lane][t + 1];
                     const int j0 = v0 ? r0 : 0, j1 = v1 ? r1 : 0;
-                    const uint32_t q0 = s.sg[w][j0], q1 = s.sg[w][j1];
-                    const R4 e0 = s.st[w][j0], e1 = s.st[w][j1];
+                    const uint32_t q0 = s.sg[r][j0], q1 = s.sg[r][j1];
+                    const R4 e0 = s.st[r][j0], e1 = s.st[r][j1];
                     const R4 v0m = cd.vm[q0], v1m = cd.vm[q1];
                     const R4 a0 = gd.g0[q0], a1 = gd.g0[q1];
                     const R4 b0 = gd.g1[q0], b1 = gd.g1[q1];
@@ -578,42 +600,66 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
                 acc.az += (double)b.az;
                 acc.du += (double)b.du;
             };
-            int kk = 0, pp = 0;
-            do {
-                if (!single) stage_wave<R, true, NACC_F>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, kk, pp, Hst, mstage);
-                else kk = nsrc;
-                const int selfj = self_index(s, w, ti_);
-                int seg = 0, jj = s.nseg[w] > 0 ? s.seg_b[w][0] : 0;
+            // walk of region r, its lists evaluated as they fill and at the end
+            auto sweep = [&](int r) {
+                const int selfj = self_index(s, r, ti_);
+                int seg = 0, jj = s.nseg[r] > 0 ? s.seg_b[r][0] : 0;
                 int cnt = 0;
                 while (true) {
-                    cnt = walk<R, true, NACC_F>(s, w, lane, on, ti.x, ti.y, ti.z, fxi, fyi, fzi, ti.h, fh, margin,
+                    cnt = walk<R, true, NACC_F>(s, w, r, lane, on, ti.x, ti.y, ti.z, fxi, fyi, fzi, ti.h, fh, margin,
                                                 selfj, seg, jj, cnt);
-                    process(cnt);
+                    process(cnt, r);
                     cnt = 0;
-                    if (seg >= s.nseg[w]) break;
+                    if (seg >= s.nseg[r]) break;
                 }
-            } while (kk < nsrc);
-            if (on) {
-                atomicAdd(&s.red[0][lane], acc.ax);
-                atomicAdd(&s.red[1][lane], acc.ay);
-                atomicAdd(&s.red[2][lane], acc.az);
-                atomicAdd(&s.red[3][lane], acc.du);
-                atomicAdd(&s.red[4][lane], (double)acc.n);
-                // signal speeds are >= 0, where the order of the bit patterns is the order of the values
-                atomicMax((unsigned long long*)&s.red[5][lane],
-                          (unsigned long long)__double_as_longlong((double)acc.vsig));
+            };
+            int kk = 0, pp = 0;
+            if (shared) {
+                // batch rounds: every wavefront stages its next batch, then all
+                // walk the four regions; the rounds end together
+                while (true) {
+                    if (!all_single) {
+                        stage_wave<R, true, NACC_F>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, kk, pp, Hst, mstage);
+                        if (lane == 0) s.done[w] = kk >= nsrc ? 1 : 0;
+                    }
+                    __syncthreads();   // the four regions are staged
+                    const bool last = all_single || (s.done[0] & s.done[1] & s.done[2] & s.done[3]) != 0;
+                    for (int r = 0; r < NW; r++) sweep(r);
+                    __syncthreads();   // every wavefront is done with the regions and with done[]
+                    if (last) break;
+                }
+            } else {
+                do {
+                    if (!single) stage_wave<R, true, NACC_F>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, kk, pp, Hst, mstage);
+                    else kk = nsrc;
+                    sweep(w);
+                } while (kk < nsrc);
+                if (on) {
+                    atomicAdd(&s.red[0][lane], acc.ax);
+                    atomicAdd(&s.red[1][lane], acc.ay);
+                    atomicAdd(&s.red[2][lane], acc.az);
+                    atomicAdd(&s.red[3][lane], acc.du);
+                    atomicAdd(&s.red[4][lane], (double)acc.n);
+                    // signal speeds are >= 0, where the order of the bit patterns is the order of the values
+                    atomicMax((unsigned long long*)&s.red[5][lane],
+                              (unsigned long long)__double_as_longlong((double)acc.vsig));
+                }
             }
             __syncthreads();
-            if (w == 0 && on) {
+            if ((shared || w == 0) && on) {
                 const uint32_t pi = dc.perm[gi];
-                if (out.ax) out.ax[pi] = s.red[0][lane];
-                if (out.ay) out.ay[pi] = s.red[1][lane];
-                if (out.az) out.az[pi] = s.red[2][lane];
-                if (out.dudt) out.dudt[pi] = s.red[3][lane];
-                if (out.npairs) out.npairs[pi] = (int32_t)s.red[4][lane];
+                const double ax = shared ? acc.ax : s.red[0][lane], ay = shared ? acc.ay : s.red[1][lane];
+                const double az = shared ? acc.az : s.red[2][lane], du = shared ? acc.du : s.red[3][lane];
+                const double np_ = shared ? (double)acc.n : s.red[4][lane];
+                const double vsg = shared ? (double)acc.vsig : s.red[5][lane];
+                if (out.ax) out.ax[pi] = ax;
+                if (out.ay) out.ay[pi] = ay;
+                if (out.az) out.az[pi] = az;
+                if (out.dudt) out.dudt[pi] = du;
+                if (out.npairs) out.npairs[pi] = (int32_t)np_;
                 if (out.dt) {
                     // j = i contributes 2 c_i (no approach speed)
-                    const double vs = fmax(s.red[5][lane], 2.0 * (double)ti.c);
+                    const double vs = fmax(vsg, 2.0 * (double)ti.c);
                     out.dt[pi] = vs > 0.0 ? pc.cfl * 2.0 * (double)ti.h / vs : (double)INFINITY;
                 }
             }

@@ -139,6 +139,7 @@ struct PassConsts {
     double h_margin;
     double cfl;         // C_CFL of Eq. (6)
     int balsara_div;    // 1: |div v| over the Balsara denominator, 0: |curl v|
+    int shared_min;     // cells of more particles than this are swept shared
 };
 
 }  // namespace sph

@@ -129,6 +129,7 @@ struct Smem {
     float seg_dr[NW][kMaxSegW];       // staleness of the source cell's stored projections
     int nseg[NW];
     int self_b[NW], self_t0[NW], self_n[NW];  // self segment: staged start, first cell index, count
+    int done[NW];                     // shared sweeps: every source of the wavefront staged
     int unit;
 };
 
@@ -297,7 +298,8 @@ template <typename P> __device__ __forceinline__ void append(P& p, uint64_t m)
 }
 __device__ __forceinline__ uint64_t lanes(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
-// Walk of wavefront w over its staged segments, one segment at a time for
+// Walk of wavefront w over the staged segments of region r (its own, r = w,
+// or in the shared sweeps any of the four), one segment at a time for
 // all lanes together: every lane reads the same staged particle (an LDS
 // broadcast), tests it against its own radius, and appends it to its list
 // when in range.  The segment is left as soon as no lane is still within its
@@ -314,13 +316,13 @@ __device__ __forceinline__ uint64_t lanes(bool p) { return __builtin_amdgcn_ball
 // pair in range and possibly a few just outside, which the pair arithmetic
 // (its own tests of r against h) discards.
 template <typename R, bool FORCE, int NACC, int CFG = 0>
-__device__ __forceinline__ int walk(Smem<R, NACC, FORCE, CFG>& s, int w, int lane, bool act, R xi, R yi, R zi, float fxi,
+__device__ __forceinline__ int walk(Smem<R, NACC, FORCE, CFG>& s, int w, int r, int lane, bool act, R xi, R yi, R zi, float fxi,
                                     float fyi, float fzi, R rad, float fh, float margin, int selfj, int& seg_io,
                                     int& jj_io, int cnt)
 {
     constexpr int LISTW = Smem<R, NACC, FORCE, CFG>::LISTW;
     constexpr int STEP = WALK_STEP;
-    const int nseg = uniform(s.nseg[w]);
+    const int nseg = uniform(s.nseg[r]);
     // lane constants of the test: K_i, and the range (rad^2 / 2, rounded up)
     const R ki = half_sq_lo(xi, yi, zi);
     const R c_half = (R)0.5 * rad * rad * ((R)1 + (R)8 * std::numeric_limits<R>::epsilon());
@@ -357,8 +359,8 @@ __device__ __forceinline__ int walk(Smem<R, NACC, FORCE, CFG>& s, int w, int lan
         R hj2[STEP];
 #pragma unroll
         for (int k = 0; k < STEP; k++) {
-            e[k] = s.st[w][jj + k];
-            hj2[k] = FORCE ? s.sh[w][FORCE ? jj + k : 0] : (R)0;
+            e[k] = s.st[r][jj + k];
+            hj2[k] = FORCE ? s.sh[r][FORCE ? jj + k : 0] : (R)0;
         }
         // hits as lane masks, combined in scalar registers
         uint64_t hit[STEP];
@@ -375,9 +377,9 @@ __device__ __forceinline__ int walk(Smem<R, NACC, FORCE, CFG>& s, int w, int lan
         }
     };
     while (seg < nseg) {
-        const int je = uniform(s.seg_e[w][seg]);
-        const float ux = s.seg_u[w][seg][0], uy = s.seg_u[w][seg][1], uz = s.seg_u[w][seg][2];
-        const float hx = s.seg_hx[w][seg];
+        const int je = uniform(s.seg_e[r][seg]);
+        const float ux = s.seg_u[r][seg][0], uy = s.seg_u[r][seg][1], uz = s.seg_u[r][seg][2];
+        const float hx = s.seg_hx[r][seg];
         // the self segment has u = 0; a uniform flag
         const bool self = uniform((ux == 0.0f) & (uy == 0.0f) & (uz == 0.0f)) != 0;
         if (self) {
@@ -392,11 +394,11 @@ __device__ __forceinline__ int walk(Smem<R, NACC, FORCE, CFG>& s, int w, int lan
             // beyond bound + 2d leaves every later one beyond bound.  A pair in
             // range is within the bound, so only the exit reads projections.
             const float bound =
-                !act ? -INFINITY : ux * fxi + uy * fyi + uz * fzi + fmaxf(fh, hx) + margin + 2.0f * s.seg_dr[w][seg];
+                !act ? -INFINITY : ux * fxi + uy * fyi + uz * fzi + fmaxf(fh, hx) + margin + 2.0f * s.seg_dr[r][seg];
             while (jj < je) {
                 if (wave_any(wp > wfull)) { full = true; break; }
                 const int jl = jj + STEP - 1;
-                const uint64_t in_last = jl < je ? lanes(s.sp[w][jl] <= bound) : 0ull;
+                const uint64_t in_last = jl < je ? lanes(s.sp[r][jl] <= bound) : 0ull;
                 step(je, jj, false);
                 jj += STEP;
                 // projections grow along the segment: once the last entry of a step
@@ -406,7 +408,7 @@ __device__ __forceinline__ int walk(Smem<R, NACC, FORCE, CFG>& s, int w, int lan
         }
         if (full) break;
         seg++;
-        jj = seg < nseg ? uniform(s.seg_b[w][seg]) : 0;
+        jj = seg < nseg ? uniform(s.seg_b[r][seg]) : 0;
     }
     cnt = (int)(wp - lst);
     seg_io = seg;

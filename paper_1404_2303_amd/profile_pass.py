@@ -26,6 +26,8 @@ def main():
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
     ap.add_argument("--passes", type=int, default=2)
     ap.add_argument("--copy-mib", type=int, default=0)
+    ap.add_argument("--shared-min", type=int, default=128,
+                    help="cells of more particles than this are swept shared (sph_params.shared_min)")
     args = ap.parse_args()
     import time
 
@@ -71,7 +73,7 @@ def main():
     else:
         ps, params = workloads.config2(), {"max_depth": 10, "split_count": 256}
     parts = sph.Particles.from_numpy(ps, "cuda:0")
-    ctx = sph.Context(ps.box, precision=args.precision, **params)
+    ctx = sph.Context(ps.box, precision=args.precision, shared_min=args.shared_min, **params)
     if args.workload == "mixture":
         ctx.estimate_h(parts)
         ctx.run(parts)

@@ -43,7 +43,7 @@ class sph_params(ctypes.Structure):
                 ("cell_target", ctypes.c_int), ("h_margin", ctypes.c_double),
                 ("max_rebuilds", ctypes.c_int), ("max_depth", ctypes.c_int), ("split_count", ctypes.c_int),
                 ("split_frac", ctypes.c_double), ("cfl", ctypes.c_double), ("balsara_form", ctypes.c_int),
-                ("reuse", ctypes.c_int), ("staging", ctypes.c_int)]
+                ("reuse", ctypes.c_int), ("staging", ctypes.c_int), ("shared_min", ctypes.c_int)]
 
 
 class sph_particles(ctypes.Structure):

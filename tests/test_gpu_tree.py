@@ -42,6 +42,19 @@ def test_mixture_30000(mixture, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("shared_min", [64, 1 << 30])
+def test_mixture_large_leaves_shared_force(mixture, precision, shared_min):
+    """Leaves of up to 256 particles (split count 256): the force stage swept
+    shared (each wavefront its own 64 targets over all four staged regions)
+    for every leaf of more than 64 particles, and never; both against the
+    oracle."""
+    ps, ref = mixture
+    log(f"case tree mixture 30000 {precision}, split count 256, force shared above {shared_min}")
+    g = gpu_run(ps, precision, estimate=True, max_depth=8, split_count=256, shared_min=shared_min)
+    compare(g, ref, precision, label=f"mixture-shared{shared_min}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_uniform_split_once(precision):
     # top cells of about 1100 particles (3 per dimension) whose h is below half
     # their edge split once: the uniform set runs on leaves of level 1
