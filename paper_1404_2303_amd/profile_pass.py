@@ -28,6 +28,8 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0)
     ap.add_argument("--shared-min", type=int, default=128,
                     help="cells of more particles than this are swept shared (sph_params.shared_min)")
+    ap.add_argument("--staging", choices=("compact", "wide"), default="compact",
+                    help="density staging of the lattice and mixture workloads (sph_params.staging)")
     args = ap.parse_args()
     import time
 
@@ -73,7 +75,8 @@ def main():
     else:
         ps, params = workloads.config2(), {"max_depth": 10, "split_count": 256}
     parts = sph.Particles.from_numpy(ps, "cuda:0")
-    ctx = sph.Context(ps.box, precision=args.precision, shared_min=args.shared_min, **params)
+    staging = sph.SPH_STAGING_WIDE if args.staging == "wide" else sph.SPH_STAGING_COMPACT
+    ctx = sph.Context(ps.box, precision=args.precision, shared_min=args.shared_min, staging=staging, **params)
     if args.workload == "mixture":
         ctx.estimate_h(parts)
         ctx.run(parts)

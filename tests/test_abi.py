@@ -35,6 +35,7 @@ def test_status_strings_and_defaults():
     p = sph.sph_default_params()
     assert p.n_ngb == 48.0 and abs(p.gamma - 5 / 3) < 1e-15 and p.alpha == 0.8 and p.balsara_eps == 1e-4
     assert p.precision == sph.SPH_FP32_ACC64
+    assert p.staging == sph.SPH_STAGING_COMPACT and p.shared_min == 128
 
 
 def test_argument_validation_without_gpu():
@@ -56,4 +57,10 @@ def test_argument_validation_without_gpu():
     assert lib.sph_create(ctypes.byref(bad), ctypes.byref(ctx)) == sph.SPH_E_INVALID_ARG
     bad = sph.sph_default_params()
     bad.precision = 7
+    assert lib.sph_create(ctypes.byref(bad), ctypes.byref(ctx)) == sph.SPH_E_INVALID_ARG
+    bad = sph.sph_default_params()
+    bad.staging = 2
+    assert lib.sph_create(ctypes.byref(bad), ctypes.byref(ctx)) == sph.SPH_E_INVALID_ARG
+    bad = sph.sph_default_params()
+    bad.shared_min = 63   # a shared sweep needs more than one group of 64 targets
     assert lib.sph_create(ctypes.byref(bad), ctypes.byref(ctx)) == sph.SPH_E_INVALID_ARG
