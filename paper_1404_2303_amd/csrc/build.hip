@@ -579,7 +579,6 @@ __global__ __launch_bounds__(256) void k_sources(const CellInfo* cells, const in
 // One workgroup per (cell, direction).  Each particle's rank is the number of
 // particles with a smaller projection, ties broken by cell-order index, so
 // the ordering is a permutation and stable.
-constexpr int SORT_THREADS = 64;
 constexpr int SORT_MAX = 4096;
 constexpr int kWaveSortMax = 4 * kWave;   // cells up to this size are sorted by one wavefront
 
@@ -730,43 +729,97 @@ __global__ __launch_bounds__(kWave) void k_sort13_wave(const CellInfo* cells, co
     }
 }
 
-// Larger cells: one workgroup per (cell, direction); each particle's rank is
-// the number of particles with a smaller key, ties broken by cell order.
-template <typename R>
-__global__ __launch_bounds__(SORT_THREADS) void k_sort13(const CellInfo* cells, const int32_t* big,
-                                                         CellData<R> cd, int64_t n, Sorted<R> so,
-                                                         uint32_t* status)
+// Larger cells (Sec. 3.3: a parent's ordering from the sorted orderings of
+// its parts, merged in O(n) per level): one workgroup per (cell, direction).
+// The cell's particles, in cell order, are cut into runs of 256, the runs
+// are sorted (a bitonic network inside each run), and sorted runs are merged
+// pairwise until one remains.  A word is (order-preserving image of the
+// projection) << 32 | cell index, so equal projections keep cell order, as
+// the wavefront sort does.  In a merge each word's place is its index in its
+// run plus the number of words of the partner run before it (a binary search).
+constexpr int MERGE_THREADS = 256;
+constexpr int MERGE_RUN = 256;
+
+// the number of words of run [b, b + len) below x (strict) or at most x
+__device__ __forceinline__ int count_before(const uint64_t* a, int b, int len, uint64_t x, bool strict)
 {
-    __shared__ uint32_t key[SORT_MAX];
+    int lo = 0, hi = len;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const uint64_t y = a[b + mid];
+        if (strict ? (y < x) : (y <= x)) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <typename R>
+__global__ __launch_bounds__(MERGE_THREADS) void k_sort13(const CellInfo* cells, const int32_t* big,
+                                                          CellData<R> cd, int64_t n, Sorted<R> so,
+                                                          uint32_t* status)
+{
+    __shared__ uint64_t buf[2][SORT_MAX];
+    const int tid = threadIdx.x;
     const int64_t units = (int64_t)big[0] * kSortDirs;  // the cells k_sort13_wave left
     for (int64_t unit = blockIdx.x; unit < units; unit += gridDim.x) {
         const int c = big[kBigHeader + (int)(unit / kSortDirs)];
         const int s = (int)(unit % kSortDirs);
         const CellInfo C = cells[c];
-        if (C.count > SORT_MAX) { if (threadIdx.x == 0) atomicOr(status, ST_CAPACITY); continue; }
+        if (C.count > SORT_MAX) { if (tid == 0) atomicOr(status, ST_CAPACITY); continue; }
+        // padded to whole runs with words above every real one
+        const int np = (C.count + MERGE_RUN - 1) / MERGE_RUN * MERGE_RUN;
         float su[3];
         dir_unit(s + 13, su);
-        __syncthreads();
-        // ranks are taken on an order-preserving integer image of the projection,
-        // a total order (NaN included), so every cell's ordering is a permutation
-        for (int t = threadIdx.x; t < C.count; t += SORT_THREADS) {
-            int64_t k = C.start + t;
-            const typename CellData<R>::R4 q = cd.rp[k];
-            const float f = su[0] * (float)q.x + su[1] * (float)q.y + su[2] * (float)q.z;
-            const uint32_t b = __float_as_uint(f);
-            key[t] = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+        __syncthreads();   // the last unit's words are written out
+        for (int t = tid; t < np; t += MERGE_THREADS) {
+            uint64_t wd = ~0ull;
+            if (t < C.count) {
+                const typename CellData<R>::R4 q = cd.rp[C.start + t];
+                const float f = su[0] * (float)q.x + su[1] * (float)q.y + su[2] * (float)q.z;
+                const uint32_t b = __float_as_uint(f);
+                const uint32_t key = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+                wd = ((uint64_t)key << 32) | (uint32_t)t;
+            }
+            buf[0][t] = wd;
         }
         __syncthreads();
-        for (int t = threadIdx.x; t < C.count; t += SORT_THREADS) {
-            const uint32_t kt = key[t];
-            int rank = 0;
-            for (int j = 0; j < C.count; j++) {
-                const uint32_t kj = key[j];
-                rank += (kj < kt) || (kj == kt && j < t);
+        // each run sorted: bitonic stages of span <= MERGE_RUN stay inside a run;
+        // the last (k = MERGE_RUN) leaves every run ascending
+        for (int k = 2; k <= MERGE_RUN; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = tid; i < np; i += MERGE_THREADS) {
+                    const int l = i ^ j;
+                    if (l > i) {
+                        const uint64_t a = buf[0][i], b = buf[0][l];
+                        if ((a > b) == ((i & k & (MERGE_RUN - 1)) == 0)) { buf[0][i] = b; buf[0][l] = a; }
+                    }
+                }
+                __syncthreads();
             }
-            int64_t o = (int64_t)s * n + C.start + rank;
+        }
+        // merges: runs of `w` words into runs of 2w, alternating buffers
+        int src = 0;
+        for (int w = MERGE_RUN; w < np; w <<= 1) {
+            const uint64_t* in = buf[src];
+            uint64_t* outb = buf[src ^ 1];
+            for (int i = tid; i < np; i += MERGE_THREADS) {
+                const int pair = i / (2 * w) * (2 * w);      // first word of the two runs
+                const int la = min(w, np - pair);            // first run (whole unless the last)
+                const int lb = min(w, np - pair - la);       // partner run (possibly empty)
+                const uint64_t x = in[i];
+                int place;
+                if (i < pair + la) place = (i - pair) + count_before(in, pair + la, lb, x, true);
+                else place = (i - pair - la) + count_before(in, pair, la, x, false);
+                outb[pair + place] = x;
+            }
+            src ^= 1;
+            __syncthreads();
+        }
+        for (int r = tid; r < C.count; r += MERGE_THREADS) {
+            const uint64_t wd = buf[src][r];
+            const uint32_t kt = (uint32_t)(wd >> 32);
             const uint32_t b = (kt & 0x80000000u) ? (kt & 0x7fffffffu) : ~kt;
-            so.rec[o] = SortRec{__uint_as_float(b), (uint32_t)t};
+            so.rec[(int64_t)s * n + C.start + r] = SortRec{__uint_as_float(b), (uint32_t)wd};
         }
     }
 }
@@ -925,7 +978,7 @@ void launch_sort13(const CellInfo* cells, const int32_t* ncells, const CellData<
     // at most n / (kWaveSortMax + 1) cells are left; the grid strides over them
     const int64_t units = (cell_cap / (kWaveSortMax + 1) + 1) * kSortDirs;
     const unsigned grid = (unsigned)(units < 2048 ? units : 2048);
-    hipLaunchKernelGGL(k_sort13<R>, dim3(grid), dim3(SORT_THREADS), 0, st, cells, big, cd, n, so, status);
+    hipLaunchKernelGGL(k_sort13<R>, dim3(grid), dim3(MERGE_THREADS), 0, st, cells, big, cd, n, so, status);
 }
 template void launch_sort13<float>(const CellInfo*, const int32_t*, const CellData<float>&, int64_t,
                                    const Sorted<float>&, int32_t*, uint32_t*, int64_t, hipStream_t);

@@ -122,6 +122,21 @@ def test_large_cells_fp32(n, cell_target, lo, hi, staging):
     compare(g, oracle_run(ps), "fp32", label=f"cells {cell_target}")
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,cell_target,lo,hi", [(30000, 1000, 256, 1500), (100000, 3000, 2048, 4096)])
+def test_cells_ordered_by_merging(n, cell_target, lo, hi, precision):
+    """Cells of more than 256 particles: their orderings are made by one
+    work-group from sorted runs of 256 merged pairwise (up to 4096 particles,
+    four merge levels); any misplaced particle would cut the sorted sweeps
+    short and lose pairs."""
+    ps = workloads.uniform(n, seed=11, sigma_v=0.3)
+    g = gpu_run(ps, precision, cell_target=cell_target)
+    mean = ps.n / g["stats"]["n_cells"]
+    log(f"case merged orderings {precision} n={n} cell_target={cell_target}: {g['stats']['n_cells']} cells, mean {mean:.0f}")
+    assert lo < mean <= hi
+    compare(g, oracle_run(ps), precision, label=f"merged cells {cell_target}")
+
+
 def test_momentum_and_energy_conservation_gpu():
     ps = workloads.uniform(8000, seed=5, sigma_v=0.5)
     log("case conservation 8000 fp64")
