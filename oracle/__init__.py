@@ -94,8 +94,8 @@ def _load():
         lib.ora_signal.argtypes = [i64, P, P, P, P, P, P, P, P, P, d, i64, P, P, P, P, P]
         lib.ora_force.restype = i32
         lib.ora_force.argtypes = [i64, P, P, P, P, P, P, P, P, P, P, P, P, P, d, i64, P] + [P] * 10
-        lib.ora_brute_count.restype = None
-        lib.ora_brute_count.argtypes = [i64, P, P, P, P, P, P]
+        lib.ora_bands.restype = i32
+        lib.ora_bands.argtypes = [i64, P, P, P, P, P, P, i64, P, P, P]
         lib.ora_num_threads.restype = i32
         lib.ora_num_threads.argtypes = []
         _lib = lib
@@ -259,15 +259,29 @@ def signal_dt(pos, vel, h, c, box, cfl=CFL, sel=None):
     return out
 
 
-def brute_count(pos, R, box):
-    """O(N^2) count of j != i with minimum-image r_ij < R_i."""
+def bands(pos, h, box, width, sel=None):
+    """Pairs that a smoothing length known to relative precision ``width``
+    (scalar or one value per particle) may classify either way: per particle,
+    the pairs within that relative distance of the density range r < h_i
+    ("dband") and of the force range r < max(h_i, h_j) ("fband", with the
+    width of whichever particle has the larger h).  Counting only."""
     lib = _load()
     x, y, z = _split(pos)
     n = len(x)
-    R = _c(np.broadcast_to(np.asarray(R, dtype=np.float64), (n,)))
-    cnt = np.empty(n, dtype=np.int32)
-    lib.ora_brute_count(n, _p(x), _p(y), _p(z), _p(_c(box)), _p(R), _p(cnt))
-    return cnt
+    bw = _c(np.broadcast_to(np.asarray(width, dtype=np.float64), (n,)))
+    ns, s = _sel(sel, n)
+    out = {"dband": np.full(n, -1, dtype=np.int32), "fband": np.full(n, -1, dtype=np.int32)}
+    st = lib.ora_bands(n, _p(x), _p(y), _p(z), _p(_c(h)), _p(bw), _p(_c(box)), ns, _p(s),
+                       _p(out["dband"]), _p(out["fband"]))
+    _check(st, "bands")
+    return out
+
+
+def h_precision(h, dndh, h_rel, ngb_tol):
+    """Relative precision of a smoothing length solved to |N - n_ngb| <= ngb_tol
+    with h itself compared to h_rel: max(h_rel, ngb_tol / (h |dN/dh|)), and no
+    finer than the 1e-6 rounding band of the support."""
+    return np.maximum(np.maximum(h_rel, 1e-6), ngb_tol / (np.asarray(h) * np.abs(np.asarray(dndh))))
 
 
 def full_pass(pos, vel, m, u, h0, box, target=N_NGB, tol=1e-10, maxit=100,

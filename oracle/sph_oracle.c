@@ -605,23 +605,58 @@ int ora_force(int64_t np, const double *x, const double *y, const double *z,
     return status;
 }
 
-/* Brute-force O(N^2) neighbour count with the minimum image (pin for the
- * cell list): number of j != i with r_ij < R_i. */
-void ora_brute_count(int64_t np, const double *x, const double *y, const double *z,
-                     const double L[3], const double *R, int32_t *count)
+/*
+ * Pairs that a smoothing length known only to a relative precision b may
+ * classify either way.  With b_i the relative precision of h_i:
+ *   dband_i: pairs j != i with |r_ij / h_i - 1| < b_i           (density range)
+ *   fband_i: pairs j != i with |r_ij / max(h_i, h_j) - 1| < b_ij, b_ij the b
+ *            of whichever of i, j has the larger h                (force range)
+ * Only counts; no SPH arithmetic.  Either output may be NULL.
+ */
+int ora_bands(int64_t np, const double *x, const double *y, const double *z, const double *h,
+              const double *bw, const double L[3], int64_t nsel, const int64_t *sel,
+              int32_t *dband, int32_t *fband)
 {
-#pragma omp parallel for schedule(static)
+    if (np <= 0 || !x || !h || !bw) return ORA_E_ARG;
+    double hmax = 0.0, hmin = INFINITY, bmax = 0.0;
     for (int64_t i = 0; i < np; i++) {
-        int32_t c = 0;
-        for (int64_t j = 0; j < np; j++) {
-            if (j == i) continue;
-            double dx = min_image(x[i] - x[j], L[0]);
-            double dy = min_image(y[i] - y[j], L[1]);
-            double dz = min_image(z[i] - z[j], L[2]);
-            if (sqrt(dx * dx + dy * dy + dz * dz) < R[i]) c++;
-        }
-        count[i] = c;
+        if (h[i] > hmax) hmax = h[i];
+        if (h[i] < hmin) hmin = h[i];
+        if (bw[i] > bmax) bmax = bw[i];
     }
+    ora_grid g;
+    int st = grid_build(&g, np, x, y, z, L, hmin);
+    if (st) return st;
+    int status = ORA_OK;
+#pragma omp parallel
+    {
+        ora_list l = {0};
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t k = 0; k < nsel; k++) {
+            int64_t i = sel_index(sel, k);
+            int e = grid_gather(&g, x[i], y[i], z[i], fmax(h[i], hmax) * (1.0 + 2.0 * bmax), &l);
+            if (e) {
+#pragma omp critical
+                { if (status == ORA_OK) status = e; }
+                continue;
+            }
+            int32_t db = 0, fb = 0;
+            for (int64_t t = 0; t < l.n; t++) {
+                int64_t j = l.v[t].j;
+                if (j == i) continue;
+                double r = sqrt(l.v[t].r2);
+                if (fabs(r / h[i] - 1.0) < bw[i]) db++;
+                double hij = fmax(h[i], h[j]);
+                double bij = h[i] >= h[j] ? bw[i] : bw[j];
+                if (fabs(r / hij - 1.0) < bij) fb++;
+            }
+            if (dband) dband[i] = db;
+            if (fband) fband[i] = fb;
+        }
+        free(l.v);
+    }
+    grid_free(&g);
+    return status;
 }
 
 int ora_num_threads(void)
