@@ -18,14 +18,21 @@ sum_i n_pairs_i pair interactions.  Extra Newton rounds are timed but not
 credited.
 
 Roofline: the interaction kernels are bound by plain FP32/FP64 vector ALU
-work.  Algorithmic FLOPs per launch (FMA = 2, add/mul = 1, sqrt/div = 1,
-compare/select = 0, counted from the equations once per unordered pair as a
-symmetric evaluation would do them):
-    density: 12 per pair (separation, distance, velocity difference)
-             + 41 per side with r < h_side (kernel, derivative, four sums,
-               divergence, curl)
-    force:   68 per pair (both kernel gradients, viscosity, both sides'
-               acceleration and du/dt)
+work.  Algorithmic FLOPs per launch (FMA = 2, add/mul = 1, sqrt/rsqrt/div = 1,
+compare/select = 0, counted term by term from Eqs. (2)-(5) and the Sec. 4.1
+viscosity once per unordered pair, as a symmetric evaluation would do them):
+    density: 26 per pair (separation 3, r^2 5, r 1, velocity difference 3,
+               dv.dx 5, dv x dx 9: shared by both sides)
+             + 26 per side with r < h_side (q 1, w 5, w' 3, q w' 1, w'/q 1,
+               the four sums of rho, N, dN/dh, drho/dh 6, m g 1, divergence 2,
+               curl 6)
+    force:   68 per pair (separation 3, r^2 5, 1/r 1, r 1, dv 3, dv.dx 5,
+               w_ij 1, q_i, q_j 2, both gradients 6, signal speed 3,
+               Pi_ij 5, f_i + f_j 1, the viscous factor 3, the pressure
+               scalar 3, the two scalings by the masses 4, both sides'
+               accelerations 12 and du/dt 10)
+The line also gives the fraction at round per-pair constants of 70 (density)
+and 120 (force) FLOP, an earlier estimate of the same work.
 """
 from __future__ import annotations
 
@@ -40,9 +47,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FLOPS_DENSITY_PAIR = 12
-FLOPS_DENSITY_SIDE = 41
+FLOPS_DENSITY_PAIR = 26
+FLOPS_DENSITY_SIDE = 26
 FLOPS_FORCE_PAIR = 68
+FLOPS_ROUND = {"density": 70, "force": 120}   # round per-pair estimate, reported beside the count
 PEAK = {"fp32": 157.3, "fp64": 78.6}   # MI355X vector TFLOP/s (published)
 
 METRIC = "pair interactions/sec (density+force) at 1M particles; plain vs batched/FP32 form"
@@ -222,7 +230,7 @@ def adjoint_section(steps, warmup):
     rt = torch.as_tensor(workloads.density_target(ps.pos, float(np.sum(ps.m))), device="cuda:0")
     parts = sph.Particles.from_numpy(ps, "cuda:0")
     h0 = parts.h.clone()
-    ctx = sph.Context(ps.box, precision="fp32")
+    ctx = sph.Context(ps.box, precision="fp32", keep_adjoint=1)
     ctx.enable_timing(True)
 
     def forward():
@@ -386,23 +394,48 @@ def roofline(res):
     achieved = flops / (ms * 1e-3) / 1e12
     peak = PEAK["fp64" if res["precision"] == "fp64" else "fp32"]
     traffic = measured_traffic() if (name == "density" and res["precision"] == "fp32") else None
+    round_flops = FLOPS_ROUND[name] * P_unordered
     return {"bound": "alu", "kernel": name, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": achieved / peak, "traffic": traffic,
+            "flop_per_unit": {"density_pair": FLOPS_DENSITY_PAIR, "density_side": FLOPS_DENSITY_SIDE,
+                              "force_pair": FLOPS_FORCE_PAIR, "units": {"pairs": P_unordered, "sides": res["S"]}},
+            "frac_at_round_constants": round_flops / (ms * 1e-3) / 1e12 / peak,
             "other": {c[0]: {"TFLOP/s": c[1] / (c[2] * 1e-3) / 1e12, "ms": c[2]} for c in cand}}
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(seed=0):
-    """The FP64 oracle on a bounded sample: the same lattice law on 128 x 64 x 32 sites."""
+    """The FP64 oracle on a bounded sample: the same lattice law on 128 x 64 x 32
+    sites, timed with every thread OpenMP offers (the value) and on one core."""
     import oracle
     from paper_1404_2303_amd import workloads
     ps = workloads.lattice((128, 64, 32), 1.0 / 128, 0.1, 0.1, seed)
-    t0 = time.perf_counter()
-    out = oracle.full_pass(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box, tol=1e-10)
-    dt = time.perf_counter() - t0
-    P = int(np.sum(out["force"]["count"]))
-    return {"value": P / dt, "unit": "pair interactions/s", "cores": oracle.num_threads(), "kind": "oracle",
+
+    def timed():
+        t0 = time.perf_counter()
+        out = oracle.full_pass(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box, tol=1e-10)
+        return time.perf_counter() - t0, int(np.sum(out["force"]["count"]))
+
+    threads = oracle.num_threads()
+    dt, P = timed()
+    oracle.set_num_threads(1)
+    dt1, P1 = timed()
+    oracle.set_num_threads(threads)
+    return {"value": P / dt, "unit": "pair interactions/s", "cores": threads, "kind": "oracle",
             "sample": f"FP64 oracle, full density(h-iteration)+force pass on a 128x64x32 jittered lattice "
-                      f"({ps.n} particles, same spacing/jitter/velocity law), {dt:.2f} s, P={P}"}
+                      f"({ps.n} particles, same spacing/jitter/velocity law), {dt:.2f} s, P={P}",
+            "one_core": {"value": P1 / dt1, "cores": 1, "seconds": dt1},
+            "nproc": os.cpu_count(), "cpu": _cpu_model()}
 
 
 def integrate_section(steps, warmup):

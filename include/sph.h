@@ -97,6 +97,13 @@ typedef struct {
                             staged by all four, so that a batch of sources is staged once
                             per 256 targets rather than per 64); >= 64; results agree
                             with the other sweep up to summation order */
+    int fixed_h;         /* 0: sph_density solves h (Eq. (3)); 1: sph_density evaluates every
+                            sum at the caller's h as given (no Newton iteration, n_iter = 0),
+                            the forward pass of the fixed-h derivative of sph_backward; cells
+                            are rebuilt when a given h outgrows them */
+    int keep_adjoint;    /* 1: sph_density also keeps the per-particle sums the reverse pass
+                            needs (64 bytes per particle), which sph_backward requires;
+                            0 (default): forward-only passes write nothing of the kind */
 } sph_params;
 
 /* Staging of the FP32 density stage.  A target cell's sources are copied into
@@ -300,11 +307,17 @@ typedef struct {
  *   implicit_h = 1: h_i is the solved root of N_i(h_i) = n_ngb (Eq. (3)), so
  *     dh_i/dx = -(dN_i/dx)/(dN_i/dh_i) is included in dL/dx (implicit
  *     function theorem; exact at the root, up to the ngb_tol of the solve).
+ * `generation` names the density evaluation the caller means (the
+ * sph_stats.generation read after it); 0 takes whichever ran last.  A
+ * nonzero value that is not the last one (another forward pass ran on ctx
+ * since) is refused, since its state is gone.  With implicit_h = 1 the h of
+ * that evaluation must have been solved (params.fixed_h = 0).
  * Pair arithmetic in the context's precision, sums in FP64.  Does not
  * synchronise.  Errors: SPH_E_INVALID_ARG, SPH_E_STATE (no sph_density yet,
- * or a different particle count), SPH_E_OOM, SPH_E_HIP. */
+ * a different particle count, a stale generation, a context without
+ * params.keep_adjoint, or implicit_h with a fixed h), SPH_E_OOM, SPH_E_HIP. */
 sph_status sph_backward(sph_ctx *ctx, const sph_particles *p, const sph_grad_in *grad_in,
-                        sph_grad_out *grad_out, int implicit_h, void *stream);
+                        sph_grad_out *grad_out, int implicit_h, uint64_t generation, void *stream);
 
 /* One kick-drift-kick velocity-Verlet step (Sec. 4.1) with fixed dt:
  *   v += dt/2 a, u += dt/2 du/dt  (a, du/dt of the previous step, from `acc`),
@@ -403,6 +416,9 @@ typedef struct {
     int32_t refreshes;       /* sph_refresh calls since the last build */
     double drift;            /* box 0: the largest displacement since the last build
                                 (as of the last sph_refresh) */
+    uint64_t generation;     /* count of density evaluations on ctx: sph_density,
+                                sph_density_async and every sph_graph_launch add one; the
+                                state sph_backward differentiates is that of this one */
 } sph_stats;
 
 sph_status sph_get_stats(const sph_ctx *ctx, sph_stats *out);

@@ -98,6 +98,8 @@ def _load():
         lib.ora_bands.argtypes = [i64, P, P, P, P, P, P, i64, P, P, P]
         lib.ora_num_threads.restype = i32
         lib.ora_num_threads.argtypes = []
+        lib.ora_set_num_threads.restype = None
+        lib.ora_set_num_threads.argtypes = [i32]
         _lib = lib
     return _lib
 
@@ -119,6 +121,11 @@ def _check(st, what):
 
 def num_threads() -> int:
     return int(_load().ora_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the OpenMP loops of the calls that follow."""
+    _load().ora_set_num_threads(int(n))
 
 
 def kernel_w(q):

@@ -667,3 +667,13 @@ int ora_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the parallel loops that follow (n >= 1). */
+void ora_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

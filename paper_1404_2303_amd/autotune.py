@@ -62,6 +62,20 @@ def save_cache(cache: dict, path: str = CACHE) -> None:
     os.replace(tmp, path)
 
 
+class CandidateUnusable(Exception):
+    """Raised by a timer for a candidate the workload cannot use: it is skipped."""
+
+
+def _unusable(e: Exception) -> bool:
+    """A candidate the workload cannot use: the timer says so, or the library
+    refused it for capacity (a cell or grid beyond the kernels' limits) or
+    state.  Anything else (a HIP error, a wrong result, a bug) is raised."""
+    if isinstance(e, CandidateUnusable):
+        return True
+    from . import sph
+    return isinstance(e, sph.SPHError) and e.status in (sph.SPH_E_CAPACITY, sph.SPH_E_STATE)
+
+
 def choose(timings: dict) -> dict:
     """Fastest candidate (ties: the earlier one)."""
     best_key = min(timings, key=lambda k: (timings[k], list(timings).index(k)))
@@ -72,24 +86,27 @@ def tune(time_candidate: Callable[[dict], float], key: str, arch: str, candidate
          cache_path: str = CACHE, force: bool = False) -> dict:
     """Return the best parameters for (arch, key), timing candidates if needed.
 
-    time_candidate(params) -> seconds per pass (lower is better); it may raise
-    for candidates the workload cannot use, which are then skipped.
+    time_candidate(params) -> seconds per pass (lower is better).  A candidate
+    the workload cannot use (CandidateUnusable, or the library's capacity or
+    state refusal) is skipped; every other exception propagates.
     """
     candidates = CANDIDATES if candidates is None else candidates
     cache = load_cache(cache_path)
     full = f"{arch}|{key}"
     if not force and full in cache:
         return dict(cache[full]["best"], cached=True)
-    timings = {}
+    timings, skipped = {}, {}
     for c in candidates:
         try:
             timings[json.dumps(c, sort_keys=True)] = float(time_candidate(c))
-        except Exception:
-            continue
+        except Exception as e:
+            if not _unusable(e):
+                raise
+            skipped[json.dumps(c, sort_keys=True)] = str(e)
     if not timings:
         raise RuntimeError("no autotune candidate ran")
     best = choose(timings)
-    cache[full] = {"best": best, "timings": timings, "when": time.time()}
+    cache[full] = {"best": best, "timings": timings, "skipped": skipped, "when": time.time()}
     save_cache(cache, cache_path)
     return dict(best, cached=False)
 

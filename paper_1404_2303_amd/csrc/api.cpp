@@ -92,6 +92,8 @@ struct sph_ctx {
     std::vector<int64_t> batch_off;
     std::vector<double> batch_len;
     bool built = false, sorted = false, have_density = false;
+    bool adjoint_ready = false;                      // the last density kept the reverse-pass sums
+    uint64_t generation = 0;                         // density evaluations so far
     unsigned ev_recorded = 0;                        // events recorded at least once (bit per event)
     sph_stats stats{};
     // optional kernel timing
@@ -153,7 +155,8 @@ static GhostData<R> ghost_data(sph_ctx* c)
     GhostData<R> g;
     g.g0 = c->g0.as<R4>(); g.g1 = c->g1.as<R4>();
     g.cell_hmax = c->cell_hmax.as<float>();
-    g.sd0 = c->sd0.as<double4>(); g.sd1 = c->sd1.as<double4>();
+    g.sd0 = c->prm.keep_adjoint ? c->sd0.as<double4>() : nullptr;
+    g.sd1 = c->prm.keep_adjoint ? c->sd1.as<double4>() : nullptr;
     g.active = c->mts_masked ? c->mts_active.as<uint8_t>() : nullptr;
     const bool st = c->mts_masked || c->mts_store;
     g.s_rho = st ? c->mts_rho.as<double>() : nullptr;
@@ -196,6 +199,7 @@ static PassConsts pass_consts(const sph_params& p)
     pc.cfl = p.cfl;
     pc.balsara_div = p.balsara_form == SPH_BALSARA_DIV ? 1 : 0;
     pc.shared_min = p.shared_min;
+    pc.fixed_h = p.fixed_h;
     return pc;
 }
 
@@ -234,7 +238,7 @@ static bool ensure_particles(sph_ctx* c, int64_t n)
     ok &= c->vm.ensure(N * 4 * R);
     ok &= c->g0.ensure(N * 4 * R) && c->g1.ensure(N * 4 * R);
     ok &= c->cell_hmax.ensure(N * 4);
-    ok &= c->sd0.ensure(N * sizeof(double4)) && c->sd1.ensure(N * sizeof(double4));
+    if (c->prm.keep_adjoint) ok &= c->sd0.ensure(N * sizeof(double4)) && c->sd1.ensure(N * sizeof(double4));
     ok &= c->qhead.ensure(16) && c->status.ensure(16);
     return ok;
 }
@@ -264,6 +268,8 @@ void sph_default_params(sph_params* p)
     p->reuse = 0;
     p->staging = SPH_STAGING_COMPACT;
     p->shared_min = 128;
+    p->fixed_h = 0;
+    p->keep_adjoint = 0;
 }
 
 const char* sph_status_string(sph_status s)
@@ -301,6 +307,8 @@ static bool params_ok(const sph_params& p)
     if (p.reuse != SPH_REUSE_OFF && p.reuse != SPH_REUSE_ORDERINGS && p.reuse != SPH_REUSE_CELLS) return false;
     if (p.staging != SPH_STAGING_COMPACT && p.staging != SPH_STAGING_WIDE) return false;
     if (p.shared_min < 64) return false;
+    if (p.fixed_h != 0 && p.fixed_h != 1) return false;
+    if (p.keep_adjoint != 0 && p.keep_adjoint != 1) return false;
     return true;
 }
 
@@ -757,6 +765,8 @@ sph_status sph_density(sph_ctx* c, sph_particles* p, sph_density_out* o, void* s
         }
         if (bits & ST_REBUILD) return SPH_E_H_TOO_LARGE;
         c->have_density = true;
+        c->adjoint_ready = c->prm.keep_adjoint != 0;
+        c->generation++;
         if (bits & ST_NOT_CONVERGED) return SPH_E_NOT_CONVERGED;
         return SPH_OK;
     }
@@ -778,6 +788,8 @@ sph_status sph_density_async(sph_ctx* c, sph_particles* p, sph_density_out* o, v
         if (hipGetLastError() != hipSuccess) return SPH_E_HIP;
     }
     c->have_density = true;
+    c->adjoint_ready = c->prm.keep_adjoint != 0;
+    c->generation++;
     c->dens_async_timed = c->timing && c->n > 0;
     return SPH_OK;
 }
@@ -840,10 +852,13 @@ static sph_status backward_launch(sph_ctx* c, const sph_grad_in* gi, sph_grad_ou
 }  // extern "C++"
 
 sph_status sph_backward(sph_ctx* c, const sph_particles* p, const sph_grad_in* gi, sph_grad_out* go,
-                        int implicit_h, void* stream)
+                        int implicit_h, uint64_t generation, void* stream)
 {
     if (!c || !particles_ok(p) || !gi || !go) return SPH_E_INVALID_ARG;
     if (!c->have_density || p->n != c->n) return SPH_E_STATE;
+    if (!c->adjoint_ready) return SPH_E_STATE;                          // nothing kept to differentiate
+    if (generation != 0 && generation != c->generation) return SPH_E_STATE;   // that state is gone
+    if (implicit_h && c->prm.fixed_h) return SPH_E_STATE;                // h was given, not solved
     hipStream_t st = (hipStream_t)stream;
     c->adj_timed = false;
     if (c->n == 0) return SPH_OK;
@@ -1164,7 +1179,9 @@ sph_status sph_graph_launch(sph_ctx* c, void* stream)
 {
     if (!c) return SPH_E_INVALID_ARG;
     if (!c->graph_exec) return SPH_E_STATE;
-    return hipGraphLaunch(c->graph_exec, (hipStream_t)stream) == hipSuccess ? SPH_OK : SPH_E_HIP;
+    if (hipGraphLaunch(c->graph_exec, (hipStream_t)stream) != hipSuccess) return SPH_E_HIP;
+    c->generation++;   // the replay's density stage replaced the state
+    return SPH_OK;
 }
 
 sph_status sph_enable_timing(sph_ctx* c, int on)
@@ -1200,6 +1217,7 @@ sph_status sph_get_stats(const sph_ctx* c, sph_stats* out)
     if (!c || !out) return SPH_E_INVALID_ARG;
     *out = c->stats;
     out->depth = c->depth;
+    out->generation = c->generation;
     if (!c->box_host.empty()) {
         BoxInfo b0;
         if (c->built && hipMemcpy(&b0, c->boxes.p, sizeof(BoxInfo), hipMemcpyDeviceToHost) == hipSuccess) {

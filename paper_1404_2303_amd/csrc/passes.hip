@@ -198,7 +198,12 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
             double lo = 0.0, hi = INFINITY, h_rebuild = 0.0;
             int iters = 0;
             bool failed = false;
-            bool conv = !on;
+            bool conv = !on || pc.fixed_h;
+            if (pc.fixed_h && on && cd.h[gi] > h_lim) {
+                // a given h beyond what the cells allow: rebuilt for it, then swept again
+                if (w == 0) atomicOr(dc.status, ST_REBUILD);
+                h_rebuild = cd.h[gi];
+            }
             // neighbour lists of this wavefront: valid while every lane's h <= hcache
             bool cached = false;
             bool cached_all = false;  // the lists were built with every valid lane active
@@ -295,7 +300,7 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
             // ends there if it confirms convergence.  Once every lane has
             // converged, one evaluation with every sum ends it too.
             const double step_final = sqrt(pc.tol / (10.0 * pc.n_ngb));
-            bool full = false;
+            bool full = pc.fixed_h != 0;   // a given h: straight to the full sums
             int cit = 0;  // count steps since the buffers were last cleared
             for (int a = w; a < 2; a += NW) s.red[a][lane] = 0.0;
             __syncthreads();

@@ -140,6 +140,7 @@ struct PassConsts {
     double cfl;         // C_CFL of Eq. (6)
     int balsara_div;    // 1: |div v| over the Balsara denominator, 0: |curl v|
     int shared_min;     // cells of more particles than this are swept shared
+    int fixed_h;        // 1: every sum at the given h, no iteration
 };
 
 }  // namespace sph

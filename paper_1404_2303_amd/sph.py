@@ -43,7 +43,8 @@ class sph_params(ctypes.Structure):
                 ("cell_target", ctypes.c_int), ("h_margin", ctypes.c_double),
                 ("max_rebuilds", ctypes.c_int), ("max_depth", ctypes.c_int), ("split_count", ctypes.c_int),
                 ("split_frac", ctypes.c_double), ("cfl", ctypes.c_double), ("balsara_form", ctypes.c_int),
-                ("reuse", ctypes.c_int), ("staging", ctypes.c_int), ("shared_min", ctypes.c_int)]
+                ("reuse", ctypes.c_int), ("staging", ctypes.c_int), ("shared_min", ctypes.c_int),
+                ("fixed_h", ctypes.c_int), ("keep_adjoint", ctypes.c_int)]
 
 
 class sph_particles(ctypes.Structure):
@@ -86,7 +87,7 @@ class sph_stats(ctypes.Structure):
     _fields_ = [("n_cells", ctypes.c_int64), ("n_units", ctypes.c_int64), ("grid", ctypes.c_int32 * 3),
                 ("rebuilds", ctypes.c_int32), ("max_iter_used", ctypes.c_int32),
                 ("unconverged", ctypes.c_int32), ("depth", ctypes.c_int32), ("refreshes", ctypes.c_int32),
-                ("drift", ctypes.c_double)]
+                ("drift", ctypes.c_double), ("generation", ctypes.c_uint64)]
 
 
 _lib = None
@@ -149,7 +150,7 @@ def load_library():
         lib.sph_graph_launch.argtypes = [P, P]
         lib.sph_backward.restype = st
         lib.sph_backward.argtypes = [P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_grad_in),
-                                     ctypes.POINTER(sph_grad_out), ctypes.c_int, P]
+                                     ctypes.POINTER(sph_grad_out), ctypes.c_int, ctypes.c_uint64, P]
         lib.sph_estimate_h.restype = st
         lib.sph_estimate_h.argtypes = [P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_batch), P]
         lib.sph_status_string.restype = ctypes.c_char_p
@@ -258,9 +259,10 @@ def sph_graph_launch(ctx, stream):
     return load_library().sph_graph_launch(ctx, stream)
 
 
-def sph_backward(ctx, parts: sph_particles, gin: sph_grad_in, gout: sph_grad_out, implicit_h: int, stream):
+def sph_backward(ctx, parts: sph_particles, gin: sph_grad_in, gout: sph_grad_out, implicit_h: int, generation: int,
+                 stream):
     return load_library().sph_backward(ctx, ctypes.byref(parts), ctypes.byref(gin), ctypes.byref(gout),
-                                       int(implicit_h), stream)
+                                       int(implicit_h), int(generation), stream)
 
 
 # ---------------------------------------------------------------- tensor layer
@@ -441,9 +443,12 @@ class Context:
                              ctypes.byref(steps), _stream()), "sph_integrate", (SPH_E_NOT_CONVERGED,))
         return acc, int(steps.value)
 
-    def backward(self, parts: Particles, g_rho=None, g_a=None, g_dudt=None, implicit_h=True, want_h=False):
+    def backward(self, parts: Particles, g_rho=None, g_a=None, g_dudt=None, implicit_h=True, want_h=False,
+                 generation: int = 0):
         """Gradients of L at the state of the last density(): dL/dx as (N,3) and, if want_h
-        (fixed h only), dL/dh.  g_a is (N,3) or None; missing upstream gradients count as 0."""
+        (fixed h only), dL/dh.  g_a is (N,3) or None; missing upstream gradients count as 0.
+        generation (from stats()) names the density evaluation meant; 0 takes the last one.
+        Needs a context created with keep_adjoint=1."""
         n = parts.n
         dev = parts.x.device
 
@@ -455,7 +460,8 @@ class Context:
         gx, gy, gz = (torch.empty(n, dtype=torch.float64, device=dev) for _ in range(3))
         gh = torch.empty(n, dtype=torch.float64, device=dev) if want_h else None
         gout = sph_grad_out(_ptr(gx), _ptr(gy), _ptr(gz), _ptr(gh))
-        _check(sph_backward(self.ctx, parts.c_struct(), gin, gout, int(bool(implicit_h)), _stream()), "sph_backward")
+        _check(sph_backward(self.ctx, parts.c_struct(), gin, gout, int(bool(implicit_h)), generation, _stream()),
+               "sph_backward")
         gpos = torch.stack([gx, gy, gz], dim=1)
         return (gpos, gh) if want_h else gpos
 
@@ -501,7 +507,7 @@ class Context:
         s = sph_stats()
         _check(load_library().sph_get_stats(self.ctx, ctypes.byref(s)), "sph_get_stats")
         return {"n_cells": s.n_cells, "n_units": s.n_units, "grid": tuple(s.grid), "rebuilds": s.rebuilds,
-                "depth": s.depth, "refreshes": s.refreshes, "drift": s.drift}
+                "depth": s.depth, "refreshes": s.refreshes, "drift": s.drift, "generation": int(s.generation)}
 
     def run(self, parts: Particles, batch: Optional[Batch] = None, allow_unconverged=False):
         """build -> sort -> density (h solved in place) -> force."""
@@ -512,32 +518,76 @@ class Context:
         return d, f
 
 
+def _parts_from(pos, vel, m, u, h):
+    pos = pos.detach().to(torch.float64)
+    vel = vel.detach().to(torch.float64)
+    return Particles(x=pos[:, 0].contiguous(), y=pos[:, 1].contiguous(), z=pos[:, 2].contiguous(),
+                     vx=vel[:, 0].contiguous(), vy=vel[:, 1].contiguous(), vz=vel[:, 2].contiguous(),
+                     u=_as_f64(u.detach()), m=_as_f64(m.detach()), h=h.detach().to(torch.float64).clone())
+
+
+def _forward_on(context: "Context", parts: Particles, fctx, fixed: bool):
+    p = context.params
+    if not p.keep_adjoint:
+        raise ValueError("the context must be created with keep_adjoint=1 to be differentiated")
+    if bool(p.fixed_h) != fixed:
+        raise ValueError("SPHPassFixedH needs a context with fixed_h=1, SPHPass one with fixed_h=0")
+    d, f = context.run(parts)
+    fctx.context = context
+    fctx.parts = parts
+    fctx.generation = context.stats()["generation"]
+    return d, f
+
+
 class SPHPass(torch.autograd.Function):
     """rho, a (N,3) and du/dt of one pass as a differentiable function of the
     positions pos (N,3), with h the solved root of Eq. (3) (its dependence on
     the positions enters through the implicit derivative).
 
     SPHPass.apply(pos, vel, m, u, h0, context) runs build, sort, density (h
-    solved from the guess h0) and force through ``context``; backward calls
-    sph_backward.  The solved h is left in context.last_h.  Velocities,
-    masses and u are treated as constants.
+    solved from the guess h0) and force through ``context`` (created with
+    keep_adjoint=1, fixed_h=0); backward calls sph_backward on the density
+    evaluation of this forward, and fails (SPH_E_STATE) if another forward
+    pass has run on the context since.  The solved h is left in
+    context.last_h.  Velocities, masses and u are treated as constants.
     """
 
     @staticmethod
     def forward(fctx, pos, vel, m, u, h0, context: "Context"):
-        pos = pos.detach().to(torch.float64)
-        vel = vel.detach().to(torch.float64)
-        parts = Particles(x=pos[:, 0].contiguous(), y=pos[:, 1].contiguous(), z=pos[:, 2].contiguous(),
-                          vx=vel[:, 0].contiguous(), vy=vel[:, 1].contiguous(), vz=vel[:, 2].contiguous(),
-                          u=_as_f64(u.detach()), m=_as_f64(m.detach()), h=h0.detach().to(torch.float64).clone())
-        d, f = context.run(parts)
+        parts = _parts_from(pos, vel, m, u, h0)
+        d, f = _forward_on(context, parts, fctx, fixed=False)
         context.last_h = parts.h
-        fctx.context = context
-        fctx.parts = parts
         a = torch.stack([f["ax"], f["ay"], f["az"]], dim=1)
         return d["rho"], a, f["dudt"]
 
     @staticmethod
     def backward(fctx, g_rho, g_a, g_dudt):
-        gpos = fctx.context.backward(fctx.parts, g_rho, g_a, g_dudt, implicit_h=True)
+        gpos = fctx.context.backward(fctx.parts, g_rho, g_a, g_dudt, implicit_h=True, generation=fctx.generation)
         return gpos, None, None, None, None, None
+
+
+class SPHPassFixedH(torch.autograd.Function):
+    """rho, a (N,3) and du/dt of one pass as a differentiable function of the
+    positions pos (N,3) and of the smoothing lengths h (N,), both independent
+    inputs: the sums of Eqs. (2)-(5) at the given h, without the iteration of
+    Eq. (3) (so N_i need not equal n_ngb).
+
+    SPHPassFixedH.apply(pos, h, vel, m, u, context) runs build, sort, density
+    and force through ``context`` (created with fixed_h=1, keep_adjoint=1);
+    backward returns dL/dpos and dL/dh from sph_backward with implicit_h = 0
+    on the density evaluation of this forward.  Velocities, masses and u are
+    treated as constants.
+    """
+
+    @staticmethod
+    def forward(fctx, pos, h, vel, m, u, context: "Context"):
+        parts = _parts_from(pos, vel, m, u, h)
+        d, f = _forward_on(context, parts, fctx, fixed=True)
+        a = torch.stack([f["ax"], f["ay"], f["az"]], dim=1)
+        return d["rho"], a, f["dudt"]
+
+    @staticmethod
+    def backward(fctx, g_rho, g_a, g_dudt):
+        gpos, gh = fctx.context.backward(fctx.parts, g_rho, g_a, g_dudt, implicit_h=False, want_h=True,
+                                         generation=fctx.generation)
+        return gpos, gh, None, None, None, None

@@ -14,13 +14,11 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 
 import oracle  # noqa: E402
+import sample_columns  # noqa: E402
 from paper_1404_2303_amd import workloads  # noqa: E402
-
-COLUMNS = ["index", "h", "rho", "omega", "div", "f", "P", "c", "ax", "ay", "az", "dudt", "kappa_a", "kappa_u",
-           "count", "band", "dndh", "dt", "vsig_lo", "vsig_hi", "sens_a", "sens_u"]
-
 
 def sample_indices(ps, k=64, seed=4):
     rng = np.random.default_rng(seed)
@@ -36,14 +34,8 @@ def main():
     sel = sample_indices(ps)
     out = oracle.full_pass(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box, tol=1e-12, force_sel=sel, balsara_form=1,
                            gamma=ps.meta["gamma"])
-    d, g, f, s = out["dens"], out["ghost"], out["force"], out["signal"]
-    rows = np.column_stack([sel, out["h"][sel], d["rho"][sel], g["omega"][sel], d["div"][sel], g["f"][sel],
-                            g["P"][sel], g["c"][sel], f["a"][sel], f["dudt"][sel], f["kappa_a"][sel],
-                            f["kappa_u"][sel], f["count"][sel], f["band"][sel], d["dndh"][sel], s["dt"][sel],
-                            s["vsig_lo"][sel], s["vsig_hi"][sel], f["sens_a"][sel], f["sens_u"][sel]])
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "sod_sample.txt")
-    np.savetxt(path, rows, fmt="%.17g", header=" ".join(COLUMNS))
-    print("wrote", path, rows.shape)
+    cols, data = sample_columns.rows(ps, out, sel, signal=True)
+    sample_columns.write(os.path.join(os.path.dirname(os.path.abspath(__file__)), "sod_sample.txt"), cols, data)
 
 
 if __name__ == "__main__":

@@ -60,7 +60,7 @@ def _dense_state(n=1200, seed=17):
 
 def _gpu_vjp(ps, precision, w, implicit):
     parts = sph.Particles.from_numpy(ps, "cuda:0")
-    ctx = sph.Context(ps.box, precision=precision)
+    ctx = sph.Context(ps.box, precision=precision, keep_adjoint=1)
     ctx.run(parts)
     gx, gh = ctx.backward(parts, _dev(w[0]), _dev(w[1]), _dev(w[2]), implicit_h=implicit, want_h=True)
     torch.cuda.synchronize()
@@ -94,7 +94,7 @@ def test_adjoint_each_upstream_alone(which):
     ps, w = _dense_state(900, 23)
     log(f"case adjoint upstream {which} alone fp64")
     parts = sph.Particles.from_numpy(ps, "cuda:0")
-    ctx = sph.Context(ps.box, precision="fp64")
+    ctx = sph.Context(ps.box, precision="fp64", keep_adjoint=1)
     ctx.run(parts)
     kw = {"rho": (w[0], None, None), "a": (None, w[1], None), "dudt": (None, None, w[2])}[which]
     gx, gh = ctx.backward(parts, *[None if a is None else _dev(a) for a in kw], implicit_h=False, want_h=True)
@@ -112,7 +112,7 @@ def test_autograd_function_matches_dense_oracle():
     ps, _ = _dense_state(1000, 29)
     rt = workloads.density_target(ps.pos, float(np.sum(ps.m)))
     log("case SPHPass autograd 1000 fp64")
-    ctx = sph.Context(ps.box, precision="fp64")
+    ctx = sph.Context(ps.box, precision="fp64", keep_adjoint=1)
     pos = _dev(ps.pos).requires_grad_(True)
     rho, a, dudt = sph.SPHPass.apply(pos, _dev(ps.vel), _dev(ps.m), _dev(ps.u), _dev(ps.h0), ctx)
     L = ((rho - _dev(rt)) ** 2).sum() + (a ** 2).sum()
@@ -125,6 +125,59 @@ def test_autograd_function_matches_dense_oracle():
     ctx.close()
 
 
+def test_fixed_h_autograd_function_matches_dense_oracle():
+    """SPHPassFixedH: the sums at a given h (not the root of Eq. (3)) and their
+    gradients in the positions and in h, against the dense model at that h."""
+    ps, _ = _dense_state(1000, 37)
+    rng = np.random.default_rng(37)
+    hs, _ = oracle.solve_h(ps.pos, ps.h0, ps.box, tol=1e-13)
+    h = hs * rng.uniform(0.97, 1.03, ps.n)
+    rt = workloads.density_target(ps.pos, float(np.sum(ps.m)))
+    log("case SPHPassFixedH autograd 1000 fp64")
+    ctx = sph.Context(ps.box, precision="fp64", keep_adjoint=1, fixed_h=1)
+    pos = _dev(ps.pos).requires_grad_(True)
+    ht = _dev(h).requires_grad_(True)
+    rho, a, dudt = sph.SPHPassFixedH.apply(pos, ht, _dev(ps.vel), _dev(ps.m), _dev(ps.u), ctx)
+    ref_d = oracle.density(ps.pos, ps.vel, ps.m, h, ps.box)
+    e_rho = np.max(np.abs(rho.detach().cpu().numpy() / ref_d["rho"] - 1))
+    L = ((rho - _dev(rt)) ** 2).sum() + (a ** 2).sum()
+    gx, gh = torch.autograd.grad(L, (pos, ht))
+    rx, rh, Lref, _ = og.gradients(ps.pos, ps.vel, ps.m, ps.u, h, ps.box, rt, solve=False)
+    ex, eh = _err(gx.cpu().numpy(), rx), _err(gh.cpu().numpy(), rh)
+    log(f"  rho err {e_rho:.2e} L {float(L):.12e} ref {Lref:.12e} err x {ex:.2e} h {eh:.2e}")
+    assert e_rho <= 1e-10
+    assert abs(float(L) / Lref - 1.0) <= 1e-9
+    assert ex <= TOL_DENSE["fp64"] and eh <= TOL_DENSE["fp64"]
+    ctx.close()
+
+
+def test_backward_of_a_replaced_state_is_refused():
+    """A second forward pass on the same context replaces the state the first
+    one's backward would differentiate: that backward fails (SPH_E_STATE)
+    instead of returning the gradients of the other state.  A context
+    without keep_adjoint has nothing to differentiate."""
+    ps, _ = _dense_state(800, 41)
+    log("case stale backward 800 fp64")
+    ctx = sph.Context(ps.box, precision="fp64", keep_adjoint=1)
+    pos1 = _dev(ps.pos).requires_grad_(True)
+    out1 = sph.SPHPass.apply(pos1, _dev(ps.vel), _dev(ps.m), _dev(ps.u), _dev(ps.h0), ctx)
+    pos2 = _dev(ps.pos + 1e-3).requires_grad_(True)
+    out2 = sph.SPHPass.apply(pos2, _dev(ps.vel), _dev(ps.m), _dev(ps.u), _dev(ps.h0), ctx)
+    with pytest.raises(sph.SPHError) as e:
+        torch.autograd.grad(out1[0].sum(), pos1)
+    assert e.value.status == sph.SPH_E_STATE
+    (g2,) = torch.autograd.grad(out2[0].sum(), pos2)   # the current state still differentiates
+    assert torch.isfinite(g2).all()
+    ctx.close()
+    plain = sph.Context(ps.box, precision="fp64")
+    parts = sph.Particles.from_numpy(ps, "cuda:0")
+    plain.run(parts)
+    with pytest.raises(sph.SPHError) as e:
+        plain.backward(parts, _dev(np.ones(ps.n)), None, None, implicit_h=True)
+    assert e.value.status == sph.SPH_E_STATE
+    plain.close()
+
+
 def test_adjoint_translation_invariance_fp32():
     # with h solved, the loss of a frozen per-particle target is invariant under
     # a rigid shift of all particles, so sum_k dL/dx_k = 0
@@ -132,7 +185,7 @@ def test_adjoint_translation_invariance_fp32():
     rt = workloads.density_target(ps.pos, float(np.sum(ps.m)))
     log("case adjoint translation invariance 262144 fp32")
     parts = sph.Particles.from_numpy(ps, "cuda:0")
-    ctx = sph.Context(ps.box, precision="fp32")
+    ctx = sph.Context(ps.box, precision="fp32", keep_adjoint=1)
     d, f = ctx.run(parts)
     a = torch.stack([f["ax"], f["ay"], f["az"]], 1)
     gx = ctx.backward(parts, 2 * (d["rho"] - _dev(rt)), 2 * a, None, implicit_h=True)
@@ -166,7 +219,7 @@ def test_adjoint_matches_central_differences_262144(fd_case, precision):
     ps, rt = fd_case["ps"], fd_case["rt"]
     log(f"case adjoint FD 262144 {precision}")
     parts = sph.Particles.from_numpy(ps, "cuda:0")
-    ctx = sph.Context(ps.box, precision=precision)
+    ctx = sph.Context(ps.box, precision=precision, keep_adjoint=1)
     d, f = ctx.run(parts)
     a = torch.stack([f["ax"], f["ay"], f["az"]], 1)
     g_rho, g_a = 2 * (d["rho"] - _dev(rt)), 2 * a

@@ -9,7 +9,7 @@ import torch
 
 import oracle
 from paper_1404_2303_amd import sph, workloads
-from parity_util import compare, log
+from parity_util import compare, log, oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -65,7 +65,7 @@ def test_batched_parity_against_oracle():
     torch.cuda.synchronize()
     for b, ps in enumerate(sets):
         sl = slice(offsets[b], offsets[b + 1])
-        ref = oracle.full_pass(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box)
+        ref = oracle_run(ps)
         g = {k: v[sl].cpu().numpy() for k, v in d.items()}
         g.update({k: v[sl].cpu().numpy() for k, v in f.items()})
         g["h"] = parts.h[sl].cpu().numpy()
@@ -112,7 +112,7 @@ def test_density_async_and_check():
     c = sph.sph_density_out(*[sph._ptr(d.get(k)) for k in sph.DENSITY_FIELDS])
     assert sph.sph_density_async(ctx.ctx, parts.c_struct(), c, sph._stream()) == sph.SPH_OK
     assert ctx.check() == sph.SPH_OK
-    ref = oracle.full_pass(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box)
+    ref = oracle_run(ps)
     assert np.allclose(d["rho"].cpu().numpy(), ref["dens"]["rho"], rtol=1e-9)
     ctx.close()
 
@@ -147,7 +147,7 @@ def test_full_batch_as_the_bench_runs_it(cell_target):
     for b in boxes:
         sl = slice(offsets[b], offsets[b + 1])
         ps = workloads.uniform(int(counts[b]), seed=b)
-        ref = oracle.full_pass(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box)
+        ref = oracle_run(ps)
         g = {k: v[sl].cpu().numpy() for k, v in dout.items()}
         g.update({k: v[sl].cpu().numpy() for k, v in fout.items()})
         g["h"] = parts.h[sl].cpu().numpy()

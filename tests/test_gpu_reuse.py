@@ -12,7 +12,7 @@ import torch
 
 import oracle
 from paper_1404_2303_amd import sph, workloads
-from parity_util import compare, log
+from parity_util import compare, log, oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -71,7 +71,7 @@ def test_refresh_within_the_slack(precision):
     st = g["stats"]
     log(f"  stats {st}")
     assert st["refreshes"] == 1 and st["rebuilds"] == 0 and st["drift"] > 0
-    ref = oracle.full_pass(q.pos, q.vel, q.m, q.u, ps.h0, q.box)
+    ref = oracle_run(q, h0=ps.h0)
     compare(g, ref, precision, label="refresh")
 
 
@@ -84,7 +84,7 @@ def test_refresh_beyond_the_slack_rebuilds(precision):
     g = _refresh_run(ps, q, precision)
     log(f"  stats {g['stats']}")
     assert g["stats"]["rebuilds"] >= 1
-    ref = oracle.full_pass(q.pos, q.vel, q.m, q.u, ps.h0, q.box)
+    ref = oracle_run(q, h0=ps.h0)
     compare(g, ref, precision, label="refresh-rebuild")
 
 
@@ -99,7 +99,7 @@ def test_refresh_across_the_periodic_face(precision):
     assert crossing > 0
     g = _refresh_run(ps, q, precision)
     assert g["stats"]["rebuilds"] == 0
-    ref = oracle.full_pass(q.pos, q.vel, q.m, q.u, ps.h0, q.box)
+    ref = oracle_run(q, h0=ps.h0)
     compare(g, ref, precision, label="refresh-periodic")
 
 
@@ -127,7 +127,7 @@ def test_refresh_moving_next_to_resting(precision, resort):
     ctx.close()
     log(f"  stats {g['stats']}")
     assert g["stats"]["refreshes"] == 1 and g["stats"]["rebuilds"] == 0
-    ref = oracle.full_pass(q.pos, q.vel, q.m, q.u, ps.h0, q.box)
+    ref = oracle_run(q, h0=ps.h0)
     compare(g, ref, precision, label="refresh-half")
 
 
@@ -153,7 +153,7 @@ def test_refresh_on_the_hierarchy():
     ctx.close()
     log(f"  stats {g['stats']}")
     assert g["stats"]["depth"] > 0 and g["stats"]["refreshes"] == 1 and g["stats"]["rebuilds"] == 0
-    ref = oracle.full_pass(q.pos, q.vel, q.m, q.u, h_built, q.box)
+    ref = oracle_run(q, h0=h_built)
     compare(g, ref, "fp32", label="refresh-tree")
 
 

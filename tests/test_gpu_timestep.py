@@ -24,7 +24,7 @@ import oracle
 from oracle import grad as og
 from oracle import riemann
 from paper_1404_2303_amd import sph, workloads
-from parity_util import compare, gpu_run, log
+from parity_util import compare, compare_sample, gpu_run, load_sample, log, oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -58,7 +58,7 @@ def test_time_step_matches_oracle(precision):
     ps = _state()
     log(f"case dt uniform {ps.n} {precision}")
     g = gpu_run(ps, precision)
-    ref = oracle.full_pass(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box)
+    ref = oracle_run(ps)
     _check_dt(g, ref, precision, "dt")
     # the self term bounds every step: dt <= C_CFL h / c
     assert np.all(g["dt"] <= CFL * g["h"] / g["sound"] * (1 + T_VSIG[precision]))
@@ -75,7 +75,7 @@ def test_time_step_on_the_hierarchy(precision):
     ps.u[:] = rng.uniform(0.5, 1.5, ps.n)
     log(f"case dt hierarchy {ps.n} {precision}")
     g = gpu_run(ps, precision, estimate=True, max_depth=6, split_count=64, split_frac=0.5)
-    ref = oracle.full_pass(ps.pos, ps.vel, ps.m, ps.u, g["h"], ps.box)
+    ref = oracle_run(ps)
     assert g["stats"]["depth"] > 0
     _check_dt(g, ref, precision, "dt tree")
 
@@ -85,10 +85,10 @@ def test_balsara_div_form_matches_oracle(precision):
     ps = _state(2000, 72)
     log(f"case balsara div form {ps.n} {precision}")
     g = gpu_run(ps, precision, balsara_form=sph.SPH_BALSARA_DIV)
-    ref = oracle.full_pass(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box, balsara_form=1)
+    ref = oracle_run(ps, balsara_form=1)
     compare(g, ref, precision, label="balsara-div")
     # not the printed form: the two switches differ
-    ref0 = oracle.full_pass(ps.pos, ps.vel, ps.m, ps.u, ps.h0, ps.box, balsara_form=0)
+    ref0 = oracle_run(ps, balsara_form=0)
     assert np.max(np.abs(ref0["ghost"]["f"] - ref["ghost"]["f"])) > 0.1
 
 
@@ -99,7 +99,7 @@ def test_adjoint_balsara_div_form(precision):
     w = (rng.normal(size=ps.n), rng.normal(size=(ps.n, 3)), rng.normal(size=ps.n))
     log(f"case adjoint balsara div 1200 {precision}")
     parts = sph.Particles.from_numpy(ps, "cuda:0")
-    ctx = sph.Context(ps.box, precision=precision, balsara_form=sph.SPH_BALSARA_DIV)
+    ctx = sph.Context(ps.box, precision=precision, balsara_form=sph.SPH_BALSARA_DIV, keep_adjoint=1)
     ctx.run(parts)
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
     gx = ctx.backward(parts, dev(w[0]), dev(w[1]), dev(w[2]), implicit_h=True).cpu().numpy()
@@ -340,44 +340,20 @@ def test_sedov_blast_follows_the_similarity_solution():
 
 def _load_sample(name):
     import os
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
-    ref = np.loadtxt(path)
-    cols = open(path).readline().lstrip("# ").split()
-    return {c: ref[:, k] for k, c in enumerate(cols)}
+    return load_sample(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name))
 
 
-def _check_sample(g, R):
-    """First-pass outputs of the FP32 form at the oracle's sampled particles,
-    with Eq. (6)'s signal velocity inside the oracle's band; a and du/dt
-    against kappa plus the h tolerance's reach through sens."""
-    from parity_util import TOL
+def _check_sample(g, R, label):
+    """First-pass outputs of the FP32 form at the oracle's sampled particles
+    (compare_sample), and Eq. (6)'s signal velocity inside the oracle's band."""
+    compare_sample(g, R, "fp32", label=label)
     idx = R["index"].astype(np.int64)
-    t = TOL["fp32"]
-    e = {}
-    h_band = np.maximum(t["h"], t["ngb"] / (R["h"] * np.abs(R["dndh"])))
-    e["h"] = np.max(np.abs(g["h"][idx] / R["h"] - 1) / h_band) * t["h"]
-    e["rho"] = np.max(np.abs(g["rho"][idx] / R["rho"] - 1))
-    e["P"] = np.max(np.abs(g["pressure"][idx] / R["P"] - 1))
-    e["c"] = np.max(np.abs(g["sound"][idx] / R["c"] - 1))
-    e["omega"] = np.max(np.abs(g["omega"][idx] - R["omega"]))
-    e["f"] = np.max(np.abs(g["balsara"][idx] - R["f"]))
-    rd = np.sqrt(np.mean(R["div"] ** 2)) + 1e-300
-    e["div"] = np.max(np.abs(g["div_v"][idx] - R["div"]) / (rd + np.abs(R["div"])))
-    a = np.stack([R["ax"], R["ay"], R["az"]], 1)
-    ka = R["kappa_a"] + t["h"] / t["a"] * R["sens_a"]
-    ku = R["kappa_u"] + t["h"] / t["a"] * R["sens_u"] + 1e-300
-    e["a"] = np.max(np.linalg.norm(g["a"][idx] - a, axis=1) / ka)
-    e["dudt"] = np.max(np.abs(g["dudt"][idx] - R["dudt"]) / ku)
-    e["count"] = int(np.max(np.abs(g["n_pairs"][idx] - R["count"]) - R["band"]))
     vs = CFL * 2.0 * g["h"][idx] / g["dt"][idx]
     tv = T_VSIG["fp32"] + T_H["fp32"]
-    e["vsig_below"] = float(-np.min(vs / R["vsig_lo"] - 1.0))
-    e["vsig_above"] = float(np.max(vs / R["vsig_hi"] - 1.0))
-    log("  " + " ".join(f"{k}={v:.2e}" if isinstance(v, float) else f"{k}={v}" for k, v in e.items()))
-    assert e["h"] <= t["h"] and e["rho"] <= t["rho"] and e["P"] <= t["rho"] and e["c"] <= t["rho"]
-    assert e["omega"] <= t["omega"] and e["f"] <= t["f"] and e["div"] <= t["vec"]
-    assert e["a"] <= t["a"] and e["dudt"] <= t["a"] and e["count"] <= 0
-    assert e["vsig_below"] <= tv and e["vsig_above"] <= tv
+    below = float(-np.min(vs / R["vsig_lo"] - 1.0))
+    above = float(np.max(vs / R["vsig_hi"] - 1.0))
+    log(f"  vsig below band {below:.2e} above band {above:.2e}")
+    assert below <= tv and above <= tv
 
 
 def test_sod_at_the_bench_size_sampled():
@@ -389,7 +365,7 @@ def test_sod_at_the_bench_size_sampled():
     ps = workloads.sod(37)
     log(f"case sod bench size {ps.n} fp32, wide staging")
     g = gpu_run(ps, "fp32", balsara_form=sph.SPH_BALSARA_DIV, staging=sph.SPH_STAGING_WIDE)
-    _check_sample(g, R)
+    _check_sample(g, R, "sod")
 
 
 def test_sedov_at_the_bench_size_sampled():
@@ -406,7 +382,7 @@ def test_sedov_at_the_bench_size_sampled():
     ps = workloads.sedov(63)
     log(f"case sedov bench size {ps.n} fp32, compact staging")
     g = gpu_run(ps, "fp32", balsara_form=sph.SPH_BALSARA_DIV)
-    _check_sample(g, R)
+    _check_sample(g, R, "sedov")
     dtb = 0.7 * float(R["dt"].min())
     tv = T_VSIG["fp32"] + T_H["fp32"]
     dt_lo = CFL * 2.0 * R["h"] / R["vsig_hi"] / (1.0 + tv)

@@ -11,7 +11,7 @@ import torch
 import oracle
 from oracle import grad as og
 from paper_1404_2303_amd import sph, workloads
-from parity_util import TOL, compare, gpu_run, log, oracle_run
+from parity_util import TOL, compare, compare_sample, gpu_run, load_sample, log, oracle_run
 
 pytestmark = pytest.mark.gpu
 
@@ -122,7 +122,7 @@ def test_adjoint_on_the_hierarchy():
     w = (rng.normal(size=ps.n), rng.normal(size=(ps.n, 3)), rng.normal(size=ps.n))
     log(f"case tree adjoint {ps.n}")
     parts = sph.Particles.from_numpy(ps, "cuda:0")
-    ctx = sph.Context(ps.box, precision="fp64", max_depth=6, split_count=16, split_frac=0.5)
+    ctx = sph.Context(ps.box, precision="fp64", max_depth=6, split_count=16, split_frac=0.5, keep_adjoint=1)
     ctx.estimate_h(parts)
     ctx.run(parts)
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
@@ -142,32 +142,13 @@ def test_config2_sampled_fp32(split_count):
     the oracle's sample (tests/golden/config2_sample.txt, written by
     make_config2_sample.py from the oracle alone); split count 256 is the
     bench's autotuned launch configuration."""
-    path = os.path.join(HERE, "golden", "config2_sample.txt")
-    ref = np.loadtxt(path)
-    cols = open(path).readline().lstrip("# ").split()
-    R = {c: ref[:, k] for k, c in enumerate(cols)}
-    idx = R["index"].astype(np.int64)
+    R = load_sample(os.path.join(HERE, "golden", "config2_sample.txt"))
     ps = workloads.config2()
     log(f"case tree config2 {ps.n} fp32 split_count {split_count}")
     g = gpu_run(ps, "fp32", estimate=True, max_depth=10, split_count=split_count)
     st = g["stats"]
     log(f"  leaves {st['n_cells']} depth {st['depth']} top grid {st['grid']} rebuilds {st['rebuilds']}")
-    t = TOL["fp32"]
-    e = {}
-    h_band = np.maximum(t["h"], t["ngb"] / (R["h"] * np.abs(R["dndh"])))
-    e["h"] = np.max(np.abs(g["h"][idx] / R["h"] - 1) / h_band) * t["h"]
-    e["rho"] = np.max(np.abs(g["rho"][idx] / R["rho"] - 1))
-    e["omega"] = np.max(np.abs(g["omega"][idx] - R["omega"]))
-    e["f"] = np.max(np.abs(g["balsara"][idx] - R["f"]))
-    rd = np.sqrt(np.mean(R["div"] ** 2))
-    e["div"] = np.max(np.abs(g["div_v"][idx] - R["div"]) / (rd + np.abs(R["div"])))
-    a = np.stack([R["ax"], R["ay"], R["az"]], 1)
-    e["a"] = np.max(np.linalg.norm(g["a"][idx] - a, axis=1) / R["kappa_a"])
-    e["dudt"] = np.max(np.abs(g["dudt"][idx] - R["dudt"]) / R["kappa_u"])
-    e["count"] = int(np.max(np.abs(g["n_pairs"][idx] - R["count"]) - R["band"]))
-    log("  " + " ".join(f"{k}={v:.2e}" if isinstance(v, float) else f"{k}={v}" for k, v in e.items()))
-    assert e["h"] <= t["h"] and e["rho"] <= t["rho"] and e["omega"] <= t["omega"] and e["f"] <= t["f"]
-    assert e["div"] <= t["vec"] and e["a"] <= t["a"] and e["dudt"] <= t["a"] and e["count"] <= 0
+    compare_sample(g, R, "fp32", label=f"config2 split {split_count}")
 
 
 def test_graph_replay_on_the_hierarchy(mixture):
