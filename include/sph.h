@@ -437,6 +437,28 @@ typedef struct {
 sph_status sph_enable_timing(sph_ctx *ctx, int on);
 sph_status sph_get_kernel_times(sph_ctx *ctx, sph_kernel_times *out);
 
+/* Allocation-free pass, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same as sph_build_cells + sph_sort + sph_density +
+ * sph_force on a context created with *params, for one periodic box
+ * (params->box) of p->n <= SPH_NOALLOC_MAX_PARTICLES particles, with every
+ * device buffer taken from a fixed array of 32 MiB inside the library (one per
+ * GPU, held from the library's load until the process ends) instead of being
+ * allocated: it calls no device or host allocation routine (its first call on
+ * a device looks the array's address up, once).  p->h is the initial guess and receives
+ * the solved h; dout (may be NULL, and any field of it) and fout (required;
+ * any field may be NULL) are caller-owned device arrays as in sph_density and
+ * sph_force.  Synchronises `stream` as sph_density does.  Calls on one GPU
+ * share the array: calls that overlap on one GPU (two host threads, two
+ * streams) race, and each call overwrites what the last one left there.
+ * Requires params->max_depth == 0, params->reuse == SPH_REUSE_OFF and
+ * params->keep_adjoint == 0 (no reverse pass).
+ * Errors: SPH_E_INVALID_ARG, SPH_E_CAPACITY (p->n above the maximum, or a
+ * workspace that would not fit the array), and those of the four calls. */
+#define SPH_NOALLOC_MAX_PARTICLES 32768
+sph_status sph_pass_noalloc(const sph_params *params, sph_particles *p, sph_density_out *dout,
+                            sph_force_out *fout, void *stream);
+
 /* Human-readable text of a status (static storage). */
 const char *sph_status_string(sph_status s);
 

@@ -16,13 +16,29 @@ using namespace sph;
 
 namespace {
 
-// grow-only device buffer
+// A fixed region of device memory handed out front to back (256-byte
+// aligned pieces); nothing is returned before the region is reset.
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0, used = 0;
+};
+
+// grow-only device buffer: its own allocation, or a piece of an arena
 struct DBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    Arena* arena = nullptr;
     bool ensure(size_t nb)
     {
         if (nb <= bytes) return true;
+        if (arena) {
+            const size_t off = (arena->used + 255) & ~(size_t)255;
+            if (off > arena->cap || nb > arena->cap - off) return false;
+            p = arena->base + off;
+            bytes = nb;
+            arena->used = off + nb;
+            return true;
+        }
         if (p) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
@@ -32,7 +48,7 @@ struct DBuf {
     }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p && !arena) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
     }
@@ -78,6 +94,13 @@ struct sph_ctx {
     int mts_max_bin = 0;
     uint32_t* status_host = nullptr;                 // pinned
     int32_t* ncells_host = nullptr;                  // pinned
+    // allocation-free context (sph_pass_noalloc): every buffer is a piece of
+    // the arena, and host copies go through the static arrays below
+    bool noalloc = false;
+    Arena arena;
+    uint32_t status_static[4] = {};
+    int32_t ncells_static[4] = {};
+    BoxInfo box_static = {};
     // state of the current decomposition
     int64_t n = 0;
     int nbox = 0;
@@ -333,9 +356,9 @@ sph_status sph_create(const sph_params* params, sph_ctx** out)
     return SPH_OK;
 }
 
-sph_status sph_destroy(sph_ctx* c)
+// every workspace buffer of a context
+extern "C++" template <typename F> static void for_each_buf(sph_ctx* c, F f)
 {
-    if (!c) return SPH_OK;
     DBuf* all[] = {&c->boxes, &c->keys, &c->keys2, &c->vals, &c->vals2, &c->rs_scratch, &c->flag,
                    &c->cellx, &c->cell_of, &c->sc_scratch, &c->cells, &c->ncells, &c->big_cells, &c->cell_map,
                    &c->src, &c->src_count, &c->srec, &c->r0, &c->cell_drift, &c->rp, &c->h,
@@ -345,7 +368,14 @@ sph_status sph_destroy(sph_ctx* c)
                    &c->src_off, &c->t_chg, &c->t_node_of, &c->t_node_start, &c->t_node_flag, &c->t_node_hmax,
                    &c->t_node_H, &c->t_node_leaf, &c->t_nnodes, &c->t_flag, &c->t_scan, &c->t_small,
                    &c->t_psmall, &c->t_lev, &c->t_group};
-    for (DBuf* b : all) b->release();
+    for (DBuf* b : all) f(b);
+}
+
+sph_status sph_destroy(sph_ctx* c)
+{
+    if (!c) return SPH_OK;
+    if (c->noalloc) return SPH_E_INVALID_ARG;   // the library's own, never destroyed
+    for_each_buf(c, [](DBuf* b) { b->release(); });
     if (c->status_host) (void)hipHostFree(c->status_host);
     if (c->ncells_host) (void)hipHostFree(c->ncells_host);
     for (hipEvent_t& e : c->ev) if (e) (void)hipEventDestroy(e);
@@ -374,11 +404,14 @@ static sph_status setup_boxes(sph_ctx* c, int64_t n, const sph_batch* batch)
 {
     int nbox = batch ? batch->nbox : 1;
     if (nbox < 1) return SPH_E_INVALID_ARG;
-    c->box_host.assign(nbox, BoxInfo{});
+    // the allocation-free context keeps its one box in the context itself
+    if (c->noalloc && nbox != 1) return SPH_E_INVALID_ARG;
+    if (!c->noalloc) c->box_host.assign(nbox, BoxInfo{});
+    BoxInfo* const boxes = c->noalloc ? &c->box_static : c->box_host.data();
     int64_t map_total = 0;
     int max_nc = 1;
     for (int b = 0; b < nbox; b++) {
-        BoxInfo& B = c->box_host[b];
+        BoxInfo& B = boxes[b];
         std::memset(&B, 0, sizeof(B));
         int64_t beg = batch ? batch->box_offsets[b] : 0;
         int64_t end = batch ? batch->box_offsets[b + 1] : n;
@@ -419,7 +452,7 @@ static sph_status setup_boxes(sph_ctx* c, int64_t n, const sph_batch* batch)
     depth = std::min(depth, 21 - tb);
     if (depth < 0) depth = 0;
     if (depth > 0 && n >= ((int64_t)1 << 27)) return SPH_E_CAPACITY;
-    for (int b = 0; b < nbox; b++) c->box_host[b].depth = depth;
+    for (int b = 0; b < nbox; b++) boxes[b].depth = depth;
     c->depth = depth;
     c->nbox = nbox;
     c->top_bits = tb;
@@ -431,6 +464,11 @@ static sph_status setup_boxes(sph_ctx* c, int64_t n, const sph_batch* batch)
 // copy can be part of a captured graph).
 static bool upload_boxes(sph_ctx* c, hipStream_t st)
 {
+    if (c->noalloc) {
+        // one box, copied from host memory of the context (the copy waits for it)
+        if (c->nbox != 1) return false;
+        return hipMemcpyAsync(c->boxes.p, &c->box_static, sizeof(BoxInfo), hipMemcpyHostToDevice, st) == hipSuccess;
+    }
     if (c->box_pinned_cap < c->nbox) {
         if (c->box_pinned) (void)hipHostFree(c->box_pinned);
         c->box_pinned = nullptr;
@@ -1226,6 +1264,88 @@ sph_status sph_get_stats(const sph_ctx* c, sph_stats* out)
         }
     }
     return SPH_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- allocation-free pass
+// sph_pass_noalloc keeps its whole workspace in `scratch`, a fixed array of
+// device memory (each GPU holds its own copy from the library's load until
+// the process ends).  Host code never uses the array's name as an address:
+// on a device's first call its address is looked up once and kept per
+// device, and the context of that device hands pieces of it out as its
+// buffers.  Calls that overlap on one GPU share the array and race.
+namespace {
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+constexpr int kNoAllocMaxDevices = 64;
+static_assert(SPH_NOALLOC_MAX_PARTICLES <= 32768, "the scratch array is sized for 32,768 particles");
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+struct NoAllocSlot {
+    bool ready = false;
+    void* ptr = nullptr;   // device address of this GPU's copy of scratch
+    sph_ctx* ctx = nullptr;
+};
+NoAllocSlot g_noalloc[kNoAllocMaxDevices];
+alignas(sph_ctx) unsigned char g_noalloc_ctx[kNoAllocMaxDevices][sizeof(sph_ctx)];
+}  // namespace
+
+// Once per device, with that device current: the address of its copy of the
+// scratch array, and the context whose buffers are carved from it.
+static sph_status noalloc_setup(int dev)
+{
+    NoAllocSlot& sl = g_noalloc[dev];
+    if (sl.ready) return SPH_OK;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SPH_E_HIP;
+    sph_ctx* c = new (g_noalloc_ctx[dev]) sph_ctx();
+    c->noalloc = true;
+    c->device = dev;
+    c->arena.base = static_cast<char*>(ptr);
+    c->arena.cap = kNoAllocScratchBytes;
+    c->status_host = c->status_static;
+    c->ncells_host = c->ncells_static;
+    for_each_buf(c, [c](DBuf* b) { b->arena = &c->arena; });
+    sl.ptr = ptr;
+    sl.ctx = c;
+    sl.ready = true;
+    return SPH_OK;
+}
+
+extern "C" {
+
+sph_status sph_pass_noalloc(const sph_params* params, sph_particles* p, sph_density_out* dout,
+                            sph_force_out* fout, void* stream)
+{
+    if (!params || !particles_ok(p) || !fout) return SPH_E_INVALID_ARG;
+    if (!params_ok(*params) || params->max_depth != 0 || params->reuse != SPH_REUSE_OFF || params->keep_adjoint)
+        return SPH_E_INVALID_ARG;
+    if (p->n > SPH_NOALLOC_MAX_PARTICLES) return SPH_E_CAPACITY;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return SPH_E_HIP;
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return SPH_E_INVALID_ARG;
+    sph_status s = noalloc_setup(dev);
+    if (s != SPH_OK) return s;
+    sph_ctx* c = g_noalloc[dev].ctx;
+    c->prm = *params;
+    // every buffer carved afresh from the start of the array
+    c->arena.used = 0;
+    for_each_buf(c, [](DBuf* b) { b->p = nullptr; b->bytes = 0; });
+    c->built = c->sorted = c->have_density = c->adjoint_ready = false;
+    c->stats = sph_stats{};
+    s = sph_build_cells(c, p, nullptr, stream);
+    if (s == SPH_E_OOM) return SPH_E_CAPACITY;   // the array is full
+    if (s == SPH_OK) s = sph_sort(c, stream);
+    if (s == SPH_OK || s == SPH_E_NOT_CONVERGED) {
+        const sph_status sd = sph_density(c, p, dout, stream);
+        if (sd != SPH_OK && sd != SPH_E_NOT_CONVERGED) return sd == SPH_E_OOM ? SPH_E_CAPACITY : sd;
+        s = sph_force(c, p, fout, stream);
+        if (s == SPH_OK) s = sd;
+    }
+    return s == SPH_E_OOM ? SPH_E_CAPACITY : s;
 }
 
 }  // extern "C"

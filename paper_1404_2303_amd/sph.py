@@ -151,6 +151,9 @@ def load_library():
         lib.sph_backward.restype = st
         lib.sph_backward.argtypes = [P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_grad_in),
                                      ctypes.POINTER(sph_grad_out), ctypes.c_int, ctypes.c_uint64, P]
+        lib.sph_pass_noalloc.restype = st
+        lib.sph_pass_noalloc.argtypes = [ctypes.POINTER(sph_params), ctypes.POINTER(sph_particles),
+                                         ctypes.POINTER(sph_density_out), ctypes.POINTER(sph_force_out), P]
         lib.sph_estimate_h.restype = st
         lib.sph_estimate_h.argtypes = [P, ctypes.POINTER(sph_particles), ctypes.POINTER(sph_batch), P]
         lib.sph_status_string.restype = ctypes.c_char_p
@@ -263,6 +266,16 @@ def sph_backward(ctx, parts: sph_particles, gin: sph_grad_in, gout: sph_grad_out
                  stream):
     return load_library().sph_backward(ctx, ctypes.byref(parts), ctypes.byref(gin), ctypes.byref(gout),
                                        int(implicit_h), int(generation), stream)
+
+
+SPH_NOALLOC_MAX_PARTICLES = 32768
+
+
+def sph_pass_noalloc(params: sph_params, parts: sph_particles, dout: Optional[sph_density_out],
+                     fout: sph_force_out, stream):
+    return load_library().sph_pass_noalloc(ctypes.byref(params), ctypes.byref(parts),
+                                           ctypes.byref(dout) if dout is not None else None, ctypes.byref(fout),
+                                           stream)
 
 
 # ---------------------------------------------------------------- tensor layer
@@ -516,6 +529,32 @@ class Context:
         d = self.density(parts, allow_unconverged=allow_unconverged)
         f = self.force(parts)
         return d, f
+
+
+def pass_noalloc(parts: Particles, box=(1.0, 1.0, 1.0), precision: str = "fp32", dout: Optional[dict] = None,
+                 fout: Optional[dict] = None, allow_unconverged=False, **kw):
+    """build -> sort -> density (h solved in place) -> force through sph_pass_noalloc,
+    which allocates no device memory: the library works in its fixed per-GPU array.
+    The output tensors (dout, fout: dicts of DENSITY_FIELDS / FORCE_FIELDS keys)
+    are the caller's; missing ones are made here, before the call."""
+    p = sph_default_params()
+    for d in range(3):
+        p.box[d] = float(box[d])
+    p.precision = SPH_FP64 if precision in ("fp64", SPH_FP64) else SPH_FP32_ACC64
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    n, dev = parts.n, parts.x.device
+    if fout is None:
+        fout = Context.force_buffers(n, dev)
+    dc = None
+    if dout is not None:
+        dc = sph_density_out(*[_ptr(dout.get(k)) for k in DENSITY_FIELDS])
+    fc = sph_force_out(*[_ptr(fout.get(k)) for k in FORCE_FIELDS])
+    allow = (SPH_E_NOT_CONVERGED,) if allow_unconverged else ()
+    _check(sph_pass_noalloc(p, parts.c_struct(), dc, fc, _stream()), "sph_pass_noalloc", allow)
+    return dout, fout
 
 
 def _parts_from(pos, vel, m, u, h):
