@@ -67,12 +67,12 @@ def ensure_built():
         __graft_entry__.build()
 
 
-def run_form(ps, precision, steps, warmup):
+def run_form(ps, precision, steps, warmup, **params):
     import torch
     from paper_1404_2303_amd import sph
     parts = sph.Particles.from_numpy(ps, "cuda:0")
     h0 = parts.h.clone()
-    ctx = sph.Context(ps.box, precision=precision)
+    ctx = sph.Context(ps.box, precision=precision, **params)
     ctx.enable_timing(True)
     n = parts.n
     fout = {k: torch.empty(n, dtype=torch.float64, device="cuda:0") for k in ("ax", "ay", "az", "dudt")}
@@ -576,6 +576,7 @@ def main():
     ap.add_argument("--no-multires", action="store_true", help="skip the 2M-particle Plummer mixture")
     ap.add_argument("--no-integrate", action="store_true", help="skip the Sod time-integration timing")
     ap.add_argument("--no-mts", action="store_true", help="skip the multiple time-stepping timing")
+    ap.add_argument("--no-layouts", action="store_true", help="skip the timing of the shared sweep layout")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -629,6 +630,15 @@ def main():
     if plain is not None:
         line["plain_fp64"] = {"value": plain["P"] / (plain["ms_per_step"] * 1e-3), "ms_per_step": plain["ms_per_step"],
                               "kernel_ms": plain["kernel_ms"], "roofline": roofline(plain)}
+    if not args.no_layouts:
+        # the other sweep layout (sph_params.sweep) on the same workload, for the record
+        from paper_1404_2303_amd import sph
+        lay = {}
+        for prec in ("fp32", "fp64"):
+            r = run_form(ps, prec, max(3, args.steps // 4), 2, sweep=sph.SPH_SWEEP_SHARED)
+            lay[prec] = {"ms_per_step": r["ms_per_step"], "kernel_ms": r["kernel_ms"], "P": r["P"]}
+        line["sweep_shared"] = lay
+        log("sweep_shared:", json.dumps(lay))
     if not args.no_batched:
         line["batched"] = batched_section(max(3, args.steps // 4), 2)
         log("batched:", json.dumps(line["batched"]))

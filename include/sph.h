@@ -104,7 +104,22 @@ typedef struct {
     int keep_adjoint;    /* 1: sph_density also keeps the per-particle sums the reverse pass
                             needs (64 bytes per particle), which sph_backward requires;
                             0 (default): forward-only passes write nothing of the kind */
+    int sweep;           /* work layout of the density and force kernels (SPH_SWEEP_*) */
 } sph_params;
+
+/* Work layout of the density and force kernels.  Both sweep the same sorted
+ * segments of Sec. 3.3 with the same early exit and give the same results up
+ * to the order of summation. */
+enum {
+    SPH_SWEEP_AUTO = 0,   /* SPLIT (the faster of the two on every workload measured) */
+    SPH_SWEEP_SHARED = 1, /* four wavefronts per target cell: each stages a share of the sources
+                             and all of them read every share; each target is served by four
+                             lanes holding its whole neighbour list.  Cells whose sources do not
+                             fit in one staging batch are swept by SPLIT right after */
+    SPH_SWEEP_SPLIT = 2   /* four wavefronts per target cell, each staging a share of the
+                             sources and sweeping only its own (the staging and shared_min
+                             parameters apply) */
+};
 
 /* Staging of the FP32 density stage.  A target cell's sources are copied into
  * LDS per wavefront; when they do not fit, every Newton step stages and walks

@@ -68,12 +68,14 @@ class CandidateUnusable(Exception):
 
 def _unusable(e: Exception) -> bool:
     """A candidate the workload cannot use: the timer says so, or the library
-    refused it for capacity (a cell or grid beyond the kernels' limits) or
-    state.  Anything else (a HIP error, a wrong result, a bug) is raised."""
+    refused it for capacity (a cell or grid beyond the kernels' limits), state
+    or a grid too coarse for h in a periodic box.  Anything else (a HIP error,
+    a wrong result, a bug) is raised."""
     if isinstance(e, CandidateUnusable):
         return True
     from . import sph
-    return isinstance(e, sph.SPHError) and e.status in (sph.SPH_E_CAPACITY, sph.SPH_E_STATE)
+    return isinstance(e, sph.SPHError) and e.status in (sph.SPH_E_CAPACITY, sph.SPH_E_STATE,
+                                                       sph.SPH_E_H_TOO_LARGE)
 
 
 def choose(timings: dict) -> dict:

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsph_mi355x.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["build.hip", "tree.hip", "passes.hip", "adjoint.hip", "step.hip", "api.cpp"]
+SOURCES = ["build.hip", "tree.hip", "passes.hip", "passes_shared.hip", "adjoint.hip", "step.hip", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -156,7 +156,7 @@ __global__ __launch_bounds__(WGS) void k_adj_sweep(Decomp dc, CellData<R> cd, So
         const float mstage = margin + cell_dr(dc, unit);   // targets may have left the cell by this
         const float Hst = gd.cell_hmax[unit];
         int k = 0, p = 0;
-        stage_wave<R, true, NACC_ADJ>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, mstage);
+        stage_wave<R, true>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, mstage);
         const bool single = k >= nsrc;
         for (int c0 = 0; c0 < T.count; c0 += kWave) {
             const int ti = c0 + lane;
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(WGS) void k_adj_sweep(Decomp dc, CellData<R> cd, So
             };
             int kk = 0, pp = 0;
             do {
-                if (!single) stage_wave<R, true, NACC_ADJ>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, kk, pp, Hst, mstage);
+                if (!single) stage_wave<R, true>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, kk, pp, Hst, mstage);
                 else kk = nsrc;
                 const int selfj = self_index(s, w, ti);
                 int seg = 0, jj = s.nseg[w] > 0 ? s.seg_b[w][0] : 0;

@@ -65,6 +65,7 @@ struct sph_ctx {
     // workspace
     DBuf boxes, keys, keys2, vals, vals2, rs_scratch, flag, cellx, cell_of, sc_scratch;
     DBuf cells, ncells, cell_map, src, src_count, srec;
+    DBuf deferred;                                   // cells the shared sweep leaves to the split one
     DBuf big_cells;                                  // count, then the cells the wavefront sort leaves
     DBuf rp, h, vm, u;                               // cell order
     DBuf r0;                                         // cell-relative positions at the last build
@@ -237,7 +238,7 @@ static bool ensure_particles(sph_ctx* c, int64_t n)
     ok &= c->rs_scratch.ensure(radix_scratch_words((int64_t)N) * 4);
     ok &= c->flag.ensure(N * 4) && c->cellx.ensure(N * 4) && c->cell_of.ensure(N * 4);
     ok &= c->sc_scratch.ensure(scan_scratch_words((int64_t)N) * 4 + 16);
-    ok &= c->cells.ensure(N * sizeof(CellInfo)) && c->ncells.ensure(16);
+    ok &= c->cells.ensure(N * sizeof(CellInfo)) && c->ncells.ensure(16) && c->deferred.ensure(N * 4);
     ok &= c->big_cells.ensure((N / 256 + 1 + kBigHeader) * 4);
     // interaction lists: 27 per cell on the single-level grid; on the hierarchy
     // a bound per particle (exceeding it sets SPH_E_CAPACITY)
@@ -293,6 +294,7 @@ void sph_default_params(sph_params* p)
     p->shared_min = 128;
     p->fixed_h = 0;
     p->keep_adjoint = 0;
+    p->sweep = SPH_SWEEP_AUTO;
 }
 
 const char* sph_status_string(sph_status s)
@@ -332,6 +334,7 @@ static bool params_ok(const sph_params& p)
     if (p.shared_min < 64) return false;
     if (p.fixed_h != 0 && p.fixed_h != 1) return false;
     if (p.keep_adjoint != 0 && p.keep_adjoint != 1) return false;
+    if (p.sweep != SPH_SWEEP_AUTO && p.sweep != SPH_SWEEP_SHARED && p.sweep != SPH_SWEEP_SPLIT) return false;
     return true;
 }
 
@@ -360,7 +363,7 @@ sph_status sph_create(const sph_params* params, sph_ctx** out)
 extern "C++" template <typename F> static void for_each_buf(sph_ctx* c, F f)
 {
     DBuf* all[] = {&c->boxes, &c->keys, &c->keys2, &c->vals, &c->vals2, &c->rs_scratch, &c->flag,
-                   &c->cellx, &c->cell_of, &c->sc_scratch, &c->cells, &c->ncells, &c->big_cells, &c->cell_map,
+                   &c->cellx, &c->cell_of, &c->sc_scratch, &c->deferred, &c->cells, &c->ncells, &c->big_cells, &c->cell_map,
                    &c->src, &c->src_count, &c->srec, &c->r0, &c->cell_drift, &c->rp, &c->h,
                    &c->vm, &c->u, &c->g0, &c->g1, &c->cell_hmax, &c->qhead, &c->status, &c->step_tmp, &c->dt_box, &c->dt_min, &c->t_box, &c->mts_active, &c->mts_rho, &c->mts_A,
                    &c->mts_c, &c->mts_f, &c->mts_count, &c->mts_units, &c->mts_flag,
@@ -702,6 +705,9 @@ static sph_status status_error(uint32_t bits)
     return SPH_OK;
 }
 
+// the shared sweep (params.sweep; AUTO takes the split one)
+static bool shared_sweep(const sph_ctx* c) { return c->prm.sweep == SPH_SWEEP_SHARED; }
+
 extern "C++" {
 template <typename R>
 static void density_launch(sph_ctx* c, const sph_particles* p, const sph_density_out* o, hipStream_t st)
@@ -714,8 +720,13 @@ static void density_launch(sph_ctx* c, const sph_particles* p, const sph_density
         out.iters = o->n_iter;
         out.ndens = o->n_dens;
     }
-    launch_density<R>(decomp(c), cell_data<R>(c), sorted_data<R>(c), ghost_data<R>(c), out, pass_consts(c->prm),
-                      c->prm.staging, st);
+    if (shared_sweep(c))
+        launch_density_shared<R>(decomp(c), cell_data<R>(c), sorted_data<R>(c), ghost_data<R>(c), out,
+                                 pass_consts(c->prm), c->prm.staging, c->deferred.as<int32_t>(),
+                                 c->qhead.as<int32_t>(), st);
+    else
+        launch_density<R>(decomp(c), cell_data<R>(c), sorted_data<R>(c), ghost_data<R>(c), out,
+                          pass_consts(c->prm), c->prm.staging, st);
 }
 }  // extern "C++"
 
@@ -854,8 +865,20 @@ sph_status sph_force(sph_ctx* c, const sph_particles* p, sph_force_out* o, void*
     ForceOut out{};
     out.ax = o->ax; out.ay = o->ay; out.az = o->az; out.dudt = o->dudt; out.npairs = o->n_pairs;
     out.dt = o->dt;
-    int grid = force_occupancy_grid(c->prm.precision);
     ev_record(c, EV_FORCE0, st);
+    const int grid = force_occupancy_grid(c->prm.precision);
+    if (shared_sweep(c)) {
+        if (c->prm.precision == SPH_FP64)
+            launch_force_shared<double>(decomp(c), cell_data<double>(c), sorted_data<double>(c),
+                                        ghost_data<double>(c), out, pass_consts(c->prm), grid,
+                                        c->deferred.as<int32_t>(), c->qhead.as<int32_t>(), st);
+        else
+            launch_force_shared<float>(decomp(c), cell_data<float>(c), sorted_data<float>(c), ghost_data<float>(c),
+                                       out, pass_consts(c->prm), grid, c->deferred.as<int32_t>(),
+                                       c->qhead.as<int32_t>(), st);
+        ev_record(c, EV_FORCE1, st);
+        return hipGetLastError() == hipSuccess ? SPH_OK : SPH_E_HIP;
+    }
     if (c->prm.precision == SPH_FP64)
         launch_force<double>(decomp(c), cell_data<double>(c), sorted_data<double>(c), ghost_data<double>(c), out,
                              pass_consts(c->prm), grid, st);

@@ -196,6 +196,19 @@ void launch_mts_prepare(const Decomp& dc, const CellData<R>& cd, const GhostData
                         int32_t* nunits, uint32_t* cell_flag, const uint32_t* cell_of, int64_t n, hipStream_t st);
 int force_occupancy_grid(int precision);
 
+// passes_shared.hip -- sources staged once per work-group, four lanes per
+// target; cells whose sources need several batches are left to the split
+// kernels above, launched right after over the deferred list.  counters: three
+// ints (work counters and the deferred count).
+template <typename R>
+void launch_density_shared(const Decomp& dc, const CellData<R>& cd, const Sorted<R>& so, const GhostData<R>& gd,
+                           const DensityOut& out, const PassConsts& pc, int staging, int32_t* deferred,
+                           int32_t* counters, hipStream_t st);
+template <typename R>
+void launch_force_shared(const Decomp& dc, const CellData<R>& cd, const Sorted<R>& so, const GhostData<R>& gd,
+                         const ForceOut& out, const PassConsts& pc, int split_grid, int32_t* deferred,
+                         int32_t* counters, hipStream_t st);
+
 // adjoint.hip
 template <typename R>
 void launch_adjoint(const Decomp& dc, const CellData<R>& cd, const Sorted<R>& so, const GhostData<R>& gd,

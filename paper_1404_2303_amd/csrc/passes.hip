@@ -41,81 +41,10 @@
 //
 // Arithmetic: pair terms in R (float or double); every per-particle sum and
 // the Newton step in double.
-#include "sweep.h"
+#include "pairs.h"
 
 namespace sph {
 // ---------------------------------------------------------------- density
-struct DensAcc {
-    double w, qdw;
-    int n;
-};
-// the mass-weighted sums of one pass over a list, in the pair precision:
-// added to the FP64 totals once per list (at most LISTW pairs)
-template <typename R>
-struct DensPart {
-    R mw, mqdw, div, cx, cy, cz;
-};
-
-// w(q) and q w'(q) of the kernel of Sec. 2.1 without branches, t = 1 - q and
-// u = max(1 - 2q, 0): w = 2 t^3 - u^3 and q w' = 6 q (u^2 - t^2), which are
-// 1 - 6q^2 + 6q^3 and q (18q^2 - 12q) for q <= 1/2 (callers mask q >= 1)
-template <typename R>
-__device__ __forceinline__ void kern_w_qdw(R q, R& w, R& qdw)
-{
-    const R t = (R)1 - q, u = fmax(fma((R)-2, q, (R)1), (R)0);
-    const R t2 = t * t, u2 = u * u;
-    w = fma((R)2 * t2, t, -(u2 * u));
-    qdw = (R)6 * q * (u2 - t2);
-}
-
-// Newton evaluation: the two sums of Eq. (3) (N and dN/dh need w and q w'),
-// into partial sums of one list in the pair precision
-template <typename R>
-__device__ __forceinline__ void count_pair(R& sw, R& sq, bool ok, R xi, R yi, R zi, R hinv, R h2,
-                                           typename Vec4T<R>::T e)
-{
-    const R dx = xi - e.x, dy = yi - e.y, dz = zi - e.z;
-    const R r2 = dx * dx + dy * dy + dz * dz;
-    ok = ok && r2 < h2;
-    const R q = fast_sqrt(r2) * hinv;
-    R w, qdw;
-    kern_w_qdw(q, w, qdw);
-    sw += ok ? w : (R)0;
-    sq += ok ? qdw : (R)0;
-}
-
-// All density-stage terms of one pair: Eq. (2), Eq. (3), d rho/dh and the
-// velocity divergence and curl of Sec. 4.1 (gradient prefactor applied later)
-template <typename R>
-__device__ __forceinline__ void density_pair(DensAcc& a, DensPart<R>& b, bool ok, R xi, R yi, R zi, R vxi, R vyi, R vzi, R h,
-                                             R hinv, R h2, typename Vec4T<R>::T e, typename Vec4T<R>::T vm)
-{
-    const R dx = xi - e.x, dy = yi - e.y, dz = zi - e.z;
-    const R r2 = dx * dx + dy * dy + dz * dz;
-    ok = ok && r2 < h2;
-    const R rinv = r2 > (R)0 ? fast_rsqrt(r2) : (R)0;
-    const R q = r2 * rinv * hinv;
-    // the kernel without branches, t = 1 - q, u = max(1 - 2q, 0): w = 2 t^3 - u^3,
-    // g = w'/q = -6 (u + t) min(1, t/q), which is 18q - 12 for q <= 1/2 and
-    // -6 t^2 / q above (zero at r = 0, where the pair adds nothing anyway)
-    const R t = (R)1 - q, u = fmax(fma((R)-2, q, (R)1), (R)0);
-    const R w = fma((R)2 * t * t, t, -(u * u * u));
-    const R gq = (R)-6 * (u + t) * fmin((R)1, t * (h * rinv));
-    const R qdw = gq * q * q;
-    const R mj = ok ? vm.w : (R)0;  // masked pairs contribute nothing
-    const R dvx = vm.x - vxi, dvy = vm.y - vyi, dvz = vm.z - vzi;
-    const R mg = mj * gq;
-    a.w += (double)(ok ? w : (R)0);
-    a.qdw += (double)(ok ? qdw : (R)0);
-    b.mw += mj * w;
-    b.mqdw += mj * qdw;
-    b.div += mg * (dvx * dx + dvy * dy + dvz * dz);
-    b.cx += mg * (dvy * dz - dvz * dy);
-    b.cy += mg * (dvz * dx - dvx * dz);
-    b.cz += mg * (dvx * dy - dvy * dx);
-    a.n += ok ? 1 : 0;
-}
-
 // waves per SIMD the register budget is held to: in FP32, four work-groups of
 // four wavefronts per CU for configuration 0 (at most 128 VGPRs, the LDS of a
 // work-group under 40 KiB), three for configuration 1 (its larger staging);
@@ -180,7 +109,7 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
 
         // staging of the first batch, kept while it holds every source of the wavefront
         int k = 0, p = 0;
-        stage_wave<R, false, NACC_D, CFG>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, mstage);
+        stage_wave<R, false>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, mstage);
         bool single = k >= nsrc;
 
         for (int c0 = 0; c0 < T.count; c0 += kWave) {
@@ -226,9 +155,12 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
                             const int j1 = v1 ? (int)s.list[w][lane][t + 1] : 0;
                             const R4 e0 = s.st[w][j0], e1 = s.st[w][j1];
                             const R4 q0 = cd.vm[s.sg[w][j0]], q1 = cd.vm[s.sg[w][j1]];
-                            density_pair<R>(acc, b, v0, xi, yi, zi, vmi.x, vmi.y, vmi.z, hr, hinv, h2, e0, q0);
-                            density_pair<R>(acc, b, v1, xi, yi, zi, vmi.x, vmi.y, vmi.z, hr, hinv, h2, e1, q1);
+                            density_pair<R>(b, v0, xi, yi, zi, vmi.x, vmi.y, vmi.z, hr, hinv, h2, e0, q0);
+                            density_pair<R>(b, v1, xi, yi, zi, vmi.x, vmi.y, vmi.z, hr, hinv, h2, e1, q1);
                         }
+                        acc.w += (double)b.w;
+                        acc.qdw += (double)b.qdw;
+                        acc.n += b.n;
                         // into the FP64 totals of the four wavefronts (cleared before
                         // the evaluation); nothing of them stays in registers
                         if (act) {
@@ -267,7 +199,7 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
                 bool flushed = false;
                 int kk = 0, pp = 0;
                 do {
-                    if (!single) stage_wave<R, false, NACC_D, CFG>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, kk, pp, Hst, mstage);
+                    if (!single) stage_wave<R, false>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, kk, pp, Hst, mstage);
                     else kk = nsrc;
                     const int selfj = self_index(s, w, ti);
                     int seg = 0, jj = s.nseg[w] > 0 ? s.seg_b[w][0] : 0;
@@ -380,7 +312,7 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
                     const double hm = wave_max(conv ? 0.0 : h);
                     Hst = (float)fmin(fmax((double)Hst, hm * (1.0 + pc.h_margin)), h_lim);
                     k = 0; p = 0;
-                    stage_wave<R, false, NACC_D, CFG>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, mstage);
+                    stage_wave<R, false>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, mstage);
                     single = k >= nsrc;
                     cached = false;
                 }
@@ -459,65 +391,6 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
 
 // ---------------------------------------------------------------- force
 template <typename R>
-struct ForceAcc {
-    double ax, ay, az, du;
-    R vsig;   // largest c_i + c_j - 3 w_ij over the pairs in range (Eq. (6))
-    int n;
-};
-// the sums of one pass over a list (at most LISTW pairs) in the pair precision
-template <typename R>
-struct ForcePart {
-    R ax, ay, az, du;
-};
-
-template <typename R>
-struct ForceTarget {
-    R x, y, z, vx, vy, vz, h, hinv, gk, A, rho, c, f;
-};
-
-// Eqs. (4)-(5) and the Monaghan-Balsara viscosity of Sec. 4.1 for one pair
-// (one-sided: the contribution of j to particle i).  Pairs outside both
-// supports contribute exactly zero (both kernel gradients vanish there).
-template <typename R>
-__device__ __forceinline__ void force_pair(ForceAcc<R>& a, ForcePart<R>& b, bool ok, const ForceTarget<R>& ti, R alpha,
-                                           typename Vec4T<R>::T e, typename Vec4T<R>::T vm,
-                                           typename Vec4T<R>::T g0, typename Vec4T<R>::T g1)
-{
-    const R dx = ti.x - e.x, dy = ti.y - e.y, dz = ti.z - e.z;
-    const R r2 = dx * dx + dy * dy + dz * dz;
-    const R rinv = r2 > (R)0 ? fast_rsqrt(r2) : (R)0;
-    const R r = r2 * rinv;
-    const R qi = r * ti.hinv, qj = r * g0.x;
-    // grad W(r, h) = 8/(pi h^5) g(q) r_vec with g = w'/q = -6 (u + t) min(1, t/q),
-    // t = max(1 - q, 0), u = max(1 - 2q, 0): 18q - 12 for q <= 1/2, -6 t^2/q
-    // up to q = 1, zero beyond and (rinv = 0) at r = 0, without branches
-    auto grad = [&](R q, R h, R gk) {
-        const R t = fmax((R)1 - q, (R)0), u = fmax(fma((R)-2, q, (R)1), (R)0);
-        return gk * (R)-6 * (u + t) * fmin((R)1, t * (h * rinv));
-    };
-    const R gwi = grad(qi, ti.h, ti.gk);
-    const R gwj = grad(qj, g1.z, g0.y);
-    const R mj = ok ? vm.w : (R)0;  // masked pairs contribute nothing
-    const R vr = (ti.vx - vm.x) * dx + (ti.vy - vm.y) * dy + (ti.vz - vm.z) * dz;
-    const R wij = fmin(vr * rinv, (R)0);
-    const R vsig = ti.c + g1.x - (R)3 * wij;   // signal speed of Eq. (6), >= 0
-    const R Pi = -alpha * vsig * wij * fast_rcp(ti.rho + g0.w);
-    const R T = Pi * (gwi + gwj) * (ti.f + g1.y);
-    const R agi = ti.A * gwi;
-    const R sc = -mj * (agi + g0.z * gwj + (R)0.25 * T);
-    const R pdu = mj * vr * (agi + (R)0.125 * T);
-    b.ax += sc * dx;
-    b.ay += sc * dy;
-    b.az += sc * dz;
-    b.du += pdu;
-    // lists may hold a few pairs just outside both supports: they add nothing
-    // above (zero gradients) and are neither counted nor signal pairs
-    const bool in = ok && (qi < (R)1 || qj < (R)1);
-    a.vsig = in ? fmax(a.vsig, vsig) : a.vsig;
-    a.n += in ? 1 : 0;
-}
-
-template <typename R>
 __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted<R> so, GhostData<R> gd,
                                                ForceOut out, PassConsts pc)
 {
@@ -550,7 +423,7 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
         const bool cell_on = __builtin_amdgcn_readfirstlane(__any(any_on) ? 1 : 0) != 0;
         if (!cell_on) nsrc = 0;   // no target here: nothing to stage or sweep
         int k = 0, p = 0;
-        stage_wave<R, true, NACC_F>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, mstage);
+        stage_wave<R, true>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, mstage);
         const bool single = k >= nsrc;
         // Cells of more than shared_min particles are swept shared: each
         // wavefront takes its own 64 targets and walks the staged sources of all
@@ -624,7 +497,7 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
                 // walk the four regions; the rounds end together
                 while (true) {
                     if (!all_single) {
-                        stage_wave<R, true, NACC_F>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, kk, pp, Hst, mstage);
+                        stage_wave<R, true>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, kk, pp, Hst, mstage);
                         if (lane == 0) s.done[w] = kk >= nsrc ? 1 : 0;
                     }
                     __syncthreads();   // the four regions are staged
@@ -635,7 +508,7 @@ __global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted
                 }
             } else {
                 do {
-                    if (!single) stage_wave<R, true, NACC_F>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, kk, pp, Hst, mstage);
+                    if (!single) stage_wave<R, true>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, kk, pp, Hst, mstage);
                     else kk = nsrc;
                     sweep(w);
                 } while (kk < nsrc);

@@ -95,6 +95,15 @@ template <typename R> __device__ __forceinline__ R half_sq_lo(R x, R y, R z)
     return (x * x + y * y + z * z) * lo;
 }
 
+// Convergence point of the wavefront, free at run time (no instruction): it
+// opens the body of every loop that holds wave-level operations (ballots,
+// lane reads, shuffles).  Such a loop can have iterations without any side
+// effect for some lanes, and the compiler may then take those lanes out of
+// the loop early (a thread must make progress), leaving the wave-level
+// operations with part of the wavefront; a wave barrier has a side effect in
+// every lane and keeps them all in the loop together.
+__device__ __forceinline__ void converge() { __builtin_amdgcn_wave_barrier(); }
+
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 // the value of lane l (uniform) of v
 __device__ __forceinline__ int lane_of(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
@@ -109,6 +118,7 @@ struct Smem {
     using R4 = typename Vec4T<R>::T;
     static constexpr int CAPW = PCfg<R, STAGE_H, CFG>::CAPW;
     static constexpr int LISTW = PCfg<R, STAGE_H, CFG>::LISTW;
+    static constexpr int MAXSEG = kMaxSegW;
     // staged (x, y, z in T's frame, |x|^2 / 2 less its rounding allowance); the
     // walk reads up to WALK_PAD entries past a segment's end (masked off)
     R4 st[NW][CAPW + WALK_PAD];
@@ -135,15 +145,17 @@ struct Smem {
 
 // Stage, for wavefront w, its sources from cursor (k, p) on; advance the
 // cursor past what was staged (k == nsrc when every source is staged).  The
-// sources of the target cell are read 64 at a time, one per lane.
-template <typename R, bool FORCE, int NACC, int CFG = 0>
-__device__ void stage_wave(Smem<R, NACC, FORCE, CFG>& s, const int w, const Decomp& dc, const CellData<R>& cd,
+// sources of the target cell are read 64 at a time, one per lane.  SM is an
+// LDS layout with this one's staging members (st, sh, sp, sg, seg_*, nseg,
+// self_*), their capacity CAPW and segment count MAXSEG per wavefront.
+template <typename R, bool FORCE, typename SM>
+__device__ void stage_wave(SM& s, const int w, const Decomp& dc, const CellData<R>& cd,
                            const Sorted<R>& so, const GhostData<R>& gd, const BoxInfo& B, const int tcell,
                            const int tlevel, const int nsrc, int& k, int& p, const float Hst, const float margin)
 {
     using R4 = typename Vec4T<R>::T;
     const int lane = threadIdx.x & (kWave - 1);
-    const int CAPW = Smem<R, NACC, FORCE, CFG>::CAPW;
+    const int CAPW = SM::CAPW;
     // edges of the target cell and the finest-level unit of the source offsets
     const float et[3] = {(float)ldexp(B.e[0], -tlevel), (float)ldexp(B.e[1], -tlevel),
                          (float)ldexp(B.e[2], -tlevel)};
@@ -161,6 +173,7 @@ __device__ void stage_wave(Smem<R, NACC, FORCE, CFG>& s, const int w, const Deco
     float my_ds = 0.f, my_hx = 0.f;
     if (lane == 0) s.self_n[w] = 0;
     while (true) {
+        converge();
         if (k >= nsrc) { k = nsrc; p = 0; break; }
         if ((k & ~(kWave - 1)) != chunk) {  // lane-parallel view of the next 64 sources
             chunk = k & ~(kWave - 1);
@@ -179,7 +192,7 @@ __device__ void stage_wave(Smem<R, NACC, FORCE, CFG>& s, const int w, const Deco
         const uint64_t m = mask & (~0ull << (k - chunk));
         if (m == 0) { k = chunk + kWave; p = 0; continue; }
         k = chunk + __builtin_ctzll(m);
-        if (nseg == kMaxSegW || fill >= CAPW) break;
+        if (nseg == SM::MAXSEG || fill >= CAPW) break;
         const int sl = uniform(k - chunk);
         const int sdir = lane_of((int)my.dir, sl);
         const int sox = lane_of((int)my.ox, sl), soy = lane_of((int)my.oy, sl), soz = lane_of((int)my.oz, sl);
@@ -220,6 +233,7 @@ __device__ void stage_wave(Smem<R, NACC, FORCE, CFG>& s, const int w, const Deco
                                 hs + margin + ds;
             const int64_t sbase = (int64_t)sd * dc.n + S.start;
             while (p < S.count) {
+                converge();
                 const int pos = p + lane;
                 bool ok = false;
                 int l = 0;

@@ -26,6 +26,7 @@ SPH_FP64, SPH_FP32_ACC64 = 0, 1
 SPH_BALSARA_CURL, SPH_BALSARA_DIV = 0, 1
 SPH_REUSE_OFF, SPH_REUSE_ORDERINGS, SPH_REUSE_CELLS = 0, 1, 2
 SPH_STAGING_COMPACT, SPH_STAGING_WIDE = 0, 1
+SPH_SWEEP_AUTO, SPH_SWEEP_SHARED, SPH_SWEEP_SPLIT = 0, 1, 2
 
 EXPORTED = ["sph_default_params", "sph_create", "sph_destroy", "sph_build_cells", "sph_sort",
             "sph_density", "sph_force", "sph_step", "sph_get_stats", "sph_status_string",
@@ -44,7 +45,7 @@ class sph_params(ctypes.Structure):
                 ("max_rebuilds", ctypes.c_int), ("max_depth", ctypes.c_int), ("split_count", ctypes.c_int),
                 ("split_frac", ctypes.c_double), ("cfl", ctypes.c_double), ("balsara_form", ctypes.c_int),
                 ("reuse", ctypes.c_int), ("staging", ctypes.c_int), ("shared_min", ctypes.c_int),
-                ("fixed_h", ctypes.c_int), ("keep_adjoint", ctypes.c_int)]
+                ("fixed_h", ctypes.c_int), ("keep_adjoint", ctypes.c_int), ("sweep", ctypes.c_int)]
 
 
 class sph_particles(ctypes.Structure):
