@@ -564,6 +564,32 @@ def mts_section(base_steps):
             "speedup_mts": g["ms"] / m0["ms"], "speedup_mts_reuse": g["ms"] / m1["ms"]}
 
 
+def orderings_section(reps=5):
+    """Time of the 13 orderings (sph_sort) where cells exceed one wavefront's
+    sort (256 particles): a uniform-random 2^20 set on grids of ~300, ~1000
+    and ~2000 particles per cell, whose orderings are made from those of
+    their sub-cells shifted and merged (Sec. 3.3)."""
+    import torch
+    from paper_1404_2303_amd import sph, workloads
+    ps = workloads.uniform(1 << 20, seed=1, sigma_v=0.1)
+    parts = sph.Particles.from_numpy(ps, "cuda:0")
+    out = {"workload": "uniform-random 2^20 particles, unit periodic box, FP32 positions in the cell frame"}
+    for ct in (300, 1000, 2000):
+        ctx = sph.Context(ps.box, precision="fp32", cell_target=ct)
+        ctx.enable_timing(True)
+        ts = []
+        for r in range(reps + 1):
+            ctx.build_cells(parts)
+            ctx.sort()
+            torch.cuda.synchronize()
+            if r:
+                ts.append(ctx.kernel_times()["sort_ms"])
+        nc = int(ctx.stats()["n_cells"])
+        ctx.close()
+        out[f"cell_target_{ct}"] = {"sort_ms": float(np.median(ts)), "cells": nc, "mean_per_cell": ps.n / nc}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -577,6 +603,7 @@ def main():
     ap.add_argument("--no-integrate", action="store_true", help="skip the Sod time-integration timing")
     ap.add_argument("--no-mts", action="store_true", help="skip the multiple time-stepping timing")
     ap.add_argument("--no-layouts", action="store_true", help="skip the timing of the shared sweep layout")
+    ap.add_argument("--no-orderings", action="store_true", help="skip the timing of big-cell orderings")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -639,6 +666,9 @@ def main():
             lay[prec] = {"ms_per_step": r["ms_per_step"], "kernel_ms": r["kernel_ms"], "P": r["P"]}
         line["sweep_shared"] = lay
         log("sweep_shared:", json.dumps(lay))
+    if not args.no_orderings:
+        line["orderings"] = orderings_section()
+        log("orderings:", json.dumps(line["orderings"]))
     if not args.no_batched:
         line["batched"] = batched_section(max(3, args.steps // 4), 2)
         log("batched:", json.dumps(line["batched"]))

@@ -671,11 +671,11 @@ sph_status sph_sort(sph_ctx* c, void* stream)
     if (c->n > 0) {
         ev_record(c, EV_SORT0, st);
         if (c->prm.precision == SPH_FP64)
-            launch_sort13<double>(c->cells.as<CellInfo>(), c->ncells.as<int32_t>(), cell_data<double>(c), c->n,
+            launch_sort13<double>(c->cells.as<CellInfo>(), c->ncells.as<int32_t>(), decomp(c).boxes, cell_data<double>(c), c->n,
                                   sorted_data<double>(c), c->big_cells.as<int32_t>(), c->status.as<uint32_t>(),
                                   c->n, st);
         else
-            launch_sort13<float>(c->cells.as<CellInfo>(), c->ncells.as<int32_t>(), cell_data<float>(c), c->n,
+            launch_sort13<float>(c->cells.as<CellInfo>(), c->ncells.as<int32_t>(), decomp(c).boxes, cell_data<float>(c), c->n,
                                  sorted_data<float>(c), c->big_cells.as<int32_t>(), c->status.as<uint32_t>(),
                                  c->n, st);
         ev_record(c, EV_SORT1, st);

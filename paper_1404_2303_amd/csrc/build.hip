@@ -729,16 +729,34 @@ __global__ __launch_bounds__(kWave) void k_sort13_wave(const CellInfo* cells, co
     }
 }
 
-// Larger cells (Sec. 3.3: a parent's ordering from the sorted orderings of
-// its parts, merged in O(n) per level): one workgroup per (cell, direction).
-// The cell's particles, in cell order, are cut into runs of 256, the runs
-// are sorted (a bitonic network inside each run), and sorted runs are merged
-// pairwise until one remains.  A word is (order-preserving image of the
-// projection) << 32 | cell index, so equal projections keep cell order, as
-// the wavefront sort does.  In a merge each word's place is its index in its
-// run plus the number of words of the partner run before it (a binary search).
-constexpr int MERGE_THREADS = 256;
+// Larger cells (Sec. 3.3, Fig. HierarchySorting): a split cell's orderings
+// are made from those of its eight sub-cells, each shifted into the
+// parent's frame, by merges that take O(n) per level.  One work-group per
+// (cell, direction).  The cell is split D levels deep (D = 1, 2 or 3: the
+// shallowest whose sub-cells hold at most kSubRun particles each); the
+// sub-cells of depth D are ordered directly (each particle's rank in its
+// sub-cell), with keys in the sub-cell's own frame.  Then, level by level up
+// to the cell, every run is shifted into its parent's frame (its key plus
+// the projection of the sub-cell's corner relative to the parent's) and the
+// eight sibling runs are merged pairwise in three rounds.  A merge places
+// each word at its index in its run plus the number of words of the partner
+// run before it (a binary search on the key: strictly below for the first
+// run, at most equal for the second, so equal keys keep their run order).
+// A shift adds the same amount to every key of a run, which keeps it
+// ordered.  The stored key is the projection so obtained: within a few
+// units of rounding of the cell's size of the projection computed in the
+// cell's frame, and monotone along the ordering.
+//
+// A cell whose particles crowd more than kSubRun into one sub-cell of
+// depth 3 is ordered by merging runs of 256 consecutive particles instead
+// (each run sorted by a bitonic network).  Words: (order-preserving image of
+// the projection) << 32 | cell index.
+constexpr int MERGE_THREADS = 1024;   // latency-bound: many wavefronts per cell
 constexpr int MERGE_RUN = 256;
+constexpr int kSubDepth = 3;                            // deepest split of a big cell
+constexpr int kSubCells = 1 << (3 * kSubDepth);         // sub-cells of that depth
+constexpr int kSubRun = 64;                             // largest sub-cell ordered directly
+constexpr int kSubRunMax = 256;                         // ... at depth 3, before the fallback
 
 // the number of words of run [b, b + len) below x (strict) or at most x
 __device__ __forceinline__ int count_before(const uint64_t* a, int b, int len, uint64_t x, bool strict)
@@ -752,13 +770,55 @@ __device__ __forceinline__ int count_before(const uint64_t* a, int b, int len, u
     }
     return lo;
 }
+// the same on the keys alone (the high 32 bits)
+__device__ __forceinline__ int keys_before(const uint64_t* a, int b, int len, uint32_t x, bool strict)
+{
+    int lo = 0, hi = len;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const uint32_t y = (uint32_t)(a[b + mid] >> 32);
+        if (strict ? (y < x) : (y <= x)) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint64_t make_word(float f, uint32_t t) { return ((uint64_t)float_key(f) << 32) | t; }
+__device__ __forceinline__ float word_key(uint64_t w) { return key_float((uint32_t)(w >> 32)); }
+
+// Morton index of sub-cell (ix, iy, iz) of depth kSubDepth (x in the highest
+// bit of each triple, as the cell order's keys)
+__device__ __forceinline__ int sub_morton(int ix, int iy, int iz)
+{
+    int m = 0;
+#pragma unroll
+    for (int b = kSubDepth - 1; b >= 0; b--) m = (m << 3) | (((ix >> b) & 1) << 2) | (((iy >> b) & 1) << 1) | ((iz >> b) & 1);
+    return m;
+}
+// lower corner, in units of the depth-kSubDepth edge, of the depth-L sub-cell
+// holding depth-kSubDepth sub-cell m
+__device__ __forceinline__ void sub_corner(int m, int L, int c[3])
+{
+    c[0] = c[1] = c[2] = 0;
+    for (int b = kSubDepth - 1; b >= kSubDepth - L; b--) {
+        const int tri = (m >> (3 * b)) & 7;
+        c[0] |= ((tri >> 2) & 1) << b;
+        c[1] |= ((tri >> 1) & 1) << b;
+        c[2] |= (tri & 1) << b;
+    }
+}
 
 template <typename R>
-__global__ __launch_bounds__(MERGE_THREADS) void k_sort13(const CellInfo* cells, const int32_t* big,
-                                                          CellData<R> cd, int64_t n, Sorted<R> so,
-                                                          uint32_t* status)
+__global__ __launch_bounds__(MERGE_THREADS) void k_sort13(const CellInfo* cells, const BoxInfo* boxes,
+                                                          const int32_t* big, CellData<R> cd, int64_t n,
+                                                          Sorted<R> so, uint32_t* status)
 {
     __shared__ uint64_t buf[2][SORT_MAX];
+    __shared__ uint16_t subof[SORT_MAX];        // depth-3 sub-cell of each particle (cell order)
+    __shared__ int off[kSubCells + 1];          // particles per depth-3 sub-cell, then run starts
+    __shared__ int fill[kSubCells];
+    __shared__ int runmax[kSubDepth + 1];       // largest sub-cell of each depth
+    __shared__ int part[kSubCells / 8];         // counts of the depth-2 sub-cells
     const int tid = threadIdx.x;
     const int64_t units = (int64_t)big[0] * kSortDirs;  // the cells k_sort13_wave left
     for (int64_t unit = blockIdx.x; unit < units; unit += gridDim.x) {
@@ -766,60 +826,175 @@ __global__ __launch_bounds__(MERGE_THREADS) void k_sort13(const CellInfo* cells,
         const int s = (int)(unit % kSortDirs);
         const CellInfo C = cells[c];
         if (C.count > SORT_MAX) { if (tid == 0) atomicOr(status, ST_CAPACITY); continue; }
-        // padded to whole runs with words above every real one
-        const int np = (C.count + MERGE_RUN - 1) / MERGE_RUN * MERGE_RUN;
+        const BoxInfo& B = boxes[C.box];
         float su[3];
         dir_unit(s + 13, su);
+        // edge of the depth-3 sub-cells
+        const float es[3] = {(float)ldexp(B.e[0], -C.level - kSubDepth), (float)ldexp(B.e[1], -C.level - kSubDepth),
+                             (float)ldexp(B.e[2], -C.level - kSubDepth)};
         __syncthreads();   // the last unit's words are written out
-        for (int t = tid; t < np; t += MERGE_THREADS) {
-            uint64_t wd = ~0ull;
-            if (t < C.count) {
-                const typename CellData<R>::R4 q = cd.rp[C.start + t];
-                const float f = su[0] * (float)q.x + su[1] * (float)q.y + su[2] * (float)q.z;
-                const uint32_t b = __float_as_uint(f);
-                const uint32_t key = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
-                wd = ((uint64_t)key << 32) | (uint32_t)t;
-            }
-            buf[0][t] = wd;
+        for (int m = tid; m <= kSubCells; m += MERGE_THREADS) off[m] = 0;
+        for (int m = tid; m < kSubCells; m += MERGE_THREADS) fill[m] = 0;
+        if (tid <= kSubDepth) runmax[tid] = 0;
+        __syncthreads();
+        // ---- the depth-3 sub-cell of every particle, and their counts
+        for (int t = tid; t < C.count; t += MERGE_THREADS) {
+            const typename CellData<R>::R4 q = cd.rp[C.start + t];
+            int ix = (int)((float)q.x / es[0]), iy = (int)((float)q.y / es[1]), iz = (int)((float)q.z / es[2]);
+            constexpr int top = (1 << kSubDepth) - 1;
+            ix = min(max(ix, 0), top); iy = min(max(iy, 0), top); iz = min(max(iz, 0), top);
+            const int m = sub_morton(ix, iy, iz);
+            subof[t] = (uint16_t)m;
+            atomicAdd(&off[m], 1);
         }
         __syncthreads();
-        // each run sorted: bitonic stages of span <= MERGE_RUN stay inside a run;
-        // the last (k = MERGE_RUN) leaves every run ascending
-        for (int k = 2; k <= MERGE_RUN; k <<= 1) {
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int i = tid; i < np; i += MERGE_THREADS) {
-                    const int l = i ^ j;
-                    if (l > i) {
-                        const uint64_t a = buf[0][i], b = buf[0][l];
-                        if ((a > b) == ((i & k & (MERGE_RUN - 1)) == 0)) { buf[0][i] = b; buf[0][l] = a; }
-                    }
+        // largest sub-cell of each depth (a depth-L sub-cell is a run of 8^(3-L)
+        // depth-3 ones): counts of depth 2 into part[0..63], of depth 1 from those
+        for (int m = tid; m < kSubCells; m += MERGE_THREADS) atomicMax(&runmax[3], off[m]);
+        if (tid < kSubCells / 8) {
+            int a = 0;
+            for (int k = 0; k < 8; k++) a += off[8 * tid + k];
+            part[tid] = a;
+            atomicMax(&runmax[2], a);
+        }
+        __syncthreads();
+        if (tid < kSubCells / 64) {
+            int a = 0;
+            for (int k = 0; k < 8; k++) a += part[8 * tid + k];
+            atomicMax(&runmax[1], a);
+        }
+        __syncthreads();
+        int D = 0;
+        for (int L = 1; L <= kSubDepth && D == 0; L++)
+            if (runmax[L] <= kSubRun) D = L;
+        if (D == 0 && runmax[kSubDepth] <= kSubRunMax) D = kSubDepth;
+
+        int src = 0;
+        if (D > 0) {
+            // ---- run starts: exclusive scan of the 512 counts by the first
+            // wavefront, eight consecutive counts per lane
+            static_assert(kSubCells == 8 * kWave, "eight counts per lane");
+            if (tid < kWave) {
+                int v[8], a = 0;
+#pragma unroll
+                for (int k = 0; k < 8; k++) { v[k] = off[8 * tid + k]; a += v[k]; }
+                int inc = a;
+#pragma unroll
+                for (int d = 1; d < kWave; d <<= 1) {
+                    const int y = __shfl_up(inc, d, kWave);
+                    if (tid >= d) inc += y;
                 }
+                int e = inc - a;
+#pragma unroll
+                for (int k = 0; k < 8; k++) { off[8 * tid + k] = e; e += v[k]; }
+                if (tid == kWave - 1) off[kSubCells] = inc;
+            }
+            __syncthreads();
+            // ---- words in the frame of their depth-D sub-cell, grouped by sub-cell
+            const int gsh = 3 * (kSubDepth - D);   // depth-3 sub-cells per depth-D one: 1 << gsh
+            for (int t = tid; t < C.count; t += MERGE_THREADS) {
+                const int m = subof[t];
+                int cc[3];
+                sub_corner(m, D, cc);
+                const typename CellData<R>::R4 q = cd.rp[C.start + t];
+                const float f = su[0] * ((float)q.x - (float)cc[0] * es[0]) + su[1] * ((float)q.y - (float)cc[1] * es[1]) +
+                                su[2] * ((float)q.z - (float)cc[2] * es[2]);
+                const int mg = m >> gsh << gsh;    // first depth-3 sub-cell of the depth-D one
+                buf[0][off[mg] + atomicAdd(&fill[mg], 1)] = make_word(f, (uint32_t)t);
+            }
+            __syncthreads();
+            // ---- each depth-D sub-cell ordered: a word's place is its rank in its run
+            for (int i = tid; i < C.count; i += MERGE_THREADS) {
+                const uint64_t x = buf[0][i];
+                const int m = subof[(uint32_t)x];
+                const int mg = m >> gsh << gsh;
+                const int a = off[mg], b = off[mg + (1 << gsh)];
+                int r = 0;
+                for (int j = a; j < b; j++) r += buf[0][j] < x;
+                buf[1][a + r] = x;
+            }
+            src = 1;
+            __syncthreads();
+            // ---- up the levels: shift into the parent's frame, merge eight siblings
+            for (int L = D; L >= 1; L--) {
+                const int csh = 3 * (kSubDepth - L);   // a depth-L sub-cell spans 1 << csh depth-3 ones
+                for (int i = tid; i < C.count; i += MERGE_THREADS) {
+                    const uint64_t x = buf[src][i];
+                    const int m = subof[(uint32_t)x];
+                    int cl[3], cp[3];
+                    sub_corner(m, L, cl);
+                    sub_corner(m, L - 1, cp);
+                    const float sh = su[0] * (float)(cl[0] - cp[0]) * es[0] + su[1] * (float)(cl[1] - cp[1]) * es[1] +
+                                     su[2] * (float)(cl[2] - cp[2]) * es[2];
+                    buf[src][i] = make_word(word_key(x) + sh, (uint32_t)x);
+                }
+                __syncthreads();
+                for (int q = 0; q < 3; q++) {
+                    // runs of 2^q siblings merged with their partners into runs of 2^(q+1)
+                    const uint64_t* in = buf[src];
+                    uint64_t* outb = buf[src ^ 1];
+                    for (int i = tid; i < C.count; i += MERGE_THREADS) {
+                        const uint64_t x = in[i];
+                        const int m = subof[(uint32_t)x];
+                        const int g = m >> (csh + q);               // the word's run of 2^q siblings
+                        const int a0 = off[g << (csh + q)], a1 = off[(g + 1) << (csh + q)];
+                        const int p = g ^ 1;                        // partner run
+                        const int b0 = off[p << (csh + q)], b1 = off[(p + 1) << (csh + q)];
+                        const bool first = (g & 1) == 0;
+                        const int place = (i - a0) + keys_before(in, b0, b1 - b0, (uint32_t)(x >> 32), first);
+                        outb[min(a0, b0) + place] = x;
+                    }
+                    src ^= 1;
+                    __syncthreads();
+                }
+            }
+        } else {
+            // ---- crowded: runs of MERGE_RUN consecutive particles, sorted and merged
+            const int np = (C.count + MERGE_RUN - 1) / MERGE_RUN * MERGE_RUN;
+            for (int t = tid; t < np; t += MERGE_THREADS) {
+                uint64_t wd = ~0ull;
+                if (t < C.count) {
+                    const typename CellData<R>::R4 q = cd.rp[C.start + t];
+                    wd = make_word(su[0] * (float)q.x + su[1] * (float)q.y + su[2] * (float)q.z, (uint32_t)t);
+                }
+                buf[0][t] = wd;
+            }
+            __syncthreads();
+            // each run sorted: bitonic stages of span <= MERGE_RUN stay inside a run;
+            // the last (k = MERGE_RUN) leaves every run ascending
+            for (int k = 2; k <= MERGE_RUN; k <<= 1) {
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    for (int i = tid; i < np; i += MERGE_THREADS) {
+                        const int l = i ^ j;
+                        if (l > i) {
+                            const uint64_t a = buf[0][i], b = buf[0][l];
+                            if ((a > b) == ((i & k & (MERGE_RUN - 1)) == 0)) { buf[0][i] = b; buf[0][l] = a; }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            // merges: runs of `w` words into runs of 2w, alternating buffers
+            for (int w = MERGE_RUN; w < np; w <<= 1) {
+                const uint64_t* in = buf[src];
+                uint64_t* outb = buf[src ^ 1];
+                for (int i = tid; i < np; i += MERGE_THREADS) {
+                    const int pair = i / (2 * w) * (2 * w);      // first word of the two runs
+                    const int la = min(w, np - pair);            // first run (whole unless the last)
+                    const int lb = min(w, np - pair - la);       // partner run (possibly empty)
+                    const uint64_t x = in[i];
+                    int place;
+                    if (i < pair + la) place = (i - pair) + count_before(in, pair + la, lb, x, true);
+                    else place = (i - pair - la) + count_before(in, pair, la, x, false);
+                    outb[pair + place] = x;
+                }
+                src ^= 1;
                 __syncthreads();
             }
         }
-        // merges: runs of `w` words into runs of 2w, alternating buffers
-        int src = 0;
-        for (int w = MERGE_RUN; w < np; w <<= 1) {
-            const uint64_t* in = buf[src];
-            uint64_t* outb = buf[src ^ 1];
-            for (int i = tid; i < np; i += MERGE_THREADS) {
-                const int pair = i / (2 * w) * (2 * w);      // first word of the two runs
-                const int la = min(w, np - pair);            // first run (whole unless the last)
-                const int lb = min(w, np - pair - la);       // partner run (possibly empty)
-                const uint64_t x = in[i];
-                int place;
-                if (i < pair + la) place = (i - pair) + count_before(in, pair + la, lb, x, true);
-                else place = (i - pair - la) + count_before(in, pair, la, x, false);
-                outb[pair + place] = x;
-            }
-            src ^= 1;
-            __syncthreads();
-        }
         for (int r = tid; r < C.count; r += MERGE_THREADS) {
             const uint64_t wd = buf[src][r];
-            const uint32_t kt = (uint32_t)(wd >> 32);
-            const uint32_t b = (kt & 0x80000000u) ? (kt & 0x7fffffffu) : ~kt;
-            so.rec[(int64_t)s * n + C.start + r] = SortRec{__uint_as_float(b), (uint32_t)wd};
+            so.rec[(int64_t)s * n + C.start + r] = SortRec{word_key(wd), (uint32_t)wd};
         }
     }
 }
@@ -968,8 +1143,8 @@ void launch_sources(const CellInfo* cells, const int32_t* ncells, const BoxInfo*
 }
 
 template <typename R>
-void launch_sort13(const CellInfo* cells, const int32_t* ncells, const CellData<R>& cd, int64_t n,
-                   const Sorted<R>& so, int32_t* big, uint32_t* status, int64_t cell_cap, hipStream_t st)
+void launch_sort13(const CellInfo* cells, const int32_t* ncells, const BoxInfo* boxes, const CellData<R>& cd,
+                   int64_t n, const Sorted<R>& so, int32_t* big, uint32_t* status, int64_t cell_cap, hipStream_t st)
 {
     hipLaunchKernelGGL(k_zero_header, dim3(1), dim3(1), 0, st, big);
     unsigned gw = (unsigned)(cell_cap < 65536 ? cell_cap : 65536);
@@ -978,11 +1153,11 @@ void launch_sort13(const CellInfo* cells, const int32_t* ncells, const CellData<
     // at most n / (kWaveSortMax + 1) cells are left; the grid strides over them
     const int64_t units = (cell_cap / (kWaveSortMax + 1) + 1) * kSortDirs;
     const unsigned grid = (unsigned)(units < 2048 ? units : 2048);
-    hipLaunchKernelGGL(k_sort13<R>, dim3(grid), dim3(MERGE_THREADS), 0, st, cells, big, cd, n, so, status);
+    hipLaunchKernelGGL(k_sort13<R>, dim3(grid), dim3(MERGE_THREADS), 0, st, cells, boxes, big, cd, n, so, status);
 }
-template void launch_sort13<float>(const CellInfo*, const int32_t*, const CellData<float>&, int64_t,
+template void launch_sort13<float>(const CellInfo*, const int32_t*, const BoxInfo*, const CellData<float>&, int64_t,
                                    const Sorted<float>&, int32_t*, uint32_t*, int64_t, hipStream_t);
-template void launch_sort13<double>(const CellInfo*, const int32_t*, const CellData<double>&, int64_t,
+template void launch_sort13<double>(const CellInfo*, const int32_t*, const BoxInfo*, const CellData<double>&, int64_t,
                                     const Sorted<double>&, int32_t*, uint32_t*, int64_t, hipStream_t);
 
 }  // namespace sph

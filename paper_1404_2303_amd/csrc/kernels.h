@@ -140,8 +140,8 @@ void launch_sources(const CellInfo* cells, const int32_t* ncells, const BoxInfo*
                     const int32_t* cell_map, Source* src, int32_t* src_off, int32_t* src_count,
                     int64_t cell_cap, hipStream_t st);
 template <typename R>
-void launch_sort13(const CellInfo* cells, const int32_t* ncells, const CellData<R>& cd, int64_t n,
-                   const Sorted<R>& so, int32_t* big, uint32_t* status, int64_t cell_cap, hipStream_t st);
+void launch_sort13(const CellInfo* cells, const int32_t* ncells, const BoxInfo* boxes, const CellData<R>& cd,
+                   int64_t n, const Sorted<R>& so, int32_t* big, uint32_t* status, int64_t cell_cap, hipStream_t st);
 // big[0]: the number of cells left to the rank sort, big[kBigHeader..]: those cells
 constexpr int kBigHeader = 1;
 

@@ -161,15 +161,32 @@ def test_large_cells_fp32(n, cell_target, lo, hi, staging):
 @pytest.mark.parametrize("n,cell_target,lo,hi", [(30000, 1000, 256, 1500), (100000, 3000, 2048, 4096)])
 def test_cells_ordered_by_merging(n, cell_target, lo, hi, precision):
     """Cells of more than 256 particles: their orderings are made by one
-    work-group from sorted runs of 256 merged pairwise (up to 4096 particles,
-    four merge levels); any misplaced particle would cut the sorted sweeps
-    short and lose pairs."""
+    work-group from those of their sub-cells of depth 1 to 3, shifted into
+    the parent's frame and merged (Sec. 3.3); any misplaced particle would cut
+    the sorted sweeps short and lose pairs."""
     ps = workloads.uniform(n, seed=11, sigma_v=0.3)
     g = gpu_run(ps, precision, cell_target=cell_target)
     mean = ps.n / g["stats"]["n_cells"]
     log(f"case merged orderings {precision} n={n} cell_target={cell_target}: {g['stats']['n_cells']} cells, mean {mean:.0f}")
     assert lo < mean <= hi
     compare(g, oracle_run(ps), precision, label=f"merged cells {cell_target}")
+
+
+def test_crowded_cell_ordering():
+    """A clump of 400 particles inside a cube of 1/64 of a big cell's edge:
+    more than 256 in one depth-3 sub-cell, so that cell's orderings come from
+    runs of 256 consecutive particles instead; the other big cells take the
+    sub-cell construction.  FP64 only: the clump's spacing is 3e-3 of the
+    cell's edge, so FP32 positions in the cell's frame resolve its pair
+    separations to ~3e-5 only, above the FP32 parity bound."""
+    precision = "fp64"
+    ps = workloads.uniform(12000, seed=13, sigma_v=0.2)
+    rng = np.random.default_rng(13)
+    ps.pos[:400] = 0.52 + 0.004 * rng.random((400, 3))
+    ps.h0[:400] = 0.005
+    g = gpu_run(ps, precision, cell_target=1000)
+    log(f"case crowded cell {precision}: {g['stats']['n_cells']} cells")
+    compare(g, oracle_run(ps), precision, label="crowded cell")
 
 
 def test_momentum_and_energy_conservation_gpu():
