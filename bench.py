@@ -207,7 +207,7 @@ def batched_section(steps, warmup, tune=True):
     params, tuned = {}, None
     if tune:
         key = autotune.workload_class(ps.n, len(offsets) - 1, "fp32")
-        tuned = autotune.tune(autotune.gpu_timer(ps, "fp32", batch=_BatchArgs(offsets, lens)), key, arch)
+        tuned = autotune.tune_staged(autotune.gpu_timer(ps, "fp32", batch=_BatchArgs(offsets, lens)), key, arch)
         params = {k: v for k, v in tuned.items() if k != "cached"}
     g = run_graph(ps, "fp32", steps, warmup, batch=(offsets, lens), params=params)
     loop = run_per_box_loop(ps, "fp32", offsets, lens, params=params)
@@ -584,6 +584,7 @@ def orderings_section(reps=5):
             torch.cuda.synchronize()
             if r:
                 ts.append(ctx.kernel_times()["sort_ms"])
+        ctx.check()   # reads the cell count back
         nc = int(ctx.stats()["n_cells"])
         ctx.close()
         out[f"cell_target_{ct}"] = {"sort_ms": float(np.median(ts)), "cells": nc, "mean_per_cell": ps.n / nc}
@@ -604,6 +605,7 @@ def main():
     ap.add_argument("--no-mts", action="store_true", help="skip the multiple time-stepping timing")
     ap.add_argument("--no-layouts", action="store_true", help="skip the timing of the shared sweep layout")
     ap.add_argument("--no-orderings", action="store_true", help="skip the timing of big-cell orderings")
+    ap.add_argument("--no-tune", action="store_true", help="default parameters for the headline pass (no autotuning)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -617,13 +619,22 @@ def main():
     from paper_1404_2303_amd import workloads
     ps = workloads.config1()
     log(f"workload: {ps.n} particles, box {ps.box.tolist()}")
-    fast = run_form(ps, "fp32", args.steps, args.warmup)
+    # the FP32 pass's decomposition and tiles, tuned on this workload (cached per class)
+    params, tuned = {}, None
+    if not args.no_tune:
+        from paper_1404_2303_amd import autotune
+        arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+        key = "grid|" + autotune.workload_class(ps.n, 1, "fp32")
+        tuned = autotune.tune_staged(autotune.gpu_timer(ps, "fp32"), key, arch)
+        params = {k: v for k, v in tuned.items() if k != "cached"}
+        log("tuned:", json.dumps(tuned))
+    fast = run_form(ps, "fp32", args.steps, args.warmup, **params)
     log("fp32_acc64:", json.dumps(fast))
     plain = None
     if not args.no_plain:
         plain = run_form(ps, "fp64", args.steps, args.warmup)
         log("fp64:", json.dumps(plain))
-    graph = run_graph(ps, "fp32", args.steps, args.warmup)
+    graph = run_graph(ps, "fp32", args.steps, args.warmup, params=params)
     log("fp32 graph:", json.dumps(graph))
     rl = roofline(fast)
     # the chosen form: the captured FP32 pass when it is the faster one
@@ -650,7 +661,7 @@ def main():
                    "eager_ms_per_step": fast["ms_per_step"], "graph_ms_per_step": graph["ms_per_step"],
                    "pairs_per_step": fast["P"], "kernel_ms": fast["kernel_ms"],
                    "newton_mean": fast["newton_mean"], "newton_max": fast["newton_max"],
-                   "cells": fast["cells"], "grid": fast["grid"],
+                   "cells": fast["cells"], "grid": fast["grid"], "tuned": tuned,
                    "pair_kernel_rate": fast["P"] / ((fast["kernel_ms"]["density_ms"] + fast["kernel_ms"]["force_ms"]) * 1e-3)},
         "roofline": rl,
     }

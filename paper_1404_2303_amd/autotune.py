@@ -1,13 +1,22 @@
-"""Autotuner for the decomposition parameters of the interaction kernels.
+"""Autotuner for the decomposition and tile parameters of the interaction kernels.
 
-The kernels' LDS tiles are fixed at compile time; what changes the work per
-unit at run time is the size of the cells (``cell_target``: particles per
-top cell at the mean density, subject to edge >= max h; on the hierarchy,
-``split_count``: the particle count above which a cell is split) and the
-slack on h when cells are built (``h_margin``).  For a given workload the tuner times a
-captured pass (build, sort, density, force) for each candidate and keeps the
-fastest.  Results are cached per (GPU architecture, precision, workload
-class) in a JSON file, so a workload of the same class is not re-tuned.
+The kernels' LDS tiles are fixed at compile time, in a few variants chosen at
+run time; what the tuner searches:
+  - the decomposition: the size of the cells (``cell_target``: particles per
+    top cell at the mean density, subject to edge >= max h; on the
+    hierarchy, ``split_count``: the particle count above which a cell is
+    split) and the slack on h when cells are built (``h_margin``);
+  - the tiles: the work layout of the sweeps (``sweep``: sources split
+    between the four wavefronts of a unit, or staged once and shared, with
+    16 targets per wavefront), the density staging (``staging``: compact,
+    four work-groups per CU, or wide, room for larger cells) and the cell
+    size above which the force sweep takes 256 targets per unit
+    (``shared_min``).
+For a given workload the tuner times a captured pass (build, sort, density,
+force) for each candidate, one group of parameters at a time (the best of a
+group is kept while the next is searched), and keeps the fastest.  Results
+are cached per (GPU architecture, precision, workload class) in a JSON
+file, so a workload of the same class is not re-tuned.
 """
 from __future__ import annotations
 
@@ -26,6 +35,16 @@ CANDIDATES = [
     {"cell_target": 128, "h_margin": 0.1},
     {"cell_target": 64, "h_margin": 0.05},
 ]
+
+# tile groups searched after the decomposition (sph.SPH_SWEEP_* and
+# sph.SPH_STAGING_* values: 2 split, 1 shared; 0 compact, 1 wide)
+LAYOUT_CANDIDATES = [
+    {"sweep": 2, "staging": 0},
+    {"sweep": 2, "staging": 1},
+    {"sweep": 1, "staging": 0},
+]
+SHARED_MIN_CANDIDATES = [{"shared_min": 128}, {"shared_min": 64}, {"shared_min": 256}]
+STAGES = [CANDIDATES, LAYOUT_CANDIDATES, SHARED_MIN_CANDIDATES]
 
 # hierarchical decomposition: leaf size (the split rule's count) for multi-resolution sets
 TREE_CANDIDATES = [
@@ -108,6 +127,41 @@ def tune(time_candidate: Callable[[dict], float], key: str, arch: str, candidate
     if not timings:
         raise RuntimeError("no autotune candidate ran")
     best = choose(timings)
+    cache[full] = {"best": best, "timings": timings, "skipped": skipped, "when": time.time()}
+    save_cache(cache, cache_path)
+    return dict(best, cached=False)
+
+
+def tune_staged(time_candidate: Callable[[dict], float], key: str, arch: str, stages=None,
+                cache_path: str = CACHE, force: bool = False) -> dict:
+    """Coordinate search over groups of parameters: each stage's candidates
+    are timed on top of the best of the stages before (same timer contract
+    and skipping rules as tune()); the final best is cached under (arch, key)."""
+    stages = STAGES if stages is None else stages
+    cache = load_cache(cache_path)
+    full = f"{arch}|{key}|staged"
+    if not force and full in cache:
+        return dict(cache[full]["best"], cached=True)
+    best: dict = {}
+    timings, skipped = {}, {}
+    for stage in stages:
+        stage_t = {}
+        for c in stage:
+            cand = dict(best, **c)
+            k = json.dumps(cand, sort_keys=True)
+            if k in timings:
+                stage_t[k] = timings[k]
+                continue
+            try:
+                stage_t[k] = timings[k] = float(time_candidate(cand))
+            except Exception as e:
+                if not _unusable(e):
+                    raise
+                skipped[k] = str(e)
+        if stage_t:
+            best = choose(stage_t)
+    if not timings:
+        raise RuntimeError("no autotune candidate ran")
     cache[full] = {"best": best, "timings": timings, "skipped": skipped, "when": time.time()}
     save_cache(cache, cache_path)
     return dict(best, cached=False)
