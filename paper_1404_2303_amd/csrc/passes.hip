@@ -111,6 +111,15 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
         int k = 0, p = 0;
         stage_wave<R, false>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, mstage);
         bool single = k >= nsrc;
+        // every wavefront staged all of its sources at once (a uniform vote)
+        auto vote_all = [&](bool mine) {
+            if (lane == 0) s.done[w] = mine ? 1 : 0;
+            __syncthreads();
+            const bool all = (s.done[0] & s.done[1] & s.done[2] & s.done[3]) != 0;
+            __syncthreads();   // read before done[] is written again
+            return __builtin_amdgcn_readfirstlane(all ? 1 : 0) != 0;
+        };
+        bool all_single = vote_all(single);
 
         for (int c0 = 0; c0 < T.count; c0 += kWave) {
             const int ti = c0 + lane;
@@ -135,26 +144,61 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
             }
             // neighbour lists of this wavefront: valid while every lane's h <= hcache
             bool cached = false;
+            // block-uniform: the lists of all four wavefronts are whole (evaluated
+            // together), or some wavefront's list filled during the last walk
+            // (each wavefront then keeps to its own lists, without votes)
+            bool lists_all = false, own_mode = false;
             bool cached_all = false;  // the lists were built with every valid lane active
             float hcache = 0.0f;
             int cnt = 0;
             DensAcc acc;
 
-            // Sums over this wavefront's sources at the current h, for the lanes in
-            // `act`: the two of Eq. (3) (full = false) or all of them (full = true).
+            // Sums at the current h, for the lanes in `act`: the two of Eq. (3)
+            // (full = false) or all of them (full = true).  Lists in hand are
+            // evaluated by their own wavefront (a list that fills, or a batch of
+            // sources staged in several), or, once every wavefront holds its whole
+            // list, all four lists of a target together: wavefront w takes entries
+            // w, w + 4, ... of their concatenation, so that the list loops of the
+            // four run about equally long whatever the split of the neighbours
+            // between the regions.
             auto evaluate = [&](bool act, bool full) {
                 acc = DensAcc{};
                 const R hr = (R)h, hinv = (R)(1.0 / h), h2 = hr * hr;
-                auto process = [&](int n) {
+                // region and staged index of list entry k: of this wavefront's own
+                // list, or (ALL) of the concatenation of the four
+                auto process = [&](int n, auto all_tag) {
+                    constexpr bool ALL = decltype(all_tag)::value;
+                    int C1 = 0, C2 = 0, C3 = 0, tot = n;
+                    if constexpr (ALL) {
+                        C1 = s.lcount[0][lane];
+                        C2 = C1 + s.lcount[1][lane];
+                        C3 = C2 + s.lcount[2][lane];
+                        tot = C3 + s.lcount[3][lane];
+                    }
+                    constexpr int t0s = ALL ? 1 : 0;   // start at w (ALL) or 0
+                    constexpr int dt = ALL ? NW : 1;
+                    auto entry = [&](int kk, int& r, int& j) {
+                        if constexpr (ALL) {
+                            r = (kk >= C1) + (kk >= C2) + (kk >= C3);
+                            j = s.list[r][lane][kk - (r == 0 ? 0 : (r == 1 ? C1 : (r == 2 ? C2 : C3)))];
+                        } else {
+                            r = w;
+                            j = s.list[w][lane][kk];
+                        }
+                    };
                     if (full) {
                         DensPart<R> b = {};
-                        for (int t = 0;; t += 2) {
-                            const bool v0 = act && t < n, v1 = act && t + 1 < n;
+                        for (int t = t0s * w;; t += 2 * dt) {
+                            converge();
+                            const bool v0 = act && t < tot, v1 = act && t + dt < tot;
                             if (!__any(v0)) break;
-                            const int j0 = v0 ? (int)s.list[w][lane][t] : 0;
-                            const int j1 = v1 ? (int)s.list[w][lane][t + 1] : 0;
-                            const R4 e0 = s.st[w][j0], e1 = s.st[w][j1];
-                            const R4 q0 = cd.vm[s.sg[w][j0]], q1 = cd.vm[s.sg[w][j1]];
+                            int r0, j0, r1, j1;
+                            entry(v0 ? t : 0, r0, j0);
+                            entry(v1 ? t + dt : 0, r1, j1);
+                            j0 = v0 ? j0 : 0;
+                            j1 = v1 ? j1 : 0;
+                            const R4 e0 = s.st[r0][j0], e1 = s.st[r1][j1];
+                            const R4 q0 = cd.vm[s.sg[r0][j0]], q1 = cd.vm[s.sg[r1][j1]];
                             density_pair<R>(b, v0, xi, yi, zi, vmi.x, vmi.y, vmi.z, hr, hinv, h2, e0, q0);
                             density_pair<R>(b, v1, xi, yi, zi, vmi.x, vmi.y, vmi.z, hr, hinv, h2, e1, q1);
                         }
@@ -172,14 +216,17 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
                             atomicAdd(&s.red[7][lane], (double)b.cz);
                         }
                     } else {
-                        // partial sums of this list (at most LISTW terms), then FP64
+                        // partial sums of these terms (at most LISTW of the lane's
+                        // own list; about a quarter of four lists), then FP64
                         R sw = (R)0, sq = (R)0;
-                        for (int t = 0;; t += 2) {
-                            const bool v0 = act && t < n, v1 = act && t + 1 < n;
+                        for (int t = t0s * w;; t += 2 * dt) {
+                            converge();
+                            const bool v0 = act && t < tot, v1 = act && t + dt < tot;
                             if (lanes(v0) == 0) break;
-                            // slots t, t + 1 <= LISTW lie in the row; past the list: masked
-                            const int r0 = s.list[w][lane][t], r1 = s.list[w][lane][t + 1];
-                            const R4 e0 = s.st[w][v0 ? r0 : 0], e1 = s.st[w][v1 ? r1 : 0];
+                            int r0, j0, r1, j1;
+                            entry(v0 ? t : 0, r0, j0);
+                            entry(v1 ? t + dt : 0, r1, j1);
+                            const R4 e0 = s.st[r0][v0 ? j0 : 0], e1 = s.st[r1][v1 ? j1 : 0];
                             count_pair<R>(sw, sq, v0, xi, yi, zi, hinv, h2, e0);
                             count_pair<R>(sw, sq, v1, xi, yi, zi, hinv, h2, e1);
                         }
@@ -187,9 +234,15 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
                         acc.qdw += (double)sq;
                     }
                 };
-                const bool reuse = cached && (!full || cached_all) && __all(!act || (float)h <= hcache);
-                if (reuse) {
-                    process(cnt);
+                using Own = std::false_type;
+                using All = std::true_type;
+                const bool fit = (!full || cached_all) && __all(!act || (float)h <= hcache);
+                if (lists_all && fit) {
+                    process(0, All{});
+                    return;
+                }
+                if (!lists_all && cached && fit) {
+                    process(cnt, Own{});
                     return;
                 }
                 // sweep(s) with early exit; the lists keep r < h (1 + slack)
@@ -197,25 +250,55 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
                 const R rad = (R)hcache;
                 const float fh = hcache + margin;
                 bool flushed = false;
-                int kk = 0, pp = 0;
-                do {
-                    if (!single) stage_wave<R, false>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, kk, pp, Hst, mstage);
-                    else kk = nsrc;
+                lists_all = false;
+                if (all_single && !own_mode) {
+                    // every source is staged: walk, keeping the lists (one that fills
+                    // is evaluated at once by its owner), then all four together
                     const int selfj = self_index(s, w, ti);
                     int seg = 0, jj = s.nseg[w] > 0 ? s.seg_b[w][0] : 0;
                     cnt = 0;
                     while (true) {
-                        cnt = walk<R, false, NACC_D, CFG>(s, w, w, lane, act, xi, yi, zi, fxi, fyi, fzi, rad, fh, margin,
-                                                     selfj, seg, jj, cnt);
+                        converge();
+                        cnt = walk<R, false, NACC_D, CFG>(s, w, w, lane, act, xi, yi, zi, fxi, fyi, fzi, rad, fh,
+                                                          margin, selfj, seg, jj, cnt);
                         if (seg >= s.nseg[w]) break;
-                        process(cnt);  // a list is full: evaluate it and continue the walk
+                        process(cnt, Own{});
                         cnt = 0;
                         flushed = true;
                     }
-                    if (!single) { process(cnt); cnt = 0; flushed = true; }
-                } while (kk < nsrc);
-                if (single) process(cnt);
-                cached = single && !flushed;
+                    s.lcount[w][lane] = (uint8_t)cnt;
+                    // the vote's barriers also publish the lists and their counts
+                    lists_all = vote_all(!flushed);
+                    own_mode = !lists_all;
+                    process(0, All{});
+                    cached = !flushed;   // a wavefront's own list stays whole while it did not fill
+                } else {
+                    int kk = 0, pp = 0;
+                    do {
+                        if (!single)
+                            stage_wave<R, false>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, kk, pp, Hst, mstage);
+                        else kk = nsrc;
+                        const int selfj = self_index(s, w, ti);
+                        int seg = 0, jj = s.nseg[w] > 0 ? s.seg_b[w][0] : 0;
+                        cnt = 0;
+                        while (true) {
+                            converge();
+                            cnt = walk<R, false, NACC_D, CFG>(s, w, w, lane, act, xi, yi, zi, fxi, fyi, fzi, rad,
+                                                              fh, margin, selfj, seg, jj, cnt);
+                            if (seg >= s.nseg[w]) break;
+                            process(cnt, Own{});  // a list is full: evaluate it and continue the walk
+                            cnt = 0;
+                            flushed = true;
+                        }
+                        if (!single) {
+                            process(cnt, Own{});
+                            cnt = 0;
+                            flushed = true;
+                        }
+                    } while (kk < nsrc);
+                    if (single) process(cnt, Own{});
+                    cached = single && !flushed;
+                }
                 cached_all = __all(act || !on);
             };
 
@@ -314,7 +397,10 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
                     k = 0; p = 0;
                     stage_wave<R, false>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, mstage);
                     single = k >= nsrc;
+                    all_single = vote_all(single);
                     cached = false;
+                    lists_all = false;
+                    own_mode = false;
                 }
                 full = __all(close);  // every lane converged, or its next residual is negligible
             }

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <limits>
+#include <type_traits>
 
 #include "sph_internal.h"
 #include "kernels.h"
@@ -132,6 +133,7 @@ struct Smem {
     static_assert(CAPW <= 256, "list entries are bytes");
     static_assert(LISTW % 8 == 0, "odd dword pitch");
     uint8_t list[NW][kWave][LISTP];
+    uint8_t lcount[NW][kWave];        // density: list lengths, for evaluating all four lists together
     double red[NACC][kWave];          // partial sums of the four wavefronts
     int seg_b[NW][kMaxSegW], seg_e[NW][kMaxSegW];
     float seg_u[NW][kMaxSegW][3];
