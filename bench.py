@@ -357,6 +357,7 @@ class _BatchArgs:
 
 
 KERNEL_SOURCES = ["paper_1404_2303_amd/csrc/passes.hip", "paper_1404_2303_amd/csrc/sweep.h",
+                  "paper_1404_2303_amd/csrc/pairs.h",
                   "paper_1404_2303_amd/csrc/kernels.h", "paper_1404_2303_amd/csrc/sph_internal.h"]
 TRAFFIC_PROFILE = "profiles/traffic_lattice2p20_fp32.md"
 
@@ -606,6 +607,9 @@ def main():
     ap.add_argument("--no-layouts", action="store_true", help="skip the timing of the shared sweep layout")
     ap.add_argument("--no-orderings", action="store_true", help="skip the timing of big-cell orderings")
     ap.add_argument("--no-tune", action="store_true", help="default parameters for the headline pass (no autotuning)")
+    ap.add_argument("--params", default="",
+                    help="JSON object of sph_params fields for the headline pass in place of autotuning "
+                         "(e.g. the 'tuned' values of an earlier line, so that a profiler sees no tuning)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -621,7 +625,12 @@ def main():
     log(f"workload: {ps.n} particles, box {ps.box.tolist()}")
     # the FP32 pass's decomposition and tiles, tuned on this workload (cached per class)
     params, tuned = {}, None
-    if not args.no_tune:
+    if args.params:
+        tuned = {k: v for k, v in json.loads(args.params).items() if k != "cached"}
+        params = dict(tuned)
+        tuned["given"] = True
+        log("given:", json.dumps(params))
+    elif not args.no_tune:
         from paper_1404_2303_amd import autotune
         arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
         key = "grid|" + autotune.workload_class(ps.n, 1, "fp32")

@@ -2,6 +2,7 @@
 profilers (rocprofv3 --kernel-trace / --pmc) to record.
 
     python -m paper_1404_2303_amd.profile_pass --workload lattice --passes 2 --copy-mib 512
+    python -m paper_1404_2303_amd.profile_pass --workload lattice --params '{"h_margin": 0.05}'
     python -m paper_1404_2303_amd.profile_pass --workload sod --steps 20 --reuse 1
     python -m paper_1404_2303_amd.profile_pass --workload sedov --steps 64 --reuse 1
 
@@ -16,6 +17,7 @@ time step).
 from __future__ import annotations
 
 import argparse
+import json
 
 
 def main():
@@ -30,6 +32,9 @@ def main():
                     help="cells of more particles than this are swept shared (sph_params.shared_min)")
     ap.add_argument("--staging", choices=("compact", "wide"), default="compact",
                     help="density staging of the lattice and mixture workloads (sph_params.staging)")
+    ap.add_argument("--params", default="",
+                    help="JSON object of further sph_params fields for the lattice and mixture workloads, "
+                         "e.g. the tuned values a bench line reports; they override the options above")
     args = ap.parse_args()
     import time
 
@@ -76,7 +81,11 @@ def main():
         ps, params = workloads.config2(), {"max_depth": 10, "split_count": 256}
     parts = sph.Particles.from_numpy(ps, "cuda:0")
     staging = sph.SPH_STAGING_WIDE if args.staging == "wide" else sph.SPH_STAGING_COMPACT
-    ctx = sph.Context(ps.box, precision=args.precision, shared_min=args.shared_min, staging=staging, **params)
+    params = dict(params, shared_min=args.shared_min, staging=staging)
+    if args.params:
+        params.update({k: v for k, v in json.loads(args.params).items() if k != "cached"})
+    print("params:", json.dumps(params), flush=True)
+    ctx = sph.Context(ps.box, precision=args.precision, **params)
     if args.workload == "mixture":
         ctx.estimate_h(parts)
         ctx.run(parts)
