@@ -313,10 +313,67 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
             // A step so small that the next residual is predicted far below the
             // tolerance: the next evaluation takes every sum, and the iteration
             // ends there if it confirms convergence.  Once every lane has
-            // converged, one evaluation with every sum ends it too.
+            // converged, one evaluation with every sum ends it too.  An
+            // evaluation with every sum also holds the two of Eq. (3), so the
+            // lanes it does not confirm take their Newton step from it.
             const double step_final = sqrt(pc.tol / (10.0 * pc.n_ngb));
-            bool full = pc.fixed_h != 0;   // a given h: straight to the full sums
+            // A given h goes straight to the full sums.  So does a unit whose
+            // sources take several staging batches: each evaluation stages and
+            // walks them all again, which costs far more than the extra sums,
+            // and an h that is already converged is then confirmed by the first
+            // evaluation rather than the second.
+            bool full = pc.fixed_h != 0 || !all_single;
             int cit = 0;  // count steps since the buffers were last cleared
+            // one Newton step of a lane not yet converged, from the sums w and
+            // q dw/dq of Eq. (3) at the current h
+            auto newton = [&](double ws, double qs, bool& restage, bool& close) {
+                iters++;
+                const double N = 32.0 / 3.0 * (ws + 1.0);
+                const double dN = -32.0 / 3.0 / h * qs;
+                const double f = N - pc.n_ngb;
+                if (fabs(f) <= pc.tol) {
+                    conv = true;
+                } else if (iters >= pc.max_iter) {
+                    conv = true; failed = true;
+                } else {
+                    if (f < 0.0) lo = h; else hi = h;
+                    // Newton on g: h - g / g', g' = N' / (3 N^(2/3))
+                    const double c = cbrt(N);
+                    double hn = h - 3.0 * c * c * (c - cbrt_ngb) / dN;
+                    const bool ok = (dN > 0.0) && (hn > lo) && (hn < hi) && (hn >= 0.5 * h) && (hn <= 2.0 * h);
+                    if (!ok) hn = isinf(hi) ? 2.0 * h : 0.5 * (lo + hi);
+                    if (hn > h_lim) {
+                        if (h >= h_lim) {  // the root lies beyond what the cells allow
+                            if (w == 0) atomicOr(dc.status, ST_REBUILD);
+                            conv = true; failed = true;
+                            // the next build takes it from here, within what a
+                            // periodic box allows (three cells of edge >= h)
+                            h_rebuild = fmin(hn, h_box);
+                        } else {
+                            hn = h_lim;
+                        }
+                    }
+                    if (!conv) {
+                        close = fabs(hn - h) <= step_final * h;
+                        h = hn;
+                        restage = (float)h > Hst;
+                    }
+                }
+            };
+            // staging again for an h beyond the staged reach (a block-uniform
+            // vote: the four wavefronts hold the same lanes' states)
+            auto restage_if = [&](bool restage) {
+                if (!__any(restage)) return;
+                const double hm = wave_max(conv ? 0.0 : h);
+                Hst = (float)fmin(fmax((double)Hst, hm * (1.0 + pc.h_margin)), h_lim);
+                k = 0; p = 0;
+                stage_wave<R, false>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, mstage);
+                single = k >= nsrc;
+                all_single = vote_all(single);
+                cached = false;
+                lists_all = false;
+                own_mode = false;
+            };
             for (int a = w; a < 2; a += NW) s.red[a][lane] = 0.0;
             __syncthreads();
             while (true) {
@@ -332,18 +389,18 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
                         atomicAdd(&s.red[8][lane], (double)acc.n);
                     }
                     __syncthreads();
-                    if (!conv) {
-                        iters++;
-                        const double N = 32.0 / 3.0 * (s.red[0][lane] + 1.0);
-                        if (fabs(N - pc.n_ngb) <= pc.tol) conv = true;
-                    }
+                    bool restage = false;
+                    bool close = true;
+                    if (!conv) newton(s.red[0][lane], s.red[1][lane], restage, close);
                     if (__all(conv)) break;
-                    // not yet: back to the steps, with cleared buffers
-                    full = false;
+                    // not yet: on from the step just taken, with cleared buffers
                     cit = 0;
                     __syncthreads();
                     for (int a = w; a < 2; a += NW) s.red[a][lane] = 0.0;
                     __syncthreads();
+                    restage_if(restage);
+                    full = __all(close);
+                    continue;
                 }
                 const int rb = 2 * (cit % 3);        // this step's buffer
                 const int zb = 2 * ((cit + 1) % 3);  // the next step's buffer: last read two steps ago
@@ -357,51 +414,8 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
                 __syncthreads();
                 bool restage = false;
                 bool close = true;
-                if (!conv) {
-                    iters++;
-                    const double N = 32.0 / 3.0 * (s.red[rb][lane] + 1.0);
-                    const double dN = -32.0 / 3.0 / h * s.red[rb + 1][lane];
-                    const double f = N - pc.n_ngb;
-                    if (fabs(f) <= pc.tol) {
-                        conv = true;
-                    } else if (iters >= pc.max_iter) {
-                        conv = true; failed = true;
-                    } else {
-                        if (f < 0.0) lo = h; else hi = h;
-                        // Newton on g: h - g / g', g' = N' / (3 N^(2/3))
-                        const double c = cbrt(N);
-                        double hn = h - 3.0 * c * c * (c - cbrt_ngb) / dN;
-                        const bool ok = (dN > 0.0) && (hn > lo) && (hn < hi) && (hn >= 0.5 * h) && (hn <= 2.0 * h);
-                        if (!ok) hn = isinf(hi) ? 2.0 * h : 0.5 * (lo + hi);
-                        if (hn > h_lim) {
-                            if (h >= h_lim) {  // the root lies beyond what the cells allow
-                                if (w == 0) atomicOr(dc.status, ST_REBUILD);
-                                conv = true; failed = true;
-                                // the next build takes it from here, within what a
-                                // periodic box allows (three cells of edge >= h)
-                                h_rebuild = fmin(hn, h_box);
-                            } else {
-                                hn = h_lim;
-                            }
-                        }
-                        if (!conv) {
-                            close = fabs(hn - h) <= step_final * h;
-                            h = hn;
-                            restage = (float)h > Hst;
-                        }
-                    }
-                }
-                if (__any(restage)) {
-                    const double hm = wave_max(conv ? 0.0 : h);
-                    Hst = (float)fmin(fmax((double)Hst, hm * (1.0 + pc.h_margin)), h_lim);
-                    k = 0; p = 0;
-                    stage_wave<R, false>(s, w, dc, cd, so, gd, B, unit, T.level, nsrc, k, p, Hst, mstage);
-                    single = k >= nsrc;
-                    all_single = vote_all(single);
-                    cached = false;
-                    lists_all = false;
-                    own_mode = false;
-                }
+                if (!conv) newton(s.red[rb][lane], s.red[rb + 1][lane], restage, close);
+                restage_if(restage);
                 full = __all(close);  // every lane converged, or its next residual is negligible
             }
 
