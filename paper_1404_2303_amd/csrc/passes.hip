@@ -179,8 +179,13 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
                     constexpr int dt = ALL ? NW : 1;
                     auto entry = [&](int kk, int& r, int& j) {
                         if constexpr (ALL) {
-                            r = (kk >= C1) + (kk >= C2) + (kk >= C3);
-                            j = s.list[r][lane][kk - (r == 0 ? 0 : (r == 1 ? C1 : (r == 2 ? C2 : C3)))];
+                            // selects rather than a chain of branches on r
+                            const bool b1 = kk >= C1, b2 = kk >= C2, b3 = kk >= C3;
+                            int off = b1 ? C1 : 0;
+                            off = b2 ? C2 : off;
+                            off = b3 ? C3 : off;
+                            r = (int)b1 + (int)b2 + (int)b3;
+                            j = s.list[r][lane][kk - off];
                         } else {
                             r = w;
                             j = s.list[w][lane][kk];
