@@ -34,6 +34,10 @@ CANDIDATES = [
     {"cell_target": 96, "h_margin": 0.1},
     {"cell_target": 128, "h_margin": 0.1},
     {"cell_target": 64, "h_margin": 0.05},
+    # a wider margin stages more of each source at once: fewer stagings again
+    # when h starts far from its root (random sets solved from a uniform guess)
+    {"cell_target": 32, "h_margin": 0.2},
+    {"cell_target": 48, "h_margin": 0.2},
 ]
 
 # tile groups searched after the decomposition (sph.SPH_SWEEP_* and
