@@ -227,67 +227,106 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t* kin, 
 }
 
 // ---------------------------------------------------------------- generic exclusive scan (u32)
+// Three launches: per-tile sums, a scan of the tile sums, the tiles' scans.
+// One or two arrays (NA) are scanned together, each with its own sums.
 constexpr int SC_THREADS = 256;
 constexpr int SC_ITEMS = 8;
 constexpr int SC_TILE = SC_THREADS * SC_ITEMS;
+constexpr int SC_WAVES = SC_THREADS / kWave;
 
-__device__ inline uint32_t block_incl_scan(uint32_t v, uint32_t* sh)
+// inclusive scan across the block of one value per thread: shuffles within
+// each wavefront, then the wavefront totals through LDS
+__device__ inline uint32_t block_incl_scan(uint32_t v, uint32_t* wsum)
 {
-    const int tid = threadIdx.x;
-    sh[tid] = v;
-    __syncthreads();
-    for (int off = 1; off < SC_THREADS; off <<= 1) {
-        uint32_t t = tid >= off ? sh[tid - off] : 0;
-        __syncthreads();
-        sh[tid] += t;
-        __syncthreads();
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t t = __shfl_up(v, o, kWave);
+        if (lane >= o) v += t;
     }
-    uint32_t r = sh[tid];
+    if (lane == kWave - 1) wsum[w] = v;
     __syncthreads();
-    return r;
+    uint32_t off = 0;
+    for (int k = 0; k < w; k++) off += wsum[k];
+    __syncthreads();   // wsum may be written again
+    return v + off;
 }
 
-__global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const uint32_t* in, int64_t n, uint32_t* sums)
+// the SC_ITEMS consecutive values from base (zeros past n); two 16-byte loads
+// where the whole run is in range and the array is 16-byte aligned
+__device__ inline void scan_load(const uint32_t* in, int64_t base, int64_t n, uint32_t v[SC_ITEMS])
 {
-    __shared__ uint32_t sh[SC_THREADS];
-    int64_t base = (int64_t)blockIdx.x * SC_TILE + (int64_t)threadIdx.x * SC_ITEMS;
-    uint32_t s = 0;
-    for (int k = 0; k < SC_ITEMS; k++) if (base + k < n) s += in[base + k];
-    uint32_t inc = block_incl_scan(s, sh);
-    if (threadIdx.x == SC_THREADS - 1) sums[blockIdx.x] = inc;
-}
-
-__global__ __launch_bounds__(SC_THREADS) void k_scan_top(uint32_t* sums, int nb, uint32_t* total)
-{
-    __shared__ uint32_t sh[SC_THREADS];
-    __shared__ uint32_t last;
-    uint32_t carry = 0;
-    for (int b0 = 0; b0 < nb; b0 += SC_THREADS) {
-        int b = b0 + threadIdx.x;
-        uint32_t v = b < nb ? sums[b] : 0;
-        uint32_t inc = block_incl_scan(v, sh);
-        if (b < nb) sums[b] = carry + inc - v;
-        if (threadIdx.x == SC_THREADS - 1) last = inc;
-        __syncthreads();
-        carry += last;
-        __syncthreads();
+    if (base + SC_ITEMS <= n && (reinterpret_cast<uintptr_t>(in) & 15) == 0) {
+        const uint4 a = *reinterpret_cast<const uint4*>(in + base);
+        const uint4 b = *reinterpret_cast<const uint4*>(in + base + 4);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+        for (int k = 0; k < SC_ITEMS; k++) v[k] = base + k < n ? in[base + k] : 0u;
     }
-    if (threadIdx.x == 0 && total) *total = carry;
 }
 
-__global__ __launch_bounds__(SC_THREADS) void k_scan_down(const uint32_t* in, int64_t n,
-                                                          const uint32_t* sums, uint32_t* out)
+template <int NA>
+__global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const uint32_t* in0, const uint32_t* in1, int64_t n,
+                                                            uint32_t* sums, int nb)
 {
-    __shared__ uint32_t sh[SC_THREADS];
-    int64_t base = (int64_t)blockIdx.x * SC_TILE + (int64_t)threadIdx.x * SC_ITEMS;
-    uint32_t v[SC_ITEMS];
-    uint32_t s = 0;
-    for (int k = 0; k < SC_ITEMS; k++) { v[k] = (base + k < n) ? in[base + k] : 0; s += v[k]; }
-    uint32_t inc = block_incl_scan(s, sh);
-    uint32_t run = sums[blockIdx.x] + inc - s;
-    for (int k = 0; k < SC_ITEMS; k++) {
-        if (base + k < n) out[base + k] = run;
-        run += v[k];
+    __shared__ uint32_t wsum[SC_WAVES];
+    const int64_t base = (int64_t)blockIdx.x * SC_TILE + (int64_t)threadIdx.x * SC_ITEMS;
+#pragma unroll
+    for (int a = 0; a < NA; a++) {
+        uint32_t v[SC_ITEMS];
+        scan_load(a == 0 ? in0 : in1, base, n, v);
+        uint32_t t = 0;
+        for (int k = 0; k < SC_ITEMS; k++) t += v[k];
+        const uint32_t inc = block_incl_scan(t, wsum);
+        if (threadIdx.x == SC_THREADS - 1) sums[(int64_t)a * nb + blockIdx.x] = inc;
+    }
+}
+
+// exclusive scan of the nb tile sums of each array in place, one block: each
+// thread takes a run of consecutive sums
+template <int NA>
+__global__ __launch_bounds__(SC_THREADS) void k_scan_top(uint32_t* sums, int nb, uint32_t* total0, uint32_t* total1)
+{
+    __shared__ uint32_t wsum[SC_WAVES];
+    const int per = (nb + SC_THREADS - 1) / SC_THREADS;
+    const int b0 = threadIdx.x * per, b1 = min(nb, b0 + per);
+#pragma unroll
+    for (int a = 0; a < NA; a++) {
+        uint32_t* sa = sums + (int64_t)a * nb;
+        uint32_t t = 0;
+        for (int b = b0; b < b1; b++) t += sa[b];
+        const uint32_t inc = block_incl_scan(t, wsum);
+        uint32_t run = inc - t;
+        for (int b = b0; b < b1; b++) {
+            const uint32_t x = sa[b];
+            sa[b] = run;
+            run += x;
+        }
+        uint32_t* tot = a == 0 ? total0 : total1;
+        if (threadIdx.x == SC_THREADS - 1 && tot) *tot = inc;
+    }
+}
+
+template <int NA>
+__global__ __launch_bounds__(SC_THREADS) void k_scan_down(const uint32_t* in0, const uint32_t* in1, int64_t n,
+                                                          const uint32_t* sums, int nb, uint32_t* out0,
+                                                          uint32_t* out1)
+{
+    __shared__ uint32_t wsum[SC_WAVES];
+    const int64_t base = (int64_t)blockIdx.x * SC_TILE + (int64_t)threadIdx.x * SC_ITEMS;
+#pragma unroll
+    for (int a = 0; a < NA; a++) {
+        uint32_t v[SC_ITEMS];
+        scan_load(a == 0 ? in0 : in1, base, n, v);
+        uint32_t t = 0;
+        for (int k = 0; k < SC_ITEMS; k++) t += v[k];
+        const uint32_t inc = block_incl_scan(t, wsum);
+        uint32_t run = sums[(int64_t)a * nb + blockIdx.x] + inc - t;
+        uint32_t* out = a == 0 ? out0 : out1;
+        for (int k = 0; k < SC_ITEMS; k++) {
+            if (base + k < n) out[base + k] = run;
+            run += v[k];
+        }
     }
 }
 
@@ -1065,15 +1104,26 @@ void radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* k2, uint32_t* v2, int6
     }
 }
 
-size_t scan_scratch_words(int64_t n) { return (size_t)((n + SC_TILE - 1) / SC_TILE) + 1; }
+// tile sums of two arrays scanned together
+size_t scan_scratch_words(int64_t n) { return 2 * (size_t)((n + SC_TILE - 1) / SC_TILE) + 1; }
 
 void exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* scratch, uint32_t* total,
                     hipStream_t st)
 {
-    int nb = (int)((n + SC_TILE - 1) / SC_TILE);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(SC_THREADS), 0, st, in, n, scratch);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SC_THREADS), 0, st, scratch, nb, total);
-    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(SC_THREADS), 0, st, in, n, scratch, out);
+    const int nb = (int)((n + SC_TILE - 1) / SC_TILE);
+    if (nb > 0) hipLaunchKernelGGL(k_scan_reduce<1>, dim3(nb), dim3(SC_THREADS), 0, st, in, in, n, scratch, nb);
+    hipLaunchKernelGGL(k_scan_top<1>, dim3(1), dim3(SC_THREADS), 0, st, scratch, nb, total, total);   // total 0 if empty
+    if (nb > 0) hipLaunchKernelGGL(k_scan_down<1>, dim3(nb), dim3(SC_THREADS), 0, st, in, in, n, scratch, nb, out, out);
+}
+
+void exclusive_scan2(const uint32_t* in0, uint32_t* out0, uint32_t* total0, const uint32_t* in1, uint32_t* out1,
+                     uint32_t* total1, int64_t n, uint32_t* scratch, hipStream_t st)
+{
+    const int nb = (int)((n + SC_TILE - 1) / SC_TILE);
+    if (nb > 0) hipLaunchKernelGGL(k_scan_reduce<2>, dim3(nb), dim3(SC_THREADS), 0, st, in0, in1, n, scratch, nb);
+    hipLaunchKernelGGL(k_scan_top<2>, dim3(1), dim3(SC_THREADS), 0, st, scratch, nb, total0, total1);
+    if (nb > 0)
+        hipLaunchKernelGGL(k_scan_down<2>, dim3(nb), dim3(SC_THREADS), 0, st, in0, in1, n, scratch, nb, out0, out1);
 }
 
 void launch_cells(const uint64_t* keys, uint32_t* flag, uint32_t* cellx, int64_t n, int top_bits,

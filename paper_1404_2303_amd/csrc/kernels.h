@@ -123,6 +123,9 @@ void radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* k2, uint32_t* v2, int6
 size_t scan_scratch_words(int64_t n);
 void exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* scratch, uint32_t* total,
                     hipStream_t st);
+// two arrays of n scanned together, each with its own output and total (scratch of scan_scratch_words(n))
+void exclusive_scan2(const uint32_t* in0, uint32_t* out0, uint32_t* total0, const uint32_t* in1, uint32_t* out1,
+                     uint32_t* total1, int64_t n, uint32_t* scratch, hipStream_t st);
 void launch_cells(const uint64_t* keys, uint32_t* flag, uint32_t* cellx, int64_t n, int top_bits,
                   const BoxInfo* boxes, CellInfo* cells, int32_t* cell_map, int64_t map_total,
                   uint32_t* cell_of, int32_t* ncells, uint32_t* scan_scratch, int64_t cell_cap,

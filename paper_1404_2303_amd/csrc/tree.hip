@@ -394,8 +394,8 @@ void launch_tree(const Particles& p, const TreeView& tv, const BoxInfo* boxes, i
     hipLaunchKernelGGL(k_tree_chg, grid_for(n), dim3(256), 0, st, tv.keys, n, tv.depth, tv.chg);
     for (int l = 0; l <= tv.depth; l++) {
         hipLaunchKernelGGL(k_lvl_prep, grid_for(n), dim3(256), 0, st, tv, boxes, p.h, l);
-        exclusive_scan(tv.flag, tv.scan, n, scan_scratch, (uint32_t*)(tv.nnodes + l), st);
-        exclusive_scan(tv.small, tv.psmall, n, scan_scratch, tv.psmall + n, st);
+        exclusive_scan2(tv.flag, tv.scan, (uint32_t*)(tv.nnodes + l), tv.small, tv.psmall, tv.psmall + n, n,
+                        scan_scratch, st);
         hipLaunchKernelGGL(k_lvl_nodes, grid_for(n), dim3(256), 0, st, tv, l);
         hipLaunchKernelGGL(k_lvl_split, grid_for(n), dim3(256), 0, st, tv, l, split_count, split_frac);
     }
