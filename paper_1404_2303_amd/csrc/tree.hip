@@ -43,18 +43,31 @@ __global__ void k_tree_chg(const uint64_t* keys, int64_t n, int depth, uint8_t* 
     chg[i] = (uint8_t)(hb >= 3 * depth ? 0 : depth - hb / 3);
 }
 
-// run heads at level l, and whether h is below half the level's edge
-__global__ void k_lvl_prep(TreeView tv, const BoxInfo* boxes, const double* h, int l)
+// per particle (cell order), the number of levels whose edge is more than
+// twice its h: h is below half the edge at levels 0 .. count - 1 (the edges
+// halve with each level).  Kept in tv.lev until the leaf levels replace it.
+__global__ void k_small_levels(TreeView tv, const BoxInfo* boxes, const double* h)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= tv.n) return;
-    tv.flag[i] = tv.chg[i] <= l ? 1u : 0u;
     uint32_t c[3];
     int b;
     key_coords(tv.keys[i], tv.top_bits, tv.depth, c, &b);
     const BoxInfo& B = boxes[b];
-    const double emin = ldexp(fmin(B.e[0], fmin(B.e[1], B.e[2])), -l);
-    tv.small[i] = h[tv.perm[i]] < 0.5 * emin ? 1u : 0u;
+    const double e = fmin(B.e[0], fmin(B.e[1], B.e[2]));
+    const double hi = h[tv.perm[i]];
+    int cnt = 0;
+    while (cnt <= tv.depth && hi < 0.5 * ldexp(e, -cnt)) cnt++;
+    tv.lev[i] = (uint8_t)cnt;
+}
+
+// run heads at level l, and whether h is below half the level's edge
+__global__ void k_lvl_prep(TreeView tv, int l)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= tv.n) return;
+    tv.flag[i] = tv.chg[i] <= l ? 1u : 0u;
+    tv.small[i] = l < (int)tv.lev[i] ? 1u : 0u;
 }
 
 __global__ void k_lvl_nodes(TreeView tv, int l)
@@ -392,8 +405,9 @@ void launch_tree(const Particles& p, const TreeView& tv, const BoxInfo* boxes, i
     const int64_t n = tv.n;
     if (n <= 0) return;
     hipLaunchKernelGGL(k_tree_chg, grid_for(n), dim3(256), 0, st, tv.keys, n, tv.depth, tv.chg);
+    hipLaunchKernelGGL(k_small_levels, grid_for(n), dim3(256), 0, st, tv, boxes, p.h);
     for (int l = 0; l <= tv.depth; l++) {
-        hipLaunchKernelGGL(k_lvl_prep, grid_for(n), dim3(256), 0, st, tv, boxes, p.h, l);
+        hipLaunchKernelGGL(k_lvl_prep, grid_for(n), dim3(256), 0, st, tv, l);
         exclusive_scan2(tv.flag, tv.scan, (uint32_t*)(tv.nnodes + l), tv.small, tv.psmall, tv.psmall + n, n,
                         scan_scratch, st);
         hipLaunchKernelGGL(k_lvl_nodes, grid_for(n), dim3(256), 0, st, tv, l);
