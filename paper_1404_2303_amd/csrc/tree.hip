@@ -242,11 +242,16 @@ __device__ inline float dir_weight(int d)
 template <bool FILL>
 __global__ void k_tree_sources(TreeView tv, const CellInfo* cells, const int32_t* ncells, const BoxInfo* boxes,
                                const int32_t* cell_map, Source* src, int64_t src_cap, uint32_t* group,
-                               uint32_t* status)
+                               uint32_t* status, int64_t cell_cap)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t t = g / 27;
-    const int oi = (int)(g - t * 27);
+    // threads run over the leaves for one neighbour offset at a time: the
+    // lanes of a wavefront walk the same offset from consecutive (nearby)
+    // leaves, so their walks are alike; the counts stay leaf-major (g)
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 27 * cell_cap) return;
+    const int oi = (int)(k / cell_cap);
+    const int64_t t = k - (int64_t)oi * cell_cap;
+    const int64_t g = t * 27 + oi;
     if (t >= *ncells) return;
     const CellInfo T = cells[t];
     const BoxInfo& B = boxes[T.box];
@@ -440,10 +445,10 @@ void launch_tree_sources(const TreeView& tv, const CellInfo* cells, const int32_
     if (cell_cap <= 0) return;
     const int64_t ng = 27 * cell_cap;
     hipLaunchKernelGGL(k_tree_sources<false>, grid_for(ng), dim3(256), 0, st, tv, cells, ncells, boxes, cell_map,
-                       src, src_cap, group, status);
+                       src, src_cap, group, status, cell_cap);
     exclusive_scan(group, group, ng, scan_scratch, group + ng, st);
     hipLaunchKernelGGL(k_tree_sources<true>, grid_for(ng), dim3(256), 0, st, tv, cells, ncells, boxes, cell_map,
-                       src, src_cap, group, status);
+                       src, src_cap, group, status, cell_cap);
     // one wavefront per leaf; leaves number at most cell_cap, the grid strides over them
     const int64_t fb = (cell_cap + FIN_THREADS / kWave - 1) / (FIN_THREADS / kWave);
     hipLaunchKernelGGL(k_src_finish, dim3((unsigned)(fb < 2048 ? fb : 2048)), dim3(FIN_THREADS), 0, st, cells,
