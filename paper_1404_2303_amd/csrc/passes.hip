@@ -28,9 +28,13 @@
 //
 // Density (Eqs. (2)-(3)): the Newton iteration on h runs inside the unit.
 // The first sweep lists the neighbours within a slightly larger radius; later
-// Newton evaluations reuse the lists while h stays inside it.  The
-// per-particle quantities of the force stage (Omega, P, c, A = P/(Omega rho^2),
-// the Balsara switch of Sec. 4.1) are formed at the end.
+// Newton evaluations reuse the lists while h stays inside it.  Once every
+// wavefront holds its whole list, the four lists of a target are evaluated
+// together, their entries dealt out to the four wavefronts in turn.  A unit
+// whose sources take several staging batches starts with an evaluation of
+// every sum, which also serves as a Newton step.  The per-particle
+// quantities of the force stage (Omega, P, c, A = P/(Omega rho^2), the
+// Balsara switch of Sec. 4.1) are formed at the end.
 // Force (Eqs. (4)-(5) + Sec. 4.1 viscosity): one sweep over r < max(h_i, h_j).
 // A cell of more than shared_min particles is swept shared instead: each
 // wavefront takes its own 64 targets and walks the sources staged by all four,
