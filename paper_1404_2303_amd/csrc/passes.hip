@@ -47,6 +47,21 @@
 // the Newton step in double.
 #include "pairs.h"
 
+#ifdef SPH_COUNT_WALK
+// Counting build only: the walk tallies of the split density and force
+// kernels (candidates tested, list entries), read and cleared by the host.
+extern "C" int sph_walk_tally(unsigned long long out[4], int clear)
+{
+    if (hipMemcpyFromSymbol(out, HIP_SYMBOL(sph::g_walk_tally), 4 * sizeof(unsigned long long)) != hipSuccess)
+        return 1;
+    if (clear) {
+        const unsigned long long z[4] = {0, 0, 0, 0};
+        if (hipMemcpyToSymbol(HIP_SYMBOL(sph::g_walk_tally), z, sizeof(z)) != hipSuccess) return 1;
+    }
+    return 0;
+}
+#endif
+
 namespace sph {
 // ---------------------------------------------------------------- density
 // waves per SIMD the register budget is held to: in FP32, four work-groups of

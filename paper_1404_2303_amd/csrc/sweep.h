@@ -77,6 +77,12 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
+#ifdef SPH_COUNT_WALK
+// Counting build only: per translation unit, [density, force][candidate
+// tests, list entries] over the walks of its kernels.
+static __device__ unsigned long long g_walk_tally[2][2];
+#endif
+
 // LDS writes of one lane become visible to the other lanes of its wavefront
 __device__ __forceinline__ void wave_sync()
 {
@@ -358,6 +364,10 @@ __device__ __forceinline__ int walk(Smem<R, NACC, FORCE, CFG>& s, int w, int r, 
     // A step reads its STEP staged particles before it writes any list slot:
     // list entries are bytes, which may alias anything, so the reads could not
     // be moved ahead of the writes by the compiler.
+#ifdef SPH_COUNT_WALK
+    unsigned long long n_tests = 0;   // uniform: candidates tested by the active lanes
+    const int cnt_in = cnt;
+#endif
     using R4 = typename Vec4T<R>::T;
     auto test = [&](const R4& e, R hj2) {
         if constexpr (FORCE) {
@@ -391,6 +401,10 @@ __device__ __forceinline__ int walk(Smem<R, NACC, FORCE, CFG>& s, int w, int r, 
             *wp = (uint8_t)(jj + k);  // the free slot; kept only on a hit
             append(wp, hit[k]);
         }
+#ifdef SPH_COUNT_WALK
+        for (int k = 0; k < STEP; k++)
+            if (jj + k < je) n_tests += (unsigned long long)__popcll(mact);
+#endif
     };
     while (seg < nseg) {
         const int je = uniform(s.seg_e[r][seg]);
@@ -429,6 +443,16 @@ __device__ __forceinline__ int walk(Smem<R, NACC, FORCE, CFG>& s, int w, int r, 
     cnt = (int)(wp - lst);
     seg_io = seg;
     jj_io = jj;
+#ifdef SPH_COUNT_WALK
+    {
+        double added = (double)(cnt - cnt_in);
+        for (int o = 32; o > 0; o >>= 1) added += __shfl_xor(added, o, 64);
+        if (lane == 0) {
+            atomicAdd(&g_walk_tally[FORCE ? 1 : 0][0], n_tests);
+            atomicAdd(&g_walk_tally[FORCE ? 1 : 0][1], (unsigned long long)added);
+        }
+    }
+#endif
     return cnt;
 }
 

@@ -32,6 +32,9 @@ def main():
                     help="cells of more particles than this are swept shared (sph_params.shared_min)")
     ap.add_argument("--staging", choices=("compact", "wide"), default="compact",
                     help="density staging of the lattice and mixture workloads (sph_params.staging)")
+    ap.add_argument("--walk-counts", action="store_true",
+                    help="lattice or mixture: run the counting build (build_lib --count) and print the candidates "
+                         "the density and force walks test and the list entries they keep, per pass")
     ap.add_argument("--params", default="",
                     help="JSON object of further sph_params fields for the lattice and mixture workloads, "
                          "e.g. the tuned values a bench line reports; they override the options above")
@@ -40,6 +43,9 @@ def main():
 
     import torch
     from . import sph, workloads
+    if args.walk_counts:
+        from . import build_lib
+        sph.LIB_PATH = build_lib.COUNT_LIB
     if args.workload == "sod":
         ps = workloads.sod(37)
         parts = sph.Particles.from_numpy(ps, "cuda:0")
@@ -90,6 +96,30 @@ def main():
         ctx.estimate_h(parts)
         ctx.run(parts)
     h0 = parts.h.clone()
+    if args.walk_counts:
+        import ctypes
+        lib = sph.load_library()
+        lib.sph_walk_tally.restype = ctypes.c_int
+        lib.sph_walk_tally.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        tally = (ctypes.c_ulonglong * 4)()
+        ctx.run(parts)   # the same start as the passes below
+        torch.cuda.synchronize()
+        parts.h.copy_(h0)
+        lib.sph_walk_tally(tally, 1)
+        d, f = ctx.run(parts)
+        torch.cuda.synchronize()
+        if lib.sph_walk_tally(tally, 1) != 0:
+            raise RuntimeError("sph_walk_tally failed")
+        sides = int(d["n_dens"].sum().item())      # pairs with r < h_i, one per target side
+        pairs = int(f["n_pairs"].sum().item())      # pairs with r < max(h_i, h_j), counted from both sides
+        out = {"density_tests": tally[0], "density_list_entries": tally[1], "force_tests": tally[2],
+               "force_list_entries": tally[3], "density_sides": sides, "force_pairs_both_sides": pairs,
+               "density_tests_per_side": tally[0] / max(sides, 1),
+               "force_tests_per_pair_side": tally[2] / max(pairs, 1)}
+        print(json.dumps(out), flush=True)
+        ctx.close()
+        print("passes done", flush=True)
+        return
     for _ in range(args.passes):
         parts.h.copy_(h0)
         ctx.run(parts)
