@@ -27,6 +27,19 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+def test_counting_build_alone_exports_the_walk_tally():
+    # the counting build (build_lib --count) adds sph_walk_tally to the same
+    # ABI; the production library has no trace of it
+    from paper_1404_2303_amd import build_lib, sph
+    if not os.path.exists(build_lib.COUNT_LIB):
+        pytest.skip("the counting build is not built")
+    count = ctypes.CDLL(build_lib.COUNT_LIB)
+    assert hasattr(count, "sph_walk_tally")
+    for name in _declared():
+        assert hasattr(count, name), name
+    assert not hasattr(sph.load_library(), "sph_walk_tally")
+
+
 def test_status_strings_and_defaults():
     from paper_1404_2303_amd import sph
     lib = sph.load_library()
