@@ -67,8 +67,8 @@ namespace sph {
 // waves per SIMD the register budget is held to: in FP32, four work-groups of
 // four wavefronts per CU for configuration 0 (at most 128 VGPRs, the LDS of a
 // work-group under 40 KiB), three for configuration 1 (its larger staging);
-// FP64 is held to two by its LDS
-template <typename R, int CFG> constexpr int kDensWaves = sizeof(R) == 4 ? (CFG == 0 ? 4 : 3) : 2;
+// three in FP64 (at most 168 VGPRs, under 53 KiB of LDS)
+template <typename R, int CFG> constexpr int kDensWaves = sizeof(R) == 4 ? (CFG == 0 ? 4 : 3) : 3;
 
 template <typename R, int CFG>
 __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<R, CFG>))) void k_density(Decomp dc, CellData<R> cd, Sorted<R> so, GhostData<R> gd,
@@ -514,8 +514,9 @@ __global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(kDensWaves<
 }
 
 // ---------------------------------------------------------------- force
+// FP64: three work-groups per CU (at most 168 VGPRs); FP32 needs no bound to fit four
 template <typename R>
-__global__ __launch_bounds__(WGS) void k_force(Decomp dc, CellData<R> cd, Sorted<R> so, GhostData<R> gd,
+__global__ __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 1 : 3))) void k_force(Decomp dc, CellData<R> cd, Sorted<R> so, GhostData<R> gd,
                                                ForceOut out, PassConsts pc)
 {
     using R4 = typename Vec4T<R>::T;

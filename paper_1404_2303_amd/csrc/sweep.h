@@ -25,13 +25,14 @@ constexpr int WALK_PAD = WALK_STEP - 1;
 // serve the Newton iteration, so they are longer)
 // The FP32 density stage has two (SPH_STAGING_COMPACT and _WIDE): CFG 0 for
 // cells of up to ~80 particles (four work-groups per CU), CFG 1 with room for
-// cells of ~80-110 (three).
+// cells of ~80-110 (three).  FP64 stages 192 per wavefront, so that three
+// work-groups share a CU (under 53 KiB of LDS each).
 template <typename R, bool FORCE, int CFG = 0> struct PCfg;
 template <> struct PCfg<float, false, 0> { static constexpr int CAPW = 192, LISTW = 48; };
 template <> struct PCfg<float, false, 1> { static constexpr int CAPW = 256, LISTW = 48; };
 template <> struct PCfg<float, true, 0> { static constexpr int CAPW = 216, LISTW = 32; };
-template <int CFG> struct PCfg<double, false, CFG> { static constexpr int CAPW = 256, LISTW = 48; };
-template <> struct PCfg<double, true, 0> { static constexpr int CAPW = 256, LISTW = 32; };
+template <int CFG> struct PCfg<double, false, CFG> { static constexpr int CAPW = 192, LISTW = 48; };
+template <> struct PCfg<double, true, 0> { static constexpr int CAPW = 192, LISTW = 32; };
 
 // square root, reciprocal square root and reciprocal of the pair arithmetic:
 // the hardware instructions in FP32 (about 1 ulp), correctly rounded in FP64
