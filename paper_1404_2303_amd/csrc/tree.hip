@@ -235,6 +235,21 @@ __device__ inline float dir_weight(int d)
     return nz == 1 ? 1.0f : (nz == 2 ? 0.7f : 0.5f);
 }
 
+// Each particle's finest-level cell coordinates, decoded from its key into
+// the three per-particle arrays that are free once the leaves are built
+// (flag, small, psmall), for the walks below.
+__global__ void k_tree_coords(TreeView tv)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= tv.n) return;
+    uint32_t c[3];
+    int b;
+    key_coords(tv.keys[i], tv.top_bits, tv.depth, c, &b);
+    tv.flag[i] = c[0];
+    tv.small[i] = c[1];
+    tv.psmall[i] = c[2];
+}
+
 // One thread per (leaf T, top cell around T's): walk that top cell's subtree,
 // opening nodes within reach, and count (FILL = false) or write the leaves
 // found, in a group of 27 per leaf whose offsets come from a scan of the
@@ -281,9 +296,9 @@ __global__ void k_tree_sources(TreeView tv, const CellInfo* cells, const int32_t
             const int l = e >> 27, m = e & ((1 << 27) - 1);
             const int64_t lo = (int64_t)l * tv.stride + m;
             const uint32_t start = tv.node_start[lo], end = tv.node_start[lo + 1];
-            uint32_t cf[3];
-            int b;
-            key_coords(tv.keys[start], tv.top_bits, D, cf, &b);
+            // the node's finest-level coordinates, from its first particle's
+            // (decoded once per build by k_tree_coords)
+            const uint32_t cf[3] = {tv.flag[start], tv.small[start], tv.psmall[start]};
             const int64_t sN = 1ll << (D - l);
             double dist2 = 0.0;
             int64_t cn[3];
@@ -443,6 +458,7 @@ void launch_tree_sources(const TreeView& tv, const CellInfo* cells, const int32_
                          int64_t cell_cap, hipStream_t st)
 {
     if (cell_cap <= 0) return;
+    hipLaunchKernelGGL(k_tree_coords, grid_for(tv.n), dim3(256), 0, st, tv);
     const int64_t ng = 27 * cell_cap;
     hipLaunchKernelGGL(k_tree_sources<false>, grid_for(ng), dim3(256), 0, st, tv, cells, ncells, boxes, cell_map,
                        src, src_cap, group, status, cell_cap);
