@@ -271,19 +271,21 @@ __global__ void k_tree_sources(TreeView tv, const CellInfo* cells, const int32_t
     const CellInfo T = cells[t];
     const BoxInfo& B = boxes[T.box];
     const int D = tv.depth;
-    const int64_t sT = 1ll << (D - T.level);
+    // coordinates in finest-level units stay below 2^23 (at most 1023 top
+    // cells of 2^12 finest units per axis, and one period of shift): int32
+    const int sT = 1 << (D - T.level);
     const double ef[3] = {ldexp(B.e[0], -D), ldexp(B.e[1], -D), ldexp(B.e[2], -D)};
     const double HT = T.hlim;
     const int64_t base = FILL ? (int64_t)group[g] : 0;
     int cnt = 0;
     const int o[3] = {oi / 9 - 1, (oi / 3) % 3 - 1, oi % 3 - 1};
     int tc[3];
-    int64_t shift[3];
+    int shift[3];
     for (int d = 0; d < 3; d++) {
         int v = (T.c[d] >> D) + o[d];
         shift[d] = 0;
-        if (v < 0) { v += B.nc[d]; shift[d] = -((int64_t)B.nc[d] << D); }
-        else if (v >= B.nc[d]) { v -= B.nc[d]; shift[d] = (int64_t)B.nc[d] << D; }
+        if (v < 0) { v += B.nc[d]; shift[d] = -(B.nc[d] << D); }
+        else if (v >= B.nc[d]) { v -= B.nc[d]; shift[d] = B.nc[d] << D; }
         tc[d] = v;
     }
     const int32_t m0 = cell_map[B.map_off + ((int64_t)tc[0] * B.nc[1] + tc[1]) * B.nc[2] + tc[2]];
@@ -299,13 +301,13 @@ __global__ void k_tree_sources(TreeView tv, const CellInfo* cells, const int32_t
             // the node's finest-level coordinates, from its first particle's
             // (decoded once per build by k_tree_coords)
             const uint32_t cf[3] = {tv.flag[start], tv.small[start], tv.psmall[start]};
-            const int64_t sN = 1ll << (D - l);
+            const int sN = 1 << (D - l);
             double dist2 = 0.0;
-            int64_t cn[3];
+            int cn[3];
             for (int d = 0; d < 3; d++) {
-                cn[d] = (int64_t)((cf[d] >> (D - l)) << (D - l)) + shift[d];
-                const int64_t a0 = T.c[d], a1 = T.c[d] + sT, b0 = cn[d], b1 = cn[d] + sN;
-                const int64_t gap = b0 > a1 ? b0 - a1 : (a0 > b1 ? a0 - b1 : 0);
+                cn[d] = (int)((cf[d] >> (D - l)) << (D - l)) + shift[d];
+                const int a0 = T.c[d], a1 = T.c[d] + sT, b0 = cn[d], b1 = cn[d] + sN;
+                const int gap = b0 > a1 ? b0 - a1 : (a0 > b1 ? a0 - b1 : 0);
                 const double gd = (double)gap * ef[d];
                 dist2 += gd * gd;
             }
