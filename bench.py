@@ -360,11 +360,12 @@ KERNEL_SOURCES = ["paper_1404_2303_amd/csrc/passes.hip", "paper_1404_2303_amd/cs
                   "paper_1404_2303_amd/csrc/pairs.h",
                   "paper_1404_2303_amd/csrc/kernels.h", "paper_1404_2303_amd/csrc/sph_internal.h"]
 TRAFFIC_PROFILE = "profiles/traffic_lattice2p20_fp32.md"
+COUNTERS_PROFILE = "profiles/counters_lattice2p20_fp32.md"
 
 
-def measured_traffic():
-    """HBM bytes per launch of the density kernel from the committed rocprofv3
-    counter summary, or None when the kernel sources changed since it was taken."""
+def _profile_value(path, key):
+    """An integer a committed rocprofv3 summary records for the density kernel,
+    or None when the kernel sources changed since the counters were taken."""
     import hashlib
     try:
         h = hashlib.sha256()
@@ -372,16 +373,27 @@ def measured_traffic():
             with open(os.path.join(ROOT, f), "rb") as fh:
                 h.update(fh.read())
         fields = {}
-        with open(os.path.join(ROOT, TRAFFIC_PROFILE)) as fh:
+        with open(os.path.join(ROOT, path)) as fh:
             for line in fh:
-                if ":" in line and line.split(":")[0] in ("density_traffic_bytes", "source_sha256"):
+                if ":" in line and line.split(":")[0] in (key, "source_sha256"):
                     k, v = line.split(":", 1)
                     fields[k.strip()] = v.strip()
         if fields.get("source_sha256") != h.hexdigest():
             return None
-        return int(fields["density_traffic_bytes"])
+        return int(fields[key])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def measured_traffic():
+    """HBM bytes per launch of the density kernel (FETCH_SIZE + WRITE_SIZE, calibrated)."""
+    return _profile_value(TRAFFIC_PROFILE, "density_traffic_bytes")
+
+
+def measured_executed_flop():
+    """FP32 arithmetic the density launch issues, from the instruction-mix counters:
+    (2 FMA + MUL + ADD + TRANS) wave64 instructions x 64 lanes."""
+    return _profile_value(COUNTERS_PROFILE, "density_executed_fp32_flop")
 
 
 def roofline(res):
@@ -395,9 +407,15 @@ def roofline(res):
     achieved = flops / (ms * 1e-3) / 1e12
     peak = PEAK["fp64" if res["precision"] == "fp64" else "fp32"]
     traffic = measured_traffic() if (name == "density" and res["precision"] == "fp32") else None
+    executed = measured_executed_flop() if (name == "density" and res["precision"] == "fp32") else None
     round_flops = FLOPS_ROUND[name] * P_unordered
     return {"bound": "alu", "kernel": name, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": achieved / peak, "traffic": traffic,
+            # the counters' issued FP32 arithmetic at this run's kernel time (None once the
+            # kernel has changed since the counters were taken)
+            "executed": None if executed is None else {
+                "TFLOP/s": executed / (ms * 1e-3) / 1e12, "frac": executed / (ms * 1e-3) / 1e12 / peak,
+                "over_algorithmic": executed / flops},
             "flop_per_unit": {"density_pair": FLOPS_DENSITY_PAIR, "density_side": FLOPS_DENSITY_SIDE,
                               "force_pair": FLOPS_FORCE_PAIR, "units": {"pairs": P_unordered, "sides": res["S"]}},
             "frac_at_round_constants": round_flops / (ms * 1e-3) / 1e12 / peak,
