@@ -17,7 +17,7 @@ constexpr int WGS = NW * kWave;
 constexpr int kMaxSegW = 28;          // staged segments per wavefront and batch
 constexpr int NACC_D = 9;             // density partial sums per target
 constexpr int NACC_F = 6;             // force partial sums per target
-constexpr float kCacheSlack = 0.08f;  // neighbour lists cover h (1 + slack)
+constexpr float kCacheSlack = 0.05f;  // neighbour lists cover h (1 + slack)
 constexpr int WALK_STEP = 4;          // staged particles tested per walk step
 constexpr int WALK_PAD = WALK_STEP - 1;
 
